@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module builds inputs only: planted symmetric tensors, rank-1 factor
+lists, start vectors drawn by numpy, and a synthetic LDA-shaped corpus.  It
+holds none of the sketching or power-method arithmetic, so both the HIP path
+and the CPU oracle can take their inputs from here.
+
+Construction of the planted tensors follows the synthetic setting of the
+paper's experiments (Section 5.1): an orthonormal basis, positive weights and
+a symmetric Gaussian noise tensor drawn for i<=j<=k and copied to every
+permutation of the indices.  The noise standard deviation is 1/n^1.5 times
+the noise level, so that the Frobenius norm of the noise is about the level.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Planted:
+    T: np.ndarray          # [n][n][n] row-major, float64 or float32
+    lam: np.ndarray        # [k] float64 planted weights
+    V: np.ndarray          # [k][n] float64 planted unit vectors (rows)
+    noise: float
+
+
+def symmetric_noise(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Symmetric Gaussian tensor with std 1/n^1.5 per entry.
+
+    Entries with i<=j<=k are drawn independently; every other entry copies
+    the entry at its sorted index triple (Section 5.1 of the paper).
+    """
+    G = rng.standard_normal((n, n, n)) * (1.0 / n ** 1.5)
+    idx = np.indices((n, n, n), dtype=np.int32).reshape(3, -1)
+    idx.sort(axis=0)
+    E = G[idx[0], idx[1], idx[2]].reshape(n, n, n)
+    return E
+
+
+def planted_tensor(n: int, k: int, noise: float, seed: int,
+                   lam_range=(1.0, 2.0), dtype=np.float64) -> Planted:
+    """T = sum_i lam_i v_i^{(x)3} + noise * E with v_i orthonormal (QR of a
+    Gaussian n x k matrix) and lam_i ~ U[lam_range]."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    lam = rng.uniform(lam_range[0], lam_range[1], size=k)
+    T = np.einsum("r,ir,jr,kr->ijk", lam, Q, Q, Q, optimize=True)
+    if noise != 0.0:
+        T = T + noise * symmetric_noise(rng, n)
+    return Planted(T=np.ascontiguousarray(T.astype(dtype)), lam=lam,
+                   V=np.ascontiguousarray(Q.T), noise=noise)
+
+
+def random_unit_vectors(rng: np.random.Generator, rows: int, n: int) -> np.ndarray:
+    X = rng.standard_normal((rows, n))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    return X
+
+
+def start_vectors(seed: int, k: int, L: int, n: int) -> np.ndarray:
+    """Start vectors u0[k][L][n], each uniform on the unit sphere."""
+    rng = np.random.default_rng(seed)
+    return random_unit_vectors(rng, k * L, n).reshape(k, L, n)
+
+
+@dataclasses.dataclass
+class FactorInstance:
+    n: int
+    k: int
+    b: int
+    lam: np.ndarray        # [k] float64
+    A: np.ndarray          # [k][n] float64, unit rows (not orthogonal)
+
+
+def factor_instances(count: int, seed: int, n_range=(100, 2000), k_range=(5, 50),
+                     lam_range=(1.0, 10.0), b_choices=(4096, 16384, 65536)):
+    """Uneven low-rank tensors given only by their factors."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        b = int(rng.choice(np.asarray(b_choices)))
+        lam = rng.uniform(lam_range[0], lam_range[1], size=k)
+        A = random_unit_vectors(rng, k, n)
+        out.append(FactorInstance(n=n, k=k, b=b, lam=lam, A=A))
+    return out
+
+
+@dataclasses.dataclass
+class Corpus:
+    rowptr: np.ndarray     # [D+1] int32
+    col: np.ndarray        # [nnz] int32 word ids
+    cnt: np.ndarray        # [nnz] int32 counts
+    V: int
+    K: int
+    alpha: np.ndarray      # [K]
+    Phi: np.ndarray        # [V][K] topic-word distributions (columns sum to 1)
+
+
+def lda_corpus(D: int, V: int, K: int, seed: int, mean_len: float = 150.0,
+               beta: float = 0.01, alpha: float = 0.1, min_len: int = 3) -> Corpus:
+    """Synthetic LDA corpus: Phi_k ~ Dir(beta 1_V), theta_d ~ Dir(alpha 1_K),
+    m_d ~ Poisson(mean_len) (resampled below min_len), words ~ Cat(Phi theta_d).
+    Word counts are stored as CSR with sorted word ids."""
+    rng = np.random.default_rng(seed)
+    Phi = rng.dirichlet(np.full(V, beta), size=K).T.copy()      # [V][K]
+    alph = np.full(K, alpha)
+    rowptr = np.zeros(D + 1, dtype=np.int64)
+    cols, cnts = [], []
+    for d in range(D):
+        m = 0
+        while m < min_len:
+            m = int(rng.poisson(mean_len))
+        theta = rng.dirichlet(alph)
+        p = Phi @ theta
+        p /= p.sum()
+        c = rng.multinomial(m, p)
+        nz = np.flatnonzero(c)
+        cols.append(nz.astype(np.int32))
+        cnts.append(c[nz].astype(np.int32))
+        rowptr[d + 1] = rowptr[d] + nz.size
+    return Corpus(rowptr=rowptr.astype(np.int32), col=np.concatenate(cols),
+                  cnt=np.concatenate(cnts), V=V, K=K, alpha=alph, Phi=Phi)
