@@ -1,0 +1,176 @@
+/*
+ * tsk.h -- C ABI of the MI355X (gfx950) sketched tensor CP decomposition library.
+ *
+ * The library builds tensor sketches of a symmetric 3rd-order tensor and runs
+ * the robust tensor power method on them, computing every contraction through
+ * FFTs of sketched vectors (Wang, Tung, Smola, Anandkumar, "Fast and
+ * Guaranteed Tensor Decomposition via Sketching", NIPS 2015).
+ *
+ * Conventions shared by every call:
+ *   - Pointers are DEVICE pointers unless the argument says "host".  The
+ *     caller allocates and owns every buffer passed in; the library owns only
+ *     its context, its table objects and internal workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued asynchronously on it.
+ *   - Every call validates its arguments on the host before enqueuing any
+ *     work and returns a tsk_status; nothing throws across the ABI.  The text
+ *     of the last failure on the calling thread is tsk_last_error().
+ *   - Indices are 0-based.  The DFT is unnormalised forward,
+ *     F(x)_k = sum_t x_t exp(-2 pi i k t / b); the inverse carries 1/b.
+ *   - A sketch is stored as its half spectrum, b/2+1 complex values
+ *     (interleaved re, im), for each of the B independent sketches:
+ *       S64 : double[B][b/2+1][2]  master copy (FP64)
+ *       S32 : float [B][b/2+1][2]  working copy used by the FP32 power method
+ *   - Limits: 1 <= n <= 65535, b a power of two with 64 <= b <= 16384
+ *     (b <= 8192 for the FP64 power method), 1 <= B <= 64, L >= 1, T >= 1,
+ *     1 <= k <= n.  Larger b returns TSK_EUNSUPPORTED.
+ */
+#ifndef TSK_H
+#define TSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSK_OK = 0,
+  TSK_EINVAL = -1,       /* null pointer or out-of-range argument          */
+  TSK_ESHAPE = -2,       /* sizes inconsistent with the tables / each other */
+  TSK_ENOMEM = -3,       /* device workspace allocation failed              */
+  TSK_EHIP = -4,         /* a HIP runtime call failed                       */
+  TSK_EUNSUPPORTED = -5  /* valid request outside the built kernel limits   */
+} tsk_status;
+
+typedef enum { TSK_F32 = 0, TSK_F64 = 1 } tsk_dtype;
+
+typedef struct tsk_ctx* tsk_ctx_t;       /* per-device context + workspace  */
+typedef struct tsk_tables* tsk_tables_t; /* device copy of hash/sign tables */
+
+/* Library version string (static storage). */
+const char* tsk_version(void);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* tsk_last_error(void);
+
+/* Create a context on HIP device `device`; the device is made current.
+ * Destroy frees its workspace.  A context is not thread-safe: calls that
+ * share one must be serialised by the caller. */
+tsk_status tsk_create(tsk_ctx_t* out, int device);
+void tsk_destroy(tsk_ctx_t ctx);
+
+/* ---- Randomness (host only, no device work) ------------------------------
+ * Hash and sign tables h_j^(m): [n] -> [b], xi_j^(m): [n] -> {+1,-1} for
+ * sketch m < B and mode j in {0,1,2} (Algorithm 1, initialisation; the tensor
+ * sketch definition of Section 2).  Drawn from SplitMix64 (Steele, Lea and
+ * Flood 2014):
+ *   r  = mix64(mix64(seed ^ 0x68617368) + (m<<34 | j<<32 | i))
+ *   h  = ((r >> 32) * b) >> 32,   xi = bit 31 of r ? -1 : +1
+ * where mix64(x) is SplitMix64's output function applied to x.
+ * h_host: uint32[B][3][n], xi_host: int8[B][3][n], both host, caller-owned.
+ * Errors: TSK_EINVAL for null pointers, n < 1, b < 1, B < 1. */
+tsk_status tsk_hash_generate(uint64_t seed, int n, int b, int B,
+                             uint32_t* h_host, int8_t* xi_host);
+
+/* Start vectors drawn uniformly from the unit sphere (Algorithm 1, "draw
+ * u_0 uniformly at random from the unit sphere") for component `comp`:
+ *   r_e = mix64(mix64(seed ^ 0x75307530) + (comp<<40 | tau<<20 | 2i+e))
+ *   U_e = (r_e >> 11) 2^-53,  z_i = sqrt(-2 ln(1-U_0)) cos(2 pi U_1),
+ *   u = z / ||z||.
+ * u0_host: double[L][n], host.  Errors: TSK_EINVAL (null, L<1, n<1,
+ * L >= 2^20, n >= 2^19). */
+tsk_status tsk_init_vectors(uint64_t seed, int comp, int L, int n, double* u0_host);
+
+/* Upload tables (host arrays as produced by tsk_hash_generate, or any table
+ * with 0 <= h < b and xi in {+1,-1}) to the context's device and derive the
+ * bucket-sorted index order the kernels use for deterministic count
+ * sketches.  The tables object owns its device memory until
+ * tsk_tables_destroy.  Errors: TSK_EINVAL (range), TSK_EUNSUPPORTED (b). */
+tsk_status tsk_tables_create(tsk_ctx_t ctx, int n, int b, int B,
+                             const uint32_t* h_host, const int8_t* xi_host,
+                             tsk_tables_t* out);
+void tsk_tables_destroy(tsk_tables_t tab);
+
+/* ---- Sketch construction -------------------------------------------------
+ * Dense build, Eq. (1):  s^(m)(t) = sum over (h1(i)+h2(j)+h3(k)) mod b == t of
+ * xi1(i) xi2(j) xi3(k) T_ijk, for every m; then S64 = F(s) and S32 = (float)S64.
+ * T: [n][n][n] row-major, float (TSK_F32) or double (TSK_F64), n = tables' n.
+ * accumulate != 0 adds to S64 instead of overwriting it (the sketch is linear
+ * in T, Section 3.1).  FP32 input is accumulated in FP32 inside a work-group
+ * and summed across work-groups in FP64. */
+tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, const void* T,
+                                  tsk_dtype dtype, double* S64, float* S32,
+                                  int accumulate, void* stream);
+
+/* Factor build, Eq. (2) with linearity (Section 3.1):
+ *   S64^(m) (+)= sum_r lam_r F(s1 a_r) o F(s2 a_r) o F(s3 a_r),
+ * the tensor sum_r lam_r a_r^(x)3 is never formed.  lam: double[k],
+ * A: double[k][n] (rows a_r), both device.  All FFTs in FP64. */
+tsk_status tsk_sketch_build_factors(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam,
+                                    const double* A, int k, double* S64, float* S32,
+                                    int accumulate, void* stream);
+
+/* Spectra from time-domain sketches s_time: double[B][b] (e.g. a sketch kept
+ * by the caller), and back.  FP64 throughout. */
+tsk_status tsk_sketch_from_time(tsk_ctx_t ctx, int b, int B, const double* s_time,
+                                double* S64, float* S32, void* stream);
+tsk_status tsk_sketch_export(tsk_ctx_t ctx, int b, int B, const double* S64,
+                             double* s_time, void* stream);
+
+/* Deflation (Algorithm 1, deflation step): S64^(m) -= sum_r lam_r
+ * F(s1 u_r) o F(s2 u_r) o F(s3 u_r) for the c pairs (lam_r, u_r), then
+ * S32 = (float)S64.  lam: double[c], U: double[c][n], device.  FP64. */
+tsk_status tsk_sketch_deflate(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam,
+                              const double* U, int c, double* S64, float* S32,
+                              void* stream);
+
+/* ---- Contractions ---------------------------------------------------------
+ * One power step for L vectors (Algorithm 1 inner loop, Proposition 1):
+ *   sbar = F^-1( S^(m) o conj F(s2 u) o conj F(s3 u) ),  v^(m)_i = xi1(i) sbar[h1(i)]
+ *   vbar_i = med_m v^(m)_i,  u_out = vbar / ||vbar||.
+ * Even B takes the mean of the two middle values.  If ||vbar|| is zero or not
+ * finite, u_out = u_in and flags[tau] gets bit 0 set (flags are OR-ed, not
+ * cleared).  dtype TSK_F32 reads S32 and float vectors; TSK_F64 reads S64
+ * and double vectors.  U_in, U_out: [L][n] (may not alias).  V: nullable
+ * [L][B][n] per-sketch estimates.  flags: nullable int32[L]. */
+tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                            const double* S64, const float* S32, int L,
+                            const void* U_in, void* U_out, void* V, int32_t* flags,
+                            void* stream);
+
+/* T(u,u,u) estimates for L vectors (Eq. (3) with X = u(x)u(x)u):
+ *   lam_per[tau][m] = <s^(m), s^(m)(u^(x)3)> = sum_i u_i v^(m)_i(u),
+ *   lam_med[tau] = med_m lam_per[tau][m].
+ * U: [L][n] in dtype.  lam_med: double[L]; lam_per: nullable double[L][B]. */
+tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                            const double* S64, const float* S32, int L, const void* U,
+                            double* lam_med, double* lam_per, void* stream);
+
+/* ---- Decomposition --------------------------------------------------------
+ * Algorithm 1 for k components: per component, L restarts x T power steps on
+ * the sketches (all restarts and sketches batched in each launch), selection
+ * tau* = argmax_tau med_m T(u_T,u_T,u_T)^(m) (lowest tau on ties; non-finite
+ * values never win), u_hat = u_T^(tau*) renormalised in FP64,
+ * lam_hat = med_m <s^(m), s^(m)(u_hat^(x)3)> in FP64, deflation of S64 in FP64
+ * and refresh of S32.  The launches are recorded once per shape into a HIP
+ * graph and replayed.
+ *   dtype: precision of the power steps (TSK_F32 uses S32, TSK_F64 uses S64).
+ *   S64/S32: in: sketches of the tensor; out: sketches of the deflated tensor.
+ *   u0: nullable double[k][L][n]; NULL draws them with tsk_init_vectors(seed, c, ...).
+ *   lam_out: double[k]; U_out: double[k][n]; tau_out: nullable int32[k];
+ *   flags_out: nullable int32[k][L] (bit 0: a zero/non-finite median vector).
+ * plain != 0 runs the comparison path: one launch per (restart, step) with B
+ * work-groups each, no batching across restarts and no graph. */
+tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                         double* S64, float* S32, int k, int L, int T,
+                         const double* u0, uint64_t seed, double* lam_out,
+                         double* U_out, int32_t* tau_out, int32_t* flags_out,
+                         int plain, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSK_H */

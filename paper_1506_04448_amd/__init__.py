@@ -1,0 +1,332 @@
+"""Sketched tensor CP decomposition on MI355X -- Python binding of libtsk.so.
+
+Thin ctypes layer over the C ABI declared in ``include/tsk.h``: each function
+has the C entry point's name without the ``tsk_`` prefix, checks the torch
+tensors it is given (device, dtype, contiguity, size), passes their data
+pointers and the current HIP stream, and raises :class:`TskError` on a non-OK
+status.  Every step of the method runs in the library's HIP kernels; there is
+no fallback: if ``libtsk.so`` is missing, importing the compute functions
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
+    "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
+    "sketch_export", "sketch_deflate", "power_update", "contract_uuu", "decompose",
+    "F32", "F64",
+]
+
+F32 = 0
+F64 = 1
+_PKG = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_PKG, "libtsk.so")
+
+_STATUS = {0: "TSK_OK", -1: "TSK_EINVAL", -2: "TSK_ESHAPE", -3: "TSK_ENOMEM",
+           -4: "TSK_EHIP", -5: "TSK_EUNSUPPORTED"}
+
+
+class TskError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} -> {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.fn = fn
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_U64 = ctypes.c_uint64
+_SIGS = {
+    "tsk_version": ([], ctypes.c_char_p),
+    "tsk_last_error": ([], ctypes.c_char_p),
+    "tsk_create": ([ctypes.POINTER(_P), _I], _I),
+    "tsk_destroy": ([_P], None),
+    "tsk_hash_generate": ([_U64, _I, _I, _I, _P, _P], _I),
+    "tsk_init_vectors": ([_U64, _I, _I, _I, _P], _I),
+    "tsk_tables_create": ([_P, _I, _I, _I, _P, _P, ctypes.POINTER(_P)], _I),
+    "tsk_tables_destroy": ([_P], None),
+    "tsk_sketch_build_dense": ([_P, _P, _P, _I, _P, _P, _I, _P], _I),
+    "tsk_sketch_build_factors": ([_P, _P, _P, _P, _I, _P, _P, _I, _P], _I),
+    "tsk_sketch_from_time": ([_P, _I, _I, _P, _P, _P, _P], _I),
+    "tsk_sketch_export": ([_P, _I, _I, _P, _P, _P], _I),
+    "tsk_sketch_deflate": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
+    "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
+    "tsk_contract_uuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
+    "tsk_decompose": ([_P, _P, _I, _P, _P, _I, _I, _I, _P, _U64, _P, _P, _P, _P, _I, _P], _I),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtsk.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"libtsk.so not found at {library_path}: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        # Load torch first so the library binds to the same HIP runtime that
+        # owns torch's device memory (the two share the runtime's soname).
+        import torch  # noqa: F401
+        L = ctypes.CDLL(library_path)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        raise TskError(fn, status, lib().tsk_last_error().decode(errors="replace"))
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    return x.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _tensor(x, name, dtype, shape=None, allow_none=False):
+    import torch
+    if x is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(x.shape)}")
+    return x
+
+
+def hash_generate(seed: int, n: int, b: int, B: int):
+    """Host draw of the hash/sign tables: (h uint32[B][3][n], xi int8[B][3][n])."""
+    h = np.zeros((B, 3, n), dtype=np.uint32)
+    xi = np.zeros((B, 3, n), dtype=np.int8)
+    _check("tsk_hash_generate", lib().tsk_hash_generate(
+        seed & (2 ** 64 - 1), n, b, B, h.ctypes.data, xi.ctypes.data))
+    return h, xi
+
+
+def init_vectors(seed: int, comp: int, L: int, n: int) -> np.ndarray:
+    """Host draw of start vectors u0[L][n] (unit sphere) for one component."""
+    u = np.zeros((L, n), dtype=np.float64)
+    _check("tsk_init_vectors", lib().tsk_init_vectors(seed & (2 ** 64 - 1), comp, L, n,
+                                                        u.ctypes.data))
+    return u
+
+
+class Context:
+    """A library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = _P()
+        _check("tsk_create", lib().tsk_create(ctypes.byref(h), device))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tsk_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tables:
+    """Device copy of hash/sign tables (h[B][3][n] in [0,b), xi[B][3][n] in {+-1})."""
+
+    def __init__(self, ctx: Context, h: np.ndarray, xi: np.ndarray, b: int):
+        h = np.ascontiguousarray(h, dtype=np.uint32)
+        xi = np.ascontiguousarray(xi, dtype=np.int8)
+        if h.ndim != 3 or h.shape[1] != 3 or xi.shape != h.shape:
+            raise ValueError("tables must be [B][3][n]")
+        self.B, _, self.n = h.shape
+        self.b = b
+        self.ctx = ctx
+        t = _P()
+        _check("tsk_tables_create", lib().tsk_tables_create(
+            ctx.handle, self.n, b, self.B, h.ctypes.data, xi.ctypes.data, ctypes.byref(t)))
+        self.handle = t
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tsk_tables_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def new_sketch(tab: Tables, device="cuda"):
+    """Allocate (S64 float64[B][b/2+1][2], S32 float32[B][b/2+1][2]) for `tab`."""
+    import torch
+    H1 = tab.b // 2 + 1
+    return (torch.zeros((tab.B, H1, 2), dtype=torch.float64, device=device),
+            torch.zeros((tab.B, H1, 2), dtype=torch.float32, device=device))
+
+
+def _sk(tab, S64, S32, need32=False):
+    import torch
+    H1 = tab.b // 2 + 1
+    _tensor(S64, "S64", torch.float64, (tab.B, H1, 2))
+    _tensor(S32, "S32", torch.float32, (tab.B, H1, 2), allow_none=not need32)
+
+
+def sketch_build_dense(ctx, tab, T, S64, S32=None, accumulate=False, stream=None):
+    import torch
+    if T.dtype not in (torch.float32, torch.float64):
+        raise TypeError("T must be float32 or float64")
+    _tensor(T, "T", T.dtype, (tab.n, tab.n, tab.n))
+    _sk(tab, S64, S32)
+    dt = F32 if T.dtype == torch.float32 else F64
+    _check("tsk_sketch_build_dense", lib().tsk_sketch_build_dense(
+        ctx.handle, tab.handle, _ptr(T), dt, _ptr(S64), _ptr(S32), int(bool(accumulate)),
+        _stream(stream)))
+
+
+def sketch_build_factors(ctx, tab, lam, A, S64, S32=None, accumulate=False, stream=None):
+    import torch
+    k = lam.shape[0]
+    _tensor(lam, "lam", torch.float64, (k,))
+    _tensor(A, "A", torch.float64, (k, tab.n))
+    _sk(tab, S64, S32)
+    _check("tsk_sketch_build_factors", lib().tsk_sketch_build_factors(
+        ctx.handle, tab.handle, _ptr(lam), _ptr(A), k, _ptr(S64), _ptr(S32),
+        int(bool(accumulate)), _stream(stream)))
+
+
+def sketch_from_time(ctx, s_time, S64, S32=None, stream=None):
+    import torch
+    B, b = s_time.shape
+    _tensor(s_time, "s_time", torch.float64, (B, b))
+    _tensor(S64, "S64", torch.float64, (B, b // 2 + 1, 2))
+    _tensor(S32, "S32", torch.float32, (B, b // 2 + 1, 2), allow_none=True)
+    _check("tsk_sketch_from_time", lib().tsk_sketch_from_time(
+        ctx.handle, b, B, _ptr(s_time), _ptr(S64), _ptr(S32), _stream(stream)))
+
+
+def sketch_export(ctx, S64, b, s_time=None, stream=None):
+    import torch
+    B = S64.shape[0]
+    _tensor(S64, "S64", torch.float64, (B, b // 2 + 1, 2))
+    if s_time is None:
+        s_time = torch.empty((B, b), dtype=torch.float64, device=S64.device)
+    _tensor(s_time, "s_time", torch.float64, (B, b))
+    _check("tsk_sketch_export", lib().tsk_sketch_export(
+        ctx.handle, b, B, _ptr(S64), _ptr(s_time), _stream(stream)))
+    return s_time
+
+
+def sketch_deflate(ctx, tab, lam, U, S64, S32=None, stream=None):
+    import torch
+    c = lam.shape[0]
+    _tensor(lam, "lam", torch.float64, (c,))
+    _tensor(U, "U", torch.float64, (c, tab.n))
+    _sk(tab, S64, S32)
+    _check("tsk_sketch_deflate", lib().tsk_sketch_deflate(
+        ctx.handle, tab.handle, _ptr(lam), _ptr(U), c, _ptr(S64), _ptr(S32), _stream(stream)))
+
+
+def _spectra(tab, dt, S64, S32):
+    """The FP32 path reads S32, the FP64 path reads S64; either may be absent otherwise."""
+    import torch
+    H1 = tab.b // 2 + 1
+    _tensor(S64, "S64", torch.float64, (tab.B, H1, 2), allow_none=(dt == F32))
+    _tensor(S32, "S32", torch.float32, (tab.B, H1, 2), allow_none=(dt == F64))
+
+
+def _vdtype(dtype):
+    import torch
+    return (F32, torch.float32) if dtype in (F32, torch.float32, "f32") else (F64, torch.float64)
+
+
+def power_update(ctx, tab, U_in, S64=None, S32=None, U_out=None, V=None, flags=None,
+                 stream=None):
+    """One power step for U_in [L][n] (float32 uses S32, float64 uses S64)."""
+    import torch
+    dt, tdt = _vdtype(U_in.dtype)
+    L = U_in.shape[0]
+    _tensor(U_in, "U_in", tdt, (L, tab.n))
+    if U_out is None:
+        U_out = torch.empty_like(U_in)
+    _tensor(U_out, "U_out", tdt, (L, tab.n))
+    _tensor(V, "V", tdt, (L, tab.B, tab.n), allow_none=True)
+    _tensor(flags, "flags", torch.int32, (L,), allow_none=True)
+    _spectra(tab, dt, S64, S32)
+    _check("tsk_power_update", lib().tsk_power_update(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U_in), _ptr(U_out), _ptr(V),
+        _ptr(flags), _stream(stream)))
+    return U_out
+
+
+def contract_uuu(ctx, tab, U, S64=None, S32=None, lam_per=None, stream=None):
+    """T(u,u,u) estimates: returns (lam_med [L], lam_per [L][B]) as float64."""
+    import torch
+    dt, tdt = _vdtype(U.dtype)
+    L = U.shape[0]
+    _tensor(U, "U", tdt, (L, tab.n))
+    _spectra(tab, dt, S64, S32)
+    lam_med = torch.empty((L,), dtype=torch.float64, device=U.device)
+    if lam_per is None:
+        lam_per = torch.empty((L, tab.B), dtype=torch.float64, device=U.device)
+    _tensor(lam_per, "lam_per", torch.float64, (L, tab.B))
+    _check("tsk_contract_uuu", lib().tsk_contract_uuu(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U), _ptr(lam_med),
+        _ptr(lam_per), _stream(stream)))
+    return lam_med, lam_per
+
+
+def decompose(ctx, tab, S64, S32, k, L, T, dtype=F32, u0=None, seed=0, plain=False,
+              lam_out=None, U_out=None, tau_out=None, flags_out=None, stream=None):
+    """Algorithm 1 for k components; S64/S32 are deflated in place.
+    Returns (lam [k] f64, U [k][n] f64, tau [k] i32, flags [k][L] i32)."""
+    import torch
+    dt, _ = _vdtype(dtype)
+    dev = S64.device
+    _sk(tab, S64, S32, need32=(dt == F32))
+    _tensor(u0, "u0", torch.float64, (k, L, tab.n), allow_none=True)
+    if lam_out is None:
+        lam_out = torch.empty((k,), dtype=torch.float64, device=dev)
+    if U_out is None:
+        U_out = torch.empty((k, tab.n), dtype=torch.float64, device=dev)
+    if tau_out is None:
+        tau_out = torch.empty((k,), dtype=torch.int32, device=dev)
+    if flags_out is None:
+        flags_out = torch.empty((k, L), dtype=torch.int32, device=dev)
+    _tensor(lam_out, "lam_out", torch.float64, (k,))
+    _tensor(U_out, "U_out", torch.float64, (k, tab.n))
+    _tensor(tau_out, "tau_out", torch.int32, (k,))
+    _tensor(flags_out, "flags_out", torch.int32, (k, L))
+    _check("tsk_decompose", lib().tsk_decompose(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), k, L, T, _ptr(u0),
+        seed & (2 ** 64 - 1), _ptr(lam_out), _ptr(U_out), _ptr(tau_out), _ptr(flags_out),
+        int(bool(plain)), _stream(stream)))
+    return lam_out, U_out, tau_out, flags_out

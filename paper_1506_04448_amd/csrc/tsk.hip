@@ -1,0 +1,805 @@
+// Host side of the C ABI: context, tables, validation, kernel launches and
+// the decompose loop (recorded into a HIP graph once per shape).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+#include <vector>
+
+#include "../../include/tsk.h"
+#include "kernels.hpp"
+#include "status.hpp"
+
+using tsk::cx;
+
+namespace tsk {
+char* last_error_buffer() {
+  static thread_local char buf[512] = {0};
+  return buf;
+}
+}  // namespace tsk
+
+#define TSK_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return tsk::fail(TSK_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                             \
+  } while (0)
+
+#define TSK_TRY(expr)              \
+  do {                             \
+    tsk_status s_ = (expr);        \
+    if (s_ != TSK_OK) return s_;   \
+  } while (0)
+
+namespace {
+
+constexpr int kMinLogB = 6;
+constexpr int kMaxLogB = 14;       // FP32 power step and all FP64 transforms
+constexpr int kMaxLogB64Power = 13;
+
+int ilog2_exact(int b) {
+  if (b <= 0 || (b & (b - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < b) ++l;
+  return l;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct tsk_ctx {
+  int device = 0;
+  hipStream_t cap = nullptr;
+  std::map<int, void*> tw64, tw32;
+  std::map<int, DevBuf> ws;          // named workspaces
+  std::vector<GraphEntry> graphs;
+  std::vector<uint64_t> u0_key;      // cached generated start vectors
+};
+
+struct tsk_tables {
+  tsk_ctx* ctx = nullptr;
+  int n = 0, b = 0, B = 0, logb = 0;
+  uint32_t* hx = nullptr;
+  uint32_t* hxs = nullptr;
+  uint32_t* ord = nullptr;
+};
+
+namespace {
+
+enum WsId {
+  WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
+  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT
+};
+
+void clear_graphs(tsk_ctx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  c->graphs.clear();
+}
+
+// Grow-only device workspace.  Growing drains the device first and drops
+// recorded graphs, which may point at the old buffer.  Counter workspaces are
+// zero-filled on allocation; kernels return them to zero after use.
+tsk_status ws_get(tsk_ctx* c, int id, size_t bytes, void** out) {
+  DevBuf& d = c->ws[id];
+  if (bytes == 0) bytes = 256;
+  if (d.bytes < bytes) {
+    TSK_HIP(hipDeviceSynchronize());
+    clear_graphs(c);
+    if (d.p) TSK_HIP(hipFree(d.p));
+    d.p = nullptr;
+    d.bytes = 0;
+    size_t nb = std::max(bytes, (size_t)4096);
+    if (hipMalloc(&d.p, nb) != hipSuccess) {
+      d.p = nullptr;
+      return tsk::fail(TSK_ENOMEM, "workspace allocation of %zu bytes failed", nb);
+    }
+    TSK_HIP(hipMemset(d.p, 0, nb));
+    TSK_HIP(hipDeviceSynchronize());
+    d.bytes = nb;
+  }
+  *out = d.p;
+  return TSK_OK;
+}
+
+template <typename R>
+tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out) {
+  auto& mp = (sizeof(R) == 8) ? c->tw64 : c->tw32;
+  auto it = mp.find(logb);
+  if (it == mp.end()) {
+    const int b = 1 << logb;
+    std::vector<cx<R>> h(b);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int j = 0; j < b; ++j) {
+      // exp(-2 pi i j / b), using the quarter-wave symmetry for exact zeros/ones.
+      double cs, sn;
+      if (j == 0) { cs = 1.0; sn = 0.0; }
+      else if (4 * j == b) { cs = 0.0; sn = -1.0; }
+      else if (2 * j == b) { cs = -1.0; sn = 0.0; }
+      else if (4 * j == 3 * b) { cs = 0.0; sn = 1.0; }
+      else { const double a = two_pi * (double)j / (double)b; cs = cos(a); sn = -sin(a); }
+      h[j].x = (R)cs;
+      h[j].y = (R)sn;
+    }
+    void* d = nullptr;
+    TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * b));
+    TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * b, hipMemcpyHostToDevice));
+    it = mp.emplace(logb, d).first;
+  }
+  *out = reinterpret_cast<const cx<R>*>(it->second);
+  return TSK_OK;
+}
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+tsk_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return tsk::fail(TSK_EHIP, "%s launch failed: %s", what, hipGetErrorString(e));
+  return TSK_OK;
+}
+
+// ---- launch helpers dispatching on log2 b -----------------------------------
+
+template <typename R, int LOGB>
+tsk_status launch_power_t(const tsk::PowerArgs<R>& a, int B, int nrest, hipStream_t st) {
+  constexpr int NT = tsk::threads_for(LOGB);
+  hipLaunchKernelGGL((tsk::k_power<R, LOGB>), dim3(B, nrest), dim3(NT), 0, st, a);
+  return check_launch("k_power");
+}
+
+template <typename R>
+tsk_status launch_power(int logb, const tsk::PowerArgs<R>& a, int B, int nrest, hipStream_t st) {
+  switch (logb) {
+    case 6: return launch_power_t<R, 6>(a, B, nrest, st);
+    case 7: return launch_power_t<R, 7>(a, B, nrest, st);
+    case 8: return launch_power_t<R, 8>(a, B, nrest, st);
+    case 9: return launch_power_t<R, 9>(a, B, nrest, st);
+    case 10: return launch_power_t<R, 10>(a, B, nrest, st);
+    case 11: return launch_power_t<R, 11>(a, B, nrest, st);
+    case 12: return launch_power_t<R, 12>(a, B, nrest, st);
+    case 13: return launch_power_t<R, 13>(a, B, nrest, st);
+    case 14:
+      if constexpr (sizeof(R) == 4) return launch_power_t<R, 14>(a, B, nrest, st);
+      break;
+    default: break;
+  }
+  return tsk::fail(TSK_EUNSUPPORTED, "power step: b=2^%d not built for this precision", logb);
+}
+
+template <int LOGB>
+tsk_status launch_rank1_t(const tsk::Rank1Args& a, int B, int c, hipStream_t st) {
+  constexpr int NT = tsk::threads_for(LOGB - 1);
+  hipLaunchKernelGGL((tsk::k_rank1<LOGB>), dim3(B, c), dim3(NT), 0, st, a);
+  return check_launch("k_rank1");
+}
+template <int LOGB>
+tsk_status launch_r2c_t(const double* s, cx<double>* S64, cx<float>* S32, const cx<double>* tw,
+                        int acc, int B, hipStream_t st) {
+  constexpr int NT = tsk::threads_for(LOGB - 1);
+  hipLaunchKernelGGL((tsk::k_r2c64<LOGB>), dim3(B), dim3(NT), 0, st, s, S64, S32, tw, acc);
+  return check_launch("k_r2c64");
+}
+template <int LOGB>
+tsk_status launch_c2r_t(const cx<double>* S64, double* s, const cx<double>* tw, int B,
+                        hipStream_t st) {
+  constexpr int NT = tsk::threads_for(LOGB - 1);
+  hipLaunchKernelGGL((tsk::k_c2r64<LOGB>), dim3(B), dim3(NT), 0, st, S64, s, tw);
+  return check_launch("k_c2r64");
+}
+
+#define TSK_LOGB_SWITCH(logb, CALL)                   \
+  switch (logb) {                                     \
+    case 6: return CALL(6);                           \
+    case 7: return CALL(7);                           \
+    case 8: return CALL(8);                           \
+    case 9: return CALL(9);                           \
+    case 10: return CALL(10);                         \
+    case 11: return CALL(11);                         \
+    case 12: return CALL(12);                         \
+    case 13: return CALL(13);                         \
+    case 14: return CALL(14);                         \
+    default: break;                                   \
+  }
+
+tsk_status launch_rank1(int logb, const tsk::Rank1Args& a, int B, int c, hipStream_t st) {
+#define CALL(L) launch_rank1_t<L>(a, B, c, st)
+  TSK_LOGB_SWITCH(logb, CALL)
+#undef CALL
+  return tsk::fail(TSK_EUNSUPPORTED, "rank-1 spectra: b=2^%d not built", logb);
+}
+tsk_status launch_r2c(int logb, const double* s, cx<double>* S64, cx<float>* S32,
+                      const cx<double>* tw, int acc, int B, hipStream_t st) {
+#define CALL(L) launch_r2c_t<L>(s, S64, S32, tw, acc, B, st)
+  TSK_LOGB_SWITCH(logb, CALL)
+#undef CALL
+  return tsk::fail(TSK_EUNSUPPORTED, "r2c: b=2^%d not built", logb);
+}
+tsk_status launch_c2r(int logb, const cx<double>* S64, double* s, const cx<double>* tw, int B,
+                      hipStream_t st) {
+#define CALL(L) launch_c2r_t<L>(S64, s, tw, B, st)
+  TSK_LOGB_SWITCH(logb, CALL)
+#undef CALL
+  return tsk::fail(TSK_EUNSUPPORTED, "c2r: b=2^%d not built", logb);
+}
+
+int grid_for(size_t count, int threads) {
+  size_t g = (count + threads - 1) / threads;
+  return (int)std::min<size_t>(std::max<size_t>(g, 1), 65536);
+}
+
+tsk_status check_tables(tsk_tables_t tab, tsk_ctx_t ctx, const char* fn) {
+  if (!ctx) return tsk::fail(TSK_EINVAL, "%s: null context", fn);
+  if (!tab) return tsk::fail(TSK_EINVAL, "%s: null tables", fn);
+  if (tab->ctx != ctx) return tsk::fail(TSK_EINVAL, "%s: tables belong to another context", fn);
+  return TSK_OK;
+}
+
+tsk_status set_device(tsk_ctx_t ctx) {
+  TSK_HIP(hipSetDevice(ctx->device));
+  return TSK_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// Context and tables
+// =============================================================================
+
+extern "C" const char* tsk_version(void) { return "tsk 0.1 (gfx950)"; }
+extern "C" const char* tsk_last_error(void) { return tsk::last_error_buffer(); }
+
+extern "C" tsk_status tsk_create(tsk_ctx_t* out, int device) {
+  if (!out) return tsk::fail(TSK_EINVAL, "tsk_create: null output");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return tsk::fail(TSK_EHIP, "tsk_create: no HIP device available");
+  if (device < 0 || device >= count)
+    return tsk::fail(TSK_EINVAL, "tsk_create: device %d out of range [0,%d)", device, count);
+  TSK_HIP(hipSetDevice(device));
+  tsk_ctx* c = new tsk_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return tsk::fail(TSK_EHIP, "tsk_create: stream creation failed");
+  }
+  *out = c;
+  return TSK_OK;
+}
+
+extern "C" void tsk_destroy(tsk_ctx_t c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  clear_graphs(c);
+  for (auto& kv : c->ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : c->tw64) (void)hipFree(kv.second);
+  for (auto& kv : c->tw32) (void)hipFree(kv.second);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
+
+extern "C" tsk_status tsk_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint32_t* h_host,
+                                        const int8_t* xi_host, tsk_tables_t* out) {
+  if (!out) return tsk::fail(TSK_EINVAL, "tsk_tables_create: null output");
+  *out = nullptr;
+  if (!ctx || !h_host || !xi_host) return tsk::fail(TSK_EINVAL, "tsk_tables_create: null argument");
+  if (n < 1 || n > 65535) return tsk::fail(TSK_EINVAL, "tsk_tables_create: n=%d outside [1,65535]", n);
+  if (B < 1 || B > 64) return tsk::fail(TSK_EINVAL, "tsk_tables_create: B=%d outside [1,64]", B);
+  const int logb = ilog2_exact(b);
+  if (logb < 0) return tsk::fail(TSK_EINVAL, "tsk_tables_create: b=%d is not a power of two", b);
+  if (logb < kMinLogB || logb > kMaxLogB)
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_tables_create: b=%d outside [64,16384]", b);
+  const size_t cnt = (size_t)B * 3 * n;
+  std::vector<uint32_t> hx(cnt), hxs(cnt), ord(cnt);
+  for (size_t e = 0; e < cnt; ++e) {
+    if (h_host[e] >= (uint32_t)b)
+      return tsk::fail(TSK_EINVAL, "tsk_tables_create: h[%zu]=%u >= b=%d", e, h_host[e], b);
+    if (xi_host[e] != 1 && xi_host[e] != -1)
+      return tsk::fail(TSK_EINVAL, "tsk_tables_create: xi[%zu]=%d not +-1", e, (int)xi_host[e]);
+    hx[e] = (h_host[e] << 1) | (xi_host[e] < 0 ? 1u : 0u);
+  }
+  std::vector<uint32_t> idx(n);
+  for (int mj = 0; mj < 3 * B; ++mj) {
+    const size_t base = (size_t)mj * n;
+    std::iota(idx.begin(), idx.end(), 0u);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t p, uint32_t q) {
+      return (hx[base + p] >> 1) < (hx[base + q] >> 1);
+    });
+    for (int p = 0; p < n; ++p) {
+      ord[base + p] = idx[p];
+      hxs[base + p] = hx[base + idx[p]];
+    }
+  }
+  TSK_TRY(set_device(ctx));
+  tsk_tables* t = new tsk_tables();
+  t->ctx = ctx;
+  t->n = n;
+  t->b = b;
+  t->B = B;
+  t->logb = logb;
+  void* p = nullptr;
+  if (hipMalloc(&p, 3 * cnt * sizeof(uint32_t)) != hipSuccess) {
+    delete t;
+    return tsk::fail(TSK_ENOMEM, "tsk_tables_create: device allocation failed");
+  }
+  t->hx = reinterpret_cast<uint32_t*>(p);
+  t->hxs = t->hx + cnt;
+  t->ord = t->hxs + cnt;
+  hipError_t e1 = hipMemcpy(t->hx, hx.data(), cnt * 4, hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(t->hxs, hxs.data(), cnt * 4, hipMemcpyHostToDevice);
+  hipError_t e3 = hipMemcpy(t->ord, ord.data(), cnt * 4, hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    (void)hipFree(p);
+    delete t;
+    return tsk::fail(TSK_EHIP, "tsk_tables_create: upload failed");
+  }
+  *out = t;
+  return TSK_OK;
+}
+
+extern "C" void tsk_tables_destroy(tsk_tables_t t) {
+  if (!t) return;
+  (void)hipSetDevice(t->ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(t->hx);
+  delete t;
+}
+
+// =============================================================================
+// Sketch construction
+// =============================================================================
+
+namespace {
+
+template <typename TIn, typename TAcc>
+tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipStream_t st,
+                            double** s_time_out) {
+  const int n = tab->n, b = tab->b, B = tab->B;
+  const size_t lds_cap = 160 * 1024;
+  const size_t per_sketch = (size_t)b * sizeof(TAcc) + (size_t)3 * n * 4;
+  if (per_sketch > lds_cap)
+    return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d, n=%d need more LDS than one CU has", b, n);
+  const size_t budget = 128 * 1024;
+  int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)B, budget / per_sketch));
+  if ((size_t)G * per_sketch > lds_cap) G = 1;
+  const int ngroups = (B + G - 1) / G;
+  const long long npairs = (long long)n * n;
+  int nslab = (int)std::min<long long>(npairs, std::max(1, (2 * 256 + ngroups - 1) / ngroups));
+  const long long pps = (npairs + nslab - 1) / nslab;
+  nslab = (int)((npairs + pps - 1) / pps);
+  void* partial = nullptr;
+  void* stime = nullptr;
+  TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * b * sizeof(TAcc), &partial));
+  TSK_TRY(ws_get(ctx, WS_STIME, (size_t)B * b * sizeof(double), &stime));
+  tsk::BuildArgs<TIn, TAcc> a;
+  a.T = T;
+  a.n = n;
+  a.b = b;
+  a.B = B;
+  a.G = G;
+  a.hx = tab->hx;
+  a.pairs_per_slab = pps;
+  a.nslab = nslab;
+  a.partial = reinterpret_cast<TAcc*>(partial);
+  const size_t lds = (size_t)G * per_sketch;
+  TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_build_dense<TIn, TAcc>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((tsk::k_build_dense<TIn, TAcc>), dim3(nslab, ngroups), dim3(256), lds, st, a);
+  TSK_TRY(check_launch("k_build_dense"));
+  hipLaunchKernelGGL((tsk::k_build_reduce<TAcc>), dim3(grid_for((size_t)B * b, 256)), dim3(256), 0,
+                     st, (const TAcc*)partial, (double*)stime, b, B, G, nslab);
+  TSK_TRY(check_launch("k_build_reduce"));
+  *s_time_out = reinterpret_cast<double*>(stime);
+  return TSK_OK;
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, const void* T,
+                                             tsk_dtype dtype, double* S64, float* S32,
+                                             int accumulate, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_sketch_build_dense"));
+  if (!T || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_dense: null T or S64");
+  if (dtype != TSK_F32 && dtype != TSK_F64)
+    return tsk::fail(TSK_EINVAL, "tsk_sketch_build_dense: bad dtype %d", (int)dtype);
+  TSK_TRY(set_device(ctx));
+  const cx<double>* tw = nullptr;
+  TSK_TRY(get_tw<double>(ctx, tab->logb, &tw));
+  double* stime = nullptr;
+  if (dtype == TSK_F32)
+    TSK_TRY((build_dense_impl<float, float>(ctx, tab, (const float*)T, S(stream), &stime)));
+  else
+    TSK_TRY((build_dense_impl<double, double>(ctx, tab, (const double*)T, S(stream), &stime)));
+  return launch_r2c(tab->logb, stime, reinterpret_cast<cx<double>*>(S64),
+                    reinterpret_cast<cx<float>*>(S32), tw, accumulate ? 1 : 0, tab->B, S(stream));
+}
+
+extern "C" tsk_status tsk_sketch_from_time(tsk_ctx_t ctx, int b, int B, const double* s_time,
+                                           double* S64, float* S32, void* stream) {
+  if (!ctx || !s_time || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_from_time: null argument");
+  const int logb = ilog2_exact(b);
+  if (logb < kMinLogB || logb > kMaxLogB || B < 1 || B > 64)
+    return tsk::fail(TSK_EINVAL, "tsk_sketch_from_time: b=%d B=%d out of range", b, B);
+  TSK_TRY(set_device(ctx));
+  const cx<double>* tw = nullptr;
+  TSK_TRY(get_tw<double>(ctx, logb, &tw));
+  return launch_r2c(logb, s_time, reinterpret_cast<cx<double>*>(S64),
+                    reinterpret_cast<cx<float>*>(S32), tw, 0, B, S(stream));
+}
+
+extern "C" tsk_status tsk_sketch_export(tsk_ctx_t ctx, int b, int B, const double* S64,
+                                        double* s_time, void* stream) {
+  if (!ctx || !s_time || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_export: null argument");
+  const int logb = ilog2_exact(b);
+  if (logb < kMinLogB || logb > kMaxLogB || B < 1 || B > 64)
+    return tsk::fail(TSK_EINVAL, "tsk_sketch_export: b=%d B=%d out of range", b, B);
+  TSK_TRY(set_device(ctx));
+  const cx<double>* tw = nullptr;
+  TSK_TRY(get_tw<double>(ctx, logb, &tw));
+  return launch_c2r(logb, reinterpret_cast<const cx<double>*>(S64), s_time, tw, B, S(stream));
+}
+
+namespace {
+
+// S64 += sign * sum_r lam_r prod_r over `c` vectors U [c][n], in chunks.
+tsk_status rank1_update(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam, const double* U, int c,
+                        double sign, double* S64, float* S32, hipStream_t st) {
+  const int B = tab->B, b = tab->b, n = tab->n;
+  const int H1 = b / 2 + 1;
+  const cx<double>* tw = nullptr;
+  TSK_TRY(get_tw<double>(ctx, tab->logb, &tw));
+  const size_t per_vec = (size_t)B * H1 * sizeof(cx<double>);
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)256 << 20) / per_vec));
+  void* prod = nullptr;
+  TSK_TRY(ws_get(ctx, WS_PROD, (size_t)std::min(chunk, c) * per_vec, &prod));
+  for (int r0 = 0; r0 < c; r0 += chunk) {
+    const int cc = std::min(chunk, c - r0);
+    tsk::Rank1Args a;
+    a.hx = tab->hx;
+    a.hxs = tab->hxs;
+    a.ord = tab->ord;
+    a.n = n;
+    a.B = B;
+    a.U = U + (size_t)r0 * n;
+    a.tw = tw;
+    a.prod = reinterpret_cast<cx<double>*>(prod);
+    a.S64 = nullptr;
+    a.lam_per = nullptr;
+    TSK_TRY(launch_rank1(tab->logb, a, B, cc, st));
+    hipLaunchKernelGGL(tsk::k_spec_update, dim3(grid_for((size_t)B * H1, 256)), dim3(256), 0, st,
+                       reinterpret_cast<cx<double>*>(S64), reinterpret_cast<cx<float>*>(S32),
+                       (const cx<double>*)prod, lam + r0, sign, cc, B, H1);
+    TSK_TRY(check_launch("k_spec_update"));
+  }
+  return TSK_OK;
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_sketch_build_factors(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam,
+                                               const double* A, int k, double* S64, float* S32,
+                                               int accumulate, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_sketch_build_factors"));
+  if (!lam || !A || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_factors: null argument");
+  if (k < 1) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_factors: k=%d < 1", k);
+  TSK_TRY(set_device(ctx));
+  const size_t H1 = (size_t)tab->b / 2 + 1;
+  if (!accumulate) {
+    const size_t words = (size_t)tab->B * H1 * 4;  // doubles as u32 pairs
+    hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for(words, 256)), dim3(256), 0, S(stream),
+                       reinterpret_cast<unsigned*>(S64), 0u, words);
+    TSK_TRY(check_launch("k_fill_u32"));
+  }
+  return rank1_update(ctx, tab, lam, A, k, +1.0, S64, S32, S(stream));
+}
+
+extern "C" tsk_status tsk_sketch_deflate(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam,
+                                         const double* U, int c, double* S64, float* S32,
+                                         void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_sketch_deflate"));
+  if (!lam || !U || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_deflate: null argument");
+  if (c < 1) return tsk::fail(TSK_EINVAL, "tsk_sketch_deflate: c=%d < 1", c);
+  TSK_TRY(set_device(ctx));
+  return rank1_update(ctx, tab, lam, U, c, -1.0, S64, S32, S(stream));
+}
+
+// =============================================================================
+// Contractions
+// =============================================================================
+
+namespace {
+
+template <typename R>
+tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int L, int nrest,
+                        int tau0, const R* Uin, R* Uout, R* V, double* lam_per, double* lam_med,
+                        int32_t* flags, unsigned* counter, int mode, hipStream_t st) {
+  const cx<R>* tw = nullptr;
+  TSK_TRY(get_tw<R>(ctx, tab->logb, &tw));
+  tsk::PowerArgs<R> a;
+  a.hx = tab->hx;
+  a.hxs = tab->hxs;
+  a.ord = tab->ord;
+  a.n = tab->n;
+  a.B = tab->B;
+  a.S = reinterpret_cast<const cx<R>*>(spec);
+  a.tw = tw;
+  a.Uin = Uin;
+  a.Uout = Uout;
+  a.V = V;
+  a.lam_per = lam_per;
+  a.lam_med = lam_med;
+  a.flags = flags;
+  a.counter = counter;
+  a.tau0 = tau0;
+  a.mode = mode;
+  (void)L;
+  return launch_power<R>(tab->logb, a, tab->B, nrest, st);
+}
+
+tsk_status check_power_args(tsk_tables_t tab, tsk_dtype dtype, const double* S64, const float* S32,
+                            int L, const char* fn) {
+  if (dtype != TSK_F32 && dtype != TSK_F64) return tsk::fail(TSK_EINVAL, "%s: bad dtype", fn);
+  if (L < 1) return tsk::fail(TSK_EINVAL, "%s: L=%d < 1", fn, L);
+  if (dtype == TSK_F32 && !S32) return tsk::fail(TSK_EINVAL, "%s: FP32 path needs S32", fn);
+  if (dtype == TSK_F64 && !S64) return tsk::fail(TSK_EINVAL, "%s: FP64 path needs S64", fn);
+  if (dtype == TSK_F64 && tab->logb > kMaxLogB64Power)
+    return tsk::fail(TSK_EUNSUPPORTED, "%s: FP64 power method limited to b <= 8192", fn);
+  if (L > 65535) return tsk::fail(TSK_EINVAL, "%s: L=%d > 65535", fn, L);
+  return TSK_OK;
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                       const double* S64, const float* S32, int L,
+                                       const void* U_in, void* U_out, void* V, int32_t* flags,
+                                       void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_power_update"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_power_update"));
+  if (!U_in || !U_out) return tsk::fail(TSK_EINVAL, "tsk_power_update: null vector buffer");
+  if (U_in == U_out) return tsk::fail(TSK_EINVAL, "tsk_power_update: U_in and U_out alias");
+  TSK_TRY(set_device(ctx));
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  void* vbuf = V;
+  if (!vbuf) TSK_TRY(ws_get(ctx, WS_V, (size_t)L * tab->B * tab->n * es, &vbuf));
+  void* cnt = nullptr;
+  TSK_TRY(ws_get(ctx, WS_CNT, (size_t)L * sizeof(unsigned), &cnt));
+  if (dtype == TSK_F32)
+    return power_launch<float>(ctx, tab, S32, L, L, 0, (const float*)U_in, (float*)U_out,
+                               (float*)vbuf, nullptr, nullptr, flags, (unsigned*)cnt, 0, S(stream));
+  return power_launch<double>(ctx, tab, S64, L, L, 0, (const double*)U_in, (double*)U_out,
+                              (double*)vbuf, nullptr, nullptr, flags, (unsigned*)cnt, 0, S(stream));
+}
+
+extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                       const double* S64, const float* S32, int L, const void* U,
+                                       double* lam_med, double* lam_per, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_contract_uuu"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_contract_uuu"));
+  if (!U || !lam_med) return tsk::fail(TSK_EINVAL, "tsk_contract_uuu: null U or lam_med");
+  TSK_TRY(set_device(ctx));
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  void* vbuf = nullptr;
+  TSK_TRY(ws_get(ctx, WS_V, (size_t)L * tab->B * tab->n * es, &vbuf));
+  void* lp = lam_per;
+  if (!lp) TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * tab->B * sizeof(double), &lp));
+  void* cnt = nullptr;
+  TSK_TRY(ws_get(ctx, WS_CNT, (size_t)L * sizeof(unsigned), &cnt));
+  if (dtype == TSK_F32)
+    return power_launch<float>(ctx, tab, S32, L, L, 0, (const float*)U, nullptr, (float*)vbuf,
+                               (double*)lp, lam_med, nullptr, (unsigned*)cnt, 1, S(stream));
+  return power_launch<double>(ctx, tab, S64, L, L, 0, (const double*)U, nullptr, (double*)vbuf,
+                              (double*)lp, lam_med, nullptr, (unsigned*)cnt, 1, S(stream));
+}
+
+// =============================================================================
+// Decomposition
+// =============================================================================
+
+namespace {
+
+struct DecompWs {
+  void* U0;       // R[L][n]
+  void* U1;       // R[L][n]
+  void* V;        // R[L][B][n]
+  double* lam_per;
+  double* lam_med;
+  unsigned* cnt;
+  int32_t* flags;  // [k][L]
+  double* u_hat;   // [n]
+  double* lam64;   // [B]
+  void* prod;      // cx<double>[B][b/2+1]
+  double* u0;      // [k][L][n] generated start vectors (when caller passes none)
+};
+
+template <typename R>
+tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, double* S64,
+                             float* S32, int k, int L, int T, const double* u0, double* lam_out,
+                             double* U_out, int32_t* tau_out, int32_t* flags, const DecompWs& w,
+                             bool plain, hipStream_t st) {
+  const int n = tab->n, B = tab->B, b = tab->b;
+  const int H1 = b / 2 + 1;
+  const cx<double>* tw64 = nullptr;
+  TSK_TRY(get_tw<double>(ctx, tab->logb, &tw64));
+  R* Ub[2] = {reinterpret_cast<R*>(w.U0), reinterpret_cast<R*>(w.U1)};
+  for (int c = 0; c < k; ++c) {
+    const size_t LN = (size_t)L * n;
+    hipLaunchKernelGGL(tsk::k_cvt<R>, dim3(grid_for(LN, 256)), dim3(256), 0, st,
+                       u0 + (size_t)c * LN, Ub[0], LN);
+    TSK_TRY(check_launch("k_cvt"));
+    int cur = 0;
+    int32_t* fl = flags + (size_t)c * L;
+    if (!plain) {
+      for (int t = 0; t < T; ++t) {
+        TSK_TRY(power_launch<R>(ctx, tab, spec, L, L, 0, Ub[cur], Ub[cur ^ 1], (R*)w.V, nullptr,
+                                nullptr, fl, w.cnt, 0, st));
+        cur ^= 1;
+      }
+      TSK_TRY(power_launch<R>(ctx, tab, spec, L, L, 0, Ub[cur], nullptr, (R*)w.V, w.lam_per,
+                              w.lam_med, nullptr, w.cnt, 1, st));
+    } else {
+      for (int tau = 0; tau < L; ++tau) {
+        int cc = 0;
+        for (int t = 0; t < T; ++t) {
+          TSK_TRY(power_launch<R>(ctx, tab, spec, L, 1, tau, Ub[cc], Ub[cc ^ 1], (R*)w.V, nullptr,
+                                  nullptr, fl, w.cnt, 0, st));
+          cc ^= 1;
+        }
+        cur = cc;
+        TSK_TRY(power_launch<R>(ctx, tab, spec, L, 1, tau, Ub[cc], nullptr, (R*)w.V, w.lam_per,
+                                w.lam_med, nullptr, w.cnt, 1, st));
+      }
+    }
+    hipLaunchKernelGGL(tsk::k_select<R>, dim3(1), dim3(256), 0, st, (const double*)w.lam_med, L,
+                       (const R*)Ub[cur], n, w.u_hat, U_out + (size_t)c * n,
+                       tau_out ? tau_out + c : nullptr);
+    TSK_TRY(check_launch("k_select"));
+    tsk::Rank1Args a;
+    a.hx = tab->hx;
+    a.hxs = tab->hxs;
+    a.ord = tab->ord;
+    a.n = n;
+    a.B = B;
+    a.U = w.u_hat;
+    a.tw = tw64;
+    a.prod = reinterpret_cast<cx<double>*>(w.prod);
+    a.S64 = reinterpret_cast<const cx<double>*>(S64);
+    a.lam_per = w.lam64;
+    TSK_TRY(launch_rank1(tab->logb, a, B, 1, st));
+    hipLaunchKernelGGL(tsk::k_median_scalar, dim3(1), dim3(64), 0, st, (const double*)w.lam64, B,
+                       lam_out + c);
+    TSK_TRY(check_launch("k_median_scalar"));
+    hipLaunchKernelGGL(tsk::k_spec_update, dim3(grid_for((size_t)B * H1, 256)), dim3(256), 0, st,
+                       reinterpret_cast<cx<double>*>(S64), reinterpret_cast<cx<float>*>(S32),
+                       (const cx<double>*)w.prod, (const double*)(lam_out + c), -1.0, 1, B, H1);
+    TSK_TRY(check_launch("k_spec_update"));
+  }
+  return TSK_OK;
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, double* S64,
+                                    float* S32, int k, int L, int T, const double* u0,
+                                    uint64_t seed, double* lam_out, double* U_out,
+                                    int32_t* tau_out, int32_t* flags_out, int plain,
+                                    void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_decompose"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_decompose"));
+  if (!S64) return tsk::fail(TSK_EINVAL, "tsk_decompose: S64 (deflated in FP64) is required");
+  if (!lam_out || !U_out) return tsk::fail(TSK_EINVAL, "tsk_decompose: null lam_out or U_out");
+  if (k < 1 || k > tab->n) return tsk::fail(TSK_EINVAL, "tsk_decompose: k=%d outside [1,n]", k);
+  if (T < 1) return tsk::fail(TSK_EINVAL, "tsk_decompose: T=%d < 1", T);
+  if (!u0 && (L >= (1 << 20) || tab->n >= (1 << 19)))
+    return tsk::fail(TSK_EINVAL, "tsk_decompose: too large to draw start vectors");
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  const int n = tab->n, B = tab->B, b = tab->b;
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  DecompWs w;
+  TSK_TRY(ws_get(ctx, WS_U, 2 * (size_t)L * n * es, &w.U0));
+  w.U1 = reinterpret_cast<char*>(w.U0) + (size_t)L * n * es;
+  TSK_TRY(ws_get(ctx, WS_V, (size_t)L * B * n * es, &w.V));
+  void* p;
+  TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * B * 8, &p));
+  w.lam_per = (double*)p;
+  TSK_TRY(ws_get(ctx, WS_LAMMED, (size_t)L * 8, &p));
+  w.lam_med = (double*)p;
+  TSK_TRY(ws_get(ctx, WS_CNT, (size_t)L * 4, &p));
+  w.cnt = (unsigned*)p;
+  TSK_TRY(ws_get(ctx, WS_UHAT, (size_t)n * 8, &p));
+  w.u_hat = (double*)p;
+  TSK_TRY(ws_get(ctx, WS_LAM64, (size_t)B * 8, &p));
+  w.lam64 = (double*)p;
+  TSK_TRY(ws_get(ctx, WS_PROD, (size_t)B * (b / 2 + 1) * 16, &w.prod));
+  int32_t* flags = flags_out;
+  if (!flags) {
+    TSK_TRY(ws_get(ctx, WS_FLAGS, (size_t)k * L * 4, &p));
+    flags = (int32_t*)p;
+  }
+  const double* u0d = u0;
+  if (!u0d) {
+    TSK_TRY(ws_get(ctx, WS_U0, (size_t)k * L * n * 8, &p));
+    std::vector<uint64_t> key = {seed, (uint64_t)k, (uint64_t)L, (uint64_t)n, (uint64_t)(uintptr_t)p};
+    if (ctx->u0_key != key) {
+      std::vector<double> h((size_t)k * L * n);
+      for (int c = 0; c < k; ++c) TSK_TRY(tsk_init_vectors(seed, c, L, n, h.data() + (size_t)c * L * n));
+      TSK_HIP(hipStreamSynchronize(st));
+      TSK_HIP(hipMemcpy(p, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+      ctx->u0_key = key;
+    }
+    u0d = (const double*)p;
+  }
+  // Flags are outputs of this call: clear them first (a fill kernel, so the
+  // recorded graph holds no memset node).
+  auto clear_flags = [&](hipStream_t s) -> tsk_status {
+    hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for((size_t)k * L, 256)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned*>(flags), 0u, (size_t)k * L);
+    return check_launch("k_fill_u32");
+  };
+  const void* spec = dtype == TSK_F32 ? (const void*)S32 : (const void*)S64;
+  {  // twiddle tables are uploaded outside any capture
+    const cx<double>* t64 = nullptr;
+    const cx<float>* t32 = nullptr;
+    TSK_TRY(get_tw<double>(ctx, tab->logb, &t64));
+    if (dtype == TSK_F32) TSK_TRY(get_tw<float>(ctx, tab->logb, &t32));
+  }
+  auto enqueue = [&](hipStream_t s) -> tsk_status {
+    TSK_TRY(clear_flags(s));
+    if (dtype == TSK_F32)
+      return decompose_enqueue<float>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out,
+                                      tau_out, flags, w, plain != 0, s);
+    return decompose_enqueue<double>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out,
+                                     tau_out, flags, w, plain != 0, s);
+  };
+  if (plain) return enqueue(st);
+
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)tab, (uint64_t)dtype, (uint64_t)(uintptr_t)S64,
+                               (uint64_t)(uintptr_t)S32, (uint64_t)k, (uint64_t)L, (uint64_t)T,
+                               (uint64_t)(uintptr_t)u0d, (uint64_t)(uintptr_t)lam_out,
+                               (uint64_t)(uintptr_t)U_out, (uint64_t)(uintptr_t)tau_out,
+                               (uint64_t)(uintptr_t)flags, (uint64_t)(uintptr_t)w.U0,
+                               (uint64_t)(uintptr_t)w.V, (uint64_t)(uintptr_t)w.prod};
+  GraphEntry* ge = nullptr;
+  for (auto& g : ctx->graphs)
+    if (g.key == key) ge = &g;
+  if (!ge) {
+    GraphEntry g;
+    g.key = key;
+    TSK_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
+    tsk_status s = enqueue(ctx->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+    if (s != TSK_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return tsk::fail(TSK_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    g.graph = graph;
+    TSK_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    if (ctx->graphs.size() >= 16) clear_graphs(ctx);
+    ctx->graphs.push_back(g);
+    ge = &ctx->graphs.back();
+  }
+  TSK_HIP(hipGraphLaunch(ge->exec, st));
+  return TSK_OK;
+}

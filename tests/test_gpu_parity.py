@@ -1,0 +1,356 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: tables bit-exact (host tests); FP64 steps within 1e-12 normwise
+relative; FP32 steps within 1e-5 normwise relative (the benchmark spec's tolerance).
+Inputs are seeded and synthetic (planted symmetric tensors, see
+paper_1506_04448_amd/workloads.py); the oracle builds its own sketches from the
+same tensor with its own tables unless a test isolates a single step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1506_04448_amd.workloads import planted_tensor
+
+torch = pytest.importorskip("torch")
+import paper_1506_04448_amd as tsk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, ref):
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    d = np.linalg.norm(ref)
+    return np.linalg.norm(a - ref) / (d if d > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tsk.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _tables(ctx, seed, n, b, B):
+    h, xi = tsk.hash_generate(seed, n, b, B)
+    return tsk.Tables(ctx, h, xi, b), h, xi
+
+
+def _time_sketch(ctx, tab, S64):
+    return tsk.sketch_export(ctx, S64, tab.b).cpu().numpy()
+
+
+def _oracle_sketches(T, h, xi, b):
+    return np.stack([oracle.sketch_dense(T, h[m], xi[m], b) for m in range(h.shape[0])])
+
+
+def _gpu_spectra_from(ctx, tab, S_time):
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_from_time(ctx, torch.from_numpy(S_time).to(DEV), S64, S32)
+    return S64, S32
+
+
+# ----------------------------------------------------------------------------- build
+
+@pytest.mark.parametrize("n,b,B,dtype", [(50, 1024, 4, np.float64), (37, 256, 3, np.float64),
+                                         (37, 256, 3, np.float32), (1, 64, 1, np.float64),
+                                         (65, 8192, 5, np.float32)])
+def test_dense_build_matches_eq1(ctx, n, b, B, dtype):
+    print(f"build n={n} b={b} B={B} {np.dtype(dtype).name}", flush=True)
+    P = planted_tensor(n, min(3, n), noise=0.05, seed=n, dtype=dtype)
+    tab, h, xi = _tables(ctx, 11, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    got = _time_sketch(ctx, tab, S64)
+    ref = _oracle_sketches(P.T.astype(np.float64), h, xi, b)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    for m in range(B):
+        assert rel(got[m], ref[m]) < tol, (m, rel(got[m], ref[m]))
+    # working copy is the master rounded to FP32
+    np.testing.assert_array_equal(S32.cpu().numpy(), S64.cpu().numpy().astype(np.float32))
+
+
+def test_dense_build_full_size_c2(ctx):
+    n, b, B = 200, 16384, 10
+    P = planted_tensor(n, 10, noise=0.05, seed=1, dtype=np.float32)
+    tab, h, xi = _tables(ctx, 1, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    got = _time_sketch(ctx, tab, S64)
+    T64 = P.T.astype(np.float64)
+    for m in (0, 9):
+        ref = oracle.sketch_dense(T64, h[m], xi[m], b)
+        assert rel(got[m], ref) < 1e-5, (m, rel(got[m], ref))
+    # linearity: accumulate doubles the spectrum
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32, accumulate=True)
+    got2 = _time_sketch(ctx, tab, S64)
+    assert rel(got2, 2 * got) < 1e-6
+
+
+def test_spectrum_roundtrip_matches_numpy_fft(ctx):
+    rng = np.random.default_rng(0)
+    for b, B in [(64, 1), (1024, 3), (16384, 2)]:
+        s = rng.standard_normal((B, b))
+        S64 = torch.zeros((B, b // 2 + 1, 2), dtype=torch.float64, device=DEV)
+        S32 = torch.zeros((B, b // 2 + 1, 2), dtype=torch.float32, device=DEV)
+        tsk.sketch_from_time(ctx, torch.from_numpy(s).to(DEV), S64, S32)
+        spec = S64.cpu().numpy()
+        ref = np.fft.rfft(s, axis=-1)
+        assert rel(spec[..., 0] + 1j * spec[..., 1], ref) < 1e-14
+        back = tsk.sketch_export(ctx, S64, b).cpu().numpy()
+        assert rel(back, s) < 1e-14
+
+
+# ----------------------------------------------------------------------------- steps
+
+@pytest.mark.parametrize("n,b,B,L,dtype,tol", [
+    (50, 1024, 4, 6, torch.float64, 1e-12),
+    (50, 1024, 5, 3, torch.float64, 1e-12),
+    (200, 16384, 10, 8, torch.float32, 1e-5),
+    (37, 2048, 3, 5, torch.float32, 1e-5),
+    (1, 64, 1, 2, torch.float64, 1e-12),
+    (300, 8192, 64, 2, torch.float64, 1e-12),
+])
+def test_power_update_matches_prop1(ctx, n, b, B, L, dtype, tol):
+    print(f"power n={n} b={b} B={B} L={L} {dtype}", flush=True)
+    P = planted_tensor(n, min(4, n), noise=0.05, seed=2)
+    tab, h, xi = _tables(ctx, 5, n, b, B)
+    S_time = _oracle_sketches(P.T, h, xi, b)
+    S64, S32 = _gpu_spectra_from(ctx, tab, S_time)
+    rng = np.random.default_rng(3)
+    U = rng.standard_normal((L, n))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    if dtype == torch.float32:
+        U = U.astype(np.float32).astype(np.float64)   # the GPU sees exactly these values
+    Ud = torch.from_numpy(U).to(device=DEV, dtype=dtype)
+    V = torch.empty((L, B, n), dtype=dtype, device=DEV)
+    flags = torch.zeros((L,), dtype=torch.int32, device=DEV)
+    Uo = tsk.power_update(ctx, tab, Ud, S64=S64, S32=S32, V=V, flags=flags)
+    Vr, Ur, fr = oracle.power_update(S_time, h, xi, U)
+    Vg = V.cpu().numpy()
+    for tau in range(L):
+        for m in range(B):
+            assert rel(Vg[tau, m], Vr[tau, m]) < tol, (tau, m, rel(Vg[tau, m], Vr[tau, m]))
+    assert rel(Uo.cpu().numpy(), Ur) < tol
+    assert flags.cpu().numpy().tolist() == fr.tolist()
+
+
+@pytest.mark.parametrize("n,b,B,L,dtype,tol", [
+    (50, 1024, 4, 6, torch.float64, 1e-12),
+    (200, 16384, 10, 8, torch.float32, 1e-5),
+    (20, 512, 7, 3, torch.float32, 1e-5),
+])
+def test_contract_uuu_matches_eq3(ctx, n, b, B, L, dtype, tol):
+    P = planted_tensor(n, 3, noise=0.05, seed=4)
+    tab, h, xi = _tables(ctx, 6, n, b, B)
+    S_time = _oracle_sketches(P.T, h, xi, b)
+    S64, S32 = _gpu_spectra_from(ctx, tab, S_time)
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((L, n))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    if dtype == torch.float32:
+        U = U.astype(np.float32).astype(np.float64)
+    lam_med, lam_per = tsk.contract_uuu(ctx, tab, torch.from_numpy(U).to(device=DEV, dtype=dtype),
+                                        S64=S64, S32=S32)
+    per_r, med_r = oracle.contract_uuu(S_time, h, xi, U)
+    scale = np.abs(per_r).max()
+    assert np.abs(lam_per.cpu().numpy() - per_r).max() / scale < tol
+    assert np.abs(lam_med.cpu().numpy() - med_r).max() / scale < tol
+
+
+def test_deflate_matches_linearity(ctx):
+    n, b, B = 40, 2048, 3
+    P = planted_tensor(n, 3, noise=0.05, seed=7)
+    tab, h, xi = _tables(ctx, 8, n, b, B)
+    S_time = _oracle_sketches(P.T, h, xi, b)
+    S64, S32 = _gpu_spectra_from(ctx, tab, S_time)
+    lam = np.array([1.3, -0.4])
+    U = P.V[:2].copy()
+    tsk.sketch_deflate(ctx, tab, torch.from_numpy(lam).to(DEV), torch.from_numpy(U).to(DEV), S64, S32)
+    got = _time_sketch(ctx, tab, S64)
+    for m in range(B):
+        ref = S_time[m] - sum(lam[r] * oracle.sketch_rank1_fft(U[r], U[r], U[r], h[m], xi[m], b)
+                              for r in range(2))
+        assert rel(got[m], ref) < 1e-12
+    np.testing.assert_array_equal(S32.cpu().numpy(), S64.cpu().numpy().astype(np.float32))
+
+
+@pytest.mark.parametrize("n,k,b,B", [(40, 5, 2048, 3), (150, 20, 16384, 2), (7, 1, 64, 1)])
+def test_factor_build_matches_eq2(ctx, n, k, b, B):
+    rng = np.random.default_rng(n)
+    lam = rng.uniform(1, 10, k)
+    A = rng.standard_normal((k, n))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    tab, h, xi = _tables(ctx, 9, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_factors(ctx, tab, torch.from_numpy(lam).to(DEV), torch.from_numpy(A).to(DEV),
+                             S64, S32)
+    got = _time_sketch(ctx, tab, S64)
+    for m in range(B):
+        ref = oracle.sketch_factors(lam, A, h[m], xi[m], b)
+        assert rel(got[m], ref) < 1e-12, (m, rel(got[m], ref))
+
+
+# ----------------------------------------------------------------------------- decompose
+
+def test_decompose_fp64_small_config(ctx):
+    """n=50 FP64, b=1024, B=4, L=10, T=20, k=5, seed 0: the whole of Algorithm 1."""
+    n, k, b, B, L, T = 50, 5, 1024, 4, 10, 20
+    P = planted_tensor(n, 5, noise=0.01, seed=0)
+    tab, h, xi = _tables(ctx, 0, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    u0 = np.stack([oracle.start_vectors_spec(0, c, L, n) for c in range(k)])
+    lam, U, tau, flags = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F64,
+                                       u0=torch.from_numpy(u0).to(DEV))
+    ref = oracle.rtpm_sketched(_oracle_sketches(P.T, h, xi, b), h, xi, k, L, T, u0)
+    assert rel(lam.cpu().numpy(), ref.lam) < 1e-12
+    assert rel(U.cpu().numpy(), ref.U) < 1e-12
+    np.testing.assert_array_equal(flags.cpu().numpy(), ref.flags)
+    assert rel(_time_sketch(ctx, tab, S64), ref.S) < 1e-12
+    # null u0: the library draws the start vectors from the same spec
+    S64b, S32b = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64b, S32b)
+    lam2, U2, _, _ = tsk.decompose(ctx, tab, S64b, S32b, k, L, T, dtype=tsk.F64, seed=0)
+    assert rel(lam2.cpu().numpy(), ref.lam) < 1e-12
+    assert rel(U2.cpu().numpy(), ref.U) < 1e-12
+
+
+def test_decompose_fp32_full_size_c2(ctx):
+    """n=200 FP32 dense, k=10, b=16384, B=10, L=50, T=30 batched: the first two
+    components against the oracle (later ones depend only on these through the
+    deflation), all ten against the planted truth."""
+    n, k, b, B, L, T = 200, 10, 16384, 10, 50, 30
+    P = planted_tensor(n, k, noise=0.05, seed=1, dtype=np.float32)
+    tab, h, xi = _tables(ctx, 1, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    u0 = np.stack([oracle.start_vectors_spec(1, c, L, n) for c in range(k)])
+    lam, U, tau, flags = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F32,
+                                       u0=torch.from_numpy(u0).to(DEV))
+    lam, U = lam.cpu().numpy(), U.cpu().numpy()
+    assert oracle.wrong_vectors(P.V, U) == 0
+    np.testing.assert_allclose(np.sort(lam), np.sort(P.lam), atol=0.05)
+    kk = 2
+    S_time = _oracle_sketches(P.T.astype(np.float64), h, xi, b)
+    ref = oracle.rtpm_sketched(S_time, h, xi, kk, L, T, u0[:kk])
+    assert np.abs(lam[:kk] - ref.lam).max() / np.abs(ref.lam).max() < 1e-5
+    assert rel(U[:kk], ref.U) < 1e-5
+
+
+def test_plain_path_equals_batched(ctx):
+    n, k, b, B, L, T = 50, 3, 1024, 4, 6, 8
+    P = planted_tensor(n, 3, noise=0.01, seed=5, dtype=np.float32)
+    tab, h, xi = _tables(ctx, 2, n, b, B)
+    out = []
+    for plain in (False, True):
+        S64, S32 = tsk.new_sketch(tab, DEV)
+        tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+        r = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F32, seed=3, plain=plain)
+        out.append([x.cpu().numpy() for x in r])
+    for a, c in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, c)
+
+
+def test_graph_replay_is_stable(ctx):
+    n, k, b, B, L, T = 64, 3, 4096, 5, 12, 10
+    P = planted_tensor(n, 3, noise=0.02, seed=6, dtype=np.float32)
+    tab, h, xi = _tables(ctx, 4, n, b, B)
+    Td = torch.from_numpy(P.T).to(DEV)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    lam = torch.empty(k, dtype=torch.float64, device=DEV)
+    U = torch.empty((k, n), dtype=torch.float64, device=DEV)
+    tau = torch.empty(k, dtype=torch.int32, device=DEV)
+    fl = torch.empty((k, L), dtype=torch.int32, device=DEV)
+    results = []
+    for rep in range(4):
+        tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+        tsk.decompose(ctx, tab, S64, S32, k, L, T, seed=7, lam_out=lam, U_out=U, tau_out=tau,
+                      flags_out=fl)
+        # eager work and a synchronisation between replays
+        junk = torch.randn(1000, device=DEV).sum()
+        torch.cuda.synchronize()
+        results.append((lam.cpu().numpy().copy(), U.cpu().numpy().copy(), float(junk)))
+    for r in results[1:]:
+        np.testing.assert_array_equal(r[0], results[0][0])
+        np.testing.assert_array_equal(r[1], results[0][1])
+    plain = tsk.decompose(ctx, tab, *tsk.new_sketch(tab, DEV), k, L, T, seed=7, plain=True)
+    del plain
+
+
+def test_injective_hash_reduces_to_dense_power_method(ctx):
+    n, b, B, k, L, T = 8, 512, 3, 3, 4, 12
+    rng = np.random.default_rng(9)
+    h = np.zeros((B, 3, n), dtype=np.uint32)
+    h[:, 0] = np.arange(n)
+    h[:, 1] = n * np.arange(n)
+    h[:, 2] = n * n * np.arange(n)
+    xi = rng.choice(np.array([-1, 1], dtype=np.int8), size=(B, 3, n))
+    tab = tsk.Tables(ctx, h, xi, b)
+    P = planted_tensor(n, k, noise=0.05, seed=3)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    u0 = np.stack([oracle.start_vectors_spec(4, c, L, n) for c in range(k)])
+    lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F64,
+                                 u0=torch.from_numpy(u0).to(DEV))
+    rd = oracle.rtpm_dense(P.T, k, L, T, u0)
+    assert np.abs(lam.cpu().numpy() - rd.lam).max() < 1e-11
+    assert np.abs(U.cpu().numpy() - rd.U).max() < 1e-11
+
+
+def test_zero_tensor_sets_flags_and_stays_finite(ctx):
+    n, b, B, k, L, T = 16, 256, 3, 2, 4, 3
+    tab, _, _ = _tables(ctx, 3, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.zeros((n, n, n), dtype=torch.float32, device=DEV), S64, S32)
+    lam, U, tau, flags = tsk.decompose(ctx, tab, S64, S32, k, L, T, seed=1)
+    assert (flags.cpu().numpy() == 1).all()
+    assert np.all(lam.cpu().numpy() == 0.0)
+    Un = U.cpu().numpy()
+    assert np.all(np.isfinite(Un))
+    np.testing.assert_allclose(np.linalg.norm(Un, axis=1), 1.0, atol=1e-6)
+
+
+def test_nan_input_is_flagged_not_propagated_into_u(ctx):
+    n, b, B, L = 16, 256, 3, 4
+    tab, _, _ = _tables(ctx, 3, n, b, B)
+    T = torch.zeros((n, n, n), dtype=torch.float32, device=DEV)
+    T[1, 2, 3] = float("nan")
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, T, S64, S32)
+    U = torch.nn.functional.normalize(torch.randn((L, n), device=DEV), dim=1)
+    flags = torch.zeros((L,), dtype=torch.int32, device=DEV)
+    Uo = tsk.power_update(ctx, tab, U, S64=S64, S32=S32, flags=flags)
+    assert (flags.cpu().numpy() == 1).all()
+    np.testing.assert_array_equal(Uo.cpu().numpy(), U.cpu().numpy())
+
+
+def test_argument_errors(ctx):
+    h, xi = tsk.hash_generate(0, 10, 256, 2)
+    with pytest.raises(tsk.TskError, match="EINVAL"):
+        tsk.Tables(ctx, h, xi, 100)                  # b not a power of two
+    with pytest.raises(tsk.TskError, match="EINVAL"):
+        tsk.Tables(ctx, h, xi, 128)                  # h >= b
+    h65, xi65 = tsk.hash_generate(0, 10, 256, 65)
+    with pytest.raises(tsk.TskError, match="EINVAL"):
+        tsk.Tables(ctx, h65, xi65, 256)              # B > 64
+    hb, xb = tsk.hash_generate(0, 10, 32768, 2)
+    with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
+        tsk.Tables(ctx, hb, xb, 32768)
+    h16, x16 = tsk.hash_generate(0, 10, 16384, 2)
+    tab16 = tsk.Tables(ctx, h16, x16, 16384)
+    S64, S32 = tsk.new_sketch(tab16, DEV)
+    U = torch.zeros((2, 10), dtype=torch.float64, device=DEV)
+    with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
+        tsk.power_update(ctx, tab16, U, S64=S64, S32=S32)   # FP64 power step limited to 8192
+    U32 = torch.zeros((2, 10), dtype=torch.float32, device=DEV)
+    L = tsk.lib()
+    st = L.tsk_power_update(ctx.handle, tab16.handle, 0, S64.data_ptr(), S32.data_ptr(), 2,
+                            U32.data_ptr(), U32.data_ptr(), None, None, None)
+    assert st == -1                                            # aliasing in/out
+    with pytest.raises(tsk.TskError, match="EINVAL"):
+        tsk.decompose(ctx, tab16, S64, S32, 11, 2, 2)          # k > n
