@@ -1,0 +1,254 @@
+"""Benchmark of the sketched robust tensor power method on one MI355X.
+
+Workload (dense FP32, one GPU): a planted symmetric tensor with n=200
+(8M entries), rank k=10, lam ~ U[1,2], orthonormal factors, noise 0.05;
+sketch length b=16384, B=10 sketches, L=50 restarts x T=30 power steps,
+10 components by deflation.  One step is the whole hot path: the dense
+sketch build of Eq. (1) followed by Algorithm 1 (all restarts and sketches
+batched in each launch, recorded in a HIP graph).
+
+Prints one JSON line.  ``value`` is sketch-updates per second over whole
+steps (build included): one sketch-update is one Proposition-1 read-off for
+one (restart, sketch) pair; a step performs k*(T+1)*L*B of them.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sketched power updates/sec + sketch_build GB/s vs plain path at fixed recovery error"
+PEAK_HBM_GBPS = 8000.0
+PEAK_FP32_VALU_TFLOPS = 157.3
+
+N, K, B_LEN, B_CNT, L, T_ITERS = 200, 10, 16384, 10, 50, 30
+NOISE, SEED = 0.05, 1
+
+
+def sketch_update_flops(b: int) -> float:
+    """Algorithmic FLOPs of one sketch-update: the packed complex FFT of the two
+    count sketches (5 b log2 b), the half-length inverse of the real product
+    (2.5 b log2 b) and the spectral products (~12 per bin over b/2 bins)."""
+    lg = np.log2(b)
+    return 5.0 * b * lg + 2.5 * b * lg + 6.0 * b
+
+
+def build_bytes(n: int, b: int, B: int) -> float:
+    """Algorithmic bytes of the dense build: the FP32 tensor read once, the B
+    sketches written once (FP32), the three 4-byte tables of each sketch."""
+    return 4.0 * n ** 3 + 4.0 * B * b + 12.0 * B * n
+
+
+def residual(Tnp, lam, U):
+    R = Tnp.astype(np.float64).copy()
+    for i in range(len(lam)):
+        R -= lam[i] * np.einsum("i,j,k->ijk", U[i], U[i], U[i])
+    return float(np.sum(R * R))
+
+
+def wrong_vectors(V_true, V_hat, thresh=0.1):
+    """Planted vectors with no recovered vector within squared distance 0.1."""
+    d2 = ((V_true[:, None, :] - V_hat[None, :, :]) ** 2).sum(-1)
+    return int(np.sum(d2.min(axis=1) > thresh))
+
+
+def cpu_baseline(P, h, xi, budget_s: float):
+    """The CPU oracle timed on a bounded sample of the same workload: the dense
+    build of all B sketches, then power steps over all L restarts until the
+    time budget is spent.  Scaled to the whole step as
+    t_step = t_build + k*(T+1) * t_power_step."""
+    import oracle
+    T64 = P.T.astype(np.float64)
+    t0 = time.perf_counter()
+    S = np.stack([oracle.sketch_dense(T64, h[m], xi[m], B_LEN) for m in range(B_CNT)])
+    t_build = time.perf_counter() - t0
+    U = np.stack([oracle.start_vectors_spec(SEED, 0, L, N)])[0]
+    steps = 0
+    t1 = time.perf_counter()
+    while True:
+        _, U, _ = oracle.power_update(S, h, xi, U)
+        steps += 1
+        if time.perf_counter() - t1 > budget_s:
+            break
+    t_step = (time.perf_counter() - t1) / steps
+    t_whole = t_build + K * (T_ITERS + 1) * t_step
+    updates = K * (T_ITERS + 1) * L * B_CNT
+    return {
+        "value": updates / t_whole, "unit": "sketch-updates/s", "cores": 1, "kind": "oracle",
+        "sample": (f"FP64 numpy oracle, 1 thread: dense build of {B_CNT} sketches "
+                   f"({t_build:.2f} s) + {steps} power steps over L={L} restarts "
+                   f"({t_step:.3f} s each), scaled to one step of k={K} components x "
+                   f"(T+1)={T_ITERS + 1} power steps"),
+        "t_build_s": t_build, "t_power_step_s": t_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle power steps in the CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(see the sharding paragraph of the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1506_04448_amd as tsk
+    from paper_1506_04448_amd.workloads import planted_tensor
+
+    dev = torch.device("cuda:0")
+    P = planted_tensor(N, K, noise=NOISE, seed=SEED, dtype=np.float32)
+    h, xi = tsk.hash_generate(SEED, N, B_LEN, B_CNT)
+    ctx = tsk.Context(0)
+    tab = tsk.Tables(ctx, h, xi, B_LEN)
+    Td = torch.from_numpy(P.T).to(dev)
+    S64, S32 = tsk.new_sketch(tab, dev)
+    lam = torch.empty(K, dtype=torch.float64, device=dev)
+    U = torch.empty((K, N), dtype=torch.float64, device=dev)
+    tau = torch.empty(K, dtype=torch.int32, device=dev)
+    flags = torch.empty((K, L), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+        tsk.decompose(ctx, tab, S64, S32, K, L, T_ITERS, dtype=tsk.F32, seed=SEED,
+                      lam_out=lam, U_out=U, tau_out=tau, flags_out=flags)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    updates = K * (T_ITERS + 1) * L * B_CNT
+    value = updates / (wall / args.steps)
+    lam_b, U_b = lam.cpu().numpy().copy(), U.cpu().numpy().copy()
+    res_b = residual(P.T, lam_b, U_b)
+    wrong_b = wrong_vectors(P.V, U_b)
+
+    # Dense build alone, HIP events on the launch stream.
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nb = 20
+    e0.record(stream)
+    for _ in range(nb):
+        tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1) / nb
+    build_gbps = build_bytes(N, B_LEN, B_CNT) / (build_ms * 1e-3) / 1e9
+
+    # Dominant kernel: the power-step kernel over all L x B (restart, sketch)
+    # pairs, launched alone (Proposition-1 read-offs for L vectors).
+    Ut = torch.nn.functional.normalize(torch.randn((L, N), device=dev), dim=1)
+    Vt = torch.empty((L, B_CNT, N), dtype=torch.float32, device=dev)
+    npw = 200
+    for _ in range(5):
+        tsk.contract_tiuu(ctx, tab, Ut, S32=S32, V=Vt)
+    e0.record(stream)
+    for i in range(npw):
+        tsk.contract_tiuu(ctx, tab, Ut, S32=S32, V=Vt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    power_ms = e0.elapsed_time(e1) / npw
+    flops_launch = sketch_update_flops(B_LEN) * L * B_CNT
+    achieved_tflops = flops_launch / (power_ms * 1e-3) / 1e12
+
+    # Decomposition alone, batched (graph) and plain (one launch per restart
+    # and step, no graph), from the same sketch: the build's LDS atomics may
+    # add in a different order from one build to the next.
+    tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+    S64_0, S32_0 = S64.clone(), S32.clone()
+    nd = 5
+    dec_ms = []
+    for _ in range(nd):
+        S64.copy_(S64_0)
+        S32.copy_(S32_0)
+        e0.record(stream)
+        tsk.decompose(ctx, tab, S64, S32, K, L, T_ITERS, dtype=tsk.F32, seed=SEED,
+                      lam_out=lam, U_out=U, tau_out=tau, flags_out=flags)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dec_ms.append(e0.elapsed_time(e1))
+    decompose_ms = float(np.median(dec_ms))
+    lam_d, U_d = lam.cpu().numpy().copy(), U.cpu().numpy().copy()
+    plain = None
+    if not args.no_plain:
+        S64.copy_(S64_0)
+        S32.copy_(S32_0)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        lp, Up, _, _ = tsk.decompose(ctx, tab, S64, S32, K, L, T_ITERS, dtype=tsk.F32, seed=SEED,
+                                     plain=True)
+        torch.cuda.synchronize()
+        plain_ms = 1e3 * (time.perf_counter() - tp)
+        lam_p, U_p = lp.cpu().numpy(), Up.cpu().numpy()
+        plain = {
+            "decompose_ms": plain_ms, "batched_decompose_ms": decompose_ms,
+            "sketch_updates_per_s": updates / (plain_ms * 1e-3),
+            "residual": residual(P.T, lam_p, U_p),
+            "batched_residual": residual(P.T, lam_d, U_d),
+            "wrong_vectors": int(wrong_vectors(P.V, U_p)),
+            "same_result_as_batched": bool(np.array_equal(lam_p, lam_d) and np.array_equal(U_p, U_d)),
+        }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P, h, xi, args.cpu_budget)
+        cpu.pop("t_build_s")
+        cpu.pop("t_power_step_s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sketch-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dense symmetric planted tensor n={N} (FP32), k={K}, noise={NOISE}; "
+                               f"b={B_LEN}, B={B_CNT}, L={L}, T={T_ITERS}; build + decompose",
+                   "n": N, "k": K, "b": B_LEN, "B": B_CNT, "L": L, "T": T_ITERS,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "k_power<float,14>",
+                     "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": None, "launch_ms": power_ms,
+                     "flops_per_launch": flops_launch},
+        "sketch_build": {"GBps": build_gbps, "ms": build_ms,
+                         "frac_hbm": build_gbps / PEAK_HBM_GBPS,
+                         "bytes": build_bytes(N, B_LEN, B_CNT)},
+        "recovery": {"residual": res_b, "wrong_vectors": int(wrong_b)},
+        "plain_path": plain,
+        "decompose_ms": decompose_ms,
+        "decompose_sketch_updates_per_s": updates / (decompose_ms * 1e-3),
+        "speedup_vs_plain": (plain["decompose_ms"] / decompose_ms) if plain else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    tab.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -21,9 +21,11 @@
  *     (interleaved re, im), for each of the B independent sketches:
  *       S64 : double[B][b/2+1][2]  master copy (FP64)
  *       S32 : float [B][b/2+1][2]  working copy used by the FP32 power method
- *   - Limits: 1 <= n <= 65535, b a power of two with 64 <= b <= 16384
- *     (b <= 8192 for the FP64 power method), 1 <= B <= 64, L >= 1, T >= 1,
- *     1 <= k <= n.  Larger b returns TSK_EUNSUPPORTED.
+ *   - Limits: 1 <= n <= 65535, b a power of two with 64 <= b <= 16384,
+ *     1 <= B <= 64, 1 <= L <= 65535, T >= 1, 1 <= k <= n.  A power step
+ *     also needs its work-group's LDS (the half spectrum, twiddles and the
+ *     n-vector) to fit one CU; requests outside the built kernel limits
+ *     return TSK_EUNSUPPORTED.
  */
 #ifndef TSK_H
 #define TSK_H
@@ -139,6 +141,14 @@ tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
                             const double* S64, const float* S32, int L,
                             const void* U_in, void* U_out, void* V, int32_t* flags,
                             void* stream);
+
+/* Per-sketch estimates of T(I,u,u) for L vectors (Proposition 1), without
+ * the median: V[tau][m][i] = xi1(i) sbar[h1(i)],
+ * sbar = F^-1( S^(m) o conj F(s2 u) o conj F(s3 u) ).  One kernel launch
+ * over all L x B (restart, sketch) pairs.  U: [L][n], V: [L][B][n] in dtype. */
+tsk_status tsk_contract_tiuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                             const double* S64, const float* S32, int L, const void* U,
+                             void* V, void* stream);
 
 /* T(u,u,u) estimates for L vectors (Eq. (3) with X = u(x)u(x)u):
  *   lam_per[tau][m] = <s^(m), s^(m)(u^(x)3)> = sum_i u_i v^(m)_i(u),

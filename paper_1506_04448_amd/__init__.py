@@ -18,7 +18,8 @@ import numpy as np
 __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
-    "sketch_export", "sketch_deflate", "power_update", "contract_uuu", "decompose",
+    "sketch_export", "sketch_deflate", "power_update", "contract_tiuu", "contract_uuu",
+    "decompose",
     "F32", "F64",
 ]
 
@@ -59,6 +60,7 @@ _SIGS = {
     "tsk_sketch_deflate": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_uuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
+    "tsk_contract_tiuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P], _I),
     "tsk_decompose": ([_P, _P, _I, _P, _P, _I, _I, _I, _P, _U64, _P, _P, _P, _P, _I, _P], _I),
 }
 
@@ -285,6 +287,21 @@ def power_update(ctx, tab, U_in, S64=None, S32=None, U_out=None, V=None, flags=N
         ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U_in), _ptr(U_out), _ptr(V),
         _ptr(flags), _stream(stream)))
     return U_out
+
+
+def contract_tiuu(ctx, tab, U, S64=None, S32=None, V=None, stream=None):
+    """Per-sketch T(I,u,u) estimates V [L][B][n] (Proposition 1, no median)."""
+    import torch
+    dt, tdt = _vdtype(U.dtype)
+    L = U.shape[0]
+    _tensor(U, "U", tdt, (L, tab.n))
+    _spectra(tab, dt, S64, S32)
+    if V is None:
+        V = torch.empty((L, tab.B, tab.n), dtype=tdt, device=U.device)
+    _tensor(V, "V", tdt, (L, tab.B, tab.n))
+    _check("tsk_contract_tiuu", lib().tsk_contract_tiuu(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U), _ptr(V), _stream(stream)))
+    return V
 
 
 def contract_uuu(ctx, tab, U, S64=None, S32=None, lam_per=None, stream=None):

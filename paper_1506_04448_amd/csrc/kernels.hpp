@@ -5,7 +5,12 @@
 //   hxs [B][3][n]  uint32  the same entries sorted by bucket (stable in i)
 //   ord [B][3][n]  uint32  the index i of each sorted entry
 //   spectra        cx<R>[B][b/2+1]  half spectrum of each of the B sketches
-//   vectors        R[L][n]
+//   vectors        R[L][n]; per-sketch estimates R[L][B][n]
+//   twiddles       cx<R>[64 + b/64 + 1]  (tlo then thi, see fft.hpp)
+//
+// Real transforms of length b use one complex transform of length H = b/2 on
+// the even/odd packing z_s = x_2s + i x_2s+1, so every work-group holds only
+// H complex values in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,7 +44,7 @@ __device__ double block_sum(double v, double* red) {
 
 // Median of the values held by lanes 0..B-1 of a wave (B <= 64), returned to
 // every lane; must be called by all 64 lanes.  Ranks break ties by lane, so
-// ranks are a permutation; for even B the two middle values are averaged.
+// they are a permutation; for even B the two middle values are averaged.
 template <typename T>
 __device__ T wave_median(T val, int B) {
   const int lane = wave_lane();
@@ -61,12 +66,12 @@ __device__ T wave_median(T val, int B) {
   return (lo + hi) * T(0.5);
 }
 
-// Deterministic count sketch of u into dst[bucket * stride + off]: the entries
-// sharing a bucket are summed by one thread in increasing index order.
-template <typename R, typename U>
-__device__ void count_sketch_lds(R* dst, int stride, int off, const uint32_t* __restrict__ hxs,
-                                 const uint32_t* __restrict__ ord, const U* __restrict__ u, int n,
-                                 int nt) {
+// Deterministic count sketch: the entries sharing a bucket are summed by one
+// thread in increasing index order; store(bucket, sum) writes the result.
+template <typename R, typename GetU, typename Store>
+__device__ __forceinline__ void count_sketch(const uint32_t* __restrict__ hxs,
+                                             const uint32_t* __restrict__ ord, int n, int nt,
+                                             GetU getu, Store store) {
   for (int p = threadIdx.x; p < n; p += nt) {
     uint32_t e = hxs[p];
     const uint32_t bk = e >> 1;
@@ -74,53 +79,42 @@ __device__ void count_sketch_lds(R* dst, int stride, int off, const uint32_t* __
     R acc = R(0);
     int q = p;
     while (true) {
-      const R val = (R)u[ord[q]];
+      const R val = getu(ord[q]);
       acc += (e & 1u) ? -val : val;
       if (++q >= n) break;
       e = hxs[q];
       if ((e >> 1) != bk) break;
     }
-    dst[(size_t)bk * stride + off] = acc;
+    store(bk, acc);
   }
 }
 
-// Threads per work-group for a transform of length 2^logb.
-constexpr int threads_for(int logb) { return logb >= 14 ? 1024 : (logb >= 13 ? 512 : 256); }
-
-// ---------------------------------------------------------------------------
-// Power step / evaluation, one work-group per (sketch m, restart tau).
-// ---------------------------------------------------------------------------
+// Store of a real sequence x_t into the even/odd packing z_{t/2}.
 template <typename R>
-struct PowerArgs {
-  const uint32_t* hx;
-  const uint32_t* hxs;
-  const uint32_t* ord;
-  int n, B;
-  const cx<R>* S;       // [B][b/2+1]
-  const cx<R>* tw;      // [b]
-  const R* Uin;         // [L][n]
-  R* Uout;              // [L][n]
-  R* V;                 // [L][B][n]
-  double* lam_per;      // [L][B]  (evaluate)
-  double* lam_med;      // [L]     (evaluate)
-  int32_t* flags;       // [L]     (power step; nullable)
-  unsigned* counter;    // [L], zero between launches
-  int tau0;             // first restart of this launch
-  int mode;             // 0 = power step, 1 = evaluate T(u,u,u)
-};
-
-// P_k = S_k conj(F(s2)_k) conj(F(s3)_k) from the packed spectrum Z of s2 + i s3.
+__device__ __forceinline__ void store_packed(const Soa<R>& buf, uint32_t t, R v) {
+  const int q = pidx((int)(t >> 1));
+  if (t & 1u) buf.im[q] = v;
+  else buf.re[q] = v;
+}
 template <typename R>
-__device__ __forceinline__ cx<R> spectrum_product(cx<R> Zk, cx<R> Zmk, cx<R> Sk) {
-  const cx<R> zc = cconj(Zmk);
-  const cx<R> s2 = cscale(cadd(Zk, zc), R(0.5));
-  const cx<R> d = csub(Zk, zc);
-  const cx<R> s3 = {R(0.5) * d.y, R(-0.5) * d.x};  // (Zk - conj Z_{b-k}) / (2i)
-  return cmulc(Sk, cmul(s2, s3));
+__device__ __forceinline__ R load_packed(const Soa<R>& buf, uint32_t t) {
+  const int q = pidx((int)(t >> 1));
+  return (t & 1u) ? buf.im[q] : buf.re[q];
 }
 
-// Half-length packing for a real inverse transform: Y_k = E_k + i O_k with
-// E_k = (X_k + conj X_{H-k})/2, O_k = (X_k - conj X_{H-k})/2 * conj(W^k).
+// X_k of a real length-b sequence from the length-H transform Z of its
+// packing: X_k = (Z_k + conj Z_{H-k})/2 + W_b^k (Z_k - conj Z_{H-k})/(2i).
+template <typename R>
+__device__ __forceinline__ cx<R> r2c_post(cx<R> Za, cx<R> Zb, cx<R> w) {
+  const cx<R> c = cconj(Zb);
+  const cx<R> e = cscale(cadd(Za, c), R(0.5));
+  const cx<R> d = csub(Za, c);
+  const cx<R> o = {R(0.5) * d.y, R(-0.5) * d.x};
+  return cadd(e, cmul(w, o));
+}
+
+// Packing for a real inverse transform: Y_k = E_k + i O_k with
+// E_k = (X_k + conj X_{H-k})/2, O_k = (X_k - conj X_{H-k})/2 * conj(W_b^k).
 template <typename R>
 __device__ __forceinline__ cx<R> c2r_pack(cx<R> Xk, cx<R> XHk, cx<R> Wk) {
   const cx<R> c = cconj(XHk);
@@ -129,69 +123,229 @@ __device__ __forceinline__ cx<R> c2r_pack(cx<R> Xk, cx<R> XHk, cx<R> Wk) {
   return {E.x - O.y, E.y + O.x};
 }
 
+// Threads per work-group for a half-length H = 2^logh transform held in LDS:
+// eight complex values per thread (radix-8 passes), 64 to 1024 threads.
+template <typename R>
+constexpr int threads_for_h(int logh) {
+  return logh >= 13 ? 1024 : (logh >= 9 ? (1 << (logh - 3)) : 64);
+}
+constexpr int twiddle_len(int b) { return 64 + b / 64 + 1; }
+
+// ---------------------------------------------------------------------------
+// Median of B <= MAXB values held in registers by one thread: the element of
+// rank (B-1)/2 (odd B) or the mean of ranks B/2-1 and B/2 (even B), ranks
+// breaking ties by index.  NaN inputs give NaN.
+// ---------------------------------------------------------------------------
+template <typename R, int MAXB>
+__device__ __forceinline__ R thread_median(const R* v, int B) {
+  const int ra = (B - 1) / 2, rb = B / 2;
+  R a = R(__builtin_nan("")), c = R(__builtin_nan(""));
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    if (i < B) {
+      int r = 0;
+#pragma unroll
+      for (int j = 0; j < MAXB; ++j)
+        if (j < B) r += (v[j] < v[i]) || (v[j] == v[i] && j < i);
+      if (r == ra) a = v[i];
+      if (r == rb) c = v[i];
+    }
+  }
+  return (B & 1) ? a : (a + c) * R(0.5);
+}
+
+// ---------------------------------------------------------------------------
+// Median prologue: u = vbar / ||vbar||, vbar_i = med_m Vprev[tau][m][i], for
+// the n coordinates of one restart, into u[] (LDS or global).  Falls back to
+// Uprev[tau] when ||vbar|| is zero or not finite.  `stage` is scratch LDS of
+// `cap` elements.  One thread per coordinate for B <= 16, one wave per
+// coordinate above.  Returns true when the median vector was usable.
+// ---------------------------------------------------------------------------
+template <typename R, int NT>
+__device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict__ Uprev, int tau,
+                                int n, int B, R* u, R* stage, int cap, double* red) {
+  const int lane = wave_lane();
+  const int wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const R* vb = Vprev + (size_t)tau * B * n;
+  const int CH = max(1, cap / B);
+  double ss = 0.0;
+  for (int c0 = 0; c0 < n; c0 += CH) {
+    const int cw = min(CH, n - c0);
+    for (int e = threadIdx.x; e < B * cw; e += NT) {
+      const int mm = e / cw, ii = e - mm * cw;
+      stage[mm * CH + ii] = vb[(size_t)mm * n + c0 + ii];
+    }
+    __syncthreads();
+    if (B <= 16) {
+      for (int ii = threadIdx.x; ii < cw; ii += NT) {
+        R v[16];
+#pragma unroll
+        for (int mm = 0; mm < 16; ++mm) v[mm] = mm < B ? stage[mm * CH + ii] : R(0);
+        const R med = thread_median<R, 16>(v, B);
+        u[c0 + ii] = med;
+        ss += (double)med * (double)med;
+      }
+    } else {
+      for (int ii = wave; ii < cw; ii += NW) {
+        const R x = lane < B ? stage[lane * CH + ii] : R(0);
+        const R med = wave_median<R>(x, B);
+        if (lane == 0) {
+          u[c0 + ii] = med;
+          ss += (double)med * (double)med;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const double nrm = sqrt(block_sum<NT>(ss, red));
+  const bool ok = nrm > 0.0 && nrm < __builtin_inf();
+  if (ok) {
+    const R inv = R(1.0 / nrm);
+    for (int i = threadIdx.x; i < n; i += NT) u[i] *= inv;
+  } else {
+    const R* up = Uprev + (size_t)tau * n;
+    for (int i = threadIdx.x; i < n; i += NT) u[i] = up[i];
+  }
+  __syncthreads();
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Power step / evaluation: one work-group per (sketch m, restart tau).
+//   u     = Uprev[tau] (prefix 0) or the normalised median of Vprev[tau] (prefix 1)
+//   A_k   = S_k conj(F(s2 u)_k);   P_k = A_k conj(F(s3 u)_k)
+//   sbar  = F^-1(P);  v_i = xi1(i) sbar[h1(i)]  -> V[tau][m]
+//   mode 1 also writes lam_per[tau][m] = u . v.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PowerArgs {
+  const uint32_t* hx;
+  const uint32_t* hxs;
+  const uint32_t* ord;
+  int n, B;
+  const cx<R>* S;       // [B][H+1]
+  const cx<R>* twg;     // [twiddle_len(b)]
+  const R* Uprev;       // [L][n]
+  const R* Vprev;       // [L][B][n]   (prefix 1)
+  R* Ucur;              // [L][n]      (prefix 1, written by m == 0)
+  int32_t* flags;       // [L]         (prefix 1, nullable)
+  R* V;                 // [L][B][n]
+  double* lam_per;      // [L][B]      (mode 1)
+  int tau0;
+  int prefix;
+  int mode;
+};
+
+// LDS of one work-group (static): the half-length sequence (padded, split
+// re/im), the twiddle table, the current vector u (at most power_max_n
+// coordinates) and a reduction scratch.
+constexpr int kLdsBytes = 160 * 1024;
 template <typename R, int LOGB>
-__global__ __launch_bounds__(threads_for(LOGB)) void k_power(PowerArgs<R> a) {
-  constexpr int NT = threads_for(LOGB);
+constexpr int power_max_n() {
+  constexpr int fixed = (int)(sizeof(R) * 2 * padded_len(1 << (LOGB - 1)) +
+                              sizeof(cx<R>) * twiddle_len(1 << LOGB) + 16 * sizeof(double));
+  constexpr int fit = (kLdsBytes - fixed) / (int)sizeof(R) / 64 * 64;
+  return fit < 4096 ? fit : 4096;
+}
+
+// Waves per SIMD the power kernel is compiled for (4 waves of a 1024-thread
+// work-group leave 128 VGPRs per lane).
+template <typename R>
+constexpr int power_min_waves(int logh) {
+  return threads_for_h<R>(logh) >= 256 ? threads_for_h<R>(logh) / 256 : 1;
+}
+
+template <typename R, int LOGB>
+__global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB - 1)) void k_power(PowerArgs<R> a) {
+  constexpr int LOGH = LOGB - 1;
+  constexpr int NT = threads_for_h<R>(LOGH);
   constexpr int b = 1 << LOGB;
   constexpr int H = b / 2;
-  __shared__ cx<R> buf[b];
-  __shared__ double red[NT / 64];
-  __shared__ int s_last;
+  constexpr int PL = padded_len(H);
+  // Thread tid owns the pairs (k, H-k) for k = tid + q NT < H/2; thread 0
+  // also owns k = H/2, which pairs with itself.
+  constexpr int PK = (H / 2 + NT - 1) / NT;
+  constexpr bool FULL = (H / 2) % NT == 0;
+  constexpr int NU = power_max_n<R, LOGB>();
+  __shared__ __align__(16) R re[2 * PL];
+  __shared__ __align__(16) cx<R> twl[twiddle_len(b)];
+  __shared__ __align__(16) R u[NU];
+  __shared__ double red[16];
+  R* im = re + PL;
+  const Soa<R> buf{re, im};
 
   const int tid = threadIdx.x;
   const int m = blockIdx.x;
   const int tau = a.tau0 + blockIdx.y;
   const int n = a.n;
   const int B = a.B;
-  const R* u = a.Uin + (size_t)tau * n;
   const size_t tb = (size_t)m * 3 * n;
+  const Twiddle<R> tw = load_twiddles<R>(twl, a.twg, b, NT);
 
-  for (int t = tid; t < b; t += NT) buf[t] = cx<R>{R(0), R(0)};
-  __syncthreads();
-  // s2 into the real parts, s3 into the imaginary parts.
-  count_sketch_lds<R, R>(reinterpret_cast<R*>(buf), 2, 0, a.hxs + tb + n, a.ord + tb + n, u, n, NT);
-  count_sketch_lds<R, R>(reinterpret_cast<R*>(buf), 2, 1, a.hxs + tb + 2 * n, a.ord + tb + 2 * n, u,
-                         n, NT);
-  __syncthreads();
-  fft_lds<R, LOGB, NT, false>(buf, a.tw, LOGB);
+  if (a.prefix) {
+    const bool ok = median_prologue<R, NT>(a.Vprev, a.Uprev, tau, n, B, u, re, 2 * PL, red);
+    if (m == 0) {
+      for (int i = tid; i < n; i += NT) a.Ucur[(size_t)tau * n + i] = u[i];
+      if (tid == 0 && !ok && a.flags) a.flags[tau] |= 1;
+    }
+  } else {
+    for (int i = tid; i < n; i += NT) u[i] = a.Uprev[(size_t)tau * n + i];
+    __syncthreads();
+  }
 
-  // Product with the tensor's spectrum and packing for the half-length inverse.
-  constexpr int NK = b / 4 + 1;
-  constexpr int PK = (NK + NT - 1) / NT;
   const cx<R>* Sm = a.S + (size_t)m * (H + 1);
-  cx<R> y0[PK], y1[PK];
+  cx<R> p0[PK], p1[PK], pmid;
+  auto getu = [&](uint32_t i) -> R { return u[i]; };
+  auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
+#pragma unroll 1
+  for (int mode_j = 1; mode_j <= 2; ++mode_j) {
+    for (int t = tid; t < PL; t += NT) {
+      re[t] = R(0);
+      im[t] = R(0);
+    }
+    __syncthreads();
+    count_sketch<R>(a.hxs + tb + (size_t)mode_j * n, a.ord + tb + (size_t)mode_j * n, n, NT, getu,
+                    store);
+    __syncthreads();
+    fft_soa<R, LOGH, NT, false>(buf, tw, b);
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+      const int k = tid + q * NT;
+      if (!FULL && k >= H / 2) break;
+      const cx<R> Za = buf.get(k);
+      const cx<R> Zb = buf.get((H - k) & (H - 1));
+      const cx<R> Xk = r2c_post(Za, Zb, tw.w(k));
+      const cx<R> XHk = r2c_post(Zb, Za, tw.w(H - k));
+      p0[q] = cmulc(mode_j == 1 ? Sm[k] : p0[q], Xk);
+      p1[q] = cmulc(mode_j == 1 ? Sm[H - k] : p1[q], XHk);
+    }
+    if (tid == 0) {
+      const cx<R> Z = buf.get(H / 2);
+      const cx<R> X = r2c_post(Z, Z, tw.w(H / 2));
+      pmid = cmulc(mode_j == 1 ? Sm[H / 2] : pmid, X);
+    }
+    __syncthreads();
+  }
+  // Half-length packing of the real inverse transform of P.
 #pragma unroll
   for (int q = 0; q < PK; ++q) {
     const int k = tid + q * NT;
-    if (k < NK) {
-      const int kk = H - k;
-      const cx<R> Pk = spectrum_product(buf[k], buf[(b - k) & (b - 1)], Sm[k]);
-      const cx<R> Pkk = spectrum_product(buf[kk], buf[H + k], Sm[kk]);
-      y0[q] = c2r_pack(Pk, Pkk, a.tw[k]);
-      y1[q] = c2r_pack(Pkk, Pk, a.tw[kk]);
-    }
+    if (!FULL && k >= H / 2) break;
+    buf.put(k, c2r_pack(p0[q], p1[q], tw.w(k)));
+    if (k > 0) buf.put(H - k, c2r_pack(p1[q], p0[q], tw.w(H - k)));
   }
+  if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, tw.w(H / 2)));
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PK; ++q) {
-    const int k = tid + q * NT;
-    if (k < NK) {
-      buf[k & (H - 1)] = y0[q];  // k = H/2 .. only k < H/2+1 <= H here
-      if (k > 0 && k < b / 4) buf[H - k] = y1[q];
-    }
-  }
-  __syncthreads();
-  fft_lds<R, LOGB - 1, NT, true>(buf, a.tw, LOGB);
+  fft_soa<R, LOGH, NT, true>(buf, tw, b);
 
-  // Read-off v_i = xi1(i) sbar[h1(i)], sbar = 2/b * (Re y, Im y) interleaved.
   const R scale = R(2) / R(b);
-  const R* sbar = reinterpret_cast<const R*>(buf);
   const uint32_t* hx1 = a.hx + tb;
   R* Vrow = a.V + ((size_t)tau * B + m) * n;
   double acc = 0.0;
   for (int i = tid; i < n; i += NT) {
     const uint32_t e = hx1[i];
-    const R val = sbar[e >> 1] * scale;
+    const R val = load_packed(buf, e >> 1) * scale;
     const R v = (e & 1u) ? -val : val;
     Vrow[i] = v;
     acc += (double)u[i] * (double)v;
@@ -200,51 +354,34 @@ __global__ __launch_bounds__(threads_for(LOGB)) void k_power(PowerArgs<R> a) {
     const double lam = block_sum<NT>(acc, red);
     if (tid == 0) a.lam_per[(size_t)tau * B + m] = lam;
   }
+}
 
-  // The last of the B work-groups of this restart takes the median.
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&a.counter[tau], 1u) == (unsigned)(B - 1));
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+// u_out[tau] = normalised median of V[tau] (fallback u_in, flag), grid = L.
+template <typename R>
+__global__ __launch_bounds__(256) void k_median_norm(const R* V, const R* Uin, R* Uout,
+                                                     int32_t* flags, int n, int B) {
+  __shared__ __align__(16) R stage[4096];
+  __shared__ double red[4];
+  const int tau = blockIdx.x;
+  R* u = Uout + (size_t)tau * n;  // the prologue writes u in place
+  const bool ok = median_prologue<R, 256>(V, Uin, tau, n, B, u, stage, 4096, red);
+  if (threadIdx.x == 0 && !ok && flags) flags[tau] |= 1;
+}
 
+// lam_med[tau] = med_m lam_per[tau][m]; one wave per restart.
+__global__ void k_lam_median(const double* lam_per, double* lam_med, int L, int B) {
+  const int tau = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (tau >= L) return;  // whole waves exit together
   const int lane = wave_lane();
-  const int wave = tid >> 6;
-  constexpr int NW = NT / 64;
-  if (a.mode == 1) {
-    if (wave == 0) {
-      const double x = lane < B ? __builtin_nontemporal_load(&a.lam_per[(size_t)tau * B + lane]) : 0.0;
-      const double med = wave_median<double>(x, B);
-      if (lane == 0) a.lam_med[tau] = med;
-    }
-  } else {
-    R* uo = a.Uout + (size_t)tau * n;
-    const R* vbase = a.V + (size_t)tau * B * n;
-    double ss = 0.0;
-    for (int i = wave; i < n; i += NW) {
-      const R x = lane < B ? __builtin_nontemporal_load(&vbase[(size_t)lane * n + i]) : R(0);
-      const R med = wave_median<R>(x, B);
-      if (lane == 0) {
-        uo[i] = med;
-        ss += (double)med * (double)med;
-      }
-    }
-    const double nrm = sqrt(block_sum<NT>(ss, red));
-    const bool ok = nrm > 0.0 && nrm < __builtin_inf();
-    if (lane == 0) {
-      const R inv = ok ? R(1.0 / nrm) : R(0);
-      for (int i = wave; i < n; i += NW) uo[i] = ok ? uo[i] * inv : u[i];
-    }
-    if (!ok && tid == 0 && a.flags) a.flags[tau] |= 1;
-  }
-  if (tid == 0) a.counter[tau] = 0u;
+  const double x = lane < B ? lam_per[(size_t)tau * B + lane] : 0.0;
+  const double med = wave_median<double>(x, B);
+  if (lane == 0) lam_med[tau] = med;
 }
 
 // ---------------------------------------------------------------------------
-// FP64 rank-1 spectra: prod[r][m] = F(s1 u_r) o F(s2 u_r) o F(s3 u_r), optional
-// lam_per[r][m] = <s^(m), s^(m)(u_r^(x)3)> by Parseval on the half spectrum.
-// One work-group per (m, r); real transforms through half-length complex FFTs.
+// FP64 rank-1 spectra, one work-group per (m, r):
+//   prod[r][m] = F(s1 u_r) o F(s2 u_r) o F(s3 u_r),
+//   lam_per[r][m] = <s^(m), s^(m)(u_r^(x)3)> (Parseval) when S64 is given.
 // ---------------------------------------------------------------------------
 struct Rank1Args {
   const uint32_t* hx;
@@ -252,59 +389,91 @@ struct Rank1Args {
   const uint32_t* ord;
   int n, B;
   const double* U;          // [c][n]
-  const cx<double>* tw;     // [b]
+  const cx<double>* twg;    // [twiddle_len(b)]
   cx<double>* prod;         // [c][B][b/2+1]
   const cx<double>* S64;    // nullable: [B][b/2+1]
   double* lam_per;          // [c][B] when S64 != null
 };
 
 template <int LOGB>
-__global__ __launch_bounds__(threads_for(LOGB - 1)) void k_rank1(Rank1Args a) {
-  constexpr int NT = threads_for(LOGB - 1);
+__global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_rank1(Rank1Args a) {
+  constexpr int LOGH = LOGB - 1;
+  constexpr int NT = threads_for_h<double>(LOGH);
   constexpr int b = 1 << LOGB;
   constexpr int H = b / 2;
-  __shared__ cx<double> buf[H];
-  __shared__ double red[NT / 64];
+  constexpr int PL = padded_len(H);
+  constexpr int PK = (H / 2 + NT - 1) / NT;
+  constexpr bool FULL = (H / 2) % NT == 0;
+  __shared__ __align__(16) double re[2 * PL];
+  __shared__ __align__(16) cx<double> twl[twiddle_len(b)];
+  __shared__ double red[16];
+  double* im = re + PL;
+  const Soa<double> buf{re, im};
   const int tid = threadIdx.x;
   const int m = blockIdx.x;
   const int r = blockIdx.y;
   const int n = a.n;
   const double* u = a.U + (size_t)r * n;
-  cx<double>* P = a.prod + ((size_t)r * a.B + m) * (H + 1);
+  const Twiddle<double> tw = load_twiddles<double>(twl, a.twg, b, NT);
+  cx<double> p0[PK], p1[PK], pmid;
+  auto getu = [&](uint32_t i) -> double { return u[i]; };
+  auto store = [&](uint32_t t, double v) { store_packed(buf, t, v); };
+#pragma unroll 1
   for (int j = 0; j < 3; ++j) {
     const size_t tb = ((size_t)m * 3 + j) * n;
-    for (int t = tid; t < H; t += NT) buf[t] = cx<double>{0.0, 0.0};
+    for (int t = tid; t < PL; t += NT) {
+      re[t] = 0.0;
+      im[t] = 0.0;
+    }
     __syncthreads();
-    count_sketch_lds<double, double>(reinterpret_cast<double*>(buf), 1, 0, a.hxs + tb, a.ord + tb, u,
-                                     n, NT);
+    count_sketch<double>(a.hxs + tb, a.ord + tb, n, NT, getu, store);
     __syncthreads();
-    fft_lds<double, LOGB - 1, NT, false>(buf, a.tw, LOGB);
-    for (int k = tid; k <= H; k += NT) {
-      const cx<double> Zk = buf[k & (H - 1)];
-      const cx<double> Zc = cconj(buf[(H - k) & (H - 1)]);
-      const cx<double> Xe = cscale(cadd(Zk, Zc), 0.5);
-      const cx<double> d = csub(Zk, Zc);
-      const cx<double> Xo = {0.5 * d.y, -0.5 * d.x};
-      const cx<double> X = cadd(Xe, cmul(a.tw[k], Xo));
-      P[k] = (j == 0) ? X : cmul(P[k], X);
+    fft_soa<double, LOGH, NT, false>(buf, tw, b);
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+      const int k = tid + q * NT;
+      if (!FULL && k >= H / 2) break;
+      const cx<double> Za = buf.get(k);
+      const cx<double> Zb = buf.get((H - k) & (H - 1));
+      const cx<double> Xk = r2c_post(Za, Zb, tw.w(k));
+      const cx<double> XHk = r2c_post(Zb, Za, tw.w(H - k));
+      p0[q] = j == 0 ? Xk : cmul(p0[q], Xk);
+      p1[q] = j == 0 ? XHk : cmul(p1[q], XHk);
+    }
+    if (tid == 0) {
+      const cx<double> Z = buf.get(H / 2);
+      const cx<double> X = r2c_post(Z, Z, tw.w(H / 2));
+      pmid = j == 0 ? X : cmul(pmid, X);
     }
     __syncthreads();
   }
-  if (a.S64) {
-    const cx<double>* S = a.S64 + (size_t)m * (H + 1);
-    double acc = 0.0;
-    for (int k = tid; k <= H; k += NT) {
-      const cx<double> s = S[k], p = P[k];
-      const double w = (k == 0 || k == H) ? 1.0 : 2.0;
-      acc += w * (s.x * p.x + s.y * p.y);
+  cx<double>* P = a.prod + ((size_t)r * a.B + m) * (H + 1);
+  double acc = 0.0;
+  const cx<double>* S = a.S64 ? a.S64 + (size_t)m * (H + 1) : nullptr;
+  // Parseval on the half spectrum: weight 1 at k = 0 and k = H, 2 elsewhere.
+#pragma unroll
+  for (int q = 0; q < PK; ++q) {
+    const int k = tid + q * NT;
+    if (!FULL && k >= H / 2) break;
+    const double w = k == 0 ? 1.0 : 2.0;
+    P[k] = p0[q];
+    P[H - k] = p1[q];
+    if (S) {
+      const cx<double> s0 = S[k], s1 = S[H - k];
+      acc += w * ((s0.x * p0[q].x + s0.y * p0[q].y) + (s1.x * p1[q].x + s1.y * p1[q].y));
     }
+  }
+  if (tid == 0) {
+    P[H / 2] = pmid;
+    if (S) acc += 2.0 * (S[H / 2].x * pmid.x + S[H / 2].y * pmid.y);
+  }
+  if (S) {
     const double lam = block_sum<NT>(acc, red) / (double)b;
     if (tid == 0) a.lam_per[(size_t)r * a.B + m] = lam;
   }
 }
 
-// S64[m][k] += sum_r coef_r prod[r][m][k]; S32 = (float)S64.
-// coef_r = sign * lam[r]; lam is a device array (e.g. lam_hat just computed).
+// S64[m][k] += sum_r coef_r prod[r][m][k]; S32 = (float)S64; coef_r = sign * lam[r].
 __global__ void k_spec_update(cx<double>* S64, cx<float>* S32, const cx<double>* prod,
                               const double* lam, double sign, int c, int B, int H1) {
   const size_t total = (size_t)B * H1;
@@ -326,26 +495,28 @@ __global__ void k_spec_update(cx<double>* S64, cx<float>* S32, const cx<double>*
 // Time domain <-> half spectrum, FP64, one work-group per sketch.
 // ---------------------------------------------------------------------------
 template <int LOGB>
-__global__ __launch_bounds__(threads_for(LOGB - 1)) void k_r2c64(const double* s_time,
-                                                                   cx<double>* S64, cx<float>* S32,
-                                                                   const cx<double>* tw, int accumulate) {
-  constexpr int NT = threads_for(LOGB - 1);
+__global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_r2c64(const double* s_time,
+                                                                     cx<double>* S64, cx<float>* S32,
+                                                                     const cx<double>* twg,
+                                                                     int accumulate) {
+  constexpr int LOGH = LOGB - 1;
+  constexpr int NT = threads_for_h<double>(LOGH);
   constexpr int b = 1 << LOGB;
   constexpr int H = b / 2;
-  __shared__ cx<double> buf[H];
+  constexpr int PL = padded_len(H);
+  __shared__ __align__(16) double re[2 * PL];
+  __shared__ __align__(16) cx<double> twl[twiddle_len(b)];
+  double* im = re + PL;
+  const Soa<double> buf{re, im};
   const int m = blockIdx.x;
+  const Twiddle<double> tw = load_twiddles<double>(twl, twg, b, NT);
   const cx<double>* src = reinterpret_cast<const cx<double>*>(s_time + (size_t)m * b);
-  for (int t = threadIdx.x; t < H; t += NT) buf[t] = src[t];
+  for (int t = threadIdx.x; t < H; t += NT) buf.put(t, src[t]);
   __syncthreads();
-  fft_lds<double, LOGB - 1, NT, false>(buf, tw, LOGB);
+  fft_soa<double, LOGH, NT, false>(buf, tw, b);
   cx<double>* S = S64 + (size_t)m * (H + 1);
   for (int k = threadIdx.x; k <= H; k += NT) {
-    const cx<double> Zk = buf[k & (H - 1)];
-    const cx<double> Zc = cconj(buf[(H - k) & (H - 1)]);
-    const cx<double> Xe = cscale(cadd(Zk, Zc), 0.5);
-    const cx<double> d = csub(Zk, Zc);
-    const cx<double> Xo = {0.5 * d.y, -0.5 * d.x};
-    cx<double> X = cadd(Xe, cmul(tw[k], Xo));
+    cx<double> X = r2c_post(buf.get(k & (H - 1)), buf.get((H - k) & (H - 1)), tw.w(k));
     if (accumulate) X = cadd(X, S[k]);
     S[k] = X;
     if (S32) S32[(size_t)m * (H + 1) + k] = cx<float>{(float)X.x, (float)X.y};
@@ -353,22 +524,30 @@ __global__ __launch_bounds__(threads_for(LOGB - 1)) void k_r2c64(const double* s
 }
 
 template <int LOGB>
-__global__ __launch_bounds__(threads_for(LOGB - 1)) void k_c2r64(const cx<double>* S64, double* s_time,
-                                                                   const cx<double>* tw) {
-  constexpr int NT = threads_for(LOGB - 1);
+__global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_c2r64(const cx<double>* S64,
+                                                                     double* s_time,
+                                                                     const cx<double>* twg) {
+  constexpr int LOGH = LOGB - 1;
+  constexpr int NT = threads_for_h<double>(LOGH);
   constexpr int b = 1 << LOGB;
   constexpr int H = b / 2;
-  __shared__ cx<double> buf[H];
+  constexpr int PL = padded_len(H);
+  __shared__ __align__(16) double re[2 * PL];
+  __shared__ __align__(16) cx<double> twl[twiddle_len(b)];
+  double* im = re + PL;
+  const Soa<double> buf{re, im};
   const int m = blockIdx.x;
+  const Twiddle<double> tw = load_twiddles<double>(twl, twg, b, NT);
   const cx<double>* S = S64 + (size_t)m * (H + 1);
-  for (int k = threadIdx.x; k < H; k += NT) buf[k] = c2r_pack(S[k], S[H - k], tw[k]);
+  for (int k = threadIdx.x; k < H; k += NT) buf.put(k, c2r_pack(S[k], S[H - k], tw.w(k)));
   __syncthreads();
-  fft_lds<double, LOGB - 1, NT, true>(buf, tw, LOGB);
+  fft_soa<double, LOGH, NT, true>(buf, tw, b);
   double* dst = s_time + (size_t)m * b;
   const double scale = 2.0 / (double)b;
   for (int t = threadIdx.x; t < H; t += NT) {
-    dst[2 * t] = buf[t].x * scale;
-    dst[2 * t + 1] = buf[t].y * scale;
+    const cx<double> y = buf.get(t);
+    dst[2 * t] = y.x * scale;
+    dst[2 * t + 1] = y.y * scale;
   }
 }
 
@@ -376,7 +555,8 @@ __global__ __launch_bounds__(threads_for(LOGB - 1)) void k_c2r64(const cx<double
 // Dense build, Eq. (1).  Work-group (slab, group): the G sketches of `group`
 // accumulate a contiguous slab of (i, j) fibres of T in LDS bins, then write
 // the bins as one partial sum.  Each wave takes whole fibres T[i][j][:] with
-// its lanes along k, so reads of T are coalesced.
+// its lanes along k (coalesced reads), two fibres per iteration; the fibre
+// offsets h1(i) + h2(j) are wave-uniform.
 // ---------------------------------------------------------------------------
 template <typename TIn, typename TAcc>
 struct BuildArgs {
@@ -388,17 +568,24 @@ struct BuildArgs {
   TAcc* partial;              // [ngroups][nslab][G][b]
 };
 
-template <typename TIn, typename TAcc>
-__global__ __launch_bounds__(256) void k_build_dense(BuildArgs<TIn, TAcc> a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// LDS of the dense build (static): BINS accumulator words and a copy of the
+// mode-3 table entries of the group's sketches when they fit (TAB entries),
+// otherwise those entries are read from global memory.
+template <typename TIn, typename TAcc, int BINS, int TAB>
+__global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn, TAcc> a) {
+  __shared__ __align__(16) TAcc bins[BINS];
+  __shared__ uint32_t tab3s[TAB];
   const int n = a.n, b = a.b, G = a.G;
   const int g0 = blockIdx.y * G;
   const int Gc = min(G, a.B - g0);
-  TAcc* bins = reinterpret_cast<TAcc*>(smem);
-  uint32_t* tab = reinterpret_cast<uint32_t*>(bins + (size_t)G * b);  // [G][3][n]
+  const bool tab_in_lds = Gc * n <= TAB;
   const int tid = threadIdx.x;
   for (int t = tid; t < G * b; t += blockDim.x) bins[t] = TAcc(0);
-  for (int t = tid; t < Gc * 3 * n; t += blockDim.x) tab[t] = a.hx[(size_t)g0 * 3 * n + t];
+  if (tab_in_lds)
+    for (int t = tid; t < Gc * n; t += blockDim.x) {
+      const int g = t / n, k = t - g * n;
+      tab3s[t] = a.hx[((size_t)(g0 + g) * 3 + 2) * n + k];
+    }
   __syncthreads();
 
   const long long npairs = (long long)n * n;
@@ -407,17 +594,30 @@ __global__ __launch_bounds__(256) void k_build_dense(BuildArgs<TIn, TAcc> a) {
   const int lane = tid & 63;
   const int nw = blockDim.x >> 6;
   const unsigned bmask = (unsigned)b - 1u;
-  for (long long q = p0 + (tid >> 6); q < p1; q += nw) {
-    const int i = (int)(q / n);
-    const int j = (int)(q - (long long)i * n);
-    const TIn* fib = a.T + q * n;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  for (long long q0 = p0 + 2 * wv; q0 < p1; q0 += 2 * nw) {
+    const bool two = q0 + 1 < p1;
+    const TIn* f0 = a.T + q0 * n;
+    const TIn* f1 = f0 + n;
+    const int i0 = (int)(q0 / n), j0 = (int)(q0 - (long long)i0 * n);
+    const int i1 = (j0 + 1 == n) ? i0 + 1 : i0, j1 = (j0 + 1 == n) ? 0 : j0 + 1;
     for (int k = lane; k < n; k += 64) {
-      const TAcc val = (TAcc)fib[k];
+      const TAcc x0 = (TAcc)f0[k];
+      const TAcc x1 = two ? (TAcc)f1[k] : TAcc(0);
       for (int g = 0; g < Gc; ++g) {
-        const uint32_t* tg = tab + (size_t)g * 3 * n;
-        const uint32_t e1 = tg[i], e2 = tg[n + j], e3 = tg[2 * n + k];
-        const unsigned t = ((e1 >> 1) + (e2 >> 1) + (e3 >> 1)) & bmask;
-        atomicAdd(&bins[(size_t)g * b + t], ((e1 ^ e2 ^ e3) & 1u) ? -val : val);
+        const uint32_t* hg = a.hx + (size_t)(g0 + g) * 3 * n;
+        const uint32_t e3 = tab_in_lds ? tab3s[g * n + k] : hg[2 * n + k];
+        TAcc* bg = bins + (size_t)g * b;
+        {
+          const uint32_t e12 = (hg[i0] >> 1) + (hg[n + j0] >> 1);
+          const uint32_t sg = (hg[i0] ^ hg[n + j0] ^ e3) & 1u;
+          atomicAdd(&bg[(e12 + (e3 >> 1)) & bmask], sg ? -x0 : x0);
+        }
+        if (two) {
+          const uint32_t e12 = (hg[i1] >> 1) + (hg[n + j1] >> 1);
+          const uint32_t sg = (hg[i1] ^ hg[n + j1] ^ e3) & 1u;
+          atomicAdd(&bg[(e12 + (e3 >> 1)) & bmask], sg ? -x1 : x1);
+        }
       }
     }
   }
@@ -451,21 +651,46 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_select(const double* lam_med, int L, const R* Ucand, int n,
                                                 double* u_hat, double* U_out_row, int32_t* tau_out) {
   __shared__ double red[4];
+  __shared__ double bv[4];
+  __shared__ int bt[4];
   __shared__ int s_tau;
+  double best = 0.0;
+  int bi = -1;
+  for (int t = threadIdx.x; t < L; t += 256) {
+    const double x = lam_med[t];
+    const bool fin = (x == x) && x > -__builtin_inf() && x < __builtin_inf();
+    if (fin && (bi < 0 || x > best)) {
+      best = x;
+      bi = t;
+    }
+  }
+  // wave reduction: larger value wins, then the lower index
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_down(best, o);
+    const int oi = __shfl_down(bi, o);
+    if (oi >= 0 && (bi < 0 || ob > best || (ob == best && oi < bi))) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    bv[threadIdx.x >> 6] = best;
+    bt[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    int best = 0;
-    double bv = -__builtin_inf();
-    bool found = false;
-    for (int t = 0; t < L; ++t) {
-      const double x = lam_med[t];
-      if (x == x && x > -__builtin_inf() && x < __builtin_inf() && (!found || x > bv)) {
-        bv = x;
-        best = t;
-        found = true;
+    double b0 = 0.0;
+    int t0 = -1;
+    for (int w = 0; w < 4; ++w) {
+      if (bt[w] < 0) continue;
+      if (t0 < 0 || bv[w] > b0 || (bv[w] == b0 && bt[w] < t0)) {
+        b0 = bv[w];
+        t0 = bt[w];
       }
     }
-    s_tau = best;
-    if (tau_out) *tau_out = best;
+    s_tau = t0 < 0 ? 0 : t0;
+    if (tau_out) *tau_out = s_tau;
   }
   __syncthreads();
   const R* u = Ucand + (size_t)s_tau * n;

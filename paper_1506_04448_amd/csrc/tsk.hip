@@ -39,8 +39,7 @@ char* last_error_buffer() {
 namespace {
 
 constexpr int kMinLogB = 6;
-constexpr int kMaxLogB = 14;       // FP32 power step and all FP64 transforms
-constexpr int kMaxLogB64Power = 13;
+constexpr int kMaxLogB = 14;       // every transform fits one work-group's LDS
 
 int ilog2_exact(int b) {
   if (b <= 0 || (b & (b - 1))) return -1;
@@ -119,28 +118,33 @@ tsk_status ws_get(tsk_ctx* c, int id, size_t bytes, void** out) {
   return TSK_OK;
 }
 
+// Two-level twiddle table for base b (see fft.hpp): tlo[j] = W_b^j for j < 64,
+// then thi[j] = W_b^(64 j) for j <= b/64, computed in FP64 and rounded once.
 template <typename R>
 tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out) {
   auto& mp = (sizeof(R) == 8) ? c->tw64 : c->tw32;
   auto it = mp.find(logb);
   if (it == mp.end()) {
     const int b = 1 << logb;
-    std::vector<cx<R>> h(b);
+    const int cnt = tsk::twiddle_len(b);
+    std::vector<cx<R>> h(cnt);
     const double two_pi = 6.283185307179586476925286766559;
-    for (int j = 0; j < b; ++j) {
-      // exp(-2 pi i j / b), using the quarter-wave symmetry for exact zeros/ones.
+    auto wb = [&](long j) {
+      j %= b;
       double cs, sn;
+      // exact values on the axes
       if (j == 0) { cs = 1.0; sn = 0.0; }
       else if (4 * j == b) { cs = 0.0; sn = -1.0; }
       else if (2 * j == b) { cs = -1.0; sn = 0.0; }
-      else if (4 * j == 3 * b) { cs = 0.0; sn = 1.0; }
+      else if (4 * j == 3 * (long)b) { cs = 0.0; sn = 1.0; }
       else { const double a = two_pi * (double)j / (double)b; cs = cos(a); sn = -sin(a); }
-      h[j].x = (R)cs;
-      h[j].y = (R)sn;
-    }
+      return cx<R>{(R)cs, (R)sn};
+    };
+    for (int j = 0; j < 64; ++j) h[j] = wb(j);
+    for (int j = 0; j <= b / 64; ++j) h[64 + j] = wb(64L * j);
     void* d = nullptr;
-    TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * b));
-    TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * b, hipMemcpyHostToDevice));
+    TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * cnt));
+    TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * cnt, hipMemcpyHostToDevice));
     it = mp.emplace(logb, d).first;
   }
   *out = reinterpret_cast<const cx<R>*>(it->second);
@@ -159,7 +163,11 @@ tsk_status check_launch(const char* what) {
 
 template <typename R, int LOGB>
 tsk_status launch_power_t(const tsk::PowerArgs<R>& a, int B, int nrest, hipStream_t st) {
-  constexpr int NT = tsk::threads_for(LOGB);
+  constexpr int NT = tsk::threads_for_h<R>(LOGB - 1);
+  constexpr int NU = tsk::power_max_n<R, LOGB>();
+  if (a.n > NU)
+    return tsk::fail(TSK_EUNSUPPORTED, "power step: n=%d exceeds %d at b=2^%d in this precision",
+                     a.n, NU, LOGB);
   hipLaunchKernelGGL((tsk::k_power<R, LOGB>), dim3(B, nrest), dim3(NT), 0, st, a);
   return check_launch("k_power");
 }
@@ -175,31 +183,29 @@ tsk_status launch_power(int logb, const tsk::PowerArgs<R>& a, int B, int nrest, 
     case 11: return launch_power_t<R, 11>(a, B, nrest, st);
     case 12: return launch_power_t<R, 12>(a, B, nrest, st);
     case 13: return launch_power_t<R, 13>(a, B, nrest, st);
-    case 14:
-      if constexpr (sizeof(R) == 4) return launch_power_t<R, 14>(a, B, nrest, st);
-      break;
+    case 14: return launch_power_t<R, 14>(a, B, nrest, st);
     default: break;
   }
-  return tsk::fail(TSK_EUNSUPPORTED, "power step: b=2^%d not built for this precision", logb);
+  return tsk::fail(TSK_EUNSUPPORTED, "power step: b=2^%d not built", logb);
 }
 
 template <int LOGB>
 tsk_status launch_rank1_t(const tsk::Rank1Args& a, int B, int c, hipStream_t st) {
-  constexpr int NT = tsk::threads_for(LOGB - 1);
+  constexpr int NT = tsk::threads_for_h<double>(LOGB - 1);
   hipLaunchKernelGGL((tsk::k_rank1<LOGB>), dim3(B, c), dim3(NT), 0, st, a);
   return check_launch("k_rank1");
 }
 template <int LOGB>
 tsk_status launch_r2c_t(const double* s, cx<double>* S64, cx<float>* S32, const cx<double>* tw,
                         int acc, int B, hipStream_t st) {
-  constexpr int NT = tsk::threads_for(LOGB - 1);
+  constexpr int NT = tsk::threads_for_h<double>(LOGB - 1);
   hipLaunchKernelGGL((tsk::k_r2c64<LOGB>), dim3(B), dim3(NT), 0, st, s, S64, S32, tw, acc);
   return check_launch("k_r2c64");
 }
 template <int LOGB>
 tsk_status launch_c2r_t(const cx<double>* S64, double* s, const cx<double>* tw, int B,
                         hipStream_t st) {
-  constexpr int NT = tsk::threads_for(LOGB - 1);
+  constexpr int NT = tsk::threads_for_h<double>(LOGB - 1);
   hipLaunchKernelGGL((tsk::k_c2r64<LOGB>), dim3(B), dim3(NT), 0, st, S64, s, tw);
   return check_launch("k_c2r64");
 }
@@ -370,20 +376,30 @@ extern "C" void tsk_tables_destroy(tsk_tables_t t) {
 
 namespace {
 
+// Two static-LDS size classes of the dense build: 128 KB of bins (one
+// work-group per CU) and 16 KB (several per CU) for small sketches.
+constexpr int kBuildTab = 4096;
+template <typename TAcc>
+constexpr int build_bins_large() { return (128 * 1024) / (int)sizeof(TAcc); }
+template <typename TAcc>
+constexpr int build_bins_small() { return (16 * 1024) / (int)sizeof(TAcc); }
+
 template <typename TIn, typename TAcc>
 tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipStream_t st,
                             double** s_time_out) {
   const int n = tab->n, b = tab->b, B = tab->B;
-  const size_t lds_cap = 160 * 1024;
-  const size_t per_sketch = (size_t)b * sizeof(TAcc) + (size_t)3 * n * 4;
-  if (per_sketch > lds_cap)
-    return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d, n=%d need more LDS than one CU has", b, n);
-  const size_t budget = 128 * 1024;
-  int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)B, budget / per_sketch));
-  if ((size_t)G * per_sketch > lds_cap) G = 1;
+  constexpr int BL = build_bins_large<TAcc>();
+  constexpr int BS = build_bins_small<TAcc>();
+  if (b > BL) return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d too long for one CU's LDS", b);
+  const bool small = B * b <= BS;
+  int G = std::max(1, std::min(B, (small ? BS : BL) / b));
   const int ngroups = (B + G - 1) / G;
+  G = (B + ngroups - 1) / ngroups;  // balance the groups
   const long long npairs = (long long)n * n;
-  int nslab = (int)std::min<long long>(npairs, std::max(1, (2 * 256 + ngroups - 1) / ngroups));
+  // About one work-group per CU in total, never slabs of fewer than 8 fibres.
+  const int target = small ? 1024 : 256;
+  int nslab = (int)std::min<long long>(std::max<long long>(1, npairs / 8),
+                                       std::max(1, (target + ngroups - 1) / ngroups));
   const long long pps = (npairs + nslab - 1) / nslab;
   nslab = (int)((npairs + pps - 1) / pps);
   void* partial = nullptr;
@@ -400,10 +416,12 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   a.pairs_per_slab = pps;
   a.nslab = nslab;
   a.partial = reinterpret_cast<TAcc*>(partial);
-  const size_t lds = (size_t)G * per_sketch;
-  TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_build_dense<TIn, TAcc>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((tsk::k_build_dense<TIn, TAcc>), dim3(nslab, ngroups), dim3(256), lds, st, a);
+  if (small)
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, TAcc, BS, 1024>), dim3(nslab, ngroups), dim3(1024), 0,
+                       st, a);
+  else
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, TAcc, BL, kBuildTab>), dim3(nslab, ngroups),
+                       dim3(1024), 0, st, a);
   TSK_TRY(check_launch("k_build_dense"));
   hipLaunchKernelGGL((tsk::k_build_reduce<TAcc>), dim3(grid_for((size_t)B * b, 256)), dim3(256), 0,
                      st, (const TAcc*)partial, (double*)stime, b, B, G, nslab);
@@ -480,7 +498,7 @@ tsk_status rank1_update(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam, cons
     a.n = n;
     a.B = B;
     a.U = U + (size_t)r0 * n;
-    a.tw = tw;
+    a.twg = tw;
     a.prod = reinterpret_cast<cx<double>*>(prod);
     a.S64 = nullptr;
     a.lam_per = nullptr;
@@ -529,9 +547,9 @@ extern "C" tsk_status tsk_sketch_deflate(tsk_ctx_t ctx, tsk_tables_t tab, const 
 namespace {
 
 template <typename R>
-tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int L, int nrest,
-                        int tau0, const R* Uin, R* Uout, R* V, double* lam_per, double* lam_med,
-                        int32_t* flags, unsigned* counter, int mode, hipStream_t st) {
+tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0,
+                        int prefix, int mode, const R* Uprev, const R* Vprev, R* Ucur,
+                        int32_t* flags, R* V, double* lam_per, hipStream_t st) {
   const cx<R>* tw = nullptr;
   TSK_TRY(get_tw<R>(ctx, tab->logb, &tw));
   tsk::PowerArgs<R> a;
@@ -541,18 +559,29 @@ tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int L
   a.n = tab->n;
   a.B = tab->B;
   a.S = reinterpret_cast<const cx<R>*>(spec);
-  a.tw = tw;
-  a.Uin = Uin;
-  a.Uout = Uout;
+  a.twg = tw;
+  a.Uprev = Uprev;
+  a.Vprev = Vprev;
+  a.Ucur = Ucur;
+  a.flags = flags;
   a.V = V;
   a.lam_per = lam_per;
-  a.lam_med = lam_med;
-  a.flags = flags;
-  a.counter = counter;
   a.tau0 = tau0;
+  a.prefix = prefix;
   a.mode = mode;
-  (void)L;
   return launch_power<R>(tab->logb, a, tab->B, nrest, st);
+}
+
+template <typename R>
+tsk_status median_norm_launch(const R* V, const R* Uin, R* Uout, int32_t* flags, int L, int n, int B,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((tsk::k_median_norm<R>), dim3(L), dim3(256), 0, st, V, Uin, Uout, flags, n, B);
+  return check_launch("k_median_norm");
+}
+
+tsk_status lam_median_launch(const double* lam_per, double* lam_med, int L, int B, hipStream_t st) {
+  hipLaunchKernelGGL(tsk::k_lam_median, dim3((L + 3) / 4), dim3(256), 0, st, lam_per, lam_med, L, B);
+  return check_launch("k_lam_median");
 }
 
 tsk_status check_power_args(tsk_tables_t tab, tsk_dtype dtype, const double* S64, const float* S32,
@@ -561,8 +590,6 @@ tsk_status check_power_args(tsk_tables_t tab, tsk_dtype dtype, const double* S64
   if (L < 1) return tsk::fail(TSK_EINVAL, "%s: L=%d < 1", fn, L);
   if (dtype == TSK_F32 && !S32) return tsk::fail(TSK_EINVAL, "%s: FP32 path needs S32", fn);
   if (dtype == TSK_F64 && !S64) return tsk::fail(TSK_EINVAL, "%s: FP64 path needs S64", fn);
-  if (dtype == TSK_F64 && tab->logb > kMaxLogB64Power)
-    return tsk::fail(TSK_EUNSUPPORTED, "%s: FP64 power method limited to b <= 8192", fn);
   if (L > 65535) return tsk::fail(TSK_EINVAL, "%s: L=%d > 65535", fn, L);
   return TSK_OK;
 }
@@ -581,13 +608,31 @@ extern "C" tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
   const size_t es = dtype == TSK_F32 ? 4 : 8;
   void* vbuf = V;
   if (!vbuf) TSK_TRY(ws_get(ctx, WS_V, (size_t)L * tab->B * tab->n * es, &vbuf));
-  void* cnt = nullptr;
-  TSK_TRY(ws_get(ctx, WS_CNT, (size_t)L * sizeof(unsigned), &cnt));
+  const int n = tab->n, B = tab->B;
+  if (dtype == TSK_F32) {
+    TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U_in, nullptr, nullptr,
+                                nullptr, (float*)vbuf, nullptr, S(stream)));
+    return median_norm_launch<float>((const float*)vbuf, (const float*)U_in, (float*)U_out, flags, L,
+                                     n, B, S(stream));
+  }
+  TSK_TRY(power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)U_in, nullptr, nullptr,
+                               nullptr, (double*)vbuf, nullptr, S(stream)));
+  return median_norm_launch<double>((const double*)vbuf, (const double*)U_in, (double*)U_out, flags,
+                                    L, n, B, S(stream));
+}
+
+extern "C" tsk_status tsk_contract_tiuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                        const double* S64, const float* S32, int L, const void* U,
+                                        void* V, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_contract_tiuu"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_contract_tiuu"));
+  if (!U || !V) return tsk::fail(TSK_EINVAL, "tsk_contract_tiuu: null U or V");
+  TSK_TRY(set_device(ctx));
   if (dtype == TSK_F32)
-    return power_launch<float>(ctx, tab, S32, L, L, 0, (const float*)U_in, (float*)U_out,
-                               (float*)vbuf, nullptr, nullptr, flags, (unsigned*)cnt, 0, S(stream));
-  return power_launch<double>(ctx, tab, S64, L, L, 0, (const double*)U_in, (double*)U_out,
-                              (double*)vbuf, nullptr, nullptr, flags, (unsigned*)cnt, 0, S(stream));
+    return power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U, nullptr, nullptr, nullptr,
+                               (float*)V, nullptr, S(stream));
+  return power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)U, nullptr, nullptr, nullptr,
+                              (double*)V, nullptr, S(stream));
 }
 
 extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
@@ -602,13 +647,13 @@ extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
   TSK_TRY(ws_get(ctx, WS_V, (size_t)L * tab->B * tab->n * es, &vbuf));
   void* lp = lam_per;
   if (!lp) TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * tab->B * sizeof(double), &lp));
-  void* cnt = nullptr;
-  TSK_TRY(ws_get(ctx, WS_CNT, (size_t)L * sizeof(unsigned), &cnt));
   if (dtype == TSK_F32)
-    return power_launch<float>(ctx, tab, S32, L, L, 0, (const float*)U, nullptr, (float*)vbuf,
-                               (double*)lp, lam_med, nullptr, (unsigned*)cnt, 1, S(stream));
-  return power_launch<double>(ctx, tab, S64, L, L, 0, (const double*)U, nullptr, (double*)vbuf,
-                              (double*)lp, lam_med, nullptr, (unsigned*)cnt, 1, S(stream));
+    TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 1, (const float*)U, nullptr, nullptr,
+                                nullptr, (float*)vbuf, (double*)lp, S(stream)));
+  else
+    TSK_TRY(power_launch<double>(ctx, tab, S64, L, 0, 0, 1, (const double*)U, nullptr, nullptr,
+                                 nullptr, (double*)vbuf, (double*)lp, S(stream)));
+  return lam_median_launch((const double*)lp, lam_med, L, tab->B, S(stream));
 }
 
 // =============================================================================
@@ -620,16 +665,38 @@ namespace {
 struct DecompWs {
   void* U0;       // R[L][n]
   void* U1;       // R[L][n]
-  void* V;        // R[L][B][n]
+  void* V0;       // R[L][B][n]
+  void* V1;       // R[L][B][n]
   double* lam_per;
   double* lam_med;
-  unsigned* cnt;
   int32_t* flags;  // [k][L]
   double* u_hat;   // [n]
   double* lam64;   // [B]
   void* prod;      // cx<double>[B][b/2+1]
   double* u0;      // [k][L][n] generated start vectors (when caller passes none)
 };
+
+// Power steps of one component for restarts [tau0, tau0 + nrest): the first
+// step uses u0 directly, every later launch (and the final evaluation) starts
+// from the normalised median of the previous launch's estimates.  Returns the
+// buffer holding u_T.
+template <typename R>
+tsk_status power_chain(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0, int T,
+                       R* const Ub[2], R* const Vb[2], double* lam_per, int32_t* fl, R** u_final,
+                       hipStream_t st) {
+  TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 0, 0, Ub[0], nullptr, nullptr, nullptr, Vb[0],
+                          nullptr, st));
+  int cu = 0, cv = 0;
+  for (int t = 1; t <= T; ++t) {
+    const int mode = (t == T) ? 1 : 0;
+    TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 1, mode, Ub[cu], Vb[cv], Ub[cu ^ 1], fl,
+                            Vb[cv ^ 1], mode ? lam_per : nullptr, st));
+    cu ^= 1;
+    cv ^= 1;
+  }
+  *u_final = Ub[cu];
+  return TSK_OK;
+}
 
 template <typename R>
 tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, double* S64,
@@ -640,37 +707,24 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
   const int H1 = b / 2 + 1;
   const cx<double>* tw64 = nullptr;
   TSK_TRY(get_tw<double>(ctx, tab->logb, &tw64));
-  R* Ub[2] = {reinterpret_cast<R*>(w.U0), reinterpret_cast<R*>(w.U1)};
+  R* const Ub[2] = {reinterpret_cast<R*>(w.U0), reinterpret_cast<R*>(w.U1)};
+  R* const Vb[2] = {reinterpret_cast<R*>(w.V0), reinterpret_cast<R*>(w.V1)};
   for (int c = 0; c < k; ++c) {
     const size_t LN = (size_t)L * n;
     hipLaunchKernelGGL(tsk::k_cvt<R>, dim3(grid_for(LN, 256)), dim3(256), 0, st,
                        u0 + (size_t)c * LN, Ub[0], LN);
     TSK_TRY(check_launch("k_cvt"));
-    int cur = 0;
     int32_t* fl = flags + (size_t)c * L;
+    R* ufin = nullptr;
     if (!plain) {
-      for (int t = 0; t < T; ++t) {
-        TSK_TRY(power_launch<R>(ctx, tab, spec, L, L, 0, Ub[cur], Ub[cur ^ 1], (R*)w.V, nullptr,
-                                nullptr, fl, w.cnt, 0, st));
-        cur ^= 1;
-      }
-      TSK_TRY(power_launch<R>(ctx, tab, spec, L, L, 0, Ub[cur], nullptr, (R*)w.V, w.lam_per,
-                              w.lam_med, nullptr, w.cnt, 1, st));
+      TSK_TRY(power_chain<R>(ctx, tab, spec, L, 0, T, Ub, Vb, w.lam_per, fl, &ufin, st));
     } else {
-      for (int tau = 0; tau < L; ++tau) {
-        int cc = 0;
-        for (int t = 0; t < T; ++t) {
-          TSK_TRY(power_launch<R>(ctx, tab, spec, L, 1, tau, Ub[cc], Ub[cc ^ 1], (R*)w.V, nullptr,
-                                  nullptr, fl, w.cnt, 0, st));
-          cc ^= 1;
-        }
-        cur = cc;
-        TSK_TRY(power_launch<R>(ctx, tab, spec, L, 1, tau, Ub[cc], nullptr, (R*)w.V, w.lam_per,
-                                w.lam_med, nullptr, w.cnt, 1, st));
-      }
+      for (int tau = 0; tau < L; ++tau)
+        TSK_TRY(power_chain<R>(ctx, tab, spec, 1, tau, T, Ub, Vb, w.lam_per, fl, &ufin, st));
     }
+    TSK_TRY(lam_median_launch(w.lam_per, w.lam_med, L, B, st));
     hipLaunchKernelGGL(tsk::k_select<R>, dim3(1), dim3(256), 0, st, (const double*)w.lam_med, L,
-                       (const R*)Ub[cur], n, w.u_hat, U_out + (size_t)c * n,
+                       (const R*)ufin, n, w.u_hat, U_out + (size_t)c * n,
                        tau_out ? tau_out + c : nullptr);
     TSK_TRY(check_launch("k_select"));
     tsk::Rank1Args a;
@@ -680,7 +734,7 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
     a.n = n;
     a.B = B;
     a.U = w.u_hat;
-    a.tw = tw64;
+    a.twg = tw64;
     a.prod = reinterpret_cast<cx<double>*>(w.prod);
     a.S64 = reinterpret_cast<const cx<double>*>(S64);
     a.lam_per = w.lam64;
@@ -718,14 +772,13 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
   DecompWs w;
   TSK_TRY(ws_get(ctx, WS_U, 2 * (size_t)L * n * es, &w.U0));
   w.U1 = reinterpret_cast<char*>(w.U0) + (size_t)L * n * es;
-  TSK_TRY(ws_get(ctx, WS_V, (size_t)L * B * n * es, &w.V));
+  TSK_TRY(ws_get(ctx, WS_V, 2 * (size_t)L * B * n * es, &w.V0));
+  w.V1 = reinterpret_cast<char*>(w.V0) + (size_t)L * B * n * es;
   void* p;
   TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * B * 8, &p));
   w.lam_per = (double*)p;
   TSK_TRY(ws_get(ctx, WS_LAMMED, (size_t)L * 8, &p));
   w.lam_med = (double*)p;
-  TSK_TRY(ws_get(ctx, WS_CNT, (size_t)L * 4, &p));
-  w.cnt = (unsigned*)p;
   TSK_TRY(ws_get(ctx, WS_UHAT, (size_t)n * 8, &p));
   w.u_hat = (double*)p;
   TSK_TRY(ws_get(ctx, WS_LAM64, (size_t)B * 8, &p));
@@ -778,7 +831,7 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
                                (uint64_t)(uintptr_t)u0d, (uint64_t)(uintptr_t)lam_out,
                                (uint64_t)(uintptr_t)U_out, (uint64_t)(uintptr_t)tau_out,
                                (uint64_t)(uintptr_t)flags, (uint64_t)(uintptr_t)w.U0,
-                               (uint64_t)(uintptr_t)w.V, (uint64_t)(uintptr_t)w.prod};
+                               (uint64_t)(uintptr_t)w.V0, (uint64_t)(uintptr_t)w.prod};
   GraphEntry* ge = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) ge = &g;
