@@ -2,8 +2,8 @@
 //
 // One work-group transforms one sequence held in LDS.  Layout: real and
 // imaginary parts in two separate arrays ("SoA"), element p stored at
-// p + p/16, so that the stride-16 writes of a radix-16 pass and the
-// unit-stride reads both hit distinct LDS banks.
+// p + 5 (p / 64) (see pidx), which keeps the passes' strided accesses on
+// distinct LDS banks.
 //
 // The transform is the Stockham auto-sort formulation: each pass reads R
 // inputs at stride N/R, applies the twiddles of the current sub-transform,
@@ -14,11 +14,9 @@
 // and a last smaller pass takes the remaining bits; every pass is unrolled at
 // compile time.
 //
-// Twiddles: W_b^j = exp(-2 pi i j / b) = thi[j >> 6] * tlo[j & 63], with
-// tlo[j] = W_b^j (j < 64) and thi[j] = W_b^(64 j) (j <= b/64), both in LDS and
-// built on the host in FP64.  Within a butterfly the powers w^r are formed
-// from w by multiplication (depth <= 4).  The inverse transform conjugates
-// and carries no 1/N factor.
+// Twiddles come from per-pass tables in global memory (see pass_table_len),
+// read straight into the butterfly; the inverse transform conjugates them and
+// carries no 1/N factor.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,10 +46,14 @@ __device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.x, -a.y}; }
 template <typename R>
 __device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return {a.x * s, a.y * s}; }
 
-// Padded LDS position of element p.
-__device__ __forceinline__ constexpr int pidx(int p) { return p + (p >> 4); }
+// Padded LDS position of element p: five spare words after every 64.  With
+// 64 four-byte banks this keeps the unit-stride reads and the stride-1, 8,
+// 64 ... writes of the radix-8 Stockham passes (nearly) free of bank
+// conflicts, and the position of p + s is pidx(p) + poff(s) for every access
+// the passes make, so offsets fold into the instructions.
+__device__ __forceinline__ constexpr int pidx(int p) { return p + 5 * (p >> 6); }
 // Words needed for an N-element padded array.
-constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
+constexpr int padded_len(int n) { return n + 5 * (n >> 6) + 6; }
 
 // Split-array view of a complex sequence in LDS.
 template <typename R>
@@ -69,24 +71,53 @@ struct Soa {
   }
 };
 
-// Two-level twiddle table for base b in LDS.
+// ---- twiddle tables ---------------------------------------------------------
+// Radix plan of an N-point transform run by NT threads: every pass uses
+// R = min(N/NT, 16) points per butterfly (a last pass takes what is left).
+constexpr int fft_rmax(int N, int NT) {
+  return (N / NT) >= 16 ? 16 : ((N / NT) >= 8 ? 8 : ((N / NT) >= 4 ? 4 : 2));
+}
+constexpr int pass_radix(int N, int NS, int RMAX) { return (N / NS) >= RMAX ? RMAX : N / NS; }
+
+// Per-pass twiddle table: for every pass with stride NS > 1 and radix R, the
+// entries W_{NS R}^{r k} for r = 1..R-1 and k < NS, stored at
+// [pass offset + (r-1) NS + k], so the lanes of a wave read consecutive
+// entries.  Built on the host in FP64 and rounded once.
+constexpr int pass_table_len(int N, int NT) {
+  int len = 0;
+  for (int ns = 1; ns < N;) {
+    const int rad = pass_radix(N, ns, fft_rmax(N, NT));
+    if (ns > 1) len += (rad - 1) * ns;
+    ns *= rad;
+  }
+  return len;
+}
+
+// Twiddles of one real transform of length b = 2H through an H-point complex
+// transform: the pass table of the H-point FFT followed by W_b^k, k = 0..H.
 template <typename R>
-struct Twiddle {
-  const cx<R>* tlo;  // [64]
-  const cx<R>* thi;  // [b/64 + 1]
-  __device__ __forceinline__ cx<R> w(int j) const { return cmul(thi[j >> 6], tlo[j & 63]); }
+struct Twid {
+  const cx<R>* pass;  // per-pass table (global)
+  const cx<R>* wk;    // W_b^k (global)
+  const cx<R>* lds;   // LDS copy of the first entries of `pass` (may be null)
+  __device__ __forceinline__ cx<R> w(int k) const { return wk[k]; }
 };
 
-// Copies the global table (tlo[64] then thi[b/64+1]) into LDS `dst`; ends
-// with a barrier, so the table is ready for every thread on return.
-template <typename R>
-__device__ __forceinline__ Twiddle<R> load_twiddles(cx<R>* dst, const cx<R>* __restrict__ src, int b,
-                                                    int nt) {
-  const int cnt = 64 + b / 64 + 1;
-  for (int t = threadIdx.x; t < cnt; t += nt) dst[t] = src[t];
-  __syncthreads();
-  return Twiddle<R>{dst, dst + 64};
+// Entries of the per-pass table worth copying to LDS: every pass whose whole
+// range lies below `cap` entries.
+constexpr int pass_table_lds_len(int N, int NT, int cap) {
+  int len = 0;
+  for (int ns = 1; ns < N;) {
+    const int rad = pass_radix(N, ns, fft_rmax(N, NT));
+    if (ns > 1) {
+      if (len + (rad - 1) * ns > cap) break;
+      len += (rad - 1) * ns;
+    }
+    ns *= rad;
+  }
+  return len;
 }
+constexpr int twid_len(int H, int NT) { return pass_table_len(H, NT) + H + 1; }
 
 // ---- radix-R DFTs in registers (y_q = sum_r x_r W_R^{rq}, W_R = e^{-+2 pi i/R}) ----
 
@@ -203,51 +234,48 @@ __device__ __forceinline__ void dft_r(cx<R>* x) {
   else dft16<R, INV>(x);
 }
 
-// v[r] *= w^r for r = 1..RAD-1.  Powers are formed on the fly from w, w^2,
-// w^4 and w^8 (multiplication depth <= 4), so only those stay live.
-template <typename R, int RAD>
-__device__ __forceinline__ void apply_twiddles(cx<R>* v, cx<R> w) {
-  v[1] = cmul(v[1], w);
-  if constexpr (RAD > 2) {
-    const cx<R> w2 = cmul(w, w);
-    v[2] = cmul(v[2], w2);
-    v[3] = cmul(v[3], cmul(w2, w));
-    if constexpr (RAD > 4) {
-      const cx<R> w4 = cmul(w2, w2);
-      v[4] = cmul(v[4], w4);
-      v[5] = cmul(v[5], cmul(w4, w));
-      v[6] = cmul(v[6], cmul(w4, w2));
-      v[7] = cmul(v[7], cmul(w4, cmul(w2, w)));
-      if constexpr (RAD > 8) {
-        const cx<R> w8 = cmul(w4, w4);
-        v[8] = cmul(v[8], w8);
-        v[9] = cmul(v[9], cmul(w8, w));
-        v[10] = cmul(v[10], cmul(w8, w2));
-        v[11] = cmul(v[11], cmul(w8, cmul(w2, w)));
-        v[12] = cmul(v[12], cmul(w8, w4));
-        v[13] = cmul(v[13], cmul(cmul(w8, w4), w));
-        v[14] = cmul(v[14], cmul(cmul(w8, w4), w2));
-        v[15] = cmul(v[15], cmul(cmul(w8, w4), cmul(w2, w)));
+// Offset, in padded positions, of element p + s from element p for the
+// accesses of a Stockham pass (s = r times the pass's power-of-two stride, p
+// aligned as the pass aligns it): pidx(p + s) - pidx(p) = s + 5 (s >> 6).
+constexpr int poff(int rs) { return rs + 5 * (rs >> 6); }
+
+// Twiddles of one pass held in registers: w[q][r-1] for the thread's q-th
+// butterfly.  Loaded one pass ahead so the global loads overlap the previous
+// pass's arithmetic.
+template <typename R, int PER, int NR>
+struct PassTw {
+  cx<R> w[PER][NR > 0 ? NR : 1];
+};
+
+template <typename R, int N, int RAD, int NS, int NT, int TOFF, int LIM>
+__device__ __forceinline__ void load_pass_tw(PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1>& t,
+                                             const Twid<R>& tw, int tid) {
+  constexpr int NB = N / RAD;
+  constexpr int PER = (NB + NT - 1) / NT;
+  // passes inside the LDS copy read it there, later ones from global memory
+  constexpr bool IN_LDS = TOFF + (RAD - 1) * NS <= LIM;
+  if constexpr (NS > 1) {
+    const cx<R>* __restrict__ src = IN_LDS ? tw.lds : tw.pass;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+        const int k = j & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) t.w[q][r - 1] = src[TOFF + (r - 1) * NS + k];
       }
     }
   }
 }
 
-// Offset, in padded positions, of element p + s from element p when s is r
-// times a power-of-two stride S and p is aligned as in a Stockham pass (the
-// group p .. p + (R-1) S never straddles a 16-block differently):
-// pidx(p + r S) - pidx(p) = r S + (r S >> 4).
-constexpr int poff(int rs) { return rs + (rs >> 4); }
-
-// One Stockham pass over an N-point sequence with radix RAD and stride NS.
+// One Stockham pass over an N-point sequence with radix RAD and stride NS,
+// using the twiddles `t` loaded for it.
 template <typename R, int N, int RAD, int NS, int NT, bool INV>
-__device__ __forceinline__ void stockham_pass(const Soa<R>& buf, const Twiddle<R>& tw, int b) {
+__device__ __forceinline__ void stockham_pass(const Soa<R>& buf,
+                                              const PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1>& t,
+                                              int tid) {
   constexpr int NB = N / RAD;
   constexpr int PER = (NB + NT - 1) / NT;
-  // Opaque copy of the thread index: addresses are recomputed in every pass
-  // instead of being hoisted and kept live across the whole kernel.
-  int tid = threadIdx.x;
-  asm volatile("" : "+v"(tid));
   cx<R> v[PER][RAD];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -260,10 +288,12 @@ __device__ __forceinline__ void stockham_pass(const Soa<R>& buf, const Twiddle<R
         v[q][r].y = buf.im[base + poff(r * NB)];
       }
       if constexpr (NS > 1) {
-        const int k = j & (NS - 1);
-        cx<R> w = tw.w(k * (b / (NS * RAD)));
-        if (INV) w.y = -w.y;
-        apply_twiddles<R, RAD>(v[q], w);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cx<R> w = t.w[q][r - 1];
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
       }
       dft_r<R, RAD, INV>(v[q]);
     }
@@ -285,23 +315,38 @@ __device__ __forceinline__ void stockham_pass(const Soa<R>& buf, const Twiddle<R
   __syncthreads();
 }
 
-template <typename R, int N, int NS, int NT, int RMAX, bool INV>
-__device__ __forceinline__ void fft_passes(const Soa<R>& buf, const Twiddle<R>& tw, int b) {
-  if constexpr (NS < N) {
-    constexpr int REM = N / NS;
-    constexpr int RAD = REM >= RMAX ? RMAX : REM;
-    stockham_pass<R, N, RAD, NS, NT, INV>(buf, tw, b);
-    fft_passes<R, N, NS * RAD, NT, RMAX, INV>(buf, tw, b);
+// Passes from stride NS on; `cur` holds this pass's twiddles.
+template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, int LIM>
+__device__ __forceinline__ void fft_passes(
+    const Soa<R>& buf, const Twid<R>& twp,
+    const PassTw<R, (N / pass_radix(N, NS, RMAX) + NT - 1) / NT, pass_radix(N, NS, RMAX) - 1>& cur) {
+  constexpr int RAD = pass_radix(N, NS, RMAX);
+  constexpr int NS2 = NS * RAD;
+  constexpr int TOFF2 = TOFF + (NS > 1 ? (RAD - 1) * NS : 0);
+  // Opaque copy of the thread index: addresses are recomputed in every pass
+  // instead of being hoisted and kept live across the whole kernel.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  if constexpr (NS2 < N) {
+    constexpr int RAD2 = pass_radix(N, NS2, RMAX);
+    PassTw<R, (N / RAD2 + NT - 1) / NT, RAD2 - 1> nxt;
+    load_pass_tw<R, N, RAD2, NS2, NT, TOFF2, LIM>(nxt, twp, tid);
+    stockham_pass<R, N, RAD, NS, NT, INV>(buf, cur, tid);
+    fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, LIM>(buf, twp, nxt);
+  } else {
+    stockham_pass<R, N, RAD, NS, NT, INV>(buf, cur, tid);
   }
 }
 
 // Complex FFT of length N = 2^LOGN in LDS (SoA, padded); ends with a barrier.
-// The radix is N/NT (each thread one butterfly per pass), at most 16.
-template <typename R, int LOGN, int NT, bool INV>
-__device__ __forceinline__ void fft_soa(const Soa<R>& buf, const Twiddle<R>& tw, int b) {
-  constexpr int PERT = (1 << LOGN) / NT;
-  constexpr int RMAX = PERT >= 16 ? 16 : (PERT >= 8 ? 8 : (PERT >= 4 ? 4 : 2));
-  fft_passes<R, (1 << LOGN), 1, NT, RMAX, INV>(buf, tw, b);
+// The first LIM entries of the pass table are read from tw.lds.
+template <typename R, int LOGN, int NT, bool INV, int LIM = 0>
+__device__ __forceinline__ void fft_soa(const Soa<R>& buf, const Twid<R>& tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int RMAX = fft_rmax(N, NT);
+  constexpr int RAD = pass_radix(N, 1, RMAX);
+  PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> first;  // the first pass has no twiddles
+  fft_passes<R, N, 1, NT, RMAX, INV, 0, LIM>(buf, tw, first);
 }
 
 }  // namespace tsk

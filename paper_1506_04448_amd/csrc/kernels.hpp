@@ -6,7 +6,7 @@
 //   ord [B][3][n]  uint32  the index i of each sorted entry
 //   spectra        cx<R>[B][b/2+1]  half spectrum of each of the B sketches
 //   vectors        R[L][n]; per-sketch estimates R[L][B][n]
-//   twiddles       cx<R>[64 + b/64 + 1]  (tlo then thi, see fft.hpp)
+//   twiddles       cx<R>[twid_len(H, NT)]: per-pass table, then W_b^k (fft.hpp)
 //
 // Real transforms of length b use one complex transform of length H = b/2 on
 // the even/odd packing z_s = x_2s + i x_2s+1, so every work-group holds only
@@ -129,7 +129,6 @@ template <typename R>
 constexpr int threads_for_h(int logh) {
   return logh >= 13 ? 1024 : (logh >= 9 ? (1 << (logh - 3)) : 64);
 }
-constexpr int twiddle_len(int b) { return 64 + b / 64 + 1; }
 
 // ---------------------------------------------------------------------------
 // Median of B <= MAXB values held in registers by one thread: the element of
@@ -225,7 +224,7 @@ struct PowerArgs {
   const uint32_t* ord;
   int n, B;
   const cx<R>* S;       // [B][H+1]
-  const cx<R>* twg;     // [twiddle_len(b)]
+  const cx<R>* twg;     // [twid_len(H, NT)]
   const R* Uprev;       // [L][n]
   const R* Vprev;       // [L][B][n]   (prefix 1)
   R* Ucur;              // [L][n]      (prefix 1, written by m == 0)
@@ -238,14 +237,30 @@ struct PowerArgs {
 };
 
 // LDS of one work-group (static): the half-length sequence (padded, split
-// re/im), the twiddle table, the current vector u (at most power_max_n
-// coordinates) and a reduction scratch.
+// re/im), the twiddle table, a reduction scratch, the count-sketch/read-off
+// table entries (power_tab_n coordinates, five words each) and the current
+// vector u (power_max_n coordinates).
 constexpr int kLdsBytes = 160 * 1024;
+// Early-pass twiddles copied to LDS (FP32 only; the FP64 kernels have no room).
+template <typename R, int LOGB>
+constexpr int power_tw_lds() {
+  return sizeof(R) == 4 ? pass_table_lds_len(1 << (LOGB - 1), threads_for_h<R>(LOGB - 1), 4096) : 0;
+}
+template <typename R, int LOGB>
+constexpr int power_base_bytes() {
+  return (int)(sizeof(R) * 2 * padded_len(1 << (LOGB - 1)) + 16 * sizeof(double) +
+               sizeof(cx<R>) * power_tw_lds<R, LOGB>());
+}
+template <typename R, int LOGB>
+constexpr int power_tab_n() {
+  constexpr int rem = kLdsBytes - power_base_bytes<R, LOGB>();
+  constexpr int t = rem / 2 / 20 / 64 * 64;
+  return t < 1024 ? t : 1024;
+}
 template <typename R, int LOGB>
 constexpr int power_max_n() {
-  constexpr int fixed = (int)(sizeof(R) * 2 * padded_len(1 << (LOGB - 1)) +
-                              sizeof(cx<R>) * twiddle_len(1 << LOGB) + 16 * sizeof(double));
-  constexpr int fit = (kLdsBytes - fixed) / (int)sizeof(R) / 64 * 64;
+  constexpr int rem = kLdsBytes - power_base_bytes<R, LOGB>() - 20 * power_tab_n<R, LOGB>();
+  constexpr int fit = rem / (int)sizeof(R) / 64 * 64;
   return fit < 4096 ? fit : 4096;
 }
 
@@ -268,9 +283,12 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
   constexpr int PK = (H / 2 + NT - 1) / NT;
   constexpr bool FULL = (H / 2) % NT == 0;
   constexpr int NU = power_max_n<R, LOGB>();
+  constexpr int kPowerTab = power_tab_n<R, LOGB>();
+  constexpr int TWL = power_tw_lds<R, LOGB>();
   __shared__ __align__(16) R re[2 * PL];
-  __shared__ __align__(16) cx<R> twl[twiddle_len(b)];
+  __shared__ __align__(16) cx<R> twl[TWL > 0 ? TWL : 1];
   __shared__ __align__(16) R u[NU];
+  __shared__ uint32_t stab[5 * kPowerTab];
   __shared__ double red[16];
   R* im = re + PL;
   const Soa<R> buf{re, im};
@@ -281,7 +299,40 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
   const int n = a.n;
   const int B = a.B;
   const size_t tb = (size_t)m * 3 * n;
-  const Twiddle<R> tw = load_twiddles<R>(twl, a.twg, b, NT);
+  const cx<R>* Sm = a.S + (size_t)m * (H + 1);
+
+  // One round of global loads up front: this sketch's spectrum values owned
+  // by the thread (they become the running products p0/p1) and the table
+  // entries of the count sketches (modes 2, 3) and of the read-off (mode 1).
+  cx<R> p0[PK], p1[PK], pmid;
+  cx<R> w0[PK], w1[PK], wmid;  // W_b^k, W_b^(H-k), W_b^(H/2) for the owned k
+  const cx<R>* wkg = a.twg + pass_table_len(H, NT);
+#pragma unroll
+  for (int q = 0; q < PK; ++q) {
+    const int k = tid + q * NT;
+    if (!FULL && k >= H / 2) break;
+    p0[q] = Sm[k];
+    p1[q] = Sm[H - k];
+    w0[q] = wkg[k];
+    w1[q] = wkg[H - k];
+  }
+  if (tid == 0) {
+    pmid = Sm[H / 2];
+    wmid = wkg[H / 2];
+  }
+  const bool tab_lds = n <= kPowerTab;
+  if (tab_lds) {
+    for (int e = tid; e < n; e += NT) {
+      stab[e] = a.hxs[tb + n + e];
+      stab[kPowerTab + e] = a.ord[tb + n + e];
+      stab[2 * kPowerTab + e] = a.hxs[tb + 2 * n + e];
+      stab[3 * kPowerTab + e] = a.ord[tb + 2 * n + e];
+      stab[4 * kPowerTab + e] = a.hx[tb + e];
+    }
+  }
+  for (int t = tid; t < TWL; t += NT) twl[t] = a.twg[t];
+  const Twid<R> tw{a.twg, a.twg + pass_table_len(H, NT), twl};
+  __syncthreads();  // staged tables visible
 
   if (a.prefix) {
     const bool ok = median_prologue<R, NT>(a.Vprev, a.Uprev, tau, n, B, u, re, 2 * PL, red);
@@ -294,8 +345,6 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
     __syncthreads();
   }
 
-  const cx<R>* Sm = a.S + (size_t)m * (H + 1);
-  cx<R> p0[PK], p1[PK], pmid;
   auto getu = [&](uint32_t i) -> R { return u[i]; };
   auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
 #pragma unroll 1
@@ -305,25 +354,26 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
       im[t] = R(0);
     }
     __syncthreads();
-    count_sketch<R>(a.hxs + tb + (size_t)mode_j * n, a.ord + tb + (size_t)mode_j * n, n, NT, getu,
-                    store);
+    if (tab_lds)
+      count_sketch<R>(stab + (mode_j - 1) * 2 * kPowerTab, stab + (mode_j - 1) * 2 * kPowerTab + kPowerTab,
+                      n, NT, getu, store);
+    else
+      count_sketch<R>(a.hxs + tb + (size_t)mode_j * n, a.ord + tb + (size_t)mode_j * n, n, NT, getu,
+                      store);
     __syncthreads();
-    fft_soa<R, LOGH, NT, false>(buf, tw, b);
+    fft_soa<R, LOGH, NT, false, TWL>(buf, tw);
 #pragma unroll
     for (int q = 0; q < PK; ++q) {
       const int k = tid + q * NT;
       if (!FULL && k >= H / 2) break;
       const cx<R> Za = buf.get(k);
       const cx<R> Zb = buf.get((H - k) & (H - 1));
-      const cx<R> Xk = r2c_post(Za, Zb, tw.w(k));
-      const cx<R> XHk = r2c_post(Zb, Za, tw.w(H - k));
-      p0[q] = cmulc(mode_j == 1 ? Sm[k] : p0[q], Xk);
-      p1[q] = cmulc(mode_j == 1 ? Sm[H - k] : p1[q], XHk);
+      p0[q] = cmulc(p0[q], r2c_post(Za, Zb, w0[q]));
+      p1[q] = cmulc(p1[q], r2c_post(Zb, Za, w1[q]));
     }
     if (tid == 0) {
       const cx<R> Z = buf.get(H / 2);
-      const cx<R> X = r2c_post(Z, Z, tw.w(H / 2));
-      pmid = cmulc(mode_j == 1 ? Sm[H / 2] : pmid, X);
+      pmid = cmulc(pmid, r2c_post(Z, Z, wmid));
     }
     __syncthreads();
   }
@@ -332,19 +382,19 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
   for (int q = 0; q < PK; ++q) {
     const int k = tid + q * NT;
     if (!FULL && k >= H / 2) break;
-    buf.put(k, c2r_pack(p0[q], p1[q], tw.w(k)));
-    if (k > 0) buf.put(H - k, c2r_pack(p1[q], p0[q], tw.w(H - k)));
+    buf.put(k, c2r_pack(p0[q], p1[q], w0[q]));
+    if (k > 0) buf.put(H - k, c2r_pack(p1[q], p0[q], w1[q]));
   }
-  if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, tw.w(H / 2)));
+  if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, wmid));
   __syncthreads();
-  fft_soa<R, LOGH, NT, true>(buf, tw, b);
+  fft_soa<R, LOGH, NT, true, TWL>(buf, tw);
 
   const R scale = R(2) / R(b);
   const uint32_t* hx1 = a.hx + tb;
   R* Vrow = a.V + ((size_t)tau * B + m) * n;
   double acc = 0.0;
   for (int i = tid; i < n; i += NT) {
-    const uint32_t e = hx1[i];
+    const uint32_t e = tab_lds ? stab[4 * kPowerTab + i] : hx1[i];
     const R val = load_packed(buf, e >> 1) * scale;
     const R v = (e & 1u) ? -val : val;
     Vrow[i] = v;
@@ -389,7 +439,7 @@ struct Rank1Args {
   const uint32_t* ord;
   int n, B;
   const double* U;          // [c][n]
-  const cx<double>* twg;    // [twiddle_len(b)]
+  const cx<double>* twg;    // [twid_len(H, NT)]
   cx<double>* prod;         // [c][B][b/2+1]
   const cx<double>* S64;    // nullable: [B][b/2+1]
   double* lam_per;          // [c][B] when S64 != null
@@ -405,7 +455,6 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_rank1(Rank1
   constexpr int PK = (H / 2 + NT - 1) / NT;
   constexpr bool FULL = (H / 2) % NT == 0;
   __shared__ __align__(16) double re[2 * PL];
-  __shared__ __align__(16) cx<double> twl[twiddle_len(b)];
   __shared__ double red[16];
   double* im = re + PL;
   const Soa<double> buf{re, im};
@@ -414,7 +463,7 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_rank1(Rank1
   const int r = blockIdx.y;
   const int n = a.n;
   const double* u = a.U + (size_t)r * n;
-  const Twiddle<double> tw = load_twiddles<double>(twl, a.twg, b, NT);
+  const Twid<double> tw{a.twg, a.twg + pass_table_len(H, NT), nullptr};
   cx<double> p0[PK], p1[PK], pmid;
   auto getu = [&](uint32_t i) -> double { return u[i]; };
   auto store = [&](uint32_t t, double v) { store_packed(buf, t, v); };
@@ -428,7 +477,7 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_rank1(Rank1
     __syncthreads();
     count_sketch<double>(a.hxs + tb, a.ord + tb, n, NT, getu, store);
     __syncthreads();
-    fft_soa<double, LOGH, NT, false>(buf, tw, b);
+    fft_soa<double, LOGH, NT, false>(buf, tw);
 #pragma unroll
     for (int q = 0; q < PK; ++q) {
       const int k = tid + q * NT;
@@ -505,15 +554,14 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_r2c64(const
   constexpr int H = b / 2;
   constexpr int PL = padded_len(H);
   __shared__ __align__(16) double re[2 * PL];
-  __shared__ __align__(16) cx<double> twl[twiddle_len(b)];
   double* im = re + PL;
   const Soa<double> buf{re, im};
   const int m = blockIdx.x;
-  const Twiddle<double> tw = load_twiddles<double>(twl, twg, b, NT);
+  const Twid<double> tw{twg, twg + pass_table_len(H, NT), nullptr};
   const cx<double>* src = reinterpret_cast<const cx<double>*>(s_time + (size_t)m * b);
   for (int t = threadIdx.x; t < H; t += NT) buf.put(t, src[t]);
   __syncthreads();
-  fft_soa<double, LOGH, NT, false>(buf, tw, b);
+  fft_soa<double, LOGH, NT, false>(buf, tw);
   cx<double>* S = S64 + (size_t)m * (H + 1);
   for (int k = threadIdx.x; k <= H; k += NT) {
     cx<double> X = r2c_post(buf.get(k & (H - 1)), buf.get((H - k) & (H - 1)), tw.w(k));
@@ -533,15 +581,14 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_c2r64(const
   constexpr int H = b / 2;
   constexpr int PL = padded_len(H);
   __shared__ __align__(16) double re[2 * PL];
-  __shared__ __align__(16) cx<double> twl[twiddle_len(b)];
   double* im = re + PL;
   const Soa<double> buf{re, im};
   const int m = blockIdx.x;
-  const Twiddle<double> tw = load_twiddles<double>(twl, twg, b, NT);
+  const Twid<double> tw{twg, twg + pass_table_len(H, NT), nullptr};
   const cx<double>* S = S64 + (size_t)m * (H + 1);
   for (int k = threadIdx.x; k < H; k += NT) buf.put(k, c2r_pack(S[k], S[H - k], tw.w(k)));
   __syncthreads();
-  fft_soa<double, LOGH, NT, true>(buf, tw, b);
+  fft_soa<double, LOGH, NT, true>(buf, tw);
   double* dst = s_time + (size_t)m * b;
   const double scale = 2.0 / (double)b;
   for (int t = threadIdx.x; t < H; t += NT) {
@@ -554,90 +601,177 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_c2r64(const
 // ---------------------------------------------------------------------------
 // Dense build, Eq. (1).  Work-group (slab, group): the G sketches of `group`
 // accumulate a contiguous slab of (i, j) fibres of T in LDS bins, then write
-// the bins as one partial sum.  Each wave takes whole fibres T[i][j][:] with
-// its lanes along k (coalesced reads), two fibres per iteration; the fibre
-// offsets h1(i) + h2(j) are wave-uniform.
+// the bins as one FP64 partial sum.  Each wave takes two fibres T[i][j][:] at
+// a time with its lanes along k (coalesced reads); the fibre offsets
+// h1(i) + h2(j) are wave-uniform.
+//
+// Bins are 64-bit fixed point: integer LDS atomics are an order of magnitude
+// faster than floating-point ones on this chip, and integer sums do not
+// depend on the order of the adds.  Each work-group scales its slab by 2^F
+// with F chosen from the slab's largest |T| and element count so that no bin
+// can overflow; a slab with a non-finite entry writes NaN partials.
 // ---------------------------------------------------------------------------
-template <typename TIn, typename TAcc>
+template <typename TIn>
 struct BuildArgs {
   const TIn* T;
   int n, b, B, G;
   const uint32_t* hx;         // [B][3][n]
   long long pairs_per_slab;
-  int nslab;
-  TAcc* partial;              // [ngroups][nslab][G][b]
+  int nslab, ngroups;
+  const unsigned long long* absmax;  // bits of max |T| (a non-negative double)
+  double* partial;            // [ngroups][nslab][G][b]
 };
 
-// LDS of the dense build (static): BINS accumulator words and a copy of the
-// mode-3 table entries of the group's sketches when they fit (TAB entries),
-// otherwise those entries are read from global memory.
-template <typename TIn, typename TAcc, int BINS, int TAB>
-__global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn, TAcc> a) {
-  __shared__ __align__(16) TAcc bins[BINS];
-  __shared__ uint32_t tab3s[TAB];
-  const int n = a.n, b = a.b, G = a.G;
-  const int g0 = blockIdx.y * G;
-  const int Gc = min(G, a.B - g0);
-  const bool tab_in_lds = Gc * n <= TAB;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < G * b; t += blockDim.x) bins[t] = TAcc(0);
-  if (tab_in_lds)
-    for (int t = tid; t < Gc * n; t += blockDim.x) {
-      const int g = t / n, k = t - g * n;
-      tab3s[t] = a.hx[((size_t)(g0 + g) * 3 + 2) * n + k];
-    }
+// *out = bits of max |T| over `count` entries (non-negative doubles compare
+// like their bit patterns; NaN and Inf compare above every finite value).
+// *out must start at 0.
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_absmax(const TIn* __restrict__ T, size_t count,
+                                                unsigned long long* out) {
+  double m = 0.0;
+  bool bad = false;
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  for (; e + 3 * stride < count; e += 4 * stride) {
+    const double x0 = fabs((double)T[e]), x1 = fabs((double)T[e + stride]);
+    const double x2 = fabs((double)T[e + 2 * stride]), x3 = fabs((double)T[e + 3 * stride]);
+    bad |= !(x0 < __builtin_inf()) || !(x1 < __builtin_inf()) || !(x2 < __builtin_inf()) ||
+           !(x3 < __builtin_inf());
+    m = fmax(fmax(m, x0), fmax(fmax(x1, x2), x3));
+  }
+  for (; e < count; e += stride) {
+    const double x = fabs((double)T[e]);
+    bad |= !(x < __builtin_inf());
+    m = fmax(m, x);
+  }
+  if (bad) m = __builtin_inf();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
+  __shared__ double wm[4];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    const double r = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// One static pool of POOL 64-bit words: the G sketches' bins (G*b) followed by
+// the three modes' table entries of those sketches ([G][3][n] 32-bit words).
+template <typename TIn, int POOL>
+__global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
+  __shared__ __align__(16) unsigned long long pool[POOL];
+  const int n = a.n, b = a.b, G = a.G;
+  // Work-groups of one slab (all groups) are numbered consecutively within
+  // one XCD (block ids are dealt round-robin over the 8 XCDs), so the slab's
+  // re-reads for the other groups hit that XCD's L2.
+  const int lin = blockIdx.x;
+  const int xcd = lin & 7, r = lin >> 3;
+  const int slab = (r / a.ngroups) * 8 + xcd;
+  const int grp = r % a.ngroups;
+  if (slab >= a.nslab) return;  // padding blocks of the XCD mapping
+  const int g0 = grp * G;
+  const int Gc = min(G, a.B - g0);
+  unsigned long long* bins = pool;
+  uint32_t* tab = reinterpret_cast<uint32_t*>(pool + (size_t)G * b);
+  const int tid = threadIdx.x;
+  for (int t = tid; t < G * b; t += blockDim.x) bins[t] = 0ull;
+  for (int t = tid; t < Gc * 3 * n; t += blockDim.x) tab[t] = a.hx[(size_t)g0 * 3 * n + t];
 
   const long long npairs = (long long)n * n;
-  const long long p0 = (long long)blockIdx.x * a.pairs_per_slab;
+  const long long p0 = (long long)slab * a.pairs_per_slab;
   const long long p1 = min(npairs, p0 + a.pairs_per_slab);
-  const int lane = tid & 63;
-  const int nw = blockDim.x >> 6;
-  const unsigned bmask = (unsigned)b - 1u;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  for (long long q0 = p0 + 2 * wv; q0 < p1; q0 += 2 * nw) {
-    const bool two = q0 + 1 < p1;
-    const TIn* f0 = a.T + q0 * n;
-    const TIn* f1 = f0 + n;
-    const int i0 = (int)(q0 / n), j0 = (int)(q0 - (long long)i0 * n);
-    const int i1 = (j0 + 1 == n) ? i0 + 1 : i0, j1 = (j0 + 1 == n) ? 0 : j0 + 1;
-    for (int k = lane; k < n; k += 64) {
-      const TAcc x0 = (TAcc)f0[k];
-      const TAcc x1 = two ? (TAcc)f1[k] : TAcc(0);
-      for (int g = 0; g < Gc; ++g) {
-        const uint32_t* hg = a.hx + (size_t)(g0 + g) * 3 * n;
-        const uint32_t e3 = tab_in_lds ? tab3s[g * n + k] : hg[2 * n + k];
-        TAcc* bg = bins + (size_t)g * b;
-        {
-          const uint32_t e12 = (hg[i0] >> 1) + (hg[n + j0] >> 1);
-          const uint32_t sg = (hg[i0] ^ hg[n + j0] ^ e3) & 1u;
-          atomicAdd(&bg[(e12 + (e3 >> 1)) & bmask], sg ? -x0 : x0);
-        }
-        if (two) {
-          const uint32_t e12 = (hg[i1] >> 1) + (hg[n + j1] >> 1);
-          const uint32_t sg = (hg[i1] ^ hg[n + j1] ^ e3) & 1u;
-          atomicAdd(&bg[(e12 + (e3 >> 1)) & bmask], sg ? -x1 : x1);
+  // Scale 2^F: |bin| <= (entries in the slab) * max|T| * 2^F < 2^62, with F
+  // kept where 2^F is a normal double.
+  const double m = __longlong_as_double((long long)*a.absmax);
+  const bool bad = !(m < __builtin_inf());
+  int e2 = 0;
+  (void)frexp(m * (double)((p1 - p0) * n) * 2.0, &e2);
+  const int F = (m > 0.0 && !bad) ? max(-1000, min(1000, 62 - e2)) : 0;
+  const double up = ldexp(1.0, F), down = ldexp(1.0, -F);
+  __syncthreads();
+
+  if (!bad) {
+    const int lane = tid & 63;
+    const int nw = blockDim.x >> 6;
+    const unsigned bmask = (unsigned)b - 1u;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    constexpr int NF = 4;  // fibres per wave iteration
+    for (long long q0 = p0 + NF * wv; q0 < p1; q0 += NF * nw) {
+      const int nf = (int)min((long long)NF, p1 - q0);
+      const TIn* f0 = a.T + q0 * n;
+      int ii[NF], jj[NF];
+      ii[0] = (int)(q0 / n);
+      jj[0] = (int)(q0 - (long long)ii[0] * n);
+#pragma unroll
+      for (int f = 1; f < NF; ++f) {
+        const bool wrap = jj[f - 1] + 1 == n;
+        ii[f] = wrap ? ii[f - 1] + 1 : ii[f - 1];
+        jj[f] = wrap ? 0 : jj[f - 1] + 1;
+      }
+      for (int kb = 0; kb < n; kb += 128) {
+        // every load of this block of the fibres before the atomics
+        long long x[NF][2];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int k = kb + lane + 64 * c;
+            x[f][c] = (f < nf && k < n) ? __double2ll_rn((double)f0[(size_t)f * n + k] * up) : 0ll;
+          }
+        for (int g = 0; g < Gc; ++g) {
+          const uint32_t* tg = tab + g * 3 * n;
+          unsigned long long* bg = bins + (size_t)g * b;
+          uint32_t off[NF];  // (h1(i) + h2(j)) << 1 | sign bit, per fibre
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const uint32_t ea = tg[ii[f]], eb = tg[n + jj[f]];
+            off[f] = (((ea >> 1) + (eb >> 1)) << 1) | ((ea ^ eb) & 1u);
+          }
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int k = kb + lane + 64 * c;
+            if (k < n) {
+              const uint32_t e3 = tg[2 * n + k];
+#pragma unroll
+              for (int f = 0; f < NF; ++f) {
+                if (f < nf) {
+                  const uint32_t t = (off[f] >> 1) + (e3 >> 1);
+                  const long long v = ((off[f] ^ e3) & 1u) ? -x[f][c] : x[f][c];
+                  atomicAdd(&bg[t & bmask], (unsigned long long)v);
+                }
+              }
+            }
+          }
         }
       }
     }
   }
   __syncthreads();
-  TAcc* out = a.partial + ((size_t)blockIdx.y * a.nslab + blockIdx.x) * (size_t)G * b;
-  for (int t = tid; t < Gc * b; t += blockDim.x) out[t] = bins[t];
+  double* out = a.partial + ((size_t)grp * a.nslab + slab) * (size_t)G * b;
+  for (int t = tid; t < Gc * b; t += blockDim.x)
+    out[t] = bad ? __builtin_nan("") : (double)(long long)bins[t] * down;
 }
 
 // s_time[m][t] = sum over slabs of the partial bins (FP64).
-template <typename TAcc>
-__global__ void k_build_reduce(const TAcc* partial, double* s_time, int b, int B, int G, int nslab) {
+__global__ void k_build_reduce(const double* partial, double* s_time, int b, int B, int G, int nslab) {
   const size_t total = (size_t)B * b;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const int m = (int)(e / b);
     const int t = (int)(e - (size_t)m * b);
     const int grp = m / G, g = m - grp * G;
-    const TAcc* p = partial + ((size_t)grp * nslab * G + g) * b + t;
+    const double* p = partial + ((size_t)grp * nslab * G + g) * b + t;
     double s = 0.0;
-    for (int sl = 0; sl < nslab; ++sl) s += (double)p[(size_t)sl * G * b];
+    int sl = 0;
+    for (; sl + 8 <= nslab; sl += 8) {
+      double t8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t8[q] = (double)p[(size_t)(sl + q) * G * b];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += t8[q];
+    }
+    for (; sl < nslab; ++sl) s += (double)p[(size_t)sl * G * b];
     s_time[e] = s;
   }
 }

@@ -82,7 +82,7 @@ namespace {
 
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
-  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT
+  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -118,33 +118,57 @@ tsk_status ws_get(tsk_ctx* c, int id, size_t bytes, void** out) {
   return TSK_OK;
 }
 
-// Two-level twiddle table for base b (see fft.hpp): tlo[j] = W_b^j for j < 64,
-// then thi[j] = W_b^(64 j) for j <= b/64, computed in FP64 and rounded once.
+// exp(-2 pi i j / M) in FP64, exact on the axes.
+static void unit_root(long j, long M, double* cs, double* sn) {
+  j %= M;
+  if (j < 0) j += M;
+  if (j == 0) { *cs = 1.0; *sn = 0.0; }
+  else if (4 * j == M) { *cs = 0.0; *sn = -1.0; }
+  else if (2 * j == M) { *cs = -1.0; *sn = 0.0; }
+  else if (4 * j == 3 * M) { *cs = 0.0; *sn = 1.0; }
+  else {
+    const double a = 6.283185307179586476925286766559 * (double)j / (double)M;
+    *cs = cos(a);
+    *sn = -sin(a);
+  }
+}
+
+// Twiddle table of a length-b real transform (see fft.hpp, Twid): the per-pass
+// table of the H = b/2 point complex FFT with the kernels' thread count, then
+// W_b^k for k = 0..H.  Computed in FP64, rounded once to R.
 template <typename R>
 tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out) {
   auto& mp = (sizeof(R) == 8) ? c->tw64 : c->tw32;
   auto it = mp.find(logb);
   if (it == mp.end()) {
-    const int b = 1 << logb;
-    const int cnt = tsk::twiddle_len(b);
-    std::vector<cx<R>> h(cnt);
-    const double two_pi = 6.283185307179586476925286766559;
-    auto wb = [&](long j) {
-      j %= b;
+    const int b = 1 << logb, H = b / 2;
+    const int NT = tsk::threads_for_h<R>(logb - 1);
+    const int rmax = tsk::fft_rmax(H, NT);
+    const int plen = tsk::pass_table_len(H, NT);
+    std::vector<cx<R>> h(tsk::twid_len(H, NT));
+    int off = 0;
+    for (int ns = 1; ns < H;) {
+      const int rad = tsk::pass_radix(H, ns, rmax);
+      if (ns > 1) {
+        for (int r = 1; r < rad; ++r)
+          for (int k = 0; k < ns; ++k) {
+            double cs, sn;
+            unit_root((long)r * k, (long)ns * rad, &cs, &sn);
+            h[off + (r - 1) * ns + k] = cx<R>{(R)cs, (R)sn};
+          }
+        off += (rad - 1) * ns;
+      }
+      ns *= rad;
+    }
+    if (off != plen) return tsk::fail(TSK_EHIP, "internal: twiddle plan mismatch");
+    for (int k = 0; k <= H; ++k) {
       double cs, sn;
-      // exact values on the axes
-      if (j == 0) { cs = 1.0; sn = 0.0; }
-      else if (4 * j == b) { cs = 0.0; sn = -1.0; }
-      else if (2 * j == b) { cs = -1.0; sn = 0.0; }
-      else if (4 * j == 3 * (long)b) { cs = 0.0; sn = 1.0; }
-      else { const double a = two_pi * (double)j / (double)b; cs = cos(a); sn = -sin(a); }
-      return cx<R>{(R)cs, (R)sn};
-    };
-    for (int j = 0; j < 64; ++j) h[j] = wb(j);
-    for (int j = 0; j <= b / 64; ++j) h[64 + j] = wb(64L * j);
+      unit_root(k, b, &cs, &sn);
+      h[plen + k] = cx<R>{(R)cs, (R)sn};
+    }
     void* d = nullptr;
-    TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * cnt));
-    TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * cnt, hipMemcpyHostToDevice));
+    TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * h.size()));
+    TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * h.size(), hipMemcpyHostToDevice));
     it = mp.emplace(logb, d).first;
   }
   *out = reinterpret_cast<const cx<R>*>(it->second);
@@ -376,23 +400,21 @@ extern "C" void tsk_tables_destroy(tsk_tables_t t) {
 
 namespace {
 
-// Two static-LDS size classes of the dense build: 128 KB of bins (one
-// work-group per CU) and 16 KB (several per CU) for small sketches.
-constexpr int kBuildTab = 4096;
-template <typename TAcc>
-constexpr int build_bins_large() { return (128 * 1024) / (int)sizeof(TAcc); }
-template <typename TAcc>
-constexpr int build_bins_small() { return (16 * 1024) / (int)sizeof(TAcc); }
+// Two static-LDS pool sizes of the dense build (64-bit words): the whole CU
+// (one work-group per CU) and 20 KB (several per CU) for small sketches.
+constexpr int kBuildPoolLarge = (159 * 1024) / 8;  // leaves room for the reduction scratch
+constexpr int kBuildPoolSmall = (20 * 1024) / 8;
 
-template <typename TIn, typename TAcc>
+template <typename TIn>
 tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipStream_t st,
                             double** s_time_out) {
   const int n = tab->n, b = tab->b, B = tab->B;
-  constexpr int BL = build_bins_large<TAcc>();
-  constexpr int BS = build_bins_small<TAcc>();
-  if (b > BL) return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d too long for one CU's LDS", b);
-  const bool small = B * b <= BS;
-  int G = std::max(1, std::min(B, (small ? BS : BL) / b));
+  const size_t per_sketch = (size_t)b * 8 + (size_t)12 * n;  // bins + 3 table words
+  if (per_sketch > (size_t)kBuildPoolLarge * 8)
+    return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d, n=%d exceed one CU's LDS", b, n);
+  const bool small = (size_t)B * per_sketch <= (size_t)kBuildPoolSmall * 8;
+  const size_t pool = (size_t)(small ? kBuildPoolSmall : kBuildPoolLarge) * 8;
+  int G = (int)std::min<size_t>((size_t)B, pool / per_sketch);
   const int ngroups = (B + G - 1) / G;
   G = (B + ngroups - 1) / ngroups;  // balance the groups
   const long long npairs = (long long)n * n;
@@ -404,9 +426,19 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   nslab = (int)((npairs + pps - 1) / pps);
   void* partial = nullptr;
   void* stime = nullptr;
-  TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * b * sizeof(TAcc), &partial));
+  void* amax = nullptr;
+  TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * b * sizeof(double), &partial));
   TSK_TRY(ws_get(ctx, WS_STIME, (size_t)B * b * sizeof(double), &stime));
-  tsk::BuildArgs<TIn, TAcc> a;
+  TSK_TRY(ws_get(ctx, WS_AMAX, sizeof(unsigned long long), &amax));
+  // max |T| for the fixed-point scale (a fill kernel clears the slot)
+  hipLaunchKernelGGL(tsk::k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(amax), 0u,
+                     (size_t)2);
+  TSK_TRY(check_launch("k_fill_u32"));
+  const size_t cnt = (size_t)n * n * n;
+  hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3((int)std::min<size_t>(1024, (cnt + 1023) / 1024)),
+                     dim3(256), 0, st, T, cnt, reinterpret_cast<unsigned long long*>(amax));
+  TSK_TRY(check_launch("k_absmax"));
+  tsk::BuildArgs<TIn> a;
   a.T = T;
   a.n = n;
   a.b = b;
@@ -415,16 +447,18 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   a.hx = tab->hx;
   a.pairs_per_slab = pps;
   a.nslab = nslab;
-  a.partial = reinterpret_cast<TAcc*>(partial);
+  a.ngroups = ngroups;
+  a.absmax = reinterpret_cast<const unsigned long long*>(amax);
+  a.partial = reinterpret_cast<double*>(partial);
+  // 1-D grid: 8 XCD lanes x ngroups x ceil(nslab / 8) (see the kernel).
+  const int nblk = 8 * ngroups * ((nslab + 7) / 8);
   if (small)
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, TAcc, BS, 1024>), dim3(nslab, ngroups), dim3(1024), 0,
-                       st, a);
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolSmall>), dim3(nblk), dim3(1024), 0, st, a);
   else
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, TAcc, BL, kBuildTab>), dim3(nslab, ngroups),
-                       dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge>), dim3(nblk), dim3(1024), 0, st, a);
   TSK_TRY(check_launch("k_build_dense"));
-  hipLaunchKernelGGL((tsk::k_build_reduce<TAcc>), dim3(grid_for((size_t)B * b, 256)), dim3(256), 0,
-                     st, (const TAcc*)partial, (double*)stime, b, B, G, nslab);
+  hipLaunchKernelGGL(tsk::k_build_reduce, dim3(grid_for((size_t)B * b, 256)), dim3(256), 0, st,
+                     (const double*)partial, (double*)stime, b, B, G, nslab);
   TSK_TRY(check_launch("k_build_reduce"));
   *s_time_out = reinterpret_cast<double*>(stime);
   return TSK_OK;
@@ -444,9 +478,9 @@ extern "C" tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, co
   TSK_TRY(get_tw<double>(ctx, tab->logb, &tw));
   double* stime = nullptr;
   if (dtype == TSK_F32)
-    TSK_TRY((build_dense_impl<float, float>(ctx, tab, (const float*)T, S(stream), &stime)));
+    TSK_TRY(build_dense_impl<float>(ctx, tab, (const float*)T, S(stream), &stime));
   else
-    TSK_TRY((build_dense_impl<double, double>(ctx, tab, (const double*)T, S(stream), &stime)));
+    TSK_TRY(build_dense_impl<double>(ctx, tab, (const double*)T, S(stream), &stime));
   return launch_r2c(tab->logb, stime, reinterpret_cast<cx<double>*>(S64),
                     reinterpret_cast<cx<float>*>(S32), tw, accumulate ? 1 : 0, tab->B, S(stream));
 }

@@ -58,7 +58,8 @@ def _gpu_spectra_from(ctx, tab, S_time):
 
 @pytest.mark.parametrize("n,b,B,dtype", [(50, 1024, 4, np.float64), (37, 256, 3, np.float64),
                                          (37, 256, 3, np.float32), (1, 64, 1, np.float64),
-                                         (65, 8192, 5, np.float32)])
+                                         (65, 8192, 5, np.float32), (300, 4096, 8, np.float32),
+                                         (120, 16384, 3, np.float64)])
 def test_dense_build_matches_eq1(ctx, n, b, B, dtype):
     print(f"build n={n} b={b} B={B} {np.dtype(dtype).name}", flush=True)
     P = planted_tensor(n, min(3, n), noise=0.05, seed=n, dtype=dtype)
