@@ -76,8 +76,8 @@ void tsk_destroy(tsk_ctx_t ctx);
 tsk_status tsk_hash_generate(uint64_t seed, int n, int b, int B,
                              uint32_t* h_host, int8_t* xi_host);
 
-/* Start vectors drawn uniformly from the unit sphere (Algorithm 1, "draw
- * u_0 uniformly at random from the unit sphere") for component `comp`:
+/* Start vectors of the restarts (Algorithm 1, initialisation of each
+ * restart: a random point of the unit sphere) for component `comp`:
  *   r_e = mix64(mix64(seed ^ 0x75307530) + (comp<<40 | tau<<20 | 2i+e))
  *   U_e = (r_e >> 11) 2^-53,  z_i = sqrt(-2 ln(1-U_0)) cos(2 pi U_1),
  *   u = z / ||z||.
