@@ -14,10 +14,13 @@ one (restart, sketch) pair; a step performs k*(T+1)*L*B of them.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
 import time
+from collections import defaultdict
 
 import numpy as np
 
@@ -30,6 +33,92 @@ PEAK_FP32_VALU_TFLOPS = 157.3
 
 N, K, B_LEN, B_CNT, L, T_ITERS = 200, 10, 16384, 10, 50, 30
 NOISE, SEED = 0.05, 1
+
+POWER_KERNEL = "k_power<float, 14, false>"
+BUILD_KERNEL = "k_build_dense<float"
+COPY_BYTES = 256 << 20
+# HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter runs,
+# stored with the hash of the kernel sources they were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_dense_n200_b16384.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1506_04448_amd", "csrc", f)
+                  for f in ("fft.hpp", "kernels.hpp")]
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str):
+    """Calibrated HBM bytes per launch of `kernel` from the stored counter
+    summary, or None when there is none or the kernels changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    val = kv.get(f"traffic[{kernel}]")
+    return float(val) if val is not None else None
+
+
+def _counter_means(path: str, counter: str):
+    """Per-kernel (mean, max, dispatches) of a counter (rocprofv3 csv, KiB)."""
+    acc = defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), max(v), len(v)) for k, v in acc.items()}
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str) -> str:
+    """Text summary of the two counter runs of ``--kernels-only all``:
+    FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
+    counter reads for a device copy of COPY_BYTES bytes."""
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    # The copy's dispatches are the largest of any copy kernel (the set-up
+    # uploads share its name), so the calibration takes the maximum.
+    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    copy_key = max(copy, key=lambda k: fetch[k][1])
+    f_fac = fetch[copy_key][1] * 1024.0 / COPY_BYTES
+    w_fac = write[copy_key][1] * 1024.0 / COPY_BYTES
+    out = [f"kernel_sources_sha256: {kernel_sources_sha256()}",
+           f"copy_kernel: {copy_key[:100]}",
+           f"copy_bytes: {COPY_BYTES}",
+           f"copy_fetch_factor: {f_fac:.4f}",
+           f"copy_write_factor: {w_fac:.4f}",
+           "# kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated bytes/dispatch"]
+    for k in sorted(fetch, key=lambda k: -fetch[k][0]):
+        fk, _, nd = fetch[k]
+        wk = write.get(k, (0.0, 0.0, 0))[0]
+        out.append(f"# {k[:90]} | {nd} | {fk:.1f} | {wk:.1f} | {1024 * (fk / f_fac + wk / w_fac):.0f}")
+    for name in (POWER_KERNEL, BUILD_KERNEL):
+        ks = [k for k in fetch if name in k]
+        if ks:
+            fk, wk = fetch[ks[0]][0], write.get(ks[0], (0.0, 0.0, 0))[0]
+            out.append(f"traffic[{name}]: {1024 * (fk / f_fac + wk / w_fac):.0f}")
+    return "\n".join(out)
+
+
+def summarize_stats(stats_csv: str, top: int = 16) -> str:
+    """Per-kernel table of a rocprofv3 --stats kernel summary."""
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    out = ["# kernel | calls | average us | min us | max us | % of GPU time"]
+    for r in rows[:top]:
+        out.append(f"{r['Name'][:100]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['Percentage']):.2f}")
+    return "\n".join(out)
 
 
 def sketch_update_flops(b: int) -> float:
@@ -90,6 +179,28 @@ def cpu_baseline(P, h, xi, budget_s: float):
     }
 
 
+def kernels_only(what, reps, ctx, tab, Td, S64, S32, dev):
+    """The launches the roofline figures cover, alone, for counter runs."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+    if what in ("all", "build"):
+        for _ in range(reps):
+            tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+    if what in ("all", "power"):
+        Ut = torch.nn.functional.normalize(torch.randn((L, N), device=dev), dim=1)
+        Vt = torch.empty((L, B_CNT, N), dtype=torch.float32, device=dev)
+        for _ in range(reps):
+            tsk.contract_tiuu(ctx, tab, Ut, S32=S32, V=Vt)
+    if what in ("all", "copy"):
+        x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(reps):
+            y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"kernels-only {what}: {reps} launches each", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,7 +210,18 @@ def main():
                     help="seconds of oracle power steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy"),
+                    help="launch only these kernels --reps times (for counter runs) and exit")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(summarize_pmc(*args.summarize_pmc))
+        return
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(see the sharding paragraph of the design notes)", file=sys.stderr)
@@ -121,6 +243,12 @@ def main():
     tau = torch.empty(K, dtype=torch.int32, device=dev)
     flags = torch.empty((K, L), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.kernels_only:
+        kernels_only(args.kernels_only, args.reps, ctx, tab, Td, S64, S32, dev)
+        tab.close()
+        ctx.close()
+        return
 
     def step():
         tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
@@ -230,14 +358,15 @@ def main():
                                f"b={B_LEN}, B={B_CNT}, L={L}, T={T_ITERS}; build + decompose",
                    "n": N, "k": K, "b": B_LEN, "B": B_CNT, "L": L, "T": T_ITERS,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "k_power<float,14>",
+        "roofline": {"bound": "alu", "kernel": POWER_KERNEL,
                      "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": None, "launch_ms": power_ms,
-                     "flops_per_launch": flops_launch},
+                     "traffic": stored_traffic(POWER_KERNEL), "traffic_unit": "bytes/launch",
+                     "launch_ms": power_ms, "flops_per_launch": flops_launch},
         "sketch_build": {"GBps": build_gbps, "ms": build_ms,
                          "frac_hbm": build_gbps / PEAK_HBM_GBPS,
-                         "bytes": build_bytes(N, B_LEN, B_CNT)},
+                         "bytes": build_bytes(N, B_LEN, B_CNT),
+                         "traffic": stored_traffic(BUILD_KERNEL)},
         "recovery": {"residual": res_b, "wrong_vectors": int(wrong_b)},
         "plain_path": plain,
         "decompose_ms": decompose_ms,

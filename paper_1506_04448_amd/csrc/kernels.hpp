@@ -232,7 +232,7 @@ struct PowerArgs {
   R* V;                 // [L][B][n]
   double* lam_per;      // [L][B]      (mode 1)
   int tau0;
-  int prefix;
+  int prefix;           // median prologue (selects the PRE instantiation)
   int mode;
 };
 
@@ -271,7 +271,9 @@ constexpr int power_min_waves(int logh) {
   return threads_for_h<R>(logh) >= 256 ? threads_for_h<R>(logh) / 256 : 1;
 }
 
-template <typename R, int LOGB>
+// PRE selects the median prologue (u from Vprev) at compile time; the two
+// variants show up as separate kernels in traces.
+template <typename R, int LOGB, bool PRE>
 __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB - 1)) void k_power(PowerArgs<R> a) {
   constexpr int LOGH = LOGB - 1;
   constexpr int NT = threads_for_h<R>(LOGH);
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
   const Twid<R> tw{a.twg, a.twg + pass_table_len(H, NT), twl};
   __syncthreads();  // staged tables visible
 
-  if (a.prefix) {
+  if constexpr (PRE) {
     const bool ok = median_prologue<R, NT>(a.Vprev, a.Uprev, tau, n, B, u, re, 2 * PL, red);
     if (m == 0) {
       for (int i = tid; i < n; i += NT) a.Ucur[(size_t)tau * n + i] = u[i];

@@ -192,7 +192,10 @@ tsk_status launch_power_t(const tsk::PowerArgs<R>& a, int B, int nrest, hipStrea
   if (a.n > NU)
     return tsk::fail(TSK_EUNSUPPORTED, "power step: n=%d exceeds %d at b=2^%d in this precision",
                      a.n, NU, LOGB);
-  hipLaunchKernelGGL((tsk::k_power<R, LOGB>), dim3(B, nrest), dim3(NT), 0, st, a);
+  if (a.prefix)
+    hipLaunchKernelGGL((tsk::k_power<R, LOGB, true>), dim3(B, nrest), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((tsk::k_power<R, LOGB, false>), dim3(B, nrest), dim3(NT), 0, st, a);
   return check_launch("k_power");
 }
 
