@@ -51,7 +51,12 @@ __device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return {a.x * s, a.y * s
 // 64 ... writes of the radix-8 Stockham passes (nearly) free of bank
 // conflicts, and the position of p + s is pidx(p) + poff(s) for every access
 // the passes make, so offsets fold into the instructions.
-__device__ __forceinline__ constexpr int pidx(int p) { return p + 5 * (p >> 6); }
+__device__ __forceinline__ constexpr int pidx(int p) {
+  // at run time a 24-bit multiply-add (full rate) rather than the 64-bit
+  // multiply-add the compiler otherwise picks for p + 5 (p >> 6)
+  return __builtin_is_constant_evaluated() ? p + 5 * (p >> 6)
+                                           : p + (int)__umul24((unsigned)(p >> 6), 5u);
+}
 // Words needed for an N-element padded array.
 constexpr int padded_len(int n) { return n + 5 * (n >> 6) + 6; }
 
@@ -99,24 +104,23 @@ template <typename R>
 struct Twid {
   const cx<R>* pass;  // per-pass table (global)
   const cx<R>* wk;    // W_b^k (global)
-  const cx<R>* lds;   // LDS copy of the first entries of `pass` (may be null)
   __device__ __forceinline__ cx<R> w(int k) const { return wk[k]; }
 };
 
-// Entries of the per-pass table worth copying to LDS: every pass whose whole
-// range lies below `cap` entries.
-constexpr int pass_table_lds_len(int N, int NT, int cap) {
-  int len = 0;
-  for (int ns = 1; ns < N;) {
-    const int rad = pass_radix(N, ns, fft_rmax(N, NT));
-    if (ns > 1) {
-      if (len + (rad - 1) * ns > cap) break;
-      len += (rad - 1) * ns;
-    }
-    ns *= rad;
+// Buffer-resource load of one complex twiddle: `voff` (per lane) and `soff`
+// (uniform) are byte offsets from the resource's base.  All twiddles of a
+// pass share one per-lane offset; the per-r row offsets go to scalar
+// registers.  Out-of-range reads return zero.
+constexpr unsigned kBufferWord3 = 0x00020000u;  // raw 32-bit buffer, gfx9 family
+template <typename R>
+__device__ __forceinline__ cx<R> tw_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(R) == 4) {
+    return __builtin_bit_cast(cx<R>, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(cx<R>, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
   }
-  return len;
 }
+
 constexpr int twid_len(int H, int NT) { return pass_table_len(H, NT) + H + 1; }
 
 // ---- radix-R DFTs in registers (y_q = sum_r x_r W_R^{rq}, W_R = e^{-+2 pi i/R}) ----
@@ -247,22 +251,22 @@ struct PassTw {
   cx<R> w[PER][NR > 0 ? NR : 1];
 };
 
-template <typename R, int N, int RAD, int NS, int NT, int TOFF, int LIM>
+template <typename R, int N, int RAD, int NS, int NT, int TOFF>
 __device__ __forceinline__ void load_pass_tw(PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1>& t,
                                              const Twid<R>& tw, int tid) {
   constexpr int NB = N / RAD;
   constexpr int PER = (NB + NT - 1) / NT;
-  // passes inside the LDS copy read it there, later ones from global memory
-  constexpr bool IN_LDS = TOFF + (RAD - 1) * NS <= LIM;
   if constexpr (NS > 1) {
-    const cx<R>* __restrict__ src = IN_LDS ? tw.lds : tw.pass;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<cx<R>*>(tw.pass), 0, (TOFF + (RAD - 1) * NS) * (int)sizeof(cx<R>), kBufferWord3);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       if ((NB % NT) == 0 || j < NB) {
-        const int k = j & (NS - 1);
+        const unsigned voff = (unsigned)(j & (NS - 1)) * (unsigned)sizeof(cx<R>);
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) t.w[q][r - 1] = src[TOFF + (r - 1) * NS + k];
+        for (int r = 1; r < RAD; ++r)
+          t.w[q][r - 1] = tw_load<R>(rs, voff, (unsigned)((TOFF + (r - 1) * NS) * sizeof(cx<R>)));
       }
     }
   }
@@ -296,6 +300,10 @@ __device__ __forceinline__ void stockham_pass(const Soa<R>& buf,
         }
       }
       dft_r<R, RAD, INV>(v[q]);
+      // Keep the butterfly ahead of the barrier: waves that have their
+      // inputs compute while the others still read.
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) asm volatile("" : "+v"(v[q][r].x), "+v"(v[q][r].y));
     }
   }
   __syncthreads();
@@ -315,8 +323,11 @@ __device__ __forceinline__ void stockham_pass(const Soa<R>& buf,
   __syncthreads();
 }
 
-// Passes from stride NS on; `cur` holds this pass's twiddles.
-template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, int LIM>
+// Passes from stride NS on; `cur` holds this pass's twiddles.  With PF the
+// next pass's twiddles are loaded before the current pass runs (their global
+// loads overlap its arithmetic, at the cost of registers); without PF each
+// pass loads its own at its start.
+template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, bool PF>
 __device__ __forceinline__ void fft_passes(
     const Soa<R>& buf, const Twid<R>& twp,
     const PassTw<R, (N / pass_radix(N, NS, RMAX) + NT - 1) / NT, pass_radix(N, NS, RMAX) - 1>& cur) {
@@ -327,26 +338,28 @@ __device__ __forceinline__ void fft_passes(
   // instead of being hoisted and kept live across the whole kernel.
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
-  if constexpr (NS2 < N) {
-    constexpr int RAD2 = pass_radix(N, NS2, RMAX);
-    PassTw<R, (N / RAD2 + NT - 1) / NT, RAD2 - 1> nxt;
-    load_pass_tw<R, N, RAD2, NS2, NT, TOFF2, LIM>(nxt, twp, tid);
+  constexpr int RAD2 = NS2 < N ? pass_radix(N, NS2, RMAX) : 2;
+  PassTw<R, (N / RAD2 + NT - 1) / NT, RAD2 - 1> nxt;
+  if constexpr (PF) {
+    if constexpr (NS2 < N) load_pass_tw<R, N, RAD2, NS2, NT, TOFF2>(nxt, twp, tid);
     stockham_pass<R, N, RAD, NS, NT, INV>(buf, cur, tid);
-    fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, LIM>(buf, twp, nxt);
   } else {
-    stockham_pass<R, N, RAD, NS, NT, INV>(buf, cur, tid);
+    PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> own;
+    load_pass_tw<R, N, RAD, NS, NT, TOFF>(own, twp, tid);
+    stockham_pass<R, N, RAD, NS, NT, INV>(buf, own, tid);
   }
+  if constexpr (NS2 < N) fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, PF>(buf, twp, nxt);
 }
 
 // Complex FFT of length N = 2^LOGN in LDS (SoA, padded); ends with a barrier.
-// The first LIM entries of the pass table are read from tw.lds.
-template <typename R, int LOGN, int NT, bool INV, int LIM = 0>
+// PF as in fft_passes.
+template <typename R, int LOGN, int NT, bool INV, bool PF = true>
 __device__ __forceinline__ void fft_soa(const Soa<R>& buf, const Twid<R>& tw) {
   constexpr int N = 1 << LOGN;
   constexpr int RMAX = fft_rmax(N, NT);
   constexpr int RAD = pass_radix(N, 1, RMAX);
   PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> first;  // the first pass has no twiddles
-  fft_passes<R, N, 1, NT, RMAX, INV, 0, LIM>(buf, tw, first);
+  fft_passes<R, N, 1, NT, RMAX, INV, 0, PF>(buf, tw, first);
 }
 
 }  // namespace tsk

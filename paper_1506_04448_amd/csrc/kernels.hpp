@@ -131,71 +131,133 @@ constexpr int threads_for_h(int logh) {
 }
 
 // ---------------------------------------------------------------------------
-// Median of B <= MAXB values held in registers by one thread: the element of
-// rank (B-1)/2 (odd B) or the mean of ranks B/2-1 and B/2 (even B), ranks
-// breaking ties by index.  NaN inputs give NaN.
+// Threads of a power-step work-group.  FP32 holds 16 points per thread
+// (radix-16 passes) from H = 1024 on, so that at b = 16384 a work-group needs
+// about 76 KB of LDS and 128 VGPRs and two of them share a CU; FP64 holds 8
+// points per thread (radix 8), one work-group per CU at that size.
 // ---------------------------------------------------------------------------
-template <typename R, int MAXB>
-__device__ __forceinline__ R thread_median(const R* v, int B) {
-  const int ra = (B - 1) / 2, rb = B / 2;
-  R a = R(__builtin_nan("")), c = R(__builtin_nan(""));
+template <typename R>
+constexpr int power_threads(int logh) {
+  return (sizeof(R) == 4 && logh >= 10) ? (1 << (logh - 4)) : threads_for_h<R>(logh);
+}
+// Waves per SIMD the power kernel is compiled for (FP32: two work-groups per CU).
+template <typename R>
+constexpr int power_waves(int logh) {
+  return power_threads<R>(logh) / (sizeof(R) == 4 ? 128 : 256) < 1
+             ? 1
+             : power_threads<R>(logh) / (sizeof(R) == 4 ? 128 : 256);
+}
+
+constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Dynamic LDS of one power-step work-group, in bytes:
+//   [0, 128)          reduction scratch (16 doubles)
+//   [128, off_u)      the padded half-length sequence, split re/im (also the
+//                     staging area of the median prologue)
+//   [off_u, off_tab)  the vector u (n values)
+//   [off_tab, end)    when `tab`: the table rows read by the count sketches of
+//                     modes 2 and 3 (sorted buckets, indices) and by the
+//                     read-off (mode 1), five rows of n words.
+template <typename R>
+constexpr size_t power_lds_off_u(int logh) {
+  return align16(128 + sizeof(R) * 2 * (size_t)padded_len(1 << logh));
+}
+template <typename R>
+constexpr size_t power_lds_off_tab(int logh, int n) {
+  return power_lds_off_u<R>(logh) + align16(sizeof(R) * (size_t)n);
+}
+template <typename R>
+constexpr size_t power_lds_bytes(int logh, int n, bool tab) {
+  return power_lds_off_tab<R>(logh, n) + (tab ? (size_t)20 * n : 0);
+}
+
+// Zero `bytes` bytes of LDS from a 16-byte aligned start, 16 bytes per store.
+template <int NT>
+__device__ __forceinline__ void zero_lds(void* p, int bytes) {
+  float4* q = reinterpret_cast<float4*>(p);
+  const int n16 = bytes >> 4;
+  for (int t = threadIdx.x; t < n16; t += NT) q[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+  float* tail = reinterpret_cast<float*>(q + n16);
+  const int nt = (bytes & 15) >> 2;
+  if ((int)threadIdx.x < nt) tail[threadIdx.x] = 0.f;
+}
+
+// Copy `count` consecutive values from global memory to LDS, U loads in
+// flight per thread before the first store.
+template <int NT, int U, typename T>
+__device__ __forceinline__ void copy_to_lds(T* dst, const T* __restrict__ src, int count) {
+  for (int base = 0; base < count; base += NT * U) {
+    T v[U];
 #pragma unroll
-  for (int i = 0; i < MAXB; ++i) {
-    if (i < B) {
-      int r = 0;
+    for (int q = 0; q < U; ++q) {
+      const int e = base + q * NT + (int)threadIdx.x;
+      if (e < count) v[q] = src[e];
+    }
 #pragma unroll
-      for (int j = 0; j < MAXB; ++j)
-        if (j < B) r += (v[j] < v[i]) || (v[j] == v[i] && j < i);
-      if (r == ra) a = v[i];
-      if (r == rb) c = v[i];
+    for (int q = 0; q < U; ++q) {
+      const int e = base + q * NT + (int)threadIdx.x;
+      if (e < count) dst[e] = v[q];
     }
   }
-  return (B & 1) ? a : (a + c) * R(0.5);
+}
+
+// Coordinates per chunk of the median prologue: B staged rows plus the two
+// selected order statistics must fit `cap` LDS values.
+__device__ __forceinline__ int median_chunk(int n, int B, int cap) {
+  const int c = cap / (B + 2);
+  return n < c ? n : c;
 }
 
 // ---------------------------------------------------------------------------
 // Median prologue: u = vbar / ||vbar||, vbar_i = med_m Vprev[tau][m][i], for
 // the n coordinates of one restart, into u[] (LDS or global).  Falls back to
-// Uprev[tau] when ||vbar|| is zero or not finite.  `stage` is scratch LDS of
-// `cap` elements.  One thread per coordinate for B <= 16, one wave per
-// coordinate above.  Returns true when the median vector was usable.
+// Uprev[tau] when ||vbar|| is zero or not finite.  The median is the element
+// of rank (B-1)/2 (odd B) or the mean of ranks B/2-1 and B/2 (even B), ranks
+// breaking ties by sketch index; any NaN among the B values gives NaN.  Every
+// (coordinate, sketch) pair ranks its value in parallel and the two selected
+// ranks are written to LDS.  `stage` is LDS scratch of `cap` values; with
+// `staged` the whole B x n block (one chunk) is already there, row m at m*n.
+// Returns true when the median vector was usable.
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
 __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict__ Uprev, int tau,
-                                int n, int B, R* u, R* stage, int cap, double* red) {
-  const int lane = wave_lane();
-  const int wave = threadIdx.x >> 6;
-  constexpr int NW = NT / 64;
+                                int n, int B, R* u, R* stage, int cap, double* red, bool staged) {
   const R* vb = Vprev + (size_t)tau * B * n;
-  const int CH = max(1, cap / B);
+  const int CH = median_chunk(n, B, cap);
+  R* selA = stage + B * CH;
+  R* selC = selA + CH;
+  const int ra = (B - 1) / 2, rb = B / 2;
   double ss = 0.0;
   for (int c0 = 0; c0 < n; c0 += CH) {
     const int cw = min(CH, n - c0);
+    if (!staged) {
+      __syncthreads();  // the previous chunk's readers are done
+      for (int e = threadIdx.x; e < B * cw; e += NT) {
+        const int mm = e / cw, ii = e - mm * cw;
+        stage[mm * CH + ii] = vb[(size_t)mm * n + c0 + ii];
+      }
+      __syncthreads();
+    }
     for (int e = threadIdx.x; e < B * cw; e += NT) {
       const int mm = e / cw, ii = e - mm * cw;
-      stage[mm * CH + ii] = vb[(size_t)mm * n + c0 + ii];
+      const R x = stage[mm * CH + ii];
+      int r = 0;
+      for (int j = 0; j < B; ++j) {
+        const R o = stage[j * CH + ii];
+        r += (o < x) || (o == x && j < mm);
+      }
+      if (r == ra) selA[ii] = x;
+      if (r == rb) selC[ii] = x;
     }
     __syncthreads();
-    if (B <= 16) {
-      for (int ii = threadIdx.x; ii < cw; ii += NT) {
-        R v[16];
-#pragma unroll
-        for (int mm = 0; mm < 16; ++mm) v[mm] = mm < B ? stage[mm * CH + ii] : R(0);
-        const R med = thread_median<R, 16>(v, B);
-        u[c0 + ii] = med;
-        ss += (double)med * (double)med;
-      }
-    } else {
-      for (int ii = wave; ii < cw; ii += NW) {
-        const R x = lane < B ? stage[lane * CH + ii] : R(0);
-        const R med = wave_median<R>(x, B);
-        if (lane == 0) {
-          u[c0 + ii] = med;
-          ss += (double)med * (double)med;
-        }
-      }
+    for (int ii = threadIdx.x; ii < cw; ii += NT) {
+      bool nan = false;
+      for (int j = 0; j < B; ++j) nan |= __builtin_isnan(stage[j * CH + ii]);
+      R med = (B & 1) ? selA[ii] : (selA[ii] + selC[ii]) * R(0.5);
+      if (nan) med = R(__builtin_nan(""));
+      u[c0 + ii] = med;
+      ss += (double)med * (double)med;
     }
-    __syncthreads();
   }
   const double nrm = sqrt(block_sum<NT>(ss, red));
   const bool ok = nrm > 0.0 && nrm < __builtin_inf();
@@ -212,7 +274,7 @@ __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict
 
 // ---------------------------------------------------------------------------
 // Power step / evaluation: one work-group per (sketch m, restart tau).
-//   u     = Uprev[tau] (prefix 0) or the normalised median of Vprev[tau] (prefix 1)
+//   u     = Uprev[tau] (PRE false) or the normalised median of Vprev[tau] (PRE)
 //   A_k   = S_k conj(F(s2 u)_k);   P_k = A_k conj(F(s3 u)_k)
 //   sbar  = F^-1(P);  v_i = xi1(i) sbar[h1(i)]  -> V[tau][m]
 //   mode 1 also writes lam_per[tau][m] = u . v.
@@ -226,57 +288,23 @@ struct PowerArgs {
   const cx<R>* S;       // [B][H+1]
   const cx<R>* twg;     // [twid_len(H, NT)]
   const R* Uprev;       // [L][n]
-  const R* Vprev;       // [L][B][n]   (prefix 1)
-  R* Ucur;              // [L][n]      (prefix 1, written by m == 0)
-  int32_t* flags;       // [L]         (prefix 1, nullable)
+  const R* Vprev;       // [L][B][n]   (PRE)
+  R* Ucur;              // [L][n]      (PRE, written by m == 0)
+  int32_t* flags;       // [L]         (PRE, nullable)
   R* V;                 // [L][B][n]
   double* lam_per;      // [L][B]      (mode 1)
   int tau0;
   int prefix;           // median prologue (selects the PRE instantiation)
   int mode;
+  int tab_lds;          // table rows staged in LDS (power_lds_bytes with tab)
 };
-
-// LDS of one work-group (static): the half-length sequence (padded, split
-// re/im), the twiddle table, a reduction scratch, the count-sketch/read-off
-// table entries (power_tab_n coordinates, five words each) and the current
-// vector u (power_max_n coordinates).
-constexpr int kLdsBytes = 160 * 1024;
-// Early-pass twiddles copied to LDS (FP32 only; the FP64 kernels have no room).
-template <typename R, int LOGB>
-constexpr int power_tw_lds() {
-  return sizeof(R) == 4 ? pass_table_lds_len(1 << (LOGB - 1), threads_for_h<R>(LOGB - 1), 4096) : 0;
-}
-template <typename R, int LOGB>
-constexpr int power_base_bytes() {
-  return (int)(sizeof(R) * 2 * padded_len(1 << (LOGB - 1)) + 16 * sizeof(double) +
-               sizeof(cx<R>) * power_tw_lds<R, LOGB>());
-}
-template <typename R, int LOGB>
-constexpr int power_tab_n() {
-  constexpr int rem = kLdsBytes - power_base_bytes<R, LOGB>();
-  constexpr int t = rem / 2 / 20 / 64 * 64;
-  return t < 1024 ? t : 1024;
-}
-template <typename R, int LOGB>
-constexpr int power_max_n() {
-  constexpr int rem = kLdsBytes - power_base_bytes<R, LOGB>() - 20 * power_tab_n<R, LOGB>();
-  constexpr int fit = rem / (int)sizeof(R) / 64 * 64;
-  return fit < 4096 ? fit : 4096;
-}
-
-// Waves per SIMD the power kernel is compiled for (4 waves of a 1024-thread
-// work-group leave 128 VGPRs per lane).
-template <typename R>
-constexpr int power_min_waves(int logh) {
-  return threads_for_h<R>(logh) >= 256 ? threads_for_h<R>(logh) / 256 : 1;
-}
 
 // PRE selects the median prologue (u from Vprev) at compile time; the two
 // variants show up as separate kernels in traces.
 template <typename R, int LOGB, bool PRE>
-__global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB - 1)) void k_power(PowerArgs<R> a) {
+__global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1)) void k_power(PowerArgs<R> a) {
   constexpr int LOGH = LOGB - 1;
-  constexpr int NT = threads_for_h<R>(LOGH);
+  constexpr int NT = power_threads<R>(LOGH);
   constexpr int b = 1 << LOGB;
   constexpr int H = b / 2;
   constexpr int PL = padded_len(H);
@@ -284,119 +312,132 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1), power_min_waves<R>(LOGB
   // also owns k = H/2, which pairs with itself.
   constexpr int PK = (H / 2 + NT - 1) / NT;
   constexpr bool FULL = (H / 2) % NT == 0;
-  constexpr int NU = power_max_n<R, LOGB>();
-  constexpr int kPowerTab = power_tab_n<R, LOGB>();
-  constexpr int TWL = power_tw_lds<R, LOGB>();
-  __shared__ __align__(16) R re[2 * PL];
-  __shared__ __align__(16) cx<R> twl[TWL > 0 ? TWL : 1];
-  __shared__ __align__(16) R u[NU];
-  __shared__ uint32_t stab[5 * kPowerTab];
-  __shared__ double red[16];
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int n = a.n;
+  const int B = a.B;
+  double* red = reinterpret_cast<double*>(lds);
+  R* re = reinterpret_cast<R*>(lds + 128);
   R* im = re + PL;
+  R* u = reinterpret_cast<R*>(lds + power_lds_off_u<R>(LOGH));
+  uint32_t* stab = reinterpret_cast<uint32_t*>(lds + power_lds_off_tab<R>(LOGH, n));
   const Soa<R> buf{re, im};
 
   const int tid = threadIdx.x;
   const int m = blockIdx.x;
   const int tau = a.tau0 + blockIdx.y;
-  const int n = a.n;
-  const int B = a.B;
   const size_t tb = (size_t)m * 3 * n;
   const cx<R>* Sm = a.S + (size_t)m * (H + 1);
+  const cx<R>* wkg = a.twg + pass_table_len(H, NT);
+  const bool tab_lds = a.tab_lds != 0;
 
   // One round of global loads up front: this sketch's spectrum values owned
-  // by the thread (they become the running products p0/p1) and the table
-  // entries of the count sketches (modes 2, 3) and of the read-off (mode 1).
+  // by the thread (they become the running products p0/p1), the twiddles
+  // W_b^tid and W_b^(q NT) (uniform), the table rows, and u or the previous
+  // step's estimates.  W_b^k for k = tid + q NT is formed as W_b^tid W_b^(q NT)
+  // when needed (two registers instead of 2 PK), W_b^(H-k) = -conj(W_b^k) and
+  // W_b^(H/2) = -i.
   cx<R> p0[PK], p1[PK], pmid;
-  cx<R> w0[PK], w1[PK], wmid;  // W_b^k, W_b^(H-k), W_b^(H/2) for the owned k
-  const cx<R>* wkg = a.twg + pass_table_len(H, NT);
+  cx<R> wq[PK];
 #pragma unroll
   for (int q = 0; q < PK; ++q) {
     const int k = tid + q * NT;
+    wq[q] = wkg[q * NT];
     if (!FULL && k >= H / 2) break;
     p0[q] = Sm[k];
     p1[q] = Sm[H - k];
-    w0[q] = wkg[k];
-    w1[q] = wkg[H - k];
   }
-  if (tid == 0) {
-    pmid = Sm[H / 2];
-    wmid = wkg[H / 2];
-  }
-  const bool tab_lds = n <= kPowerTab;
-  if (tab_lds) {
-    for (int e = tid; e < n; e += NT) {
-      stab[e] = a.hxs[tb + n + e];
-      stab[kPowerTab + e] = a.ord[tb + n + e];
-      stab[2 * kPowerTab + e] = a.hxs[tb + 2 * n + e];
-      stab[3 * kPowerTab + e] = a.ord[tb + 2 * n + e];
-      stab[4 * kPowerTab + e] = a.hx[tb + e];
+  const cx<R> wt = wkg[tid < H / 2 ? tid : 0];
+  auto wk = [&](int q) -> cx<R> { return q == 0 ? wt : cmul(wt, wq[q]); };
+  if (tid == 0) pmid = Sm[H / 2];
+  for (int e = tid; e < n; e += NT) {
+    uint32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+    R uu = R(0);
+    if (tab_lds) {
+      t0 = a.hxs[tb + n + e];
+      t1 = a.ord[tb + n + e];
+      t2 = a.hxs[tb + 2 * n + e];
+      t3 = a.ord[tb + 2 * n + e];
+      t4 = a.hx[tb + e];
     }
+    if (!PRE) uu = a.Uprev[(size_t)tau * n + e];
+    if (tab_lds) {
+      stab[e] = t0;
+      stab[n + e] = t1;
+      stab[2 * n + e] = t2;
+      stab[3 * n + e] = t3;
+      stab[4 * n + e] = t4;
+    }
+    if (!PRE) u[e] = uu;
   }
-  for (int t = tid; t < TWL; t += NT) twl[t] = a.twg[t];
-  const Twid<R> tw{a.twg, a.twg + pass_table_len(H, NT), twl};
-  __syncthreads();  // staged tables visible
+  const bool staged = PRE && median_chunk(n, B, 2 * PL) == n;
+  if (staged) copy_to_lds<NT, 4>(re, a.Vprev + (size_t)tau * B * n, B * n);
+  const Twid<R> tw{a.twg, wkg};
+  __syncthreads();  // staged tables, u or the estimates visible
 
   if constexpr (PRE) {
-    const bool ok = median_prologue<R, NT>(a.Vprev, a.Uprev, tau, n, B, u, re, 2 * PL, red);
+    const bool ok = median_prologue<R, NT>(a.Vprev, a.Uprev, tau, n, B, u, re, 2 * PL, red, staged);
     if (m == 0) {
       for (int i = tid; i < n; i += NT) a.Ucur[(size_t)tau * n + i] = u[i];
       if (tid == 0 && !ok && a.flags) a.flags[tau] |= 1;
     }
-  } else {
-    for (int i = tid; i < n; i += NT) u[i] = a.Uprev[(size_t)tau * n + i];
-    __syncthreads();
   }
 
   auto getu = [&](uint32_t i) -> R { return u[i]; };
   auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
 #pragma unroll 1
   for (int mode_j = 1; mode_j <= 2; ++mode_j) {
-    for (int t = tid; t < PL; t += NT) {
-      re[t] = R(0);
-      im[t] = R(0);
-    }
+    zero_lds<NT>(re, 2 * PL * (int)sizeof(R));
     __syncthreads();
     if (tab_lds)
-      count_sketch<R>(stab + (mode_j - 1) * 2 * kPowerTab, stab + (mode_j - 1) * 2 * kPowerTab + kPowerTab,
-                      n, NT, getu, store);
+      count_sketch<R>(stab + (mode_j - 1) * 2 * n, stab + (mode_j - 1) * 2 * n + n, n, NT, getu, store);
     else
       count_sketch<R>(a.hxs + tb + (size_t)mode_j * n, a.ord + tb + (size_t)mode_j * n, n, NT, getu,
                       store);
     __syncthreads();
-    fft_soa<R, LOGH, NT, false, TWL>(buf, tw);
+    fft_soa<R, LOGH, NT, false, false>(buf, tw);
+    // Opaque thread index: the pair indices are recomputed here rather than
+    // kept live (or spilled) from the loads at the start.
+    int ot = threadIdx.x;
+    asm volatile("" : "+v"(ot));
 #pragma unroll
     for (int q = 0; q < PK; ++q) {
-      const int k = tid + q * NT;
+      const int k = ot + q * NT;
       if (!FULL && k >= H / 2) break;
+      const cx<R> w0 = wk(q);
+      const cx<R> w1 = {-w0.x, w0.y};
       const cx<R> Za = buf.get(k);
       const cx<R> Zb = buf.get((H - k) & (H - 1));
-      p0[q] = cmulc(p0[q], r2c_post(Za, Zb, w0[q]));
-      p1[q] = cmulc(p1[q], r2c_post(Zb, Za, w1[q]));
+      p0[q] = cmulc(p0[q], r2c_post(Za, Zb, w0));
+      p1[q] = cmulc(p1[q], r2c_post(Zb, Za, w1));
     }
     if (tid == 0) {
       const cx<R> Z = buf.get(H / 2);
-      pmid = cmulc(pmid, r2c_post(Z, Z, wmid));
+      pmid = cmulc(pmid, r2c_post(Z, Z, cx<R>{R(0), R(-1)}));
     }
     __syncthreads();
   }
   // Half-length packing of the real inverse transform of P.
+  int ot = threadIdx.x;
+  asm volatile("" : "+v"(ot));
 #pragma unroll
   for (int q = 0; q < PK; ++q) {
-    const int k = tid + q * NT;
+    const int k = ot + q * NT;
     if (!FULL && k >= H / 2) break;
-    buf.put(k, c2r_pack(p0[q], p1[q], w0[q]));
-    if (k > 0) buf.put(H - k, c2r_pack(p1[q], p0[q], w1[q]));
+    const cx<R> w0 = wk(q);
+    const cx<R> w1 = {-w0.x, w0.y};
+    buf.put(k, c2r_pack(p0[q], p1[q], w0));
+    if (k > 0) buf.put(H - k, c2r_pack(p1[q], p0[q], w1));
   }
-  if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, wmid));
+  if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, cx<R>{R(0), R(-1)}));
   __syncthreads();
-  fft_soa<R, LOGH, NT, true, TWL>(buf, tw);
+  fft_soa<R, LOGH, NT, true, false>(buf, tw);
 
   const R scale = R(2) / R(b);
   const uint32_t* hx1 = a.hx + tb;
   R* Vrow = a.V + ((size_t)tau * B + m) * n;
   double acc = 0.0;
   for (int i = tid; i < n; i += NT) {
-    const uint32_t e = tab_lds ? stab[4 * kPowerTab + i] : hx1[i];
+    const uint32_t e = tab_lds ? stab[4 * n + i] : hx1[i];
     const R val = load_packed(buf, e >> 1) * scale;
     const R v = (e & 1u) ? -val : val;
     Vrow[i] = v;
@@ -416,7 +457,7 @@ __global__ __launch_bounds__(256) void k_median_norm(const R* V, const R* Uin, R
   __shared__ double red[4];
   const int tau = blockIdx.x;
   R* u = Uout + (size_t)tau * n;  // the prologue writes u in place
-  const bool ok = median_prologue<R, 256>(V, Uin, tau, n, B, u, stage, 4096, red);
+  const bool ok = median_prologue<R, 256>(V, Uin, tau, n, B, u, stage, 4096, red, false);
   if (threadIdx.x == 0 && !ok && flags) flags[tau] |= 1;
 }
 
@@ -465,7 +506,7 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_rank1(Rank1
   const int r = blockIdx.y;
   const int n = a.n;
   const double* u = a.U + (size_t)r * n;
-  const Twid<double> tw{a.twg, a.twg + pass_table_len(H, NT), nullptr};
+  const Twid<double> tw{a.twg, a.twg + pass_table_len(H, NT)};
   cx<double> p0[PK], p1[PK], pmid;
   auto getu = [&](uint32_t i) -> double { return u[i]; };
   auto store = [&](uint32_t t, double v) { store_packed(buf, t, v); };
@@ -559,7 +600,7 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_r2c64(const
   double* im = re + PL;
   const Soa<double> buf{re, im};
   const int m = blockIdx.x;
-  const Twid<double> tw{twg, twg + pass_table_len(H, NT), nullptr};
+  const Twid<double> tw{twg, twg + pass_table_len(H, NT)};
   const cx<double>* src = reinterpret_cast<const cx<double>*>(s_time + (size_t)m * b);
   for (int t = threadIdx.x; t < H; t += NT) buf.put(t, src[t]);
   __syncthreads();
@@ -586,7 +627,7 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_c2r64(const
   double* im = re + PL;
   const Soa<double> buf{re, im};
   const int m = blockIdx.x;
-  const Twid<double> tw{twg, twg + pass_table_len(H, NT), nullptr};
+  const Twid<double> tw{twg, twg + pass_table_len(H, NT)};
   const cx<double>* S = S64 + (size_t)m * (H + 1);
   for (int k = threadIdx.x; k < H; k += NT) buf.put(k, c2r_pack(S[k], S[H - k], tw.w(k)));
   __syncthreads();

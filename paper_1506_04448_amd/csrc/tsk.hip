@@ -1,6 +1,8 @@
 // Host side of the C ABI: context, tables, validation, kernel launches and
 // the decompose loop (recorded into a HIP graph once per shape).
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <math.h>
 #include <string.h>
 
@@ -142,7 +144,7 @@ tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out) {
   auto it = mp.find(logb);
   if (it == mp.end()) {
     const int b = 1 << logb, H = b / 2;
-    const int NT = tsk::threads_for_h<R>(logb - 1);
+    const int NT = tsk::power_threads<R>(logb - 1);
     const int rmax = tsk::fft_rmax(H, NT);
     const int plen = tsk::pass_table_len(H, NT);
     std::vector<cx<R>> h(tsk::twid_len(H, NT));
@@ -185,18 +187,53 @@ tsk_status check_launch(const char* what) {
 
 // ---- launch helpers dispatching on log2 b -----------------------------------
 
-template <typename R, int LOGB>
-tsk_status launch_power_t(const tsk::PowerArgs<R>& a, int B, int nrest, hipStream_t st) {
-  constexpr int NT = tsk::threads_for_h<R>(LOGB - 1);
-  constexpr int NU = tsk::power_max_n<R, LOGB>();
-  if (a.n > NU)
-    return tsk::fail(TSK_EUNSUPPORTED, "power step: n=%d exceeds %d at b=2^%d in this precision",
-                     a.n, NU, LOGB);
-  if (a.prefix)
-    hipLaunchKernelGGL((tsk::k_power<R, LOGB, true>), dim3(B, nrest), dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((tsk::k_power<R, LOGB, false>), dim3(B, nrest), dim3(NT), 0, st, a);
+// LDS of one CU on gfx950, the most one work-group can use.
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <typename R, int LOGB, bool PRE>
+tsk_status launch_power_v(const tsk::PowerArgs<R>& a, size_t lds, int B, int nrest, hipStream_t st) {
+  constexpr int NT = tsk::power_threads<R>(LOGB - 1);
+  // Allow the full LDS as dynamic shared memory, once per device and kernel.
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_power<R, LOGB, PRE>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL((tsk::k_power<R, LOGB, PRE>), dim3(B, nrest), dim3(NT), lds, st, a);
   return check_launch("k_power");
+}
+
+// LDS plan of a power step: table rows in LDS when two work-groups still fit
+// a CU with them (or one fits only with them), else without; n too large
+// for the vector alone is unsupported.
+template <typename R>
+tsk_status power_lds_plan(int logb, int n, size_t* bytes, int* tab) {
+  const size_t with = tsk::power_lds_bytes<R>(logb - 1, n, true);
+  const size_t without = tsk::power_lds_bytes<R>(logb - 1, n, false);
+  if (with <= kMaxLds / 2 || (without > kMaxLds / 2 && with <= kMaxLds)) {
+    *bytes = with;
+    *tab = 1;
+  } else if (without <= kMaxLds) {
+    *bytes = without;
+    *tab = 0;
+  } else {
+    return tsk::fail(TSK_EUNSUPPORTED,
+                     "power step: n=%d needs %zu bytes of LDS at b=2^%d in this precision (max %zu)", n,
+                     without, logb, kMaxLds);
+  }
+  return TSK_OK;
+}
+
+template <typename R, int LOGB>
+tsk_status launch_power_t(tsk::PowerArgs<R> a, int B, int nrest, hipStream_t st) {
+  size_t lds = 0;
+  TSK_TRY(power_lds_plan<R>(LOGB, a.n, &lds, &a.tab_lds));
+  if (a.prefix) return launch_power_v<R, LOGB, true>(a, lds, B, nrest, st);
+  return launch_power_v<R, LOGB, false>(a, lds, B, nrest, st);
 }
 
 template <typename R>
