@@ -15,6 +15,9 @@ Pinned by the ``-m "not gpu"`` tests in ``tests/test_oracle_*.py`` (identities
 of Eq. (2) and Proposition 1, the injective-hash special case that reduces
 every estimate to the exact dense contraction, unbiasedness by full
 enumeration of hash draws, exact recovery of planted orthogonal components).
+The gradients of the sketched T(u,u,u) estimate and of the sketched CP loss
+(``gradients``) are pinned by central finite differences and by the
+injective-hash reduction to the dense gradient.
 Parity unpinned: the full sketched power method beyond those pins (the paper
 prints no worked example to compare against).
 """
@@ -25,6 +28,7 @@ from .sketch import (count_sketch, sketch_dense, circular_convolution,
 from .contract import (median, power_update_sketch, power_update_direct,
                        tuuu_sketch, tuuu_direct, power_update, contract_uuu)
 from .rtpm import rtpm_sketched, rtpm_dense, RtpmResult
+from . import gradients
 from .dense import (dense_Tuuu, dense_TIuu, residual_dense, residual_factored,
                     wrong_vectors)
 
@@ -35,5 +39,5 @@ __all__ = [
     "median", "power_update_sketch", "power_update_direct", "tuuu_sketch",
     "tuuu_direct", "power_update", "contract_uuu",
     "rtpm_sketched", "rtpm_dense", "RtpmResult",
-    "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
+    "gradients", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
 ]

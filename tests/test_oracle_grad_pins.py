@@ -1,0 +1,144 @@
+"""Pins for the oracle's gradients of the sketched objectives (T(u,u,u) and the
+sketched CP loss), against what the mathematics fixes:
+
+  * the permuted read-off through FFTs equals its definition (the derivative
+    of the triple product along one mode) computed by direct convolution;
+  * central finite differences of the objectives themselves;
+  * the injective-hash special case (h_1(i)=i, h_2(j)=n j, h_3(k)=n^2 k,
+    b >= n^3): the sketch is a signed permutation of the tensor, so the
+    sketched CP loss equals the dense loss ||T - sum_i lam_i u_i^(x)3||^2 and
+    its gradient the dense gradient (einsum), and the gradient of the
+    T(u,u,u) estimate equals T(I,u,u) + T(u,I,u) + T(u,u,I), for a
+    non-symmetric T too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import gradients as G
+
+
+def _rand_tables(rng, n, b, B):
+    h = rng.integers(0, b, size=(B, 3, n)).astype(np.uint32)
+    xi = rng.choice(np.array([-1, 1], dtype=np.int8), size=(B, 3, n))
+    return h, xi
+
+
+def _identity_tables(n, b, B, rng):
+    h = np.zeros((B, 3, n), dtype=np.uint32)
+    h[:, 0] = np.arange(n)
+    h[:, 1] = n * np.arange(n)
+    h[:, 2] = n * n * np.arange(n)
+    assert h[:, 0].max() + h[:, 1].max() + h[:, 2].max() < b
+    xi = rng.choice(np.array([-1, 1], dtype=np.int8), size=(B, 3, n))
+    return h, xi
+
+
+@pytest.mark.parametrize("j", [0, 1, 2])
+def test_permuted_readoff_equals_definition(j):
+    rng = np.random.default_rng(11 + j)
+    n, b = 9, 32
+    h, xi = _rand_tables(rng, n, b, 1)
+    s = rng.standard_normal(b)
+    u = rng.standard_normal(n)
+    np.testing.assert_allclose(G.read_off_mode(s, h[0], xi[0], u, j),
+                               G.read_off_mode_direct(s, h[0], xi[0], u, j), atol=1e-12)
+    if j == 0:  # mode 1 is Proposition 1's read-off
+        np.testing.assert_allclose(G.read_off_mode(s, h[0], xi[0], u, 0),
+                                   oracle.power_update_sketch(s, h[0], xi[0], u), atol=1e-12)
+
+
+def test_triple_product_grad_finite_differences():
+    rng = np.random.default_rng(3)
+    n, b = 7, 64
+    h, xi = _rand_tables(rng, n, b, 1)
+    s = rng.standard_normal(b)
+    u = rng.standard_normal(n)
+    g = G.triple_product_grad(s, h[0], xi[0], u)
+    eps = 1e-6
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = eps
+        fd = (G.triple_product(s, h[0], xi[0], u + e) - G.triple_product(s, h[0], xi[0], u - e)) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i]))
+
+
+def test_median_gradient_is_the_selected_sketch():
+    rng = np.random.default_rng(4)
+    n, b, B, L = 6, 64, 5, 3
+    h, xi = _rand_tables(rng, n, b, B)
+    S = rng.standard_normal((B, b))
+    U = rng.standard_normal((L, n))
+    f_med, f_per, grad = G.tuuu_with_grad(S, h, xi, U)
+    eps = 1e-6
+    for tau in range(L):
+        for i in range(n):
+            e = np.zeros(n)
+            e[i] = eps
+            fp = np.median([G.triple_product(S[m], h[m], xi[m], U[tau] + e) for m in range(B)])
+            fm = np.median([G.triple_product(S[m], h[m], xi[m], U[tau] - e) for m in range(B)])
+            assert abs((fp - fm) / (2 * eps) - grad[tau, i]) <= 1e-6 * max(1.0, abs(grad[tau, i]))
+    # even B: the mean of the two middle sketches
+    Se, he, xie = S[:4], h[:4], xi[:4]
+    f_med, f_per, grad = G.tuuu_with_grad(Se, he, xie, U)
+    for tau in range(L):
+        order = np.argsort(f_per[tau])
+        g2 = 0.5 * (G.triple_product_grad(Se[order[1]], he[order[1]], xie[order[1]], U[tau])
+                    + G.triple_product_grad(Se[order[2]], he[order[2]], xie[order[2]], U[tau]))
+        np.testing.assert_allclose(grad[tau], g2, atol=1e-12)
+        assert f_med[tau] == pytest.approx(0.5 * (f_per[tau, order[1]] + f_per[tau, order[2]]))
+
+
+def test_cp_loss_grad_finite_differences():
+    rng = np.random.default_rng(6)
+    n, b, B, k = 6, 64, 3, 2
+    h, xi = _rand_tables(rng, n, b, B)
+    S = rng.standard_normal((B, b))
+    lam = rng.uniform(0.5, 2.0, k)
+    U = rng.standard_normal((k, n))
+    loss, g_lam, g_U = G.cp_loss_grad(S, h, xi, lam, U)
+    assert loss == pytest.approx(G.cp_loss(S, h, xi, lam, U))
+    eps = 1e-6
+    for i in range(k):
+        d = np.zeros(k)
+        d[i] = eps
+        fd = (G.cp_loss(S, h, xi, lam + d, U) - G.cp_loss(S, h, xi, lam - d, U)) / (2 * eps)
+        assert abs(fd - g_lam[i]) <= 1e-6 * max(1.0, abs(g_lam[i]))
+        for c in range(n):
+            E = np.zeros((k, n))
+            E[i, c] = eps
+            fd = (G.cp_loss(S, h, xi, lam, U + E) - G.cp_loss(S, h, xi, lam, U - E)) / (2 * eps)
+            assert abs(fd - g_U[i, c]) <= 1e-6 * max(1.0, abs(g_U[i, c]))
+
+
+def test_injective_hash_cp_loss_and_gradient_equal_dense():
+    n, b, B, k = 6, 256, 2, 3
+    rng = np.random.default_rng(8)
+    T = rng.standard_normal((n, n, n))
+    T = (T + T.transpose(1, 0, 2) + T.transpose(2, 1, 0) + T.transpose(0, 2, 1)
+         + T.transpose(1, 2, 0) + T.transpose(2, 0, 1)) / 6.0
+    h, xi = _identity_tables(n, b, B, rng)
+    S = np.stack([oracle.sketch_dense(T, h[m], xi[m], b) for m in range(B)])
+    lam = rng.uniform(0.5, 2.0, k)
+    U = rng.standard_normal((k, n))
+    loss, g_lam, g_U = G.cp_loss_grad(S, h, xi, lam, U)
+    R = T - np.einsum("r,ri,rj,rk->ijk", lam, U, U, U)
+    assert loss == pytest.approx(float(np.sum(R * R)), rel=1e-12)
+    np.testing.assert_allclose(g_lam, -2.0 * np.einsum("ijk,ri,rj,rk->r", R, U, U, U), atol=1e-10)
+    dense_gU = -2.0 * lam[:, None] * (np.einsum("ijk,rj,rk->ri", R, U, U)
+                                      + np.einsum("ijk,ri,rk->rj", R, U, U)
+                                      + np.einsum("ijk,ri,rj->rk", R, U, U))
+    np.testing.assert_allclose(g_U, dense_gU, atol=1e-10)
+
+
+def test_injective_hash_tuuu_gradient_equals_dense_nonsymmetric():
+    n, b = 5, 128
+    rng = np.random.default_rng(10)
+    T = rng.standard_normal((n, n, n))  # not symmetric: all three terms differ
+    h, xi = _identity_tables(n, b, 1, rng)
+    s = oracle.sketch_dense(T, h[0], xi[0], b)
+    u = rng.standard_normal(n)
+    dense = (np.einsum("ijk,j,k->i", T, u, u) + np.einsum("ijk,i,k->j", T, u, u)
+             + np.einsum("ijk,i,j->k", T, u, u))
+    np.testing.assert_allclose(G.triple_product_grad(s, h[0], xi[0], u), dense, atol=1e-11)
+    assert G.triple_product(s, h[0], xi[0], u) == pytest.approx(np.einsum("ijk,i,j,k->", T, u, u, u))
