@@ -158,6 +158,40 @@ tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
                             const double* S64, const float* S32, int L, const void* U,
                             double* lam_med, double* lam_per, void* stream);
 
+/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
+ * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the
+ * T(u,u,u) estimate of Eq. (3), and its gradient.  Each count sketch is linear
+ * in u, so
+ *   d f^(m) / d u_i = sum_j xi_j(i) corr(s^(m), s_a(u) * s_b(u))[h_j(i)]
+ * ({a, b} the two other modes): every term is the read-off of Proposition 1
+ * with mode j in the place of mode 1.  The median's gradient is that of the
+ * sketch it selects (even B: the mean of the two middle sketches; ranks break
+ * ties by sketch index).
+ *   U: [L][n] in dtype.  scale: nullable [L] in dtype, multiplies grad[tau].
+ *   f_med: double[L].  f_per: nullable double[L][B].  grad: [L][n] in dtype.
+ * Errors as tsk_power_update. */
+tsk_status tsk_contract_tuuu_grad(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                  const double* S64, const float* S32, int L, const void* U,
+                                  const void* scale, double* f_med, double* f_per, void* grad,
+                                  void* stream);
+
+/* Sketched CP loss: the least-squares objective of the CP decomposition
+ * (Section 2) measured through the B sketches, using their linearity
+ * (Section 3.1):
+ *   r^(m) = s^(m)(T) - sum_i lam_i s^(m)(u_i (x) u_i (x) u_i)
+ *   loss  = (1/B) sum_m ||r^(m)||^2
+ *   d loss / d lam_i = -(2/B) sum_m <r^(m), s^(m)(u_i (x) u_i (x) u_i)>
+ *   d loss / d u_i   = -(2/B) lam_i sum_m sum_j xi_j corr(r^(m), s_a(u_i) * s_b(u_i))[h_j]
+ * S64: sketches of T (read only).  lam: [k], U: [k][n] in dtype.  scale:
+ * nullable device scalar in dtype multiplying both gradients.  loss: double[1].
+ * grad_lam: nullable [k], grad_U: nullable [k][n], in dtype; with both NULL
+ * only the loss is computed.  The residual spectra are formed in FP64 (FP32
+ * inputs are widened first); the gradient read-offs run in dtype.
+ * Errors: TSK_EINVAL (null S64/lam/U/loss, k outside [1, 65535], dtype). */
+tsk_status tsk_cp_loss(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const double* S64, int k,
+                       const void* lam, const void* U, const void* scale, double* loss,
+                       void* grad_lam, void* grad_U, void* stream);
+
 /* ---- Decomposition --------------------------------------------------------
  * Algorithm 1 for k components: per component, L restarts x T power steps on
  * the sketches (all restarts and sketches batched in each launch), selection

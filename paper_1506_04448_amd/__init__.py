@@ -19,7 +19,7 @@ __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
     "sketch_export", "sketch_deflate", "power_update", "contract_tiuu", "contract_uuu",
-    "decompose",
+    "decompose", "contract_tuuu_grad", "cp_loss",
     "F32", "F64",
 ]
 
@@ -62,6 +62,8 @@ _SIGS = {
     "tsk_contract_uuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_contract_tiuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P], _I),
     "tsk_decompose": ([_P, _P, _I, _P, _P, _I, _I, _I, _P, _U64, _P, _P, _P, _P, _I, _P], _I),
+    "tsk_contract_tuuu_grad": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P], _I),
+    "tsk_cp_loss": ([_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P], _I),
 }
 
 
@@ -347,3 +349,45 @@ def decompose(ctx, tab, S64, S32, k, L, T, dtype=F32, u0=None, seed=0, plain=Fal
         seed & (2 ** 64 - 1), _ptr(lam_out), _ptr(U_out), _ptr(tau_out), _ptr(flags_out),
         int(bool(plain)), _stream(stream)))
     return lam_out, U_out, tau_out, flags_out
+
+
+def contract_tuuu_grad(ctx, tab, U, S64=None, S32=None, scale=None, f_per=None, stream=None):
+    """f(u) = med_m T(u,u,u)^(m) and its gradient for U [L][n].
+    Returns (f_med [L] f64, f_per [L][B] f64, grad [L][n] in U's dtype); ``scale``
+    ([L], U's dtype) multiplies each row of the gradient."""
+    import torch
+    dt, tdt = _vdtype(U.dtype)
+    L = U.shape[0]
+    _tensor(U, "U", tdt, (L, tab.n))
+    _tensor(scale, "scale", tdt, (L,), allow_none=True)
+    _spectra(tab, dt, S64, S32)
+    f_med = torch.empty((L,), dtype=torch.float64, device=U.device)
+    if f_per is None:
+        f_per = torch.empty((L, tab.B), dtype=torch.float64, device=U.device)
+    _tensor(f_per, "f_per", torch.float64, (L, tab.B))
+    grad = torch.empty_like(U)
+    _check("tsk_contract_tuuu_grad", lib().tsk_contract_tuuu_grad(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U), _ptr(scale), _ptr(f_med),
+        _ptr(f_per), _ptr(grad), _stream(stream)))
+    return f_med, f_per, grad
+
+
+def cp_loss(ctx, tab, S64, lam, U, scale=None, grads=True, stream=None):
+    """Sketched CP loss (1/B) sum_m ||s^(m)(T) - sum_i lam_i s^(m)(u_i^(x)3)||^2 and,
+    with ``grads``, its gradients.  lam [k], U [k][n] (float32 or float64);
+    ``scale`` (one element, same dtype) multiplies the gradients.
+    Returns (loss 0-d f64, grad_lam or None, grad_U or None)."""
+    import torch
+    dt, tdt = _vdtype(U.dtype)
+    k = U.shape[0]
+    _tensor(S64, "S64", torch.float64, (tab.B, tab.b // 2 + 1, 2))
+    _tensor(lam, "lam", tdt, (k,))
+    _tensor(U, "U", tdt, (k, tab.n))
+    _tensor(scale, "scale", tdt, (1,), allow_none=True)
+    loss = torch.empty((), dtype=torch.float64, device=U.device)
+    g_lam = torch.empty_like(lam) if grads else None
+    g_U = torch.empty_like(U) if grads else None
+    _check("tsk_cp_loss", lib().tsk_cp_loss(
+        ctx.handle, tab.handle, dt, _ptr(S64), k, _ptr(lam), _ptr(U), _ptr(scale), _ptr(loss),
+        _ptr(g_lam), _ptr(g_U), _stream(stream)))
+    return loss, g_lam, g_U

@@ -278,6 +278,8 @@ __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict
 //   A_k   = S_k conj(F(s2 u)_k);   P_k = A_k conj(F(s3 u)_k)
 //   sbar  = F^-1(P);  v_i = xi1(i) sbar[h1(i)]  -> V[tau][m]
 //   mode 1 also writes lam_per[tau][m] = u . v.
+// With the modes permuted (rd, sa, sb) the same read-off is the derivative of
+// <s, s_1(u) * s_2(u) * s_3(u)> along mode rd.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct PowerArgs {
@@ -297,6 +299,8 @@ struct PowerArgs {
   int prefix;           // median prologue (selects the PRE instantiation)
   int mode;
   int tab_lds;          // table rows staged in LDS (power_lds_bytes with tab)
+  int rd, sa, sb;       // table modes of the read-off and of the two count sketches
+                        // (0, 1, 2 for Proposition 1; permuted for gradients)
 };
 
 // PRE selects the median prologue (u from Vprev) at compile time; the two
@@ -353,11 +357,11 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
     uint32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
     R uu = R(0);
     if (tab_lds) {
-      t0 = a.hxs[tb + n + e];
-      t1 = a.ord[tb + n + e];
-      t2 = a.hxs[tb + 2 * n + e];
-      t3 = a.ord[tb + 2 * n + e];
-      t4 = a.hx[tb + e];
+      t0 = a.hxs[tb + (size_t)a.sa * n + e];
+      t1 = a.ord[tb + (size_t)a.sa * n + e];
+      t2 = a.hxs[tb + (size_t)a.sb * n + e];
+      t3 = a.ord[tb + (size_t)a.sb * n + e];
+      t4 = a.hx[tb + (size_t)a.rd * n + e];
     }
     if (!PRE) uu = a.Uprev[(size_t)tau * n + e];
     if (tab_lds) {
@@ -391,8 +395,8 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
     if (tab_lds)
       count_sketch<R>(stab + (mode_j - 1) * 2 * n, stab + (mode_j - 1) * 2 * n + n, n, NT, getu, store);
     else
-      count_sketch<R>(a.hxs + tb + (size_t)mode_j * n, a.ord + tb + (size_t)mode_j * n, n, NT, getu,
-                      store);
+      count_sketch<R>(a.hxs + tb + (size_t)(mode_j == 1 ? a.sa : a.sb) * n,
+                      a.ord + tb + (size_t)(mode_j == 1 ? a.sa : a.sb) * n, n, NT, getu, store);
     __syncthreads();
     fft_soa<R, LOGH, NT, false, false>(buf, tw);
     // Opaque thread index: the pair indices are recomputed here rather than
@@ -433,7 +437,7 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   fft_soa<R, LOGH, NT, true, false>(buf, tw);
 
   const R scale = R(2) / R(b);
-  const uint32_t* hx1 = a.hx + tb;
+  const uint32_t* hx1 = a.hx + tb + (size_t)a.rd * n;
   R* Vrow = a.V + ((size_t)tau * B + m) * n;
   double acc = 0.0;
   for (int i = tid; i < n; i += NT) {
@@ -895,6 +899,104 @@ __global__ void k_cvt(const double* src, R* dst, size_t count) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
        e += (size_t)gridDim.x * blockDim.x)
     dst[e] = (R)src[e];
+}
+
+template <typename R>
+__global__ void k_widen(const R* src, double* dst, size_t count) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = (double)src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of f(u) = med_m <s^(m), s^(m)(u (x) u (x) u)>, one work-group per
+// restart: the median's members (rank (B-1)/2, and B/2 for even B, ties by
+// sketch index) and grad = scale * mean over the members of the sum of the
+// three mode read-offs V0 + V1 + V2 ([L][B][n] each).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_tuuu_grad(const double* lam_per, const R* V0, const R* V1,
+                                                   const R* V2, const R* scale, int n, int B,
+                                                   double* f_med, R* grad) {
+  __shared__ int sel[2];
+  __shared__ int any_nan;
+  const int tau = blockIdx.x;
+  const double* lp = lam_per + (size_t)tau * B;
+  if (threadIdx.x == 0) {
+    sel[0] = 0;
+    sel[1] = 0;
+    any_nan = 0;
+  }
+  __syncthreads();
+  const int ra = (B - 1) / 2, rb = B / 2;
+  for (int m = threadIdx.x; m < B; m += blockDim.x) {
+    const double x = lp[m];
+    int r = 0;
+    for (int j = 0; j < B; ++j) r += (lp[j] < x) || (lp[j] == x && j < m);
+    if (r == ra) sel[0] = m;
+    if (r == rb) sel[1] = m;
+    if (__builtin_isnan(x)) any_nan = 1;
+  }
+  __syncthreads();
+  const int m0 = sel[0], m1 = sel[1];
+  const bool two = (B & 1) == 0;
+  if (threadIdx.x == 0)
+    f_med[tau] = any_nan ? __builtin_nan("") : (two ? 0.5 * (lp[m0] + lp[m1]) : lp[m0]);
+  const double sc = (scale ? (double)scale[tau] : 1.0) * (two ? 0.5 : 1.0);
+  const size_t r0 = ((size_t)tau * B + m0) * n, r1 = ((size_t)tau * B + m1) * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double g = (double)V0[r0 + i] + (double)V1[r0 + i] + (double)V2[r0 + i];
+    if (two) g += (double)V0[r1 + i] + (double)V1[r1 + i] + (double)V2[r1 + i];
+    grad[(size_t)tau * n + i] = (R)(sc * g);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketched CP loss from the residual spectra R = S - sum_i lam_i prod_j F(s_j u_i):
+// loss = (1/B) sum_m ||r^(m)||^2 = (1/(B b)) sum_m sum_k w_k |R_k|^2 (Parseval
+// on the half spectrum: w = 1 at k = 0 and k = b/2, 2 elsewhere).  One
+// work-group; fixed reduction order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_parseval_loss(const cx<double>* R64, int B, int b,
+                                                        double* loss) {
+  __shared__ double red[16];
+  const int H1 = b / 2 + 1;
+  double acc = 0.0;
+  for (size_t e = threadIdx.x; e < (size_t)B * H1; e += 1024) {
+    const int k = (int)(e % H1);
+    const cx<double> z = R64[e];
+    const double w = (k == 0 || k == H1 - 1) ? 1.0 : 2.0;
+    acc += w * (z.x * z.x + z.y * z.y);
+  }
+  const double s = block_sum<1024>(acc, red);
+  if (threadIdx.x == 0) loss[0] = s / ((double)B * (double)b);
+}
+
+// Gradients of the sketched CP loss, one work-group per component i:
+//   grad_lam[i] = -(2/B) scale sum_m lam_per[i][m]        (lam_per = <r^(m), s^(m)(u_i^(x)3)>)
+//   grad_U[i]   = -(2/B) scale lam_i sum_m (V0 + V1 + V2)[i][m]
+template <typename R>
+__global__ __launch_bounds__(256) void k_cp_grad(const double* lam_per, const R* V0, const R* V1,
+                                                 const R* V2, const R* lam, const R* scale, int n,
+                                                 int B, R* grad_lam, R* grad_U) {
+  const int i = blockIdx.x;
+  const double sc = (scale ? (double)scale[0] : 1.0) * (-2.0 / (double)B);
+  if (grad_lam && threadIdx.x == 0) {
+    double g = 0.0;
+    for (int m = 0; m < B; ++m) g += lam_per[(size_t)i * B + m];
+    grad_lam[i] = (R)(sc * g);
+  }
+  if (grad_U) {
+    const double f = sc * (double)lam[i];
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      double g = 0.0;
+      for (int m = 0; m < B; ++m) {
+        const size_t o = ((size_t)i * B + m) * n + c;
+        g += (double)V0[o] + (double)V1[o] + (double)V2[o];
+      }
+      grad_U[(size_t)i * n + c] = (R)(f * g);
+    }
+  }
 }
 
 __global__ void k_fill_u32(unsigned* p, unsigned v, size_t count) {

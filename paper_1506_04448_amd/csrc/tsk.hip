@@ -84,7 +84,7 @@ namespace {
 
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
-  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX
+  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -623,7 +623,7 @@ namespace {
 template <typename R>
 tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0,
                         int prefix, int mode, const R* Uprev, const R* Vprev, R* Ucur,
-                        int32_t* flags, R* V, double* lam_per, hipStream_t st) {
+                        int32_t* flags, R* V, double* lam_per, hipStream_t st, int perm = 0) {
   const cx<R>* tw = nullptr;
   TSK_TRY(get_tw<R>(ctx, tab->logb, &tw));
   tsk::PowerArgs<R> a;
@@ -643,6 +643,10 @@ tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int n
   a.tau0 = tau0;
   a.prefix = prefix;
   a.mode = mode;
+  a.tab_lds = 0;
+  a.rd = perm;
+  a.sa = (perm + 1) % 3;
+  a.sb = (perm + 2) % 3;
   return launch_power<R>(tab->logb, a, tab->B, nrest, st);
 }
 
@@ -728,6 +732,110 @@ extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
     TSK_TRY(power_launch<double>(ctx, tab, S64, L, 0, 0, 1, (const double*)U, nullptr, nullptr,
                                  nullptr, (double*)vbuf, (double*)lp, S(stream)));
   return lam_median_launch((const double*)lp, lam_med, L, tab->B, S(stream));
+}
+
+// =============================================================================
+// Gradients (extensions built on Eq. (3) and Proposition 1)
+// =============================================================================
+
+namespace {
+
+// The three mode read-offs of every (vector, sketch) pair into V3[3][L][B][n];
+// the mode-1 launch also writes lam_per[L][B] = <s^(m), s^(m)(u^(x)3)>.
+template <typename R>
+tsk_status three_readoffs(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int L, const R* U,
+                          R* V3, double* lam_per, hipStream_t st) {
+  const size_t blk = (size_t)L * tab->B * tab->n;
+  for (int perm = 0; perm < 3; ++perm)
+    TSK_TRY(power_launch<R>(ctx, tab, spec, L, 0, 0, perm == 0 ? 1 : 0, U, nullptr, nullptr, nullptr,
+                            V3 + perm * blk, perm == 0 ? lam_per : nullptr, st, perm));
+  return TSK_OK;
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_contract_tuuu_grad(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                             const double* S64, const float* S32, int L,
+                                             const void* U, const void* scale, double* f_med,
+                                             double* f_per, void* grad, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_contract_tuuu_grad"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_contract_tuuu_grad"));
+  if (!U || !f_med || !grad) return tsk::fail(TSK_EINVAL, "tsk_contract_tuuu_grad: null U, f_med or grad");
+  TSK_TRY(set_device(ctx));
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  const size_t blk = (size_t)L * tab->B * tab->n;
+  void* v3 = nullptr;
+  TSK_TRY(ws_get(ctx, WS_V3, 3 * blk * es, &v3));
+  void* lp = f_per;
+  if (!lp) TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * tab->B * sizeof(double), &lp));
+  if (dtype == TSK_F32) {
+    float* V = (float*)v3;
+    TSK_TRY(three_readoffs<float>(ctx, tab, S32, L, (const float*)U, V, (double*)lp, S(stream)));
+    hipLaunchKernelGGL(tsk::k_tuuu_grad<float>, dim3(L), dim3(256), 0, S(stream), (const double*)lp, V,
+                       V + blk, V + 2 * blk, (const float*)scale, tab->n, tab->B, f_med, (float*)grad);
+  } else {
+    double* V = (double*)v3;
+    TSK_TRY(three_readoffs<double>(ctx, tab, S64, L, (const double*)U, V, (double*)lp, S(stream)));
+    hipLaunchKernelGGL(tsk::k_tuuu_grad<double>, dim3(L), dim3(256), 0, S(stream), (const double*)lp, V,
+                       V + blk, V + 2 * blk, (const double*)scale, tab->n, tab->B, f_med,
+                       (double*)grad);
+  }
+  return check_launch("k_tuuu_grad");
+}
+
+extern "C" tsk_status tsk_cp_loss(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const double* S64,
+                                  int k, const void* lam, const void* U, const void* scale,
+                                  double* loss, void* grad_lam, void* grad_U, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_cp_loss"));
+  if (dtype != TSK_F32 && dtype != TSK_F64) return tsk::fail(TSK_EINVAL, "tsk_cp_loss: bad dtype");
+  if (!S64 || !lam || !U || !loss) return tsk::fail(TSK_EINVAL, "tsk_cp_loss: null argument");
+  if (k < 1 || k > 65535) return tsk::fail(TSK_EINVAL, "tsk_cp_loss: k=%d outside [1, 65535]", k);
+  TSK_TRY(set_device(ctx));
+  const int B = tab->B, b = tab->b, n = tab->n;
+  const size_t H1 = (size_t)b / 2 + 1;
+  const hipStream_t st = S(stream);
+  void *r64 = nullptr, *r32 = nullptr;
+  TSK_TRY(ws_get(ctx, WS_R64, (size_t)B * H1 * sizeof(cx<double>), &r64));
+  if (dtype == TSK_F32) TSK_TRY(ws_get(ctx, WS_R32, (size_t)B * H1 * sizeof(cx<float>), &r32));
+  TSK_HIP(hipMemcpyAsync(r64, S64, (size_t)B * H1 * sizeof(cx<double>), hipMemcpyDeviceToDevice, st));
+  const double* lamd = (const double*)lam;
+  const double* Ud = (const double*)U;
+  if (dtype == TSK_F32) {
+    void *ld = nullptr, *ud = nullptr;
+    TSK_TRY(ws_get(ctx, WS_LAMD, (size_t)k * sizeof(double), &ld));
+    TSK_TRY(ws_get(ctx, WS_UD, (size_t)k * n * sizeof(double), &ud));
+    hipLaunchKernelGGL(tsk::k_widen<float>, dim3(grid_for((size_t)k, 256)), dim3(256), 0, st,
+                       (const float*)lam, (double*)ld, (size_t)k);
+    hipLaunchKernelGGL(tsk::k_widen<float>, dim3(grid_for((size_t)k * n, 256)), dim3(256), 0, st,
+                       (const float*)U, (double*)ud, (size_t)k * n);
+    TSK_TRY(check_launch("k_widen"));
+    lamd = (const double*)ld;
+    Ud = (const double*)ud;
+  }
+  // residual spectra R = S - sum_i lam_i prod_j F(s_j u_i), FP64 (and FP32 copy)
+  TSK_TRY(rank1_update(ctx, tab, lamd, Ud, k, -1.0, (double*)r64, (float*)r32, st));
+  hipLaunchKernelGGL(tsk::k_parseval_loss, dim3(1), dim3(1024), 0, st, (const cx<double>*)r64, B, b, loss);
+  TSK_TRY(check_launch("k_parseval_loss"));
+  if (!grad_lam && !grad_U) return TSK_OK;
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  const size_t blk = (size_t)k * B * n;
+  void *v3 = nullptr, *lp = nullptr;
+  TSK_TRY(ws_get(ctx, WS_V3, 3 * blk * es, &v3));
+  TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)k * B * sizeof(double), &lp));
+  if (dtype == TSK_F32) {
+    float* V = (float*)v3;
+    TSK_TRY(three_readoffs<float>(ctx, tab, r32, k, (const float*)U, V, (double*)lp, st));
+    hipLaunchKernelGGL(tsk::k_cp_grad<float>, dim3(k), dim3(256), 0, st, (const double*)lp, V, V + blk,
+                       V + 2 * blk, (const float*)lam, (const float*)scale, n, B, (float*)grad_lam,
+                       (float*)grad_U);
+  } else {
+    double* V = (double*)v3;
+    TSK_TRY(three_readoffs<double>(ctx, tab, r64, k, (const double*)U, V, (double*)lp, st));
+    hipLaunchKernelGGL(tsk::k_cp_grad<double>, dim3(k), dim3(256), 0, st, (const double*)lp, V, V + blk,
+                       V + 2 * blk, (const double*)lam, (const double*)scale, n, B, (double*)grad_lam,
+                       (double*)grad_U);
+  }
+  return check_launch("k_cp_grad");
 }
 
 // =============================================================================
