@@ -213,6 +213,35 @@ tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
                          double* U_out, int32_t* tau_out, int32_t* flags_out,
                          int plain, void* stream);
 
+/* One instance of a batched decomposition: the arguments of tsk_decompose
+ * (pointers inside are device pointers, owned by the caller; plain = 0). */
+typedef struct {
+  tsk_tables_t tab;     /* the instance's tables (created on the same context) */
+  tsk_dtype dtype;      /* precision of its power steps */
+  double* S64;          /* its sketches, deflated in place */
+  float* S32;
+  int k, L, T;
+  const double* u0;     /* nullable double[k][L][n] */
+  uint64_t seed;        /* start vectors when u0 is NULL */
+  double* lam_out;      /* double[k] */
+  double* U_out;        /* double[k][n] */
+  int32_t* tau_out;     /* nullable int32[k] */
+  int32_t* flags_out;   /* nullable int32[k][L] */
+} tsk_problem;
+
+/* Algorithm 1 for `ninst` independent instances of different sizes (n, k, b,
+ * B, dtype may all differ), each exactly as tsk_decompose computes it.  The
+ * instances are spread, longest first, over up to eight branches of one HIP
+ * graph (recorded once per set of shapes and buffers and replayed), so the
+ * device runs several instances' launches at once.  probs: host array of
+ * `ninst` problems; the library keeps one workspace for all of them.
+ * Errors: TSK_EINVAL (ninst < 1, null, or an instance failing the checks of
+ * tsk_decompose; the message names the instance). */
+tsk_status tsk_decompose_batched(tsk_ctx_t ctx, int ninst, const tsk_problem* probs, void* stream);
+
+/* Device workspace, in bytes, that tsk_decompose_batched keeps for `probs`. */
+tsk_status tsk_workspace_size(tsk_ctx_t ctx, int ninst, const tsk_problem* probs, size_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,8 @@ __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
     "sketch_export", "sketch_deflate", "power_update", "contract_tiuu", "contract_uuu",
-    "decompose", "contract_tuuu_grad", "cp_loss",
+    "decompose", "contract_tuuu_grad", "cp_loss", "Problem", "decompose_batched",
+    "workspace_size",
     "F32", "F64",
 ]
 
@@ -64,6 +65,8 @@ _SIGS = {
     "tsk_decompose": ([_P, _P, _I, _P, _P, _I, _I, _I, _P, _U64, _P, _P, _P, _P, _I, _P], _I),
     "tsk_contract_tuuu_grad": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P], _I),
     "tsk_cp_loss": ([_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P], _I),
+    "tsk_decompose_batched": ([_P, _I, _P, _P], _I),
+    "tsk_workspace_size": ([_P, _I, _P, ctypes.POINTER(ctypes.c_size_t)], _I),
 }
 
 
@@ -391,3 +394,64 @@ def cp_loss(ctx, tab, S64, lam, U, scale=None, grads=True, stream=None):
         ctx.handle, tab.handle, dt, _ptr(S64), k, _ptr(lam), _ptr(U), _ptr(scale), _ptr(loss),
         _ptr(g_lam), _ptr(g_U), _stream(stream)))
     return loss, g_lam, g_U
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [("tab", _P), ("dtype", _I), ("S64", _P), ("S32", _P), ("k", _I), ("L", _I),
+                ("T", _I), ("u0", _P), ("seed", _U64), ("lam_out", _P), ("U_out", _P),
+                ("tau_out", _P), ("flags_out", _P)]
+
+
+class Problem:
+    """One instance of a batched decomposition (tsk_problem): its tables and
+    sketches, k, L, T, the precision of the power steps, optional start
+    vectors, and the outputs (allocated here when not given)."""
+
+    def __init__(self, tab, S64, S32, k, L, T, dtype=F32, u0=None, seed=0, lam_out=None,
+                 U_out=None, tau_out=None, flags_out=None):
+        import torch
+        dt, _ = _vdtype(dtype)
+        dev = S64.device
+        _sk(tab, S64, S32, need32=(dt == F32))
+        _tensor(u0, "u0", torch.float64, (k, L, tab.n), allow_none=True)
+        self.tab, self.S64, self.S32, self.k, self.L, self.T = tab, S64, S32, k, L, T
+        self.dtype, self.u0, self.seed = dt, u0, seed
+        self.lam = lam_out if lam_out is not None else torch.empty((k,), dtype=torch.float64, device=dev)
+        self.U = U_out if U_out is not None else torch.empty((k, tab.n), dtype=torch.float64, device=dev)
+        self.tau = tau_out if tau_out is not None else torch.empty((k,), dtype=torch.int32, device=dev)
+        self.flags = flags_out if flags_out is not None else torch.empty((k, L), dtype=torch.int32,
+                                                                         device=dev)
+        _tensor(self.lam, "lam_out", torch.float64, (k,))
+        _tensor(self.U, "U_out", torch.float64, (k, tab.n))
+        _tensor(self.tau, "tau_out", torch.int32, (k,))
+        _tensor(self.flags, "flags_out", torch.int32, (k, L))
+
+    def _c(self):
+        return _CProblem(self.tab.handle, self.dtype, _ptr(self.S64), _ptr(self.S32), self.k, self.L,
+                         self.T, _ptr(self.u0), self.seed & (2 ** 64 - 1), _ptr(self.lam),
+                         _ptr(self.U), _ptr(self.tau), _ptr(self.flags))
+
+
+def _problems(problems):
+    arr = (_CProblem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = p._c()
+    return arr
+
+
+def decompose_batched(ctx, problems, stream=None):
+    """Algorithm 1 for every Problem in ``problems`` in one graph launch; each
+    problem's sketches are deflated in place and its outputs filled."""
+    arr = _problems(problems)
+    _check("tsk_decompose_batched", lib().tsk_decompose_batched(
+        ctx.handle, len(problems), ctypes.cast(arr, _P), _stream(stream)))
+    return problems
+
+
+def workspace_size(ctx, problems) -> int:
+    """Device workspace bytes tsk_decompose_batched keeps for ``problems``."""
+    arr = _problems(problems)
+    out = ctypes.c_size_t(0)
+    _check("tsk_workspace_size", lib().tsk_workspace_size(
+        ctx.handle, len(problems), ctypes.cast(arr, _P), ctypes.byref(out)))
+    return int(out.value)

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <map>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "../../include/tsk.h"
@@ -70,6 +71,9 @@ struct tsk_ctx {
   std::map<int, DevBuf> ws;          // named workspaces
   std::vector<GraphEntry> graphs;
   std::vector<uint64_t> u0_key;      // cached generated start vectors
+  std::vector<uint64_t> u0b_key;     // the same for batched decompositions
+  std::vector<hipStream_t> fork;     // branch streams of batched graphs
+  std::vector<hipEvent_t> fork_ev;   // one event per branch, plus the fork event
 };
 
 struct tsk_tables {
@@ -84,7 +88,7 @@ namespace {
 
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
-  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD
+  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -364,6 +368,8 @@ extern "C" void tsk_destroy(tsk_ctx_t c) {
   for (auto& kv : c->tw64) (void)hipFree(kv.second);
   for (auto& kv : c->tw32) (void)hipFree(kv.second);
   if (c->cap) (void)hipStreamDestroy(c->cap);
+  for (auto s : c->fork) (void)hipStreamDestroy(s);
+  for (auto e : c->fork_ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -934,107 +940,284 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
 
 }  // namespace
 
+namespace {
+
+tsk_status check_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const double* S64,
+                           const float* S32, int k, int L, int T, const double* u0,
+                           const double* lam_out, const double* U_out, const char* fn) {
+  TSK_TRY(check_tables(tab, ctx, fn));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, fn));
+  if (!S64) return tsk::fail(TSK_EINVAL, "%s: S64 (deflated in FP64) is required", fn);
+  if (!lam_out || !U_out) return tsk::fail(TSK_EINVAL, "%s: null lam_out or U_out", fn);
+  if (k < 1 || k > tab->n) return tsk::fail(TSK_EINVAL, "%s: k=%d outside [1,n]", fn, k);
+  if (T < 1) return tsk::fail(TSK_EINVAL, "%s: T=%d < 1", fn, T);
+  if (!u0 && (L >= (1 << 20) || tab->n >= (1 << 19)))
+    return tsk::fail(TSK_EINVAL, "%s: too large to draw start vectors", fn);
+  return TSK_OK;
+}
+
+// Workspace of one decomposition carved from one buffer (256-byte aligned
+// pieces); with base == nullptr only the size is computed.
+size_t decomp_ws_layout(char* base, tsk_tables_t tab, tsk_dtype dtype, int k, int L, bool flags,
+                        bool u0, DecompWs* w, int32_t** fl, double** u0p) {
+  const size_t n = tab->n, B = tab->B, H1 = (size_t)tab->b / 2 + 1;
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  DecompWs d;
+  d.U0 = take(L * n * es);
+  d.U1 = take(L * n * es);
+  d.V0 = take(L * B * n * es);
+  d.V1 = take(L * B * n * es);
+  d.lam_per = (double*)take(L * B * 8);
+  d.lam_med = (double*)take((size_t)L * 8);
+  d.u_hat = (double*)take(n * 8);
+  d.lam64 = (double*)take(B * 8);
+  d.prod = take(B * H1 * 16);
+  d.flags = flags ? (int32_t*)take((size_t)k * L * 4) : nullptr;
+  d.u0 = u0 ? (double*)take((size_t)k * L * n * 8) : nullptr;
+  if (w) *w = d;
+  if (fl) *fl = d.flags;
+  if (u0p) *u0p = d.u0;
+  return off;
+}
+
+tsk_status upload_start_vectors(uint64_t seed, int k, int L, int n, double* dst, hipStream_t st) {
+  std::vector<double> h((size_t)k * L * n);
+  for (int c = 0; c < k; ++c) TSK_TRY(tsk_init_vectors(seed, c, L, n, h.data() + (size_t)c * L * n));
+  TSK_HIP(hipStreamSynchronize(st));
+  TSK_HIP(hipMemcpy(dst, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  return TSK_OK;
+}
+
+tsk_status preload_twiddles(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype) {
+  const cx<double>* t64 = nullptr;
+  const cx<float>* t32 = nullptr;
+  TSK_TRY(get_tw<double>(ctx, tab->logb, &t64));
+  if (dtype == TSK_F32) TSK_TRY(get_tw<float>(ctx, tab->logb, &t32));
+  return TSK_OK;
+}
+
+// Everything one decomposition enqueues: clear its flags (a fill kernel, so a
+// recorded graph holds no memset node), then the component loop.
+tsk_status decompose_all(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, double* S64, float* S32,
+                         int k, int L, int T, const double* u0d, double* lam_out, double* U_out,
+                         int32_t* tau_out, int32_t* flags, const DecompWs& w, bool plain,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for((size_t)k * L, 256)), dim3(256), 0, s,
+                     reinterpret_cast<unsigned*>(flags), 0u, (size_t)k * L);
+  TSK_TRY(check_launch("k_fill_u32"));
+  const void* spec = dtype == TSK_F32 ? (const void*)S32 : (const void*)S64;
+  if (dtype == TSK_F32)
+    return decompose_enqueue<float>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out,
+                                    flags, w, plain, s);
+  return decompose_enqueue<double>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out,
+                                   flags, w, plain, s);
+}
+
+GraphEntry* find_graph(tsk_ctx_t ctx, const std::vector<uint64_t>& key) {
+  for (auto& g : ctx->graphs)
+    if (g.key == key) return &g;
+  return nullptr;
+}
+
+// Record what `enqueue(stream)` launches on the capture stream into a graph
+// and keep it under `key`.
+template <typename F>
+tsk_status record_graph(tsk_ctx_t ctx, const std::vector<uint64_t>& key, F enqueue, GraphEntry** out) {
+  GraphEntry g;
+  g.key = key;
+  TSK_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
+  tsk_status s = enqueue(ctx->cap);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+  if (s != TSK_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return tsk::fail(TSK_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  g.graph = graph;
+  TSK_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+  if (ctx->graphs.size() >= 16) clear_graphs(ctx);
+  ctx->graphs.push_back(g);
+  *out = &ctx->graphs.back();
+  return TSK_OK;
+}
+
+}  // namespace
+
 extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, double* S64,
                                     float* S32, int k, int L, int T, const double* u0,
                                     uint64_t seed, double* lam_out, double* U_out,
                                     int32_t* tau_out, int32_t* flags_out, int plain,
                                     void* stream) {
-  TSK_TRY(check_tables(tab, ctx, "tsk_decompose"));
-  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_decompose"));
-  if (!S64) return tsk::fail(TSK_EINVAL, "tsk_decompose: S64 (deflated in FP64) is required");
-  if (!lam_out || !U_out) return tsk::fail(TSK_EINVAL, "tsk_decompose: null lam_out or U_out");
-  if (k < 1 || k > tab->n) return tsk::fail(TSK_EINVAL, "tsk_decompose: k=%d outside [1,n]", k);
-  if (T < 1) return tsk::fail(TSK_EINVAL, "tsk_decompose: T=%d < 1", T);
-  if (!u0 && (L >= (1 << 20) || tab->n >= (1 << 19)))
-    return tsk::fail(TSK_EINVAL, "tsk_decompose: too large to draw start vectors");
+  TSK_TRY(check_decompose(ctx, tab, dtype, S64, S32, k, L, T, u0, lam_out, U_out, "tsk_decompose"));
   TSK_TRY(set_device(ctx));
   hipStream_t st = S(stream);
-  const int n = tab->n, B = tab->B, b = tab->b;
-  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  const int n = tab->n;
+  const size_t bytes = decomp_ws_layout(nullptr, tab, dtype, k, L, !flags_out, !u0, nullptr, nullptr,
+                                        nullptr);
+  void* base = nullptr;
+  TSK_TRY(ws_get(ctx, WS_U, bytes, &base));
   DecompWs w;
-  TSK_TRY(ws_get(ctx, WS_U, 2 * (size_t)L * n * es, &w.U0));
-  w.U1 = reinterpret_cast<char*>(w.U0) + (size_t)L * n * es;
-  TSK_TRY(ws_get(ctx, WS_V, 2 * (size_t)L * B * n * es, &w.V0));
-  w.V1 = reinterpret_cast<char*>(w.V0) + (size_t)L * B * n * es;
-  void* p;
-  TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * B * 8, &p));
-  w.lam_per = (double*)p;
-  TSK_TRY(ws_get(ctx, WS_LAMMED, (size_t)L * 8, &p));
-  w.lam_med = (double*)p;
-  TSK_TRY(ws_get(ctx, WS_UHAT, (size_t)n * 8, &p));
-  w.u_hat = (double*)p;
-  TSK_TRY(ws_get(ctx, WS_LAM64, (size_t)B * 8, &p));
-  w.lam64 = (double*)p;
-  TSK_TRY(ws_get(ctx, WS_PROD, (size_t)B * (b / 2 + 1) * 16, &w.prod));
-  int32_t* flags = flags_out;
-  if (!flags) {
-    TSK_TRY(ws_get(ctx, WS_FLAGS, (size_t)k * L * 4, &p));
-    flags = (int32_t*)p;
-  }
+  int32_t* fl_ws = nullptr;
+  double* u0_ws = nullptr;
+  decomp_ws_layout((char*)base, tab, dtype, k, L, !flags_out, !u0, &w, &fl_ws, &u0_ws);
+  int32_t* flags = flags_out ? flags_out : fl_ws;
   const double* u0d = u0;
   if (!u0d) {
-    TSK_TRY(ws_get(ctx, WS_U0, (size_t)k * L * n * 8, &p));
-    std::vector<uint64_t> key = {seed, (uint64_t)k, (uint64_t)L, (uint64_t)n, (uint64_t)(uintptr_t)p};
+    std::vector<uint64_t> key = {seed, (uint64_t)k, (uint64_t)L, (uint64_t)n, (uint64_t)(uintptr_t)u0_ws};
     if (ctx->u0_key != key) {
-      std::vector<double> h((size_t)k * L * n);
-      for (int c = 0; c < k; ++c) TSK_TRY(tsk_init_vectors(seed, c, L, n, h.data() + (size_t)c * L * n));
-      TSK_HIP(hipStreamSynchronize(st));
-      TSK_HIP(hipMemcpy(p, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+      TSK_TRY(upload_start_vectors(seed, k, L, n, u0_ws, st));
       ctx->u0_key = key;
     }
-    u0d = (const double*)p;
+    u0d = u0_ws;
   }
-  // Flags are outputs of this call: clear them first (a fill kernel, so the
-  // recorded graph holds no memset node).
-  auto clear_flags = [&](hipStream_t s) -> tsk_status {
-    hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for((size_t)k * L, 256)), dim3(256), 0, s,
-                       reinterpret_cast<unsigned*>(flags), 0u, (size_t)k * L);
-    return check_launch("k_fill_u32");
-  };
-  const void* spec = dtype == TSK_F32 ? (const void*)S32 : (const void*)S64;
-  {  // twiddle tables are uploaded outside any capture
-    const cx<double>* t64 = nullptr;
-    const cx<float>* t32 = nullptr;
-    TSK_TRY(get_tw<double>(ctx, tab->logb, &t64));
-    if (dtype == TSK_F32) TSK_TRY(get_tw<float>(ctx, tab->logb, &t32));
-  }
+  TSK_TRY(preload_twiddles(ctx, tab, dtype));  // uploads stay outside any capture
   auto enqueue = [&](hipStream_t s) -> tsk_status {
-    TSK_TRY(clear_flags(s));
-    if (dtype == TSK_F32)
-      return decompose_enqueue<float>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out,
-                                      tau_out, flags, w, plain != 0, s);
-    return decompose_enqueue<double>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out,
-                                     tau_out, flags, w, plain != 0, s);
+    return decompose_all(ctx, tab, dtype, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out, flags, w,
+                         plain != 0, s);
   };
   if (plain) return enqueue(st);
-
-  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)tab, (uint64_t)dtype, (uint64_t)(uintptr_t)S64,
+  std::vector<uint64_t> key = {0, (uint64_t)(uintptr_t)tab, (uint64_t)dtype, (uint64_t)(uintptr_t)S64,
                                (uint64_t)(uintptr_t)S32, (uint64_t)k, (uint64_t)L, (uint64_t)T,
                                (uint64_t)(uintptr_t)u0d, (uint64_t)(uintptr_t)lam_out,
                                (uint64_t)(uintptr_t)U_out, (uint64_t)(uintptr_t)tau_out,
-                               (uint64_t)(uintptr_t)flags, (uint64_t)(uintptr_t)w.U0,
-                               (uint64_t)(uintptr_t)w.V0, (uint64_t)(uintptr_t)w.prod};
-  GraphEntry* ge = nullptr;
-  for (auto& g : ctx->graphs)
-    if (g.key == key) ge = &g;
-  if (!ge) {
-    GraphEntry g;
-    g.key = key;
-    TSK_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
-    tsk_status s = enqueue(ctx->cap);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
-    if (s != TSK_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return s;
-    }
-    if (e != hipSuccess) return tsk::fail(TSK_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-    g.graph = graph;
-    TSK_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
-    if (ctx->graphs.size() >= 16) clear_graphs(ctx);
-    ctx->graphs.push_back(g);
-    ge = &ctx->graphs.back();
-  }
+                               (uint64_t)(uintptr_t)flags, (uint64_t)(uintptr_t)base};
+  GraphEntry* ge = find_graph(ctx, key);
+  if (!ge) TSK_TRY(record_graph(ctx, key, enqueue, &ge));
   TSK_HIP(hipGraphLaunch(ge->exec, st));
+  return TSK_OK;
+}
+
+extern "C" tsk_status tsk_decompose_batched(tsk_ctx_t ctx, int ninst, const tsk_problem* probs,
+                                            void* stream) {
+  if (!ctx || !probs) return tsk::fail(TSK_EINVAL, "tsk_decompose_batched: null argument");
+  if (ninst < 1) return tsk::fail(TSK_EINVAL, "tsk_decompose_batched: ninst=%d < 1", ninst);
+  for (int i = 0; i < ninst; ++i) {
+    const tsk_problem& p = probs[i];
+    tsk_status s = check_decompose(ctx, p.tab, p.dtype, p.S64, p.S32, p.k, p.L, p.T, p.u0, p.lam_out,
+                                   p.U_out, "tsk_decompose_batched");
+    if (s != TSK_OK) {
+      const std::string msg = tsk_last_error();
+      return tsk::fail(s, "tsk_decompose_batched: instance %d: %s", i, msg.c_str());
+    }
+  }
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  // one workspace buffer, instances at fixed offsets
+  std::vector<size_t> off(ninst);
+  size_t total = 0;
+  for (int i = 0; i < ninst; ++i) {
+    const tsk_problem& p = probs[i];
+    off[i] = total;
+    total += decomp_ws_layout(nullptr, p.tab, p.dtype, p.k, p.L, !p.flags_out, !p.u0, nullptr, nullptr,
+                              nullptr);
+  }
+  void* base = nullptr;
+  TSK_TRY(ws_get(ctx, WS_BATCH, total, &base));
+  std::vector<DecompWs> w(ninst);
+  std::vector<int32_t*> flags(ninst);
+  std::vector<const double*> u0d(ninst);
+  std::vector<uint64_t> u0key = {(uint64_t)(uintptr_t)base};
+  for (int i = 0; i < ninst; ++i) {
+    const tsk_problem& p = probs[i];
+    int32_t* fl = nullptr;
+    double* u0w = nullptr;
+    decomp_ws_layout((char*)base + off[i], p.tab, p.dtype, p.k, p.L, !p.flags_out, !p.u0, &w[i], &fl,
+                     &u0w);
+    flags[i] = p.flags_out ? p.flags_out : fl;
+    u0d[i] = p.u0 ? p.u0 : u0w;
+    if (!p.u0) {
+      u0key.push_back(i);
+      u0key.push_back(p.seed);
+      u0key.push_back(((uint64_t)p.k << 40) | ((uint64_t)p.L << 20) | (uint64_t)p.tab->n);
+      u0key.push_back(off[i]);
+    }
+    TSK_TRY(preload_twiddles(ctx, p.tab, p.dtype));
+  }
+  if (ctx->u0b_key != u0key) {
+    for (int i = 0; i < ninst; ++i)
+      if (!probs[i].u0)
+        TSK_TRY(upload_start_vectors(probs[i].seed, probs[i].k, probs[i].L, probs[i].tab->n,
+                                     const_cast<double*>(u0d[i]), st));
+    ctx->u0b_key = u0key;
+  }
+  // Longest-first assignment of instances to at most 8 graph branches by
+  // their sketch-update work k L (T+1) B b log2 b.
+  const int nb = std::min(ninst, 8);
+  while ((int)ctx->fork.size() < nb) {
+    hipStream_t s = nullptr;
+    TSK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    ctx->fork.push_back(s);
+  }
+  while ((int)ctx->fork_ev.size() < nb + 1) {
+    hipEvent_t e = nullptr;
+    TSK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->fork_ev.push_back(e);
+  }
+  std::vector<int> order(ninst);
+  std::vector<double> work(ninst);
+  for (int i = 0; i < ninst; ++i) {
+    const tsk_problem& p = probs[i];
+    order[i] = i;
+    work[i] = (double)p.k * p.L * (p.T + 1) * p.tab->B * (double)p.tab->b * p.tab->logb;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<std::vector<int>> branch(nb);
+  std::vector<double> load(nb, 0.0);
+  for (int i : order) {
+    const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    branch[j].push_back(i);
+    load[j] += work[i];
+  }
+  std::vector<uint64_t> key = {1, (uint64_t)ninst, (uint64_t)(uintptr_t)base};
+  for (int i = 0; i < ninst; ++i) {
+    const tsk_problem& p = probs[i];
+    const uint64_t v[] = {(uint64_t)(uintptr_t)p.tab, (uint64_t)p.dtype, (uint64_t)(uintptr_t)p.S64,
+                          (uint64_t)(uintptr_t)p.S32, (uint64_t)p.k, (uint64_t)p.L, (uint64_t)p.T,
+                          (uint64_t)(uintptr_t)u0d[i], (uint64_t)(uintptr_t)p.lam_out,
+                          (uint64_t)(uintptr_t)p.U_out, (uint64_t)(uintptr_t)p.tau_out,
+                          (uint64_t)(uintptr_t)flags[i]};
+    key.insert(key.end(), std::begin(v), std::end(v));
+  }
+  auto enqueue = [&](hipStream_t cap) -> tsk_status {
+    TSK_HIP(hipEventRecord(ctx->fork_ev[nb], cap));
+    for (int j = 0; j < nb; ++j) {
+      hipStream_t s = ctx->fork[j];
+      TSK_HIP(hipStreamWaitEvent(s, ctx->fork_ev[nb], 0));
+      for (int i : branch[j]) {
+        const tsk_problem& p = probs[i];
+        TSK_TRY(decompose_all(ctx, p.tab, p.dtype, p.S64, p.S32, p.k, p.L, p.T, u0d[i], p.lam_out,
+                              p.U_out, p.tau_out, flags[i], w[i], false, s));
+      }
+      TSK_HIP(hipEventRecord(ctx->fork_ev[j], s));
+      TSK_HIP(hipStreamWaitEvent(cap, ctx->fork_ev[j], 0));
+    }
+    return TSK_OK;
+  };
+  GraphEntry* ge = find_graph(ctx, key);
+  if (!ge) TSK_TRY(record_graph(ctx, key, enqueue, &ge));
+  TSK_HIP(hipGraphLaunch(ge->exec, st));
+  return TSK_OK;
+}
+
+extern "C" tsk_status tsk_workspace_size(tsk_ctx_t ctx, int ninst, const tsk_problem* probs,
+                                         size_t* bytes) {
+  if (!ctx || !probs || !bytes) return tsk::fail(TSK_EINVAL, "tsk_workspace_size: null argument");
+  if (ninst < 1) return tsk::fail(TSK_EINVAL, "tsk_workspace_size: ninst=%d < 1", ninst);
+  size_t total = 0;
+  for (int i = 0; i < ninst; ++i) {
+    const tsk_problem& p = probs[i];
+    TSK_TRY(check_decompose(ctx, p.tab, p.dtype, p.S64, p.S32, p.k, p.L, p.T, p.u0, p.lam_out, p.U_out,
+                            "tsk_workspace_size"));
+    total += decomp_ws_layout(nullptr, p.tab, p.dtype, p.k, p.L, !p.flags_out, !p.u0, nullptr, nullptr,
+                              nullptr);
+  }
+  *bytes = total;
   return TSK_OK;
 }
