@@ -148,6 +148,83 @@ def wrong_vectors(V_true, V_hat, thresh=0.1):
     return int(np.sum(d2.min(axis=1) > thresh))
 
 
+def residual_factored(lam, A, lam_h, V_h) -> float:
+    """||sum_i lam_i a_i^(x)3 - sum_j lamh_j v_j^(x)3||^2 by Gram matrices."""
+    G_aa = (A @ A.T) ** 3
+    G_av = (A @ V_h.T) ** 3
+    G_vv = (V_h @ V_h.T) ** 3
+    return float(lam @ G_aa @ lam - 2.0 * lam @ G_av @ lam_h + lam_h @ G_vv @ lam_h)
+
+
+def c3_batched(ctx, dev, nrep: int = 3):
+    """64 uneven factor instances (tensor never formed): factor build, then
+    Algorithm 1 for all instances in one batched graph launch, against the
+    same decompositions launched one instance after another."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    from paper_1506_04448_amd.workloads import factor_instances
+    Bc, Lc, Tc = 8, 30, 20
+    insts = factor_instances(64, seed=2, b_choices=(4096, 16384, 65536))
+    probs, seq, keep, tabs = [], [], [], []
+    for i, inst in enumerate(insts):
+        b = min(inst.b, 16384)
+        h, xi = tsk.hash_generate(2 + i, inst.n, b, Bc)
+        tab = tsk.Tables(ctx, h, xi, b)
+        tabs.append(tab)
+        S64, S32 = tsk.new_sketch(tab, dev)
+        tsk.sketch_build_factors(ctx, tab, torch.from_numpy(inst.lam).to(dev),
+                                 torch.from_numpy(inst.A).to(dev), S64, S32)
+        keep.append((S64.clone(), S32.clone()))
+        probs.append(tsk.Problem(tab, S64, S32, inst.k, Lc, Tc, dtype=tsk.F32, seed=2 + i))
+        seq.append((tab, S64.clone(), S32.clone()))
+    updates = sum(inst.k for inst in insts) * (Tc + 1) * Lc * Bc
+
+    def restore():
+        for p, (a, c) in zip(probs, keep):
+            p.S64.copy_(a)
+            p.S32.copy_(c)
+        for (_, a, c), (a0, c0) in zip(seq, keep):
+            a.copy_(a0)
+            c.copy_(c0)
+        torch.cuda.synchronize()
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    tb, ts = [], []
+    seq_out = None
+    for r in range(nrep + 1):
+        restore()
+        e0.record(stream)
+        tsk.decompose_batched(ctx, probs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            tb.append(e0.elapsed_time(e1))
+        e0.record(stream)
+        seq_out = [tsk.decompose(ctx, tab, a, c, inst.k, Lc, Tc, dtype=tsk.F32, seed=2 + i)
+                   for i, ((tab, a, c), inst) in enumerate(zip(seq, insts))]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            ts.append(e0.elapsed_time(e1))
+    same = all(torch.equal(p.lam, o[0]) and torch.equal(p.U, o[1]) for p, o in zip(probs, seq_out))
+    res = [residual_factored(inst.lam, inst.A, p.lam.cpu().numpy(), p.U.cpu().numpy())
+           / residual_factored(inst.lam, inst.A, np.zeros(0), np.zeros((0, inst.n)))
+           for p, inst in zip(probs, insts)]
+    ms_b, ms_s = float(np.median(tb)), float(np.median(ts))
+    for t in tabs:
+        t.close()
+    return {
+        "workload": ("64 factor instances, n~U{100..2000}, k~U{5..50}, lam~U[1,10], unit "
+                     "non-orthogonal factors, b from {4096,16384,65536} (65536 run at 16384), "
+                     f"B={Bc}, L={Lc}, T={Tc}, FP32 power steps"),
+        "sketch_updates": updates, "batched_ms": ms_b, "sequential_ms": ms_s,
+        "sketch_updates_per_s": updates / (ms_b * 1e-3), "speedup_vs_sequential": ms_s / ms_b,
+        "same_result_as_sequential": bool(same),
+        "relative_residual_median": float(np.median(res)),
+    }
+
+
 def cpu_baseline(P, h, xi, budget_s: float):
     """The CPU oracle timed on a bounded sample of the same workload: the dense
     build of all B sketches, then power steps over all L restarts until the
@@ -210,6 +287,7 @@ def main():
                     help="seconds of oracle power steps in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched uneven-instance leg")
     ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
@@ -335,6 +413,8 @@ def main():
             "same_result_as_batched": bool(np.array_equal(lam_p, lam_d) and np.array_equal(U_p, U_d)),
         }
 
+    c3 = None if args.no_c3 else c3_batched(ctx, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(P, h, xi, args.cpu_budget)
@@ -372,6 +452,7 @@ def main():
         "decompose_ms": decompose_ms,
         "decompose_sketch_updates_per_s": updates / (decompose_ms * 1e-3),
         "speedup_vs_plain": (plain["decompose_ms"] / decompose_ms) if plain else None,
+        "batched_instances": c3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
