@@ -17,7 +17,9 @@ every estimate to the exact dense contraction, unbiasedness by full
 enumeration of hash draws, exact recovery of planted orthogonal components).
 The gradients of the sketched T(u,u,u) estimate and of the sketched CP loss
 (``gradients``) are pinned by central finite differences and by the
-injective-hash reduction to the dense gradient.
+injective-hash reduction to the dense gradient.  The whitened LDA moment of
+Appendix D (``lda``) is pinned by brute force over word positions, by the
+closed forms of the population moments and by the explicit V^3 route.
 Parity unpinned: the full sketched power method beyond those pins (the paper
 prints no worked example to compare against).
 """
@@ -28,7 +30,7 @@ from .sketch import (count_sketch, sketch_dense, circular_convolution,
 from .contract import (median, power_update_sketch, power_update_direct,
                        tuuu_sketch, tuuu_direct, power_update, contract_uuu)
 from .rtpm import rtpm_sketched, rtpm_dense, RtpmResult
-from . import gradients
+from . import gradients, lda
 from .dense import (dense_Tuuu, dense_TIuu, residual_dense, residual_factored,
                     wrong_vectors)
 
@@ -39,5 +41,5 @@ __all__ = [
     "median", "power_update_sketch", "power_update_direct", "tuuu_sketch",
     "tuuu_direct", "power_update", "contract_uuu",
     "rtpm_sketched", "rtpm_dense", "RtpmResult",
-    "gradients", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
+    "gradients", "lda", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
 ]
