@@ -114,6 +114,32 @@ tsk_status tsk_sketch_build_factors(tsk_ctx_t ctx, tsk_tables_t tab, const doubl
                                     const double* A, int k, double* S64, float* S32,
                                     int accumulate, void* stream);
 
+/* Document build (Appendix D): the B sketches of the whitened third-order
+ * moment of spectral LDA, M3(W, W, W), from word counts, without forming any
+ * K^3 or V^3 tensor.  With n the counts of a document of length m >= 3 (shorter
+ * documents are dropped), p = W^T n, w_i the i-th row of W, q = W^T M1 (M1
+ * the mean of n / m over the kept documents, D of them), a = alpha0/(alpha0+2),
+ * c = 2 alpha0^2 / ((alpha0+1)(alpha0+2)):
+ *   M3 = (1/D) sum_d [ (p^(x)3 - sum_i n_i (w_i w_i p + w_i p w_i + p w_i w_i)
+ *                        + 2 sum_i n_i w_i^(x)3) / (m (m-1)(m-2))
+ *                      - a (p p^T - sum_i n_i w_i w_i^T) / (m (m-1)) (x) q  (and its two
+ *                        mode permutations) ] + c q^(x)3,
+ * the per-document terms by Eq. (td) and the moment combination of
+ * Eq. (moment3).  Each document costs three transforms per sketch; the terms
+ * in w_i are gathered per word first (sums over the documents holding it)
+ * and cost six per word.  Every rank-1 term is sketched by Eq. (2).
+ *   rowptr: int32[D+1], col: int32[nnz] word ids in [0, V) (unique within a
+ *   document), cnt: int32[nnz] counts >= 1 -- CSR, device.
+ *   W: [V][K] in wdtype (TSK_F32 or TSK_F64; the transforms run in that
+ *   precision, the sums over documents in FP64), K = the tables' n.
+ *   accumulate != 0 adds to S64.  The call reads rowptr[D] back to the host.
+ * Errors: TSK_EINVAL (null, D < 1, V < 1, alpha0 < 0 or not finite, dtype),
+ * TSK_EUNSUPPORTED (K too large for one work-group's LDS at this b). */
+tsk_status tsk_sketch_build_docs(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowptr,
+                                 const int32_t* col, const int32_t* cnt, int D, int V,
+                                 const void* W, tsk_dtype wdtype, double alpha0, double* S64,
+                                 float* S32, int accumulate, void* stream);
+
 /* Spectra from time-domain sketches s_time: double[B][b] (e.g. a sketch kept
  * by the caller), and back.  FP64 throughout. */
 tsk_status tsk_sketch_from_time(tsk_ctx_t ctx, int b, int B, const double* s_time,

@@ -20,7 +20,7 @@ __all__ = [
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
     "sketch_export", "sketch_deflate", "power_update", "contract_tiuu", "contract_uuu",
     "decompose", "contract_tuuu_grad", "cp_loss", "Problem", "decompose_batched",
-    "workspace_size",
+    "workspace_size", "sketch_build_docs",
     "F32", "F64",
 ]
 
@@ -66,6 +66,7 @@ _SIGS = {
     "tsk_contract_tuuu_grad": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P], _I),
     "tsk_cp_loss": ([_P, _P, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P], _I),
     "tsk_decompose_batched": ([_P, _I, _P, _P], _I),
+    "tsk_sketch_build_docs": ([_P, _P, _P, _P, _P, _I, _I, _P, _I, ctypes.c_double, _P, _P, _I, _P], _I),
     "tsk_workspace_size": ([_P, _I, _P, ctypes.POINTER(ctypes.c_size_t)], _I),
 }
 
@@ -455,3 +456,20 @@ def workspace_size(ctx, problems) -> int:
     _check("tsk_workspace_size", lib().tsk_workspace_size(
         ctx.handle, len(problems), ctypes.cast(arr, _P), ctypes.byref(out)))
     return int(out.value)
+
+
+def sketch_build_docs(ctx, tab, rowptr, col, cnt, V, W, alpha0, S64, S32=None, accumulate=False,
+                      stream=None):
+    """Sketches of the whitened LDA moment M3(W,W,W) from CSR word counts
+    (rowptr int32 [D+1], col/cnt int32 [nnz]) and W [V][K] (float32 or float64)."""
+    import torch
+    D = rowptr.shape[0] - 1
+    _tensor(rowptr, "rowptr", torch.int32, (D + 1,))
+    _tensor(col, "col", torch.int32)
+    _tensor(cnt, "cnt", torch.int32, tuple(col.shape))
+    dt, tdt = _vdtype(W.dtype)
+    _tensor(W, "W", tdt, (V, tab.n))
+    _sk(tab, S64, S32)
+    _check("tsk_sketch_build_docs", lib().tsk_sketch_build_docs(
+        ctx.handle, tab.handle, _ptr(rowptr), _ptr(col), _ptr(cnt), D, V, _ptr(W), dt, float(alpha0),
+        _ptr(S64), _ptr(S32), int(bool(accumulate)), _stream(stream)))

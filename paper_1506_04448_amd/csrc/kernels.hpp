@@ -999,6 +999,368 @@ __global__ __launch_bounds__(256) void k_cp_grad(const double* lam_per, const R*
   }
 }
 
+// ===========================================================================
+// Sketch of the whitened LDA moment M3(W,W,W) from document word counts
+// (Appendix D).  Per document d with counts n (length m >= 3) and p = W^T n:
+//   c_d  = 1 / (m (m-1)(m-2)),  c'_d = 1 / (m (m-1))
+//   doc term   c_d p^(x)3 - a c'_d (p p q + p q p + q p p)           (a = alpha0/(alpha0+2))
+// and, through the per-word sums g_i = sum_d c_d n_di, g'_i = sum_d c'_d n_di,
+// R_i = sum_d c_d n_di p_d (w_i the i-th row of W),
+//   word term  2 g_i w_i^(x)3 - (w w R_i + w R_i w + R_i w w) + a g'_i (w w q + w q w + q w w),
+// then M3 = (sum of all terms) / D + c q^(x)3 with q = W^T M1.  Every rank-1
+// term x (x) y (x) z is sketched as F(s1 x) F(s2 y) F(s3 z) (Eq. (2)).
+// ===========================================================================
+
+// p_d = W^T n_d and the document coefficients; one block per document.
+template <typename R>
+__global__ __launch_bounds__(256) void k_doc_project(const int32_t* rowptr, const int32_t* col,
+                                                     const int32_t* cnt, int D, int K, const R* W,
+                                                     R* P, double* cd, double* cpd, double* invm) {
+  for (int d = blockIdx.x; d < D; d += gridDim.x) {
+    const int lo = rowptr[d], hi = rowptr[d + 1];
+    double m = 0.0;
+    for (int e = lo; e < hi; ++e) m += (double)cnt[e];
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      double p = 0.0;
+      for (int e = lo; e < hi; ++e) p += (double)cnt[e] * (double)W[(size_t)col[e] * K + k];
+      P[(size_t)d * K + k] = (R)p;
+    }
+    if (threadIdx.x == 0) {
+      const bool keep = m >= 3.0;  // documents with fewer than three words are dropped
+      cd[d] = keep ? 1.0 / (m * (m - 1.0) * (m - 2.0)) : 0.0;
+      cpd[d] = keep ? 1.0 / (m * (m - 1.0)) : 0.0;
+      invm[d] = keep ? 1.0 / m : 0.0;
+    }
+  }
+}
+
+// Partial sums of p_d / m_d and of the kept-document count over a range of
+// documents: part[g][k] for k < K, part[g][K] = count.
+template <typename R>
+__global__ __launch_bounds__(256) void k_doc_q_partial(const R* P, const double* invm, int D, int K,
+                                                       int per, double* part) {
+  const int g = blockIdx.x;
+  const int d0 = g * per, d1 = min(D, d0 + per);
+  for (int k = threadIdx.x; k <= K; k += blockDim.x) {
+    double acc = 0.0;
+    for (int d = d0; d < d1; ++d) {
+      const double w = invm[d];
+      if (k < K) acc += (double)P[(size_t)d * K + k] * w;
+      else acc += w > 0.0 ? 1.0 : 0.0;
+    }
+    part[(size_t)g * (K + 1) + k] = acc;
+  }
+}
+
+// q = (sum of partials) / D_eff, and D_eff itself; one block, fixed order.
+__global__ void k_doc_q_final(const double* part, int G, int K, double* q, double* deff) {
+  double D = 0.0;
+  for (int g = 0; g < G; ++g) D += part[(size_t)g * (K + 1) + K];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += part[(size_t)g * (K + 1) + k];
+    q[k] = D > 0.0 ? s / D : 0.0;
+  }
+  if (threadIdx.x == 0) deff[0] = D;
+}
+
+// Document index of every nonzero, and the identity permutation.
+__global__ void k_rowof(const int32_t* rowptr, int D, int32_t* rowof, int32_t* iota) {
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < D; d += gridDim.x * blockDim.x)
+    for (int e = rowptr[d]; e < rowptr[d + 1]; ++e) {
+      rowof[e] = d;
+      iota[e] = e;
+    }
+}
+
+// colptr[i] = first position of word i in the sorted word ids (binary search).
+__global__ void k_col_bounds(const int32_t* skeys, int nnz, int V, int32_t* colptr) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= V; i += gridDim.x * blockDim.x) {
+    int lo = 0, hi = nnz;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (skeys[mid] < i) lo = mid + 1;
+      else hi = mid;
+    }
+    colptr[i] = lo;
+  }
+}
+
+// Per-word sums over the documents containing the word (in document order):
+// R_i = sum_d c_d n_di p_d, g_i = sum_d c_d n_di, g'_i = sum_d c'_d n_di.
+template <typename R>
+__global__ __launch_bounds__(256) void k_word_accum(const int32_t* svals, const int32_t* colptr,
+                                                    const int32_t* rowof, const int32_t* cnt,
+                                                    const R* P, const double* cd, const double* cpd,
+                                                    int V, int K, R* Rw, double* g, double* gp) {
+  for (int i = blockIdx.x; i < V; i += gridDim.x) {
+    const int lo = colptr[i], hi = colptr[i + 1];
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      double acc = 0.0;
+      for (int e = lo; e < hi; ++e) {
+        const int idx = svals[e];
+        const int d = rowof[idx];
+        acc += cd[d] * (double)cnt[idx] * (double)P[(size_t)d * K + k];
+      }
+      Rw[(size_t)i * K + k] = (R)acc;
+    }
+    if (threadIdx.x == 0) {
+      double a = 0.0, c = 0.0;
+      for (int e = lo; e < hi; ++e) {
+        const int idx = svals[e];
+        const int d = rowof[idx];
+        a += cd[d] * (double)cnt[idx];
+        c += cpd[d] * (double)cnt[idx];
+      }
+      g[i] = a;
+      gp[i] = c;
+    }
+  }
+}
+
+// Half spectra F(s_j q) of one vector for every sketch m and mode j:
+// Qs[m][j][k], k = 0..H; one work-group per (m, j).
+template <typename R, int LOGB>
+__global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_mode_spectra(
+    const uint32_t* hxs, const uint32_t* ord, int n, const double* q, const cx<R>* twg, cx<R>* Qs) {
+  constexpr int LOGH = LOGB - 1;
+  constexpr int NT = threads_for_h<R>(LOGH);
+  constexpr int H = 1 << LOGH;
+  constexpr int PL = padded_len(H);
+  __shared__ __align__(16) R re[2 * PL];
+  R* im = re + PL;
+  const Soa<R> buf{re, im};
+  const int m = blockIdx.x, j = blockIdx.y;
+  const size_t tb = ((size_t)m * 3 + j) * n;
+  const Twid<R> tw{twg, twg + pass_table_len(H, NT)};
+  for (int t = threadIdx.x; t < 2 * PL; t += NT) re[t] = R(0);
+  __syncthreads();
+  auto getu = [&](uint32_t i) -> R { return (R)q[i]; };
+  auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
+  count_sketch<R>(hxs + tb, ord + tb, n, NT, getu, store);
+  __syncthreads();
+  fft_soa<R, LOGH, NT, false, false>(buf, tw);
+  cx<R>* out = Qs + ((size_t)m * 3 + j) * (H + 1);
+  for (int k = threadIdx.x; k <= H; k += NT)
+    out[k] = r2c_post(buf.get(k & (H - 1)), buf.get((H - k) & (H - 1)), tw.w(k));
+}
+
+struct TermArgs {
+  const uint32_t* hxs;
+  const uint32_t* ord;
+  int n, B;                // n = K, the whitened dimension
+  int nitem, per;          // items, items per work-group
+  const void* X;           // R[nitem][n]: p_d (documents) or w_i (words)
+  const void* Y;           // R[nitem][n]: R_i (words) or null
+  const double* arrA;      // [nitem]
+  const double* arrB;      // [nitem]
+  double sa, sb, gam;      // alpha = sa arrA, beta = sb arrB, gamma (Y terms)
+  const void* Qs;          // cx<R>[B][3][H+1]
+  const void* twg;
+  cx<double>* part;        // [B][nchunk][H+1]
+};
+
+// Sum over a range of items of
+//   alpha F1x F2x F3x + beta (F1x F2x Q3 + F1x Q2 F3x + Q1 F2x F3x)
+//   + gamma (F1y F2x F3x + F1x F2y F3x + F1x F2x F3y)
+// for sketch m, in FP64 registers; one work-group per (m, chunk).  The three
+// products are built mode by mode with the product rule, P = prod_j F_j x,
+// S = sum_j Q_j prod_{i != j} F_i x, Dy = sum_j F_j y prod_{i != j} F_i x, so
+// only P, S (and Dy) are held.  The owned bins are processed in NPART rounds
+// (the transforms are redone per round) to bound the registers.
+template <typename R, int LOGB, bool HAS_Y, int NPART>
+__global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a) {
+  constexpr int LOGH = LOGB - 1;
+  constexpr int NT = threads_for_h<R>(LOGH);
+  constexpr int H = 1 << LOGH;
+  constexpr int PL = padded_len(H);
+  constexpr int PK = (H / 2 + NT - 1) / NT;
+  constexpr int PKP = (PK + NPART - 1) / NPART;
+  extern __shared__ __align__(16) unsigned char lds[];
+  R* re = reinterpret_cast<R*>(lds);
+  R* im = re + PL;
+  const int n = a.n;
+  R* xv = reinterpret_cast<R*>(lds + align16(sizeof(R) * 2 * (size_t)PL));
+  R* yv = xv + ((n + 3) & ~3);
+  uint32_t* stab = reinterpret_cast<uint32_t*>(yv + ((n + 3) & ~3));  // [3][2][n]
+  const Soa<R> buf{re, im};
+  const int tid = threadIdx.x;
+  const int m = blockIdx.x;
+  const int chunk = blockIdx.y;
+  const size_t tb = (size_t)m * 3 * n;
+  const Twid<R> tw{reinterpret_cast<const cx<R>*>(a.twg),
+                   reinterpret_cast<const cx<R>*>(a.twg) + pass_table_len(H, NT)};
+  const cx<R>* Q = reinterpret_cast<const cx<R>*>(a.Qs) + (size_t)m * 3 * (H + 1);
+  const R* X = reinterpret_cast<const R*>(a.X);
+  const R* Y = reinterpret_cast<const R*>(a.Y);
+  for (int e = tid; e < n; e += NT)
+    for (int j = 0; j < 3; ++j) {
+      stab[(2 * j) * n + e] = a.hxs[tb + (size_t)j * n + e];
+      stab[(2 * j + 1) * n + e] = a.ord[tb + (size_t)j * n + e];
+    }
+  const int i0 = chunk * a.per, i1 = min(a.nitem, i0 + a.per);
+  cx<double>* out = a.part + ((size_t)m * gridDim.y + chunk) * (H + 1);
+  auto fft_mode = [&](const R* vec, int j) {
+    zero_lds<NT>(re, 2 * PL * (int)sizeof(R));
+    __syncthreads();
+    auto getu = [&](uint32_t i) -> R { return vec[i]; };
+    auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
+    count_sketch<R>(stab + (2 * j) * n, stab + (2 * j + 1) * n, n, NT, getu, store);
+    __syncthreads();
+    fft_soa<R, LOGH, NT, false, false>(buf, tw);
+  };
+  // owned bin pair (k, H-k) of slot s in round `part`; k < H/2 when valid
+  auto bin_k = [&](int part, int s) -> int {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t + (part * PKP + s) * NT;
+  };
+  auto addc = [](cx<double>& acc, double c, cx<R> v) {
+    acc.x += c * (double)v.x;
+    acc.y += c * (double)v.y;
+  };
+#pragma unroll 1
+  for (int part = 0; part < NPART; ++part) {
+    cx<double> acc0[PKP], acc1[PKP], accm = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < PKP; ++s) acc0[s] = acc1[s] = cx<double>{0.0, 0.0};
+#pragma unroll 1
+    for (int it = i0; it < i1; ++it) {
+      const double alpha = a.sa * a.arrA[it];
+      const double beta = a.sb * a.arrB[it];
+      if (alpha == 0.0 && beta == 0.0) continue;  // uniform: an empty word or a dropped document
+      __syncthreads();  // the previous item's readers of xv / yv are done
+      for (int e = tid; e < n; e += NT) {
+        xv[e] = X[(size_t)it * n + e];
+        if (HAS_Y) yv[e] = Y[(size_t)it * n + e];
+      }
+      cx<R> P0[PKP], P1[PKP], S0[PKP], S1[PKP], D0[PKP], D1[PKP], Pm, Sm, Dm;
+#pragma unroll 1
+      for (int j = 0; j < 3; ++j) {
+        fft_mode(xv, j);
+        cx<R> F0[PKP], F1[PKP], Fm;
+#pragma unroll
+        for (int s = 0; s < PKP; ++s) {
+          const int k = bin_k(part, s);
+          if (k >= H / 2) break;
+          const cx<R> Za = buf.get(k);
+          const cx<R> Zb = buf.get((H - k) & (H - 1));
+          F0[s] = r2c_post(Za, Zb, tw.w(k));
+          F1[s] = r2c_post(Zb, Za, tw.w(H - k));
+        }
+        if (tid == 0 && part == 0) {
+          const cx<R> Z = buf.get(H / 2);
+          Fm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
+        }
+        __syncthreads();
+        cx<R> G0[PKP], G1[PKP], Gm;  // F_j y
+        if constexpr (HAS_Y) {
+          fft_mode(yv, j);
+#pragma unroll
+          for (int s = 0; s < PKP; ++s) {
+            const int k = bin_k(part, s);
+            if (k >= H / 2) break;
+            const cx<R> Za = buf.get(k);
+            const cx<R> Zb = buf.get((H - k) & (H - 1));
+            G0[s] = r2c_post(Za, Zb, tw.w(k));
+            G1[s] = r2c_post(Zb, Za, tw.w(H - k));
+          }
+          if (tid == 0 && part == 0) {
+            const cx<R> Z = buf.get(H / 2);
+            Gm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
+          }
+          __syncthreads();
+        }
+        const cx<R>* Qj = Q + (size_t)j * (H + 1);
+        auto step = [&](cx<R>& P, cx<R>& S, cx<R>& Dy, cx<R> F, cx<R> G, cx<R> q) {
+          if (j == 0) {
+            if (HAS_Y) Dy = G;
+            S = q;
+            P = F;
+          } else {
+            if (HAS_Y) Dy = cadd(cmul(Dy, F), cmul(P, G));
+            S = cadd(cmul(S, F), cmul(P, q));
+            P = cmul(P, F);
+          }
+        };
+#pragma unroll
+        for (int s = 0; s < PKP; ++s) {
+          const int k = bin_k(part, s);
+          if (k >= H / 2) break;
+          step(P0[s], S0[s], D0[s], F0[s], HAS_Y ? G0[s] : F0[s], Qj[k]);
+          step(P1[s], S1[s], D1[s], F1[s], HAS_Y ? G1[s] : F1[s], Qj[H - k]);
+        }
+        if (tid == 0 && part == 0) step(Pm, Sm, Dm, Fm, HAS_Y ? Gm : Fm, Qj[H / 2]);
+      }
+      const double gam = a.gam;
+#pragma unroll
+      for (int s = 0; s < PKP; ++s) {
+        const int k = bin_k(part, s);
+        if (k >= H / 2) break;
+        addc(acc0[s], alpha, P0[s]);
+        addc(acc0[s], beta, S0[s]);
+        addc(acc1[s], alpha, P1[s]);
+        addc(acc1[s], beta, S1[s]);
+        if (HAS_Y) {
+          addc(acc0[s], gam, D0[s]);
+          addc(acc1[s], gam, D1[s]);
+        }
+      }
+      if (tid == 0 && part == 0) {
+        addc(accm, alpha, Pm);
+        addc(accm, beta, Sm);
+        if (HAS_Y) addc(accm, gam, Dm);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < PKP; ++s) {
+      const int k = bin_k(part, s);
+      if (k >= H / 2) break;
+      out[k] = acc0[s];
+      out[H - k] = acc1[s];  // k = 0 pairs with the Nyquist bin H
+    }
+    if (tid == 0 && part == 0) out[H / 2] = accm;
+  }
+}
+
+// S64[m][k] (+)= (sum of the document and word partials in chunk order) / D_eff
+//              + c prod_j Qs[m][j][k];  S32 = (float) S64.
+template <typename R>
+__global__ void k_terms_final(const cx<double>* partD, int ncD, const cx<double>* partW, int ncW,
+                              const cx<R>* Qs, const double* deff, double c3, int B, int H1,
+                              int accumulate, cx<double>* S64, cx<float>* S32) {
+  const size_t total = (size_t)B * H1;
+  const double D = deff[0];
+  const double invD = D > 0.0 ? 1.0 / D : 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int m = (int)(e / H1), k = (int)(e % H1);
+    cx<double> s = {0.0, 0.0};
+    for (int c = 0; c < ncD; ++c) {
+      const cx<double> v = partD[((size_t)m * ncD + c) * H1 + k];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    for (int c = 0; c < ncW; ++c) {
+      const cx<double> v = partW[((size_t)m * ncW + c) * H1 + k];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    const cx<R>* Qm = Qs + (size_t)m * 3 * H1;
+    const cx<double> q1 = {(double)Qm[k].x, (double)Qm[k].y};
+    const cx<double> q2 = {(double)Qm[H1 + k].x, (double)Qm[H1 + k].y};
+    const cx<double> q3 = {(double)Qm[2 * H1 + k].x, (double)Qm[2 * H1 + k].y};
+    const cx<double> qq = cmul(cmul(q1, q2), q3);
+    cx<double> r = {s.x * invD + c3 * qq.x, s.y * invD + c3 * qq.y};
+    if (accumulate) {
+      r.x += S64[e].x;
+      r.y += S64[e].y;
+    }
+    S64[e] = r;
+    if (S32) S32[e] = cx<float>{(float)r.x, (float)r.y};
+  }
+}
+
 __global__ void k_fill_u32(unsigned* p, unsigned v, size_t count) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
        e += (size_t)gridDim.x * blockDim.x)

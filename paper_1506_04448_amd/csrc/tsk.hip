@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstring>
 #include <math.h>
 #include <string.h>
 
@@ -14,6 +15,8 @@
 
 #include "../../include/tsk.h"
 #include "kernels.hpp"
+
+#include <rocprim/device/device_radix_sort.hpp>
 #include "status.hpp"
 
 using tsk::cx;
@@ -88,7 +91,8 @@ namespace {
 
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
-  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH
+  WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
+  WS_DOCS
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -140,15 +144,18 @@ static void unit_root(long j, long M, double* cs, double* sn) {
 }
 
 // Twiddle table of a length-b real transform (see fft.hpp, Twid): the per-pass
-// table of the H = b/2 point complex FFT with the kernels' thread count, then
-// W_b^k for k = 0..H.  Computed in FP64, rounded once to R.
+// table of the H = b/2 point complex FFT as run by `nt` threads (the radix
+// plan depends on it; 0 = the power kernel's thread count), then W_b^k for
+// k = 0..H.  Computed in FP64, rounded once to R; one table per (b, nt).
 template <typename R>
-tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out) {
+tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out, int nt = 0) {
   auto& mp = (sizeof(R) == 8) ? c->tw64 : c->tw32;
-  auto it = mp.find(logb);
+  if (nt == 0) nt = tsk::power_threads<R>(logb - 1);
+  const int key = (logb << 16) | nt;
+  auto it = mp.find(key);
   if (it == mp.end()) {
     const int b = 1 << logb, H = b / 2;
-    const int NT = tsk::power_threads<R>(logb - 1);
+    const int NT = nt;
     const int rmax = tsk::fft_rmax(H, NT);
     const int plen = tsk::pass_table_len(H, NT);
     std::vector<cx<R>> h(tsk::twid_len(H, NT));
@@ -175,7 +182,7 @@ tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out) {
     void* d = nullptr;
     TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * h.size()));
     TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * h.size(), hipMemcpyHostToDevice));
-    it = mp.emplace(logb, d).first;
+    it = mp.emplace(key, d).first;
   }
   *out = reinterpret_cast<const cx<R>*>(it->second);
   return TSK_OK;
@@ -738,6 +745,210 @@ extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
     TSK_TRY(power_launch<double>(ctx, tab, S64, L, 0, 0, 1, (const double*)U, nullptr, nullptr,
                                  nullptr, (double*)vbuf, (double*)lp, S(stream)));
   return lam_median_launch((const double*)lp, lam_med, L, tab->B, S(stream));
+}
+
+// =============================================================================
+// Sketch of the whitened LDA moment from document word counts (Appendix D)
+// =============================================================================
+
+namespace {
+
+template <typename R>
+size_t terms_lds_bytes(int logh, int n) {
+  const size_t PL = (size_t)tsk::padded_len(1 << logh);
+  return tsk::align16(sizeof(R) * 2 * PL) + 2 * sizeof(R) * (size_t)((n + 3) & ~3) + 24 * (size_t)n;
+}
+
+template <typename R, int LOGB, bool HAS_Y>
+tsk_status launch_terms_t(const tsk::TermArgs& a, int B, int nchunk, hipStream_t st) {
+  // the word terms hold three running products: their bins go in two rounds
+  constexpr int NPART = HAS_Y ? 2 : 1;
+  constexpr int NT = tsk::threads_for_h<R>(LOGB - 1);
+  const size_t lds = terms_lds_bytes<R>(LOGB - 1, a.n);
+  if (lds > kMaxLds)
+    return tsk::fail(TSK_EUNSUPPORTED, "document sketch: K=%d needs %zu bytes of LDS at b=2^%d", a.n, lds,
+                     LOGB);
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_terms<R, LOGB, HAS_Y, NPART>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL((tsk::k_terms<R, LOGB, HAS_Y, NPART>), dim3(B, nchunk), dim3(NT), lds, st, a);
+  return check_launch("k_terms");
+}
+
+template <typename R, bool HAS_Y>
+tsk_status launch_terms(int logb, const tsk::TermArgs& a, int B, int nchunk, hipStream_t st) {
+#define TSK_TERMS(L) launch_terms_t<R, L, HAS_Y>(a, B, nchunk, st)
+  TSK_LOGB_SWITCH(logb, TSK_TERMS);
+#undef TSK_TERMS
+  return tsk::fail(TSK_EUNSUPPORTED, "document sketch: b=2^%d not built", logb);
+}
+
+template <typename R, int LOGB>
+tsk_status launch_mode_spectra_t(tsk_tables_t tab, const double* q, const cx<R>* tw, cx<R>* Qs,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL((tsk::k_mode_spectra<R, LOGB>), dim3(tab->B, 3), dim3(tsk::threads_for_h<R>(LOGB - 1)),
+                     0, st, tab->hxs, tab->ord, tab->n, q, tw, Qs);
+  return check_launch("k_mode_spectra");
+}
+
+template <typename R>
+tsk_status launch_mode_spectra(int logb, tsk_tables_t tab, const double* q, const cx<R>* tw, cx<R>* Qs,
+                               hipStream_t st) {
+#define TSK_MSPEC(L) launch_mode_spectra_t<R, L>(tab, q, tw, Qs, st)
+  TSK_LOGB_SWITCH(logb, TSK_MSPEC);
+#undef TSK_MSPEC
+  return tsk::fail(TSK_EUNSUPPORTED, "document sketch: b=2^%d not built", logb);
+}
+
+template <typename R>
+tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowptr, const int32_t* col,
+                           const int32_t* cnt, int D, int V, int nnz, const R* W, double alpha0,
+                           double* S64, float* S32, int accumulate, hipStream_t st) {
+  const int K = tab->n, B = tab->B, b = tab->b, logb = tab->logb;
+  const int H1 = b / 2 + 1;
+  const cx<R>* tw = nullptr;  // the document kernels run threads_for_h threads
+  TSK_TRY(get_tw<R>(ctx, logb, &tw, tsk::threads_for_h<R>(logb - 1)));
+  const int G = std::max(1, std::min(1024, (D + 255) / 256));
+  const int per_q = (D + G - 1) / G;
+  const int ncD = std::max(1, std::min(128, (D + 63) / 64));
+  const int ncW = std::max(1, std::min(64, (V + 63) / 64));
+  size_t sort_tmp = 0;
+  TSK_HIP(rocprim::radix_sort_pairs(nullptr, sort_tmp, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                    (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)nnz, 0, 32, st));
+  // one workspace, 256-byte aligned pieces
+  size_t off = 0;
+  std::vector<size_t> offs;
+  auto take = [&](size_t bytes) {
+    offs.push_back(off);
+    off += (bytes + 255) & ~(size_t)255;
+  };
+  take((size_t)D * K * sizeof(R));              // 0 P
+  take((size_t)D * 8);                          // 1 cd
+  take((size_t)D * 8);                          // 2 cpd
+  take((size_t)D * 8);                          // 3 invm
+  take((size_t)G * (K + 1) * 8);                // 4 q partials
+  take((size_t)K * 8);                          // 5 q
+  take(8);                                      // 6 D_eff
+  take((size_t)nnz * 4);                        // 7 rowof
+  take((size_t)nnz * 4);                        // 8 iota
+  take((size_t)nnz * 4);                        // 9 sorted word ids
+  take((size_t)nnz * 4);                        // 10 sorted nonzero index
+  take(sort_tmp);                               // 11 sort scratch
+  take((size_t)(V + 1) * 4);                    // 12 colptr
+  take((size_t)V * K * sizeof(R));              // 13 R_i
+  take((size_t)V * 8);                          // 14 g
+  take((size_t)V * 8);                          // 15 g'
+  take((size_t)B * 3 * H1 * sizeof(cx<R>));     // 16 Q spectra
+  take((size_t)B * ncD * H1 * 16);              // 17 document partials
+  take((size_t)B * ncW * H1 * 16);              // 18 word partials
+  void* base = nullptr;
+  TSK_TRY(ws_get(ctx, WS_DOCS, off, &base));
+  auto at = [&](int i) { return reinterpret_cast<char*>(base) + offs[i]; };
+  R* P = (R*)at(0);
+  double *cd = (double*)at(1), *cpd = (double*)at(2), *invm = (double*)at(3);
+  double *qpart = (double*)at(4), *q = (double*)at(5), *deff = (double*)at(6);
+  int32_t *rowof = (int32_t*)at(7), *iota = (int32_t*)at(8), *skeys = (int32_t*)at(9);
+  int32_t *svals = (int32_t*)at(10), *colptr = (int32_t*)at(12);
+  R* Rw = (R*)at(13);
+  double *g = (double*)at(14), *gp = (double*)at(15);
+  cx<R>* Qs = (cx<R>*)at(16);
+  cx<double>* partD = (cx<double>*)at(17);
+  cx<double>* partW = (cx<double>*)at(18);
+
+  hipLaunchKernelGGL(tsk::k_doc_project<R>, dim3(std::min(D, 8192)), dim3(128), 0, st, rowptr, col, cnt,
+                     D, K, W, P, cd, cpd, invm);
+  TSK_TRY(check_launch("k_doc_project"));
+  hipLaunchKernelGGL(tsk::k_doc_q_partial<R>, dim3(G), dim3(128), 0, st, (const R*)P, (const double*)invm,
+                     D, K, per_q, qpart);
+  hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
+  TSK_TRY(check_launch("k_doc_q"));
+  // words: documents containing each word, in document order (stable sort by word)
+  if (nnz > 0) {
+    hipLaunchKernelGGL(tsk::k_rowof, dim3(grid_for((size_t)D, 256)), dim3(256), 0, st, rowptr, D, rowof,
+                       iota);
+    TSK_TRY(check_launch("k_rowof"));
+    size_t tmp = sort_tmp;
+    TSK_HIP(rocprim::radix_sort_pairs(at(11), tmp, col, skeys, (const int32_t*)iota, svals, (size_t)nnz, 0,
+                                      32, st));
+  }
+  hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
+                     (const int32_t*)skeys, nnz, V, colptr);
+  TSK_TRY(check_launch("k_col_bounds"));
+  hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)svals,
+                     (const int32_t*)colptr, (const int32_t*)rowof, cnt, (const R*)P, (const double*)cd,
+                     (const double*)cpd, V, K, Rw, g, gp);
+  TSK_TRY(check_launch("k_word_accum"));
+  TSK_TRY(launch_mode_spectra<R>(logb, tab, q, tw, Qs, st));
+  const double a = alpha0 / (alpha0 + 2.0);
+  const double c3 = 2.0 * alpha0 * alpha0 / ((alpha0 + 1.0) * (alpha0 + 2.0));
+  tsk::TermArgs ta;
+  ta.hxs = tab->hxs;
+  ta.ord = tab->ord;
+  ta.n = K;
+  ta.B = B;
+  ta.Qs = Qs;
+  ta.twg = tw;
+  // documents: c_d p^(x)3 - a c'_d (p p q + p q p + q p p)
+  ta.nitem = D;
+  ta.per = (D + ncD - 1) / ncD;
+  ta.X = P;
+  ta.Y = nullptr;
+  ta.arrA = cd;
+  ta.arrB = cpd;
+  ta.sa = 1.0;
+  ta.sb = -a;
+  ta.gam = 0.0;
+  ta.part = partD;
+  TSK_TRY((launch_terms<R, false>(logb, ta, B, ncD, st)));
+  // words: 2 g w^(x)3 + a g' (w w q + w q w + q w w) - (w w R + w R w + R w w)
+  ta.nitem = V;
+  ta.per = (V + ncW - 1) / ncW;
+  ta.X = W;
+  ta.Y = Rw;
+  ta.arrA = g;
+  ta.arrB = gp;
+  ta.sa = 2.0;
+  ta.sb = a;
+  ta.gam = -1.0;
+  ta.part = partW;
+  TSK_TRY((launch_terms<R, true>(logb, ta, B, ncW, st)));
+  hipLaunchKernelGGL(tsk::k_terms_final<R>, dim3(grid_for((size_t)B * H1, 256)), dim3(256), 0, st,
+                     (const cx<double>*)partD, ncD, (const cx<double>*)partW, ncW, (const cx<R>*)Qs,
+                     (const double*)deff, c3, B, H1, accumulate, reinterpret_cast<cx<double>*>(S64),
+                     reinterpret_cast<cx<float>*>(S32));
+  return check_launch("k_terms_final");
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_sketch_build_docs(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowptr,
+                                            const int32_t* col, const int32_t* cnt, int D, int V,
+                                            const void* W, tsk_dtype wdtype, double alpha0, double* S64,
+                                            float* S32, int accumulate, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_sketch_build_docs"));
+  if (!rowptr || !W || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: null argument");
+  if (D < 1 || V < 1) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: D=%d, V=%d must be >= 1", D, V);
+  if (wdtype != TSK_F32 && wdtype != TSK_F64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: bad dtype");
+  if (!(alpha0 >= 0.0) || alpha0 > 1e300)
+    return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: alpha0=%g must be finite and >= 0", alpha0);
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  int32_t nnz = 0;
+  TSK_HIP(hipMemcpyAsync(&nnz, rowptr + D, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TSK_HIP(hipStreamSynchronize(st));
+  if (nnz < 0) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: rowptr[D]=%d < 0", nnz);
+  if (nnz > 0 && (!col || !cnt)) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: null col or cnt");
+  if (wdtype == TSK_F32)
+    return build_docs_impl<float>(ctx, tab, rowptr, col, cnt, D, V, nnz, (const float*)W, alpha0, S64, S32,
+                                  accumulate, st);
+  return build_docs_impl<double>(ctx, tab, rowptr, col, cnt, D, V, nnz, (const double*)W, alpha0, S64,
+                                 S32, accumulate, st);
 }
 
 // =============================================================================
