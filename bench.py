@@ -225,6 +225,68 @@ def c3_batched(ctx, dev, nrep: int = 3):
     }
 
 
+def c4_docs(ctx, dev, D: int, nrep: int = 3):
+    """Spectral-LDA moment sketch from a synthetic corpus (V=20000, K=100,
+    mean length 150) and its decomposition: the document build of the
+    whitened third moment, then Algorithm 1 on the K^3 sketch."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    from paper_1506_04448_amd.workloads import lda_corpus_fast, population_whitening
+    V, K, b, B, L, T = 20000, 100, 16384, 8, 50, 30
+    t0 = time.perf_counter()
+    C = lda_corpus_fast(D, V, K, seed=3)
+    gen_s = time.perf_counter() - t0
+    alpha0 = float(C.alpha.sum())
+    W = population_whitening(C.Phi, C.alpha)
+    h, xi = tsk.hash_generate(3, K, b, B)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, dev)
+    rp = torch.from_numpy(C.rowptr).to(dev)
+    col = torch.from_numpy(C.col).to(dev)
+    cnt = torch.from_numpy(C.cnt).to(dev)
+    Wd = torch.from_numpy(W.astype(np.float32)).to(dev)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tsk.sketch_build_docs(ctx, tab, rp, col, cnt, V, Wd, alpha0, S64, S32)
+    tb = []
+    for _ in range(nrep):
+        e0.record(stream)
+        tsk.sketch_build_docs(ctx, tab, rp, col, cnt, V, Wd, alpha0, S64, S32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tb.append(e0.elapsed_time(e1))
+    build_ms = float(np.median(tb))
+    S64_0, S32_0 = S64.clone(), S32.clone()
+    td = []
+    for r in range(nrep + 1):
+        S64.copy_(S64_0)
+        S32.copy_(S32_0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, K, L, T, dtype=tsk.F32, seed=3)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            td.append(e0.elapsed_time(e1))
+    dec_ms = float(np.median(td))
+    # population components of the whitened moment: v_i ~ W^T mu_i (orthonormal)
+    Vp = (W.T @ C.Phi).T
+    Vp /= np.linalg.norm(Vp, axis=1, keepdims=True)
+    matched = int(np.sum(np.abs(Vp @ U.cpu().numpy().T).max(axis=1) > 0.9))
+    updates = K * (T + 1) * L * B
+    nnz = int(C.rowptr[-1])
+    tab.close()
+    return {
+        "workload": (f"synthetic LDA corpus D={D}, V={V}, K={K} topics (Dirichlet 0.01 topics, 0.1 "
+                     f"mixtures, Poisson(150) lengths), population whitening; b={b}, B={B}; "
+                     f"decomposition k={K}, L={L}, T={T}"),
+        "documents": D, "nnz": nnz, "words": int(C.cnt.sum()), "corpus_generation_s": gen_s,
+        "build_ms": build_ms, "documents_per_s": D / (build_ms * 1e-3),
+        "decompose_ms": dec_ms, "sketch_updates_per_s": updates / (dec_ms * 1e-3),
+        "topics_matched_0.9": matched,
+    }
+
+
 def cpu_baseline(P, h, xi, budget_s: float):
     """The CPU oracle timed on a bounded sample of the same workload: the dense
     build of all B sketches, then power steps over all L restarts until the
@@ -288,6 +350,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the batched uneven-instance leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the LDA document-build leg")
+    ap.add_argument("--c4-docs", type=int, default=500000, help="documents in the LDA corpus")
     ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
@@ -414,6 +478,7 @@ def main():
         }
 
     c3 = None if args.no_c3 else c3_batched(ctx, dev)
+    c4 = None if args.no_c4 else c4_docs(ctx, dev, args.c4_docs)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -453,6 +518,7 @@ def main():
         "decompose_sketch_updates_per_s": updates / (decompose_ms * 1e-3),
         "speedup_vs_plain": (plain["decompose_ms"] / decompose_ms) if plain else None,
         "batched_instances": c3,
+        "lda_documents": c4,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -124,3 +124,55 @@ def lda_corpus(D: int, V: int, K: int, seed: int, mean_len: float = 150.0,
         rowptr[d + 1] = rowptr[d] + nz.size
     return Corpus(rowptr=rowptr.astype(np.int32), col=np.concatenate(cols),
                   cnt=np.concatenate(cnts), V=V, K=K, alpha=alph, Phi=Phi)
+
+
+def lda_corpus_fast(D: int, V: int, K: int, seed: int, mean_len: float = 150.0,
+                    beta: float = 0.01, alpha: float = 0.1, min_len: int = 3,
+                    batch: int = 50000) -> Corpus:
+    """The same generative model as lda_corpus, drawn in bulk for large D:
+    per-document topic counts ~ Multinomial(m_d, theta_d), then each topic's
+    words ~ Cat(Phi_k) by inverse-CDF sampling, merged into CSR counts.  (Its
+    random stream differs from lda_corpus's.)"""
+    rng = np.random.default_rng(seed)
+    Phi = rng.dirichlet(np.full(V, beta), size=K).T.copy()      # [V][K]
+    cdf = np.cumsum(Phi, axis=0)
+    cdf /= cdf[-1]
+    alph = np.full(K, alpha)
+    rows, cols, cnts = [np.zeros(1, dtype=np.int64)], [], []
+    total = 0
+    for d0 in range(0, D, batch):
+        nd = min(batch, D - d0)
+        m = rng.poisson(mean_len, size=nd)
+        while (m < min_len).any():
+            bad = m < min_len
+            m[bad] = rng.poisson(mean_len, size=int(bad.sum()))
+        theta = rng.dirichlet(alph, size=nd)
+        zc = rng.multinomial(m, theta)                             # [nd][K] topic counts
+        doc_of = np.repeat(np.arange(nd), m)
+        words = np.empty(int(m.sum()), dtype=np.int64)
+        # positions grouped by topic: for each document, its words of topic k
+        topic = np.repeat(np.tile(np.arange(K), nd), zc.ravel())
+        for k in range(K):
+            sel = np.flatnonzero(topic == k)
+            if sel.size:
+                words[sel] = np.searchsorted(cdf[:, k], rng.random(sel.size), side="right")
+        np.minimum(words, V - 1, out=words)
+        key = np.unique(doc_of * V + words, return_counts=True)
+        d_idx, w_idx = np.divmod(key[0], V)
+        per_doc = np.bincount(d_idx, minlength=nd)
+        rows.append(total + np.cumsum(per_doc))
+        total += int(per_doc.sum())
+        cols.append(w_idx.astype(np.int32))
+        cnts.append(key[1].astype(np.int32))
+    rowptr = np.concatenate(rows)
+    return Corpus(rowptr=rowptr.astype(np.int32), col=np.concatenate(cols),
+                  cnt=np.concatenate(cnts), V=V, K=K, alpha=alph, Phi=Phi)
+
+
+def population_whitening(Phi: np.ndarray, alpha: np.ndarray) -> np.ndarray:
+    """W (V x K) with W^T M2 W = I for the population second moment
+    M2 = sum_i alpha_i mu_i mu_i^T / (alpha0 (alpha0 + 1)) of the LDA model."""
+    a0 = float(np.sum(alpha))
+    A = Phi * np.sqrt(alpha / (a0 * (a0 + 1.0)))
+    U, s, _ = np.linalg.svd(A, full_matrices=False)
+    return U / s
