@@ -167,7 +167,7 @@ def c3_batched(ctx, dev, nrep: int = 3):
     insts = factor_instances(64, seed=2, b_choices=(4096, 16384, 65536))
     probs, seq, keep, tabs = [], [], [], []
     for i, inst in enumerate(insts):
-        b = min(inst.b, 16384)
+        b = inst.b
         h, xi = tsk.hash_generate(2 + i, inst.n, b, Bc)
         tab = tsk.Tables(ctx, h, xi, b)
         tabs.append(tab)
@@ -216,7 +216,7 @@ def c3_batched(ctx, dev, nrep: int = 3):
         t.close()
     return {
         "workload": ("64 factor instances, n~U{100..2000}, k~U{5..50}, lam~U[1,10], unit "
-                     "non-orthogonal factors, b from {4096,16384,65536} (65536 run at 16384), "
+                     "non-orthogonal factors, b from {4096,16384,65536}, "
                      f"B={Bc}, L={Lc}, T={Tc}, FP32 power steps"),
         "sketch_updates": updates, "batched_ms": ms_b, "sequential_ms": ms_s,
         "sketch_updates_per_s": updates / (ms_b * 1e-3), "speedup_vs_sequential": ms_s / ms_b,
@@ -287,6 +287,62 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
     }
 
 
+def c5_autograd(ctx, dev, steps: int = 20):
+    """Gradient extensions at the shapes of the differentiation workload:
+    n=1000, k=100 planted orthonormal components (lam ~ U[1,2]), b=65536,
+    B=16, FP32.  The sketches are built from the factors (the 4 GB dense
+    tensor and its noise are not formed).  Timed: the T(u,u,u) estimate with
+    its gradient for 256 vectors, and the sketched CP loss with its
+    gradients; then Adam steps from a perturbed start."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    from paper_1506_04448_amd import autograd as tag
+    n, k, b, B, nb = 1000, 100, 65536, 16, 256
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    lam = rng.uniform(1.0, 2.0, k)
+    h, xi = tsk.hash_generate(4, n, b, B)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, dev)
+    tsk.sketch_build_factors(ctx, tab, torch.from_numpy(lam).to(dev), torch.from_numpy(Q.T.copy()).to(dev),
+                             S64, S32)
+    U = torch.nn.functional.normalize(torch.randn((nb, n), device=dev), dim=1)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tsk.contract_tuuu_grad(ctx, tab, U, S32=S32)
+    e0.record(stream)
+    for _ in range(3):
+        tsk.contract_tuuu_grad(ctx, tab, U, S32=S32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tuuu_ms = e0.elapsed_time(e1) / 3
+    lam0 = torch.from_numpy((lam * (1 + 0.05 * rng.standard_normal(k))).astype(np.float32)).to(dev)
+    U0 = Q.T + 0.02 * rng.standard_normal((k, n))
+    U0 = torch.from_numpy((U0 / np.linalg.norm(U0, axis=1, keepdims=True)).astype(np.float32)).to(dev)
+    tsk.cp_loss(ctx, tab, S64, lam0, U0)
+    e0.record(stream)
+    for _ in range(3):
+        tsk.cp_loss(ctx, tab, S64, lam0, U0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loss_ms = e0.elapsed_time(e1) / 3
+    sk = tag.SketchHandle(ctx, tab, S64, None)
+    t0 = time.perf_counter()
+    lam_r, U_r, losses = tag.refine_adam(sk, lam0, U0, steps=steps, lr=1e-3)
+    torch.cuda.synchronize()
+    adam_s = time.perf_counter() - t0
+    losses = losses.cpu().numpy()
+    tab.close()
+    return {
+        "workload": (f"n={n}, k={k} planted orthonormal factors, b={b}, B={B}, FP32; sketches from the "
+                     f"factors; T(u,u,u) with gradient for {nb} vectors; CP loss with gradients"),
+        "tuuu_grad_ms": tuuu_ms, "tuuu_grad_vectors_per_s": nb / (tuuu_ms * 1e-3),
+        "cp_loss_grad_ms": loss_ms,
+        "adam_steps": steps, "adam_s_per_step": adam_s / steps,
+        "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+    }
+
+
 def cpu_baseline(P, h, xi, budget_s: float):
     """The CPU oracle timed on a bounded sample of the same workload: the dense
     build of all B sketches, then power steps over all L restarts until the
@@ -352,6 +408,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the batched uneven-instance leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the LDA document-build leg")
     ap.add_argument("--c4-docs", type=int, default=500000, help="documents in the LDA corpus")
+    ap.add_argument("--no-c5", action="store_true", help="skip the gradient-extension leg")
     ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
@@ -479,6 +536,7 @@ def main():
 
     c3 = None if args.no_c3 else c3_batched(ctx, dev)
     c4 = None if args.no_c4 else c4_docs(ctx, dev, args.c4_docs)
+    c5 = None if args.no_c5 else c5_autograd(ctx, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -519,6 +577,7 @@ def main():
         "speedup_vs_plain": (plain["decompose_ms"] / decompose_ms) if plain else None,
         "batched_instances": c3,
         "lda_documents": c4,
+        "gradients": c5,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

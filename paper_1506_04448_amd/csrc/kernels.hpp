@@ -22,18 +22,30 @@ namespace tsk {
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
+// v from lane + o of the wave (own value past lane 63).  `lane` is passed in
+// so callers can hide it from the compiler: the lane addresses are then
+// recomputed per call instead of being kept live across a whole kernel.
+__device__ __forceinline__ double wave_down(double v, int o, int lane) {
+  const int idx = ((lane + o) < 64 ? lane + o : lane) << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(idx, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(idx, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over the work-group, returned to every thread.  `red` holds NT/64 doubles.
 template <int NT>
 __device__ double block_sum(double v, double* red) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  for (int o = 32; o > 0; o >>= 1) v += wave_down(v, o, lane);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  if (lane == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x < 64) {
     double s = (threadIdx.x < NT / 64) ? red[threadIdx.x] : 0.0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    for (int o = 32; o > 0; o >>= 1) s += wave_down(s, o, lane);
     if (threadIdx.x == 0) red[0] = s;
   }
   __syncthreads();
@@ -140,12 +152,13 @@ template <typename R>
 constexpr int power_threads(int logh) {
   return (sizeof(R) == 4 && logh >= 10) ? (1 << (logh - 4)) : threads_for_h<R>(logh);
 }
-// Waves per SIMD the power kernel is compiled for (FP32: two work-groups per CU).
+// Waves per SIMD the power kernel is compiled for: two FP32 work-groups per
+// CU while the sequence takes at most half the LDS (H <= 8192), one otherwise.
 template <typename R>
 constexpr int power_waves(int logh) {
-  return power_threads<R>(logh) / (sizeof(R) == 4 ? 128 : 256) < 1
+  return power_threads<R>(logh) / ((sizeof(R) == 4 && logh <= 13) ? 128 : 256) < 1
              ? 1
-             : power_threads<R>(logh) / (sizeof(R) == 4 ? 128 : 256);
+             : power_threads<R>(logh) / ((sizeof(R) == 4 && logh <= 13) ? 128 : 256);
 }
 
 constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -437,10 +450,14 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   fft_soa<R, LOGH, NT, true, false>(buf, tw);
 
   const R scale = R(2) / R(b);
-  const uint32_t* hx1 = a.hx + tb + (size_t)a.rd * n;
-  R* Vrow = a.V + ((size_t)tau * B + m) * n;
+  // Read-off addresses formed here from opaque copies of the indices, so the
+  // compiler does not keep them live (or spill them) through the transforms.
+  int om = m, otau = tau, orid = tid;
+  asm volatile("" : "+v"(orid), "+s"(om), "+s"(otau));
+  const uint32_t* hx1 = a.hx + (size_t)om * 3 * n + (size_t)a.rd * n;
+  R* Vrow = a.V + ((size_t)otau * B + om) * n;
   double acc = 0.0;
-  for (int i = tid; i < n; i += NT) {
+  for (int i = orid; i < n; i += NT) {
     const uint32_t e = tab_lds ? stab[4 * n + i] : hx1[i];
     const R val = load_packed(buf, e >> 1) * scale;
     const R v = (e & 1u) ? -val : val;
@@ -662,6 +679,7 @@ template <typename TIn>
 struct BuildArgs {
   const TIn* T;
   int n, b, B, G;
+  int nrange, lbr;            // bucket ranges per sketch, log2 of their length
   const uint32_t* hx;         // [B][3][n]
   long long pairs_per_slab;
   int nslab, ngroups;
@@ -717,13 +735,17 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   const int slab = (r / a.ngroups) * 8 + xcd;
   const int grp = r % a.ngroups;
   if (slab >= a.nslab) return;  // padding blocks of the XCD mapping
+  // Work-group `grp` holds the bins of G consecutive (sketch, bucket range)
+  // pairs; with more than one range per sketch G is 1.
   const int g0 = grp * G;
-  const int Gc = min(G, a.B - g0);
+  const int Gc = min(G, a.B * a.nrange - g0);
+  const int br = 1 << a.lbr;
+  const int sk0 = g0 / a.nrange, rq = g0 % a.nrange;
   unsigned long long* bins = pool;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(pool + (size_t)G * b);
+  uint32_t* tab = reinterpret_cast<uint32_t*>(pool + (size_t)G * br);
   const int tid = threadIdx.x;
-  for (int t = tid; t < G * b; t += blockDim.x) bins[t] = 0ull;
-  for (int t = tid; t < Gc * 3 * n; t += blockDim.x) tab[t] = a.hx[(size_t)g0 * 3 * n + t];
+  for (int t = tid; t < G * br; t += blockDim.x) bins[t] = 0ull;
+  for (int t = tid; t < Gc * 3 * n; t += blockDim.x) tab[t] = a.hx[(size_t)sk0 * 3 * n + t];
 
   const long long npairs = (long long)n * n;
   const long long p0 = (long long)slab * a.pairs_per_slab;
@@ -768,7 +790,7 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
           }
         for (int g = 0; g < Gc; ++g) {
           const uint32_t* tg = tab + g * 3 * n;
-          unsigned long long* bg = bins + (size_t)g * b;
+          unsigned long long* bg = bins + (size_t)g * br;
           uint32_t off[NF];  // (h1(i) + h2(j)) << 1 | sign bit, per fibre
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
@@ -783,9 +805,9 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
 #pragma unroll
               for (int f = 0; f < NF; ++f) {
                 if (f < nf) {
-                  const uint32_t t = (off[f] >> 1) + (e3 >> 1);
+                  const uint32_t t = ((off[f] >> 1) + (e3 >> 1)) & bmask;
                   const long long v = ((off[f] ^ e3) & 1u) ? -x[f][c] : x[f][c];
-                  atomicAdd(&bg[t & bmask], (unsigned long long)v);
+                  if ((int)(t >> a.lbr) == rq) atomicAdd(&bg[t & (unsigned)(br - 1)], (unsigned long long)v);
                 }
               }
             }
@@ -795,30 +817,34 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
     }
   }
   __syncthreads();
-  double* out = a.partial + ((size_t)grp * a.nslab + slab) * (size_t)G * b;
-  for (int t = tid; t < Gc * b; t += blockDim.x)
+  double* out = a.partial + ((size_t)grp * a.nslab + slab) * (size_t)G * br;
+  for (int t = tid; t < Gc * br; t += blockDim.x)
     out[t] = bad ? __builtin_nan("") : (double)(long long)bins[t] * down;
 }
 
-// s_time[m][t] = sum over slabs of the partial bins (FP64).
-__global__ void k_build_reduce(const double* partial, double* s_time, int b, int B, int G, int nslab) {
+// s_time[m][t] = sum over slabs of the partial bins (FP64); bucket t of
+// sketch m lives in range t >> lbr of virtual sketch m * nrange + range.
+__global__ void k_build_reduce(const double* partial, double* s_time, int b, int B, int G, int nslab,
+                               int nrange, int lbr) {
   const size_t total = (size_t)B * b;
+  const int br = 1 << lbr;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const int m = (int)(e / b);
     const int t = (int)(e - (size_t)m * b);
-    const int grp = m / G, g = m - grp * G;
-    const double* p = partial + ((size_t)grp * nslab * G + g) * b + t;
+    const int vs = m * nrange + (t >> lbr);
+    const int grp = vs / G, g = vs - grp * G;
+    const double* p = partial + ((size_t)grp * nslab * G + g) * br + (t & (br - 1));
     double s = 0.0;
     int sl = 0;
-    for (; sl + 8 <= nslab; sl += 8) {
+    for (; sl + 8 <= nslab; sl += 8) {  // eight loads in flight, summed in slab order
       double t8[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) t8[q] = (double)p[(size_t)(sl + q) * G * b];
+      for (int q = 0; q < 8; ++q) t8[q] = p[(size_t)(sl + q) * G * br];
 #pragma unroll
       for (int q = 0; q < 8; ++q) s += t8[q];
     }
-    for (; sl < nslab; ++sl) s += (double)p[(size_t)sl * G * b];
+    for (; sl < nslab; ++sl) s += p[(size_t)sl * G * br];
     s_time[e] = s;
   }
 }

@@ -15,6 +15,7 @@
 
 #include "../../include/tsk.h"
 #include "kernels.hpp"
+#include "large.hpp"
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include "status.hpp"
@@ -45,7 +46,12 @@ char* last_error_buffer() {
 namespace {
 
 constexpr int kMinLogB = 6;
-constexpr int kMaxLogB = 14;       // every transform fits one work-group's LDS
+constexpr int kMaxLogB = 16;
+// Up to this size every FP64 transform fits one work-group's LDS; longer ones
+// are split by residue into sub-transforms of 2^kSubLogM64 points (large.hpp).
+constexpr int kLdsLogB = 14;
+constexpr int kSubLogM64 = 13;
+constexpr int kSubLogM32 = 14;     // FP32 power steps at b = 65536
 
 int ilog2_exact(int b) {
   if (b <= 0 || (b & (b - 1))) return -1;
@@ -71,6 +77,7 @@ struct tsk_ctx {
   int device = 0;
   hipStream_t cap = nullptr;
   std::map<int, void*> tw64, tw32;
+  std::map<int, void*> wb64, wb32;   // full-circle tables W_b^x, x < b
   std::map<int, DevBuf> ws;          // named workspaces
   std::vector<GraphEntry> graphs;
   std::vector<uint64_t> u0_key;      // cached generated start vectors
@@ -92,7 +99,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS
+  WS_DOCS, WS_SPLIT, WS_SPLITP
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -188,6 +195,28 @@ tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out, int nt = 0) {
   return TSK_OK;
 }
 
+// W_b^x for x in [0, b), computed in FP64 and rounded once to R.
+template <typename R>
+tsk_status get_wb(tsk_ctx* c, int logb, const cx<R>** out) {
+  auto& mp = (sizeof(R) == 8) ? c->wb64 : c->wb32;
+  auto it = mp.find(logb);
+  if (it == mp.end()) {
+    const int b = 1 << logb;
+    std::vector<cx<R>> h(b);
+    for (int x = 0; x < b; ++x) {
+      double cs, sn;
+      unit_root(x, b, &cs, &sn);
+      h[x] = cx<R>{(R)cs, (R)sn};
+    }
+    void* d = nullptr;
+    TSK_HIP(hipMalloc(&d, sizeof(cx<R>) * h.size()));
+    TSK_HIP(hipMemcpy(d, h.data(), sizeof(cx<R>) * h.size(), hipMemcpyHostToDevice));
+    it = mp.emplace(logb, d).first;
+  }
+  *out = reinterpret_cast<const cx<R>*>(it->second);
+  return TSK_OK;
+}
+
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 tsk_status check_launch(const char* what) {
@@ -259,9 +288,12 @@ tsk_status launch_power(int logb, const tsk::PowerArgs<R>& a, int B, int nrest, 
     case 12: return launch_power_t<R, 12>(a, B, nrest, st);
     case 13: return launch_power_t<R, 13>(a, B, nrest, st);
     case 14: return launch_power_t<R, 14>(a, B, nrest, st);
+    case 15:
+      if constexpr (sizeof(R) == 4) return launch_power_t<R, 15>(a, B, nrest, st);
+      break;
     default: break;
   }
-  return tsk::fail(TSK_EUNSUPPORTED, "power step: b=2^%d not built", logb);
+  return tsk::fail(TSK_EUNSUPPORTED, "power step: b=2^%d not built in this precision", logb);
 }
 
 template <int LOGB>
@@ -325,6 +357,128 @@ int grid_for(size_t count, int threads) {
   return (int)std::min<size_t>(std::max<size_t>(g, 1), 65536);
 }
 
+// ---- transforms longer than one work-group's LDS (see large.hpp) ------------
+
+int sub_R64(int logb) { return 1 << (logb - 1 - kSubLogM64); }
+
+// Sub-transform buffer of the split rank-1 spectra of c vectors.
+size_t rank1_split_bytes(tsk_tables_t tab, int c) {
+  return (size_t)c * tab->B * 3 * sub_R64(tab->logb) * ((size_t)1 << kSubLogM64) * sizeof(cx<double>);
+}
+
+// Tables the split paths read, uploaded outside any graph capture.
+tsk_status preload_split_tables(tsk_ctx_t ctx, int logb, bool fp32_power) {
+  if (logb <= kLdsLogB) return TSK_OK;
+  const cx<double>* t64 = nullptr;
+  const cx<double>* w64 = nullptr;
+  TSK_TRY(get_tw<double>(ctx, kSubLogM64 + 1, &t64, tsk::threads_for_h<double>(kSubLogM64)));
+  TSK_TRY(get_wb<double>(ctx, logb, &w64));
+  if (fp32_power) {
+    const cx<float>* t32 = nullptr;
+    const cx<float>* w32 = nullptr;
+    TSK_TRY(get_tw<float>(ctx, kSubLogM32 + 1, &t32, tsk::threads_for_h<float>(kSubLogM32)));
+    TSK_TRY(get_wb<float>(ctx, logb, &w32));
+  }
+  return TSK_OK;
+}
+
+// prod / lam_per of Rank1Args a for c vectors through the split transforms.
+tsk_status rank1_split(tsk_ctx_t ctx, tsk_tables_t tab, const tsk::Rank1Args& a, int c, void* Ebuf,
+                       hipStream_t st) {
+  if (!Ebuf) return tsk::fail(TSK_EHIP, "internal: split rank-1 buffer missing");
+  const int Rr = sub_R64(tab->logb), M = 1 << kSubLogM64;
+  const cx<double>* twM = nullptr;
+  const cx<double>* Wb = nullptr;
+  TSK_TRY(get_tw<double>(ctx, kSubLogM64 + 1, &twM, tsk::threads_for_h<double>(kSubLogM64)));
+  TSK_TRY(get_wb<double>(ctx, tab->logb, &Wb));
+  tsk::SubCsArgs<double, double> sa;
+  sa.hxs = tab->hxs;
+  sa.ord = tab->ord;
+  sa.n = tab->n;
+  sa.B = tab->B;
+  sa.Rr = Rr;
+  sa.nmodes = 3;
+  sa.mode[0] = 0;
+  sa.mode[1] = 1;
+  sa.mode[2] = 2;
+  sa.U = a.U;
+  sa.twM = twM;
+  sa.E = reinterpret_cast<cx<double>*>(Ebuf);
+  hipLaunchKernelGGL((tsk::k_sub_cs<double, kSubLogM64, double>), dim3(tab->B, c, 3 * Rr),
+                     dim3(tsk::threads_for_h<double>(kSubLogM64)), 0, st, sa);
+  TSK_TRY(check_launch("k_sub_cs"));
+  hipLaunchKernelGGL(tsk::k_combine_rank1, dim3(tab->B, c), dim3(1024), 0, st,
+                     (const cx<double>*)Ebuf, tab->B, tab->b, M, Rr, Wb, a.S64, a.prod, a.lam_per);
+  return check_launch("k_combine_rank1");
+}
+
+tsk_status launch_rank1_any(tsk_ctx_t ctx, tsk_tables_t tab, const tsk::Rank1Args& a, int c, void* Ebuf,
+                            hipStream_t st) {
+  if (tab->logb <= kLdsLogB) return launch_rank1(tab->logb, a, tab->B, c, st);
+  return rank1_split(ctx, tab, a, c, Ebuf, st);
+}
+
+// Time domain -> half spectrum (FP64) at any supported b.
+tsk_status r2c_any(tsk_ctx_t ctx, int logb, const double* s, cx<double>* S64, cx<float>* S32, int acc,
+                   int B, hipStream_t st) {
+  if (logb <= kLdsLogB) {
+    const cx<double>* tw = nullptr;
+    TSK_TRY(get_tw<double>(ctx, logb, &tw));
+    return launch_r2c(logb, s, S64, S32, tw, acc, B, st);
+  }
+  const int Rr = sub_R64(logb), M = 1 << kSubLogM64, b = 1 << logb;
+  const cx<double>* twM = nullptr;
+  const cx<double>* Wb = nullptr;
+  TSK_TRY(get_tw<double>(ctx, kSubLogM64 + 1, &twM, tsk::threads_for_h<double>(kSubLogM64)));
+  TSK_TRY(get_wb<double>(ctx, logb, &Wb));
+  void* E = nullptr;
+  TSK_TRY(ws_get(ctx, WS_SPLITP, (size_t)B * Rr * M * sizeof(cx<double>), &E));
+  hipLaunchKernelGGL((tsk::k_sub_gather64<kSubLogM64>), dim3(B, Rr),
+                     dim3(tsk::threads_for_h<double>(kSubLogM64)), 0, st, s, b, Rr, twM, (cx<double>*)E);
+  TSK_TRY(check_launch("k_sub_gather64"));
+  hipLaunchKernelGGL(tsk::k_combine_r2c, dim3(grid_for((size_t)B * (b / 2 + 1), 256)), dim3(256), 0, st,
+                     (const cx<double>*)E, B, b, M, Rr, Wb, acc, S64, S32);
+  return check_launch("k_combine_r2c");
+}
+
+// Half spectrum -> time domain (FP64) at any supported b.
+tsk_status c2r_any(tsk_ctx_t ctx, int logb, const cx<double>* S64, double* s, int B, hipStream_t st) {
+  if (logb <= kLdsLogB) {
+    const cx<double>* tw = nullptr;
+    TSK_TRY(get_tw<double>(ctx, logb, &tw));
+    return launch_c2r(logb, S64, s, tw, B, st);
+  }
+  const int Rr = sub_R64(logb), M = 1 << kSubLogM64, b = 1 << logb;
+  const cx<double>* twM = nullptr;
+  const cx<double>* Wb = nullptr;
+  TSK_TRY(get_tw<double>(ctx, kSubLogM64 + 1, &twM, tsk::threads_for_h<double>(kSubLogM64)));
+  TSK_TRY(get_wb<double>(ctx, logb, &Wb));
+  void* A = nullptr;
+  TSK_TRY(ws_get(ctx, WS_SPLITP, (size_t)B * Rr * M * sizeof(cx<double>), &A));
+  hipLaunchKernelGGL(tsk::k_c2r_split_a, dim3(grid_for((size_t)B * M, 256)), dim3(256), 0, st, S64, B, b, M,
+                     Rr, Wb, (cx<double>*)A);
+  TSK_TRY(check_launch("k_c2r_split_a"));
+  hipLaunchKernelGGL((tsk::k_c2r_split_b<kSubLogM64>), dim3(B, Rr),
+                     dim3(tsk::threads_for_h<double>(kSubLogM64)), 0, st, (const cx<double>*)A, b, Rr,
+                     twM, s);
+  return check_launch("k_c2r_split_b");
+}
+
+// Buffers of the FP32 split power step (b = 65536) for nvec vectors.
+struct SplitBufs {
+  void* E = nullptr;  // cx<float>[nvec][B][2][2][M]
+  void* A = nullptr;  // cx<float>[nvec][B][2][M]
+};
+size_t power_split_bytes_E(tsk_tables_t tab, int nvec) {
+  return (size_t)nvec * tab->B * 4 * ((size_t)1 << kSubLogM32) * sizeof(cx<float>);
+}
+size_t power_split_bytes_A(tsk_tables_t tab, int nvec) {
+  return (size_t)nvec * tab->B * 2 * ((size_t)1 << kSubLogM32) * sizeof(cx<float>);
+}
+bool needs_power_split(tsk_tables_t tab, tsk_dtype dtype) {
+  return dtype == TSK_F32 && tab->logb > kLdsLogB + 1;
+}
+
 tsk_status check_tables(tsk_tables_t tab, tsk_ctx_t ctx, const char* fn) {
   if (!ctx) return tsk::fail(TSK_EINVAL, "%s: null context", fn);
   if (!tab) return tsk::fail(TSK_EINVAL, "%s: null tables", fn);
@@ -374,6 +528,8 @@ extern "C" void tsk_destroy(tsk_ctx_t c) {
     if (kv.second.p) (void)hipFree(kv.second.p);
   for (auto& kv : c->tw64) (void)hipFree(kv.second);
   for (auto& kv : c->tw32) (void)hipFree(kv.second);
+  for (auto& kv : c->wb64) (void)hipFree(kv.second);
+  for (auto& kv : c->wb32) (void)hipFree(kv.second);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto s : c->fork) (void)hipStreamDestroy(s);
   for (auto e : c->fork_ev) (void)hipEventDestroy(e);
@@ -390,7 +546,7 @@ extern "C" tsk_status tsk_tables_create(tsk_ctx_t ctx, int n, int b, int B, cons
   const int logb = ilog2_exact(b);
   if (logb < 0) return tsk::fail(TSK_EINVAL, "tsk_tables_create: b=%d is not a power of two", b);
   if (logb < kMinLogB || logb > kMaxLogB)
-    return tsk::fail(TSK_EUNSUPPORTED, "tsk_tables_create: b=%d outside [64,16384]", b);
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_tables_create: b=%d outside [64,65536]", b);
   const size_t cnt = (size_t)B * 3 * n;
   std::vector<uint32_t> hx(cnt), hxs(cnt), ord(cnt);
   for (size_t e = 0; e < cnt; ++e) {
@@ -462,25 +618,35 @@ template <typename TIn>
 tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipStream_t st,
                             double** s_time_out) {
   const int n = tab->n, b = tab->b, B = tab->B;
-  const size_t per_sketch = (size_t)b * 8 + (size_t)12 * n;  // bins + 3 table words
+  // Sketches longer than 16384 buckets are split into bucket ranges of 16384,
+  // one range per work-group (each range reads the whole tensor).
+  const int nrange = b > 16384 ? b / 16384 : 1;
+  const int br = b / nrange;
+  int lbr = 0;
+  while ((1 << lbr) < br) ++lbr;
+  const int Bv = B * nrange;                                  // (sketch, range) pairs
+  const size_t per_sketch = (size_t)br * 8 + (size_t)12 * n;  // bins + 3 table words
   if (per_sketch > (size_t)kBuildPoolLarge * 8)
     return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d, n=%d exceed one CU's LDS", b, n);
-  const bool small = (size_t)B * per_sketch <= (size_t)kBuildPoolSmall * 8;
+  const bool small = (size_t)Bv * per_sketch <= (size_t)kBuildPoolSmall * 8;
   const size_t pool = (size_t)(small ? kBuildPoolSmall : kBuildPoolLarge) * 8;
-  int G = (int)std::min<size_t>((size_t)B, pool / per_sketch);
-  const int ngroups = (B + G - 1) / G;
-  G = (B + ngroups - 1) / ngroups;  // balance the groups
+  int G = nrange > 1 ? 1 : (int)std::min<size_t>((size_t)B, pool / per_sketch);
+  const int ngroups = (Bv + G - 1) / G;
+  G = (Bv + ngroups - 1) / ngroups;  // balance the groups
   const long long npairs = (long long)n * n;
-  // About one work-group per CU in total, never slabs of fewer than 8 fibres.
-  const int target = small ? 1024 : 256;
+  // Slabs come in multiples of 8 (one per XCD lane of the grid mapping), as
+  // many as fill each XCD's 32 CUs in one round (one work-group per CU with
+  // the large pool, two with the small one), never slabs of fewer than 8
+  // fibres.
+  const int slots = 32 * (small ? 2 : 1);
   int nslab = (int)std::min<long long>(std::max<long long>(1, npairs / 8),
-                                       std::max(1, (target + ngroups - 1) / ngroups));
+                                       8LL * std::max(1, slots / ngroups));
   const long long pps = (npairs + nslab - 1) / nslab;
   nslab = (int)((npairs + pps - 1) / pps);
   void* partial = nullptr;
   void* stime = nullptr;
   void* amax = nullptr;
-  TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * b * sizeof(double), &partial));
+  TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * br * sizeof(double), &partial));
   TSK_TRY(ws_get(ctx, WS_STIME, (size_t)B * b * sizeof(double), &stime));
   TSK_TRY(ws_get(ctx, WS_AMAX, sizeof(unsigned long long), &amax));
   // max |T| for the fixed-point scale (a fill kernel clears the slot)
@@ -497,6 +663,8 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   a.b = b;
   a.B = B;
   a.G = G;
+  a.nrange = nrange;
+  a.lbr = lbr;
   a.hx = tab->hx;
   a.pairs_per_slab = pps;
   a.nslab = nslab;
@@ -511,7 +679,7 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
     hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge>), dim3(nblk), dim3(1024), 0, st, a);
   TSK_TRY(check_launch("k_build_dense"));
   hipLaunchKernelGGL(tsk::k_build_reduce, dim3(grid_for((size_t)B * b, 256)), dim3(256), 0, st,
-                     (const double*)partial, (double*)stime, b, B, G, nslab);
+                     (const double*)partial, (double*)stime, b, B, G, nslab, nrange, lbr);
   TSK_TRY(check_launch("k_build_reduce"));
   *s_time_out = reinterpret_cast<double*>(stime);
   return TSK_OK;
@@ -527,15 +695,13 @@ extern "C" tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, co
   if (dtype != TSK_F32 && dtype != TSK_F64)
     return tsk::fail(TSK_EINVAL, "tsk_sketch_build_dense: bad dtype %d", (int)dtype);
   TSK_TRY(set_device(ctx));
-  const cx<double>* tw = nullptr;
-  TSK_TRY(get_tw<double>(ctx, tab->logb, &tw));
   double* stime = nullptr;
   if (dtype == TSK_F32)
     TSK_TRY(build_dense_impl<float>(ctx, tab, (const float*)T, S(stream), &stime));
   else
     TSK_TRY(build_dense_impl<double>(ctx, tab, (const double*)T, S(stream), &stime));
-  return launch_r2c(tab->logb, stime, reinterpret_cast<cx<double>*>(S64),
-                    reinterpret_cast<cx<float>*>(S32), tw, accumulate ? 1 : 0, tab->B, S(stream));
+  return r2c_any(ctx, tab->logb, stime, reinterpret_cast<cx<double>*>(S64),
+                 reinterpret_cast<cx<float>*>(S32), accumulate ? 1 : 0, tab->B, S(stream));
 }
 
 extern "C" tsk_status tsk_sketch_from_time(tsk_ctx_t ctx, int b, int B, const double* s_time,
@@ -545,10 +711,8 @@ extern "C" tsk_status tsk_sketch_from_time(tsk_ctx_t ctx, int b, int B, const do
   if (logb < kMinLogB || logb > kMaxLogB || B < 1 || B > 64)
     return tsk::fail(TSK_EINVAL, "tsk_sketch_from_time: b=%d B=%d out of range", b, B);
   TSK_TRY(set_device(ctx));
-  const cx<double>* tw = nullptr;
-  TSK_TRY(get_tw<double>(ctx, logb, &tw));
-  return launch_r2c(logb, s_time, reinterpret_cast<cx<double>*>(S64),
-                    reinterpret_cast<cx<float>*>(S32), tw, 0, B, S(stream));
+  return r2c_any(ctx, logb, s_time, reinterpret_cast<cx<double>*>(S64), reinterpret_cast<cx<float>*>(S32), 0,
+                 B, S(stream));
 }
 
 extern "C" tsk_status tsk_sketch_export(tsk_ctx_t ctx, int b, int B, const double* S64,
@@ -558,9 +722,7 @@ extern "C" tsk_status tsk_sketch_export(tsk_ctx_t ctx, int b, int B, const doubl
   if (logb < kMinLogB || logb > kMaxLogB || B < 1 || B > 64)
     return tsk::fail(TSK_EINVAL, "tsk_sketch_export: b=%d B=%d out of range", b, B);
   TSK_TRY(set_device(ctx));
-  const cx<double>* tw = nullptr;
-  TSK_TRY(get_tw<double>(ctx, logb, &tw));
-  return launch_c2r(logb, reinterpret_cast<const cx<double>*>(S64), s_time, tw, B, S(stream));
+  return c2r_any(ctx, logb, reinterpret_cast<const cx<double>*>(S64), s_time, B, S(stream));
 }
 
 namespace {
@@ -571,11 +733,13 @@ tsk_status rank1_update(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam, cons
   const int B = tab->B, b = tab->b, n = tab->n;
   const int H1 = b / 2 + 1;
   const cx<double>* tw = nullptr;
-  TSK_TRY(get_tw<double>(ctx, tab->logb, &tw));
+  if (tab->logb <= kLdsLogB) TSK_TRY(get_tw<double>(ctx, tab->logb, &tw));
   const size_t per_vec = (size_t)B * H1 * sizeof(cx<double>);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)256 << 20) / per_vec));
   void* prod = nullptr;
   TSK_TRY(ws_get(ctx, WS_PROD, (size_t)std::min(chunk, c) * per_vec, &prod));
+  void* ebuf = nullptr;
+  if (tab->logb > kLdsLogB) TSK_TRY(ws_get(ctx, WS_SPLITP, rank1_split_bytes(tab, std::min(chunk, c)), &ebuf));
   for (int r0 = 0; r0 < c; r0 += chunk) {
     const int cc = std::min(chunk, c - r0);
     tsk::Rank1Args a;
@@ -589,7 +753,7 @@ tsk_status rank1_update(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam, cons
     a.prod = reinterpret_cast<cx<double>*>(prod);
     a.S64 = nullptr;
     a.lam_per = nullptr;
-    TSK_TRY(launch_rank1(tab->logb, a, B, cc, st));
+    TSK_TRY(launch_rank1_any(ctx, tab, a, cc, ebuf, st));
     hipLaunchKernelGGL(tsk::k_spec_update, dim3(grid_for((size_t)B * H1, 256)), dim3(256), 0, st,
                        reinterpret_cast<cx<double>*>(S64), reinterpret_cast<cx<float>*>(S32),
                        (const cx<double>*)prod, lam + r0, sign, cc, B, H1);
@@ -634,9 +798,89 @@ extern "C" tsk_status tsk_sketch_deflate(tsk_ctx_t ctx, tsk_tables_t tab, const 
 namespace {
 
 template <typename R>
+tsk_status median_norm_launch(const R* V, const R* Uin, R* Uout, int32_t* flags, int L, int n, int B,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((tsk::k_median_norm<R>), dim3(L), dim3(256), 0, st, V, Uin, Uout, flags, n, B);
+  return check_launch("k_median_norm");
+}
+
+// FP32 power step at b = 65536 through the split transforms (large.hpp); the
+// median of the previous step (prefix) is a launch of its own here.
+tsk_status power_split(tsk_ctx_t ctx, tsk_tables_t tab, const cx<float>* spec, int nrest, int tau0,
+                       int prefix, int mode, const float* Uprev, const float* Vprev, float* Ucur,
+                       int32_t* flags, float* V, double* lam_per, hipStream_t st, int perm,
+                       const SplitBufs* sb) {
+  if (!sb || !sb->E || !sb->A) return tsk::fail(TSK_EHIP, "internal: split power buffers missing");
+  const int n = tab->n, B = tab->B, b = tab->b, M = 1 << kSubLogM32;
+  const cx<float>* twM = nullptr;
+  const cx<float>* Wb = nullptr;
+  TSK_TRY(get_tw<float>(ctx, kSubLogM32 + 1, &twM, tsk::threads_for_h<float>(kSubLogM32)));
+  TSK_TRY(get_wb<float>(ctx, tab->logb, &Wb));
+  const size_t on = (size_t)tau0 * n, obn = (size_t)tau0 * B * n;
+  const float* U = Uprev + on;
+  if (prefix) {
+    TSK_TRY(median_norm_launch<float>(Vprev + obn, Uprev + on, Ucur + on, flags ? flags + tau0 : nullptr,
+                                      nrest, n, B, st));
+    U = Ucur + on;
+  }
+  tsk::SubCsArgs<float, float> a1;
+  a1.hxs = tab->hxs;
+  a1.ord = tab->ord;
+  a1.n = n;
+  a1.B = B;
+  a1.Rr = 2;
+  a1.nmodes = 2;
+  a1.mode[0] = (perm + 1) % 3;
+  a1.mode[1] = (perm + 2) % 3;
+  a1.mode[2] = 0;
+  a1.U = U;
+  a1.twM = twM;
+  a1.E = reinterpret_cast<cx<float>*>(sb->E);
+  hipLaunchKernelGGL((tsk::k_sub_cs<float, kSubLogM32, float>), dim3(B, nrest, 4),
+                     dim3(tsk::threads_for_h<float>(kSubLogM32)), 0, st, a1);
+  TSK_TRY(check_launch("k_sub_cs"));
+  tsk::SplitMidArgs a2;
+  a2.E = reinterpret_cast<const cx<float>*>(sb->E);
+  a2.S = spec;
+  a2.Wb = Wb;
+  a2.B = B;
+  a2.b = b;
+  a2.M = M;
+  a2.A = reinterpret_cast<cx<float>*>(sb->A);
+  hipLaunchKernelGGL(tsk::k_power_split_mid, dim3(B, nrest, (M / 2 + 1 + 255) / 256), dim3(256), 0, st, a2);
+  TSK_TRY(check_launch("k_power_split_mid"));
+  tsk::SplitOutArgs a3;
+  a3.A = reinterpret_cast<const cx<float>*>(sb->A);
+  a3.hx = tab->hx;
+  a3.n = n;
+  a3.B = B;
+  a3.rd = perm;
+  a3.M = M;
+  a3.b = b;
+  a3.twM = twM;
+  a3.V = V + obn;
+  hipLaunchKernelGGL((tsk::k_power_split_out<kSubLogM32>), dim3(B, nrest, 2),
+                     dim3(tsk::threads_for_h<float>(kSubLogM32)), 0, st, a3);
+  TSK_TRY(check_launch("k_power_split_out"));
+  if (mode == 1) {
+    hipLaunchKernelGGL(tsk::k_rowdot<float>, dim3(B, nrest), dim3(256), 0, st, U, (const float*)(V + obn), n,
+                       B, lam_per + (size_t)tau0 * B);
+    TSK_TRY(check_launch("k_rowdot"));
+  }
+  return TSK_OK;
+}
+
+template <typename R>
 tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0,
                         int prefix, int mode, const R* Uprev, const R* Vprev, R* Ucur,
-                        int32_t* flags, R* V, double* lam_per, hipStream_t st, int perm = 0) {
+                        int32_t* flags, R* V, double* lam_per, hipStream_t st, int perm = 0,
+                        const SplitBufs* sb = nullptr) {
+  if (tab->logb > kLdsLogB + 1 || (sizeof(R) == 8 && tab->logb > kLdsLogB)) {
+    if constexpr (sizeof(R) == 4)
+      return power_split(ctx, tab, reinterpret_cast<const cx<float>*>(spec), nrest, tau0, prefix, mode, Uprev,
+                         Vprev, Ucur, flags, V, lam_per, st, perm, sb);
+    return tsk::fail(TSK_EUNSUPPORTED, "power step: FP64 supports b <= 16384 (b=%d)", tab->b);
+  }
   const cx<R>* tw = nullptr;
   TSK_TRY(get_tw<R>(ctx, tab->logb, &tw));
   tsk::PowerArgs<R> a;
@@ -663,11 +907,15 @@ tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int n
   return launch_power<R>(tab->logb, a, tab->B, nrest, st);
 }
 
-template <typename R>
-tsk_status median_norm_launch(const R* V, const R* Uin, R* Uout, int32_t* flags, int L, int n, int B,
-                              hipStream_t st) {
-  hipLaunchKernelGGL((tsk::k_median_norm<R>), dim3(L), dim3(256), 0, st, V, Uin, Uout, flags, n, B);
-  return check_launch("k_median_norm");
+// Buffers for an eager (uncaptured) call on nvec vectors.
+tsk_status eager_split_bufs(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, int nvec, SplitBufs* sb) {
+  if (!needs_power_split(tab, dtype)) return TSK_OK;
+  void* p = nullptr;
+  const size_t e = power_split_bytes_E(tab, nvec), a = power_split_bytes_A(tab, nvec);
+  TSK_TRY(ws_get(ctx, WS_SPLIT, ((e + 255) & ~(size_t)255) + a, &p));
+  sb->E = p;
+  sb->A = (char*)p + ((e + 255) & ~(size_t)255);
+  return TSK_OK;
 }
 
 tsk_status lam_median_launch(const double* lam_per, double* lam_med, int L, int B, hipStream_t st) {
@@ -681,6 +929,8 @@ tsk_status check_power_args(tsk_tables_t tab, tsk_dtype dtype, const double* S64
   if (L < 1) return tsk::fail(TSK_EINVAL, "%s: L=%d < 1", fn, L);
   if (dtype == TSK_F32 && !S32) return tsk::fail(TSK_EINVAL, "%s: FP32 path needs S32", fn);
   if (dtype == TSK_F64 && !S64) return tsk::fail(TSK_EINVAL, "%s: FP64 path needs S64", fn);
+  if (dtype == TSK_F64 && tab->logb > kLdsLogB)
+    return tsk::fail(TSK_EUNSUPPORTED, "%s: FP64 power steps support b <= 16384 (b=%d)", fn, tab->b);
   if (L > 65535) return tsk::fail(TSK_EINVAL, "%s: L=%d > 65535", fn, L);
   return TSK_OK;
 }
@@ -700,9 +950,11 @@ extern "C" tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
   void* vbuf = V;
   if (!vbuf) TSK_TRY(ws_get(ctx, WS_V, (size_t)L * tab->B * tab->n * es, &vbuf));
   const int n = tab->n, B = tab->B;
+  SplitBufs sb;
+  TSK_TRY(eager_split_bufs(ctx, tab, dtype, L, &sb));
   if (dtype == TSK_F32) {
     TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U_in, nullptr, nullptr,
-                                nullptr, (float*)vbuf, nullptr, S(stream)));
+                                nullptr, (float*)vbuf, nullptr, S(stream), 0, &sb));
     return median_norm_launch<float>((const float*)vbuf, (const float*)U_in, (float*)U_out, flags, L,
                                      n, B, S(stream));
   }
@@ -719,9 +971,11 @@ extern "C" tsk_status tsk_contract_tiuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dty
   TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_contract_tiuu"));
   if (!U || !V) return tsk::fail(TSK_EINVAL, "tsk_contract_tiuu: null U or V");
   TSK_TRY(set_device(ctx));
+  SplitBufs sb;
+  TSK_TRY(eager_split_bufs(ctx, tab, dtype, L, &sb));
   if (dtype == TSK_F32)
     return power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U, nullptr, nullptr, nullptr,
-                               (float*)V, nullptr, S(stream));
+                               (float*)V, nullptr, S(stream), 0, &sb);
   return power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)U, nullptr, nullptr, nullptr,
                               (double*)V, nullptr, S(stream));
 }
@@ -738,9 +992,11 @@ extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
   TSK_TRY(ws_get(ctx, WS_V, (size_t)L * tab->B * tab->n * es, &vbuf));
   void* lp = lam_per;
   if (!lp) TSK_TRY(ws_get(ctx, WS_LAMPER, (size_t)L * tab->B * sizeof(double), &lp));
+  SplitBufs sb;
+  TSK_TRY(eager_split_bufs(ctx, tab, dtype, L, &sb));
   if (dtype == TSK_F32)
     TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 1, (const float*)U, nullptr, nullptr,
-                                nullptr, (float*)vbuf, (double*)lp, S(stream)));
+                                nullptr, (float*)vbuf, (double*)lp, S(stream), 0, &sb));
   else
     TSK_TRY(power_launch<double>(ctx, tab, S64, L, 0, 0, 1, (const double*)U, nullptr, nullptr,
                                  nullptr, (double*)vbuf, (double*)lp, S(stream)));
@@ -932,6 +1188,8 @@ extern "C" tsk_status tsk_sketch_build_docs(tsk_ctx_t ctx, tsk_tables_t tab, con
                                             const void* W, tsk_dtype wdtype, double alpha0, double* S64,
                                             float* S32, int accumulate, void* stream) {
   TSK_TRY(check_tables(tab, ctx, "tsk_sketch_build_docs"));
+  if (tab->logb > kLdsLogB)
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_sketch_build_docs: b=%d > 16384 is not built", tab->b);
   if (!rowptr || !W || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: null argument");
   if (D < 1 || V < 1) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: D=%d, V=%d must be >= 1", D, V);
   if (wdtype != TSK_F32 && wdtype != TSK_F64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: bad dtype");
@@ -963,9 +1221,11 @@ template <typename R>
 tsk_status three_readoffs(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int L, const R* U,
                           R* V3, double* lam_per, hipStream_t st) {
   const size_t blk = (size_t)L * tab->B * tab->n;
+  SplitBufs sb;
+  TSK_TRY(eager_split_bufs(ctx, tab, sizeof(R) == 4 ? TSK_F32 : TSK_F64, L, &sb));
   for (int perm = 0; perm < 3; ++perm)
     TSK_TRY(power_launch<R>(ctx, tab, spec, L, 0, 0, perm == 0 ? 1 : 0, U, nullptr, nullptr, nullptr,
-                            V3 + perm * blk, perm == 0 ? lam_per : nullptr, st, perm));
+                            V3 + perm * blk, perm == 0 ? lam_per : nullptr, st, perm, &sb));
   return TSK_OK;
 }
 
@@ -1073,6 +1333,8 @@ struct DecompWs {
   double* lam64;   // [B]
   void* prod;      // cx<double>[B][b/2+1]
   double* u0;      // [k][L][n] generated start vectors (when caller passes none)
+  void* esplit;    // split rank-1 sub-transforms (b > 16384)
+  SplitBufs sb;    // split FP32 power steps (b = 65536)
 };
 
 // Power steps of one component for restarts [tau0, tau0 + nrest): the first
@@ -1082,14 +1344,14 @@ struct DecompWs {
 template <typename R>
 tsk_status power_chain(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0, int T,
                        R* const Ub[2], R* const Vb[2], double* lam_per, int32_t* fl, R** u_final,
-                       hipStream_t st) {
+                       hipStream_t st, const SplitBufs* sb) {
   TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 0, 0, Ub[0], nullptr, nullptr, nullptr, Vb[0],
-                          nullptr, st));
+                          nullptr, st, 0, sb));
   int cu = 0, cv = 0;
   for (int t = 1; t <= T; ++t) {
     const int mode = (t == T) ? 1 : 0;
     TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 1, mode, Ub[cu], Vb[cv], Ub[cu ^ 1], fl,
-                            Vb[cv ^ 1], mode ? lam_per : nullptr, st));
+                            Vb[cv ^ 1], mode ? lam_per : nullptr, st, 0, sb));
     cu ^= 1;
     cv ^= 1;
   }
@@ -1105,7 +1367,7 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
   const int n = tab->n, B = tab->B, b = tab->b;
   const int H1 = b / 2 + 1;
   const cx<double>* tw64 = nullptr;
-  TSK_TRY(get_tw<double>(ctx, tab->logb, &tw64));
+  if (tab->logb <= kLdsLogB) TSK_TRY(get_tw<double>(ctx, tab->logb, &tw64));
   R* const Ub[2] = {reinterpret_cast<R*>(w.U0), reinterpret_cast<R*>(w.U1)};
   R* const Vb[2] = {reinterpret_cast<R*>(w.V0), reinterpret_cast<R*>(w.V1)};
   for (int c = 0; c < k; ++c) {
@@ -1116,10 +1378,10 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
     int32_t* fl = flags + (size_t)c * L;
     R* ufin = nullptr;
     if (!plain) {
-      TSK_TRY(power_chain<R>(ctx, tab, spec, L, 0, T, Ub, Vb, w.lam_per, fl, &ufin, st));
+      TSK_TRY(power_chain<R>(ctx, tab, spec, L, 0, T, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
     } else {
       for (int tau = 0; tau < L; ++tau)
-        TSK_TRY(power_chain<R>(ctx, tab, spec, 1, tau, T, Ub, Vb, w.lam_per, fl, &ufin, st));
+        TSK_TRY(power_chain<R>(ctx, tab, spec, 1, tau, T, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
     }
     TSK_TRY(lam_median_launch(w.lam_per, w.lam_med, L, B, st));
     hipLaunchKernelGGL(tsk::k_select<R>, dim3(1), dim3(256), 0, st, (const double*)w.lam_med, L,
@@ -1137,7 +1399,7 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
     a.prod = reinterpret_cast<cx<double>*>(w.prod);
     a.S64 = reinterpret_cast<const cx<double>*>(S64);
     a.lam_per = w.lam64;
-    TSK_TRY(launch_rank1(tab->logb, a, B, 1, st));
+    TSK_TRY(launch_rank1_any(ctx, tab, a, 1, w.esplit, st));
     hipLaunchKernelGGL(tsk::k_median_scalar, dim3(1), dim3(64), 0, st, (const double*)w.lam64, B,
                        lam_out + c);
     TSK_TRY(check_launch("k_median_scalar"));
@@ -1191,6 +1453,11 @@ size_t decomp_ws_layout(char* base, tsk_tables_t tab, tsk_dtype dtype, int k, in
   d.prod = take(B * H1 * 16);
   d.flags = flags ? (int32_t*)take((size_t)k * L * 4) : nullptr;
   d.u0 = u0 ? (double*)take((size_t)k * L * n * 8) : nullptr;
+  d.esplit = tab->logb > kLdsLogB ? take(rank1_split_bytes(tab, 1)) : nullptr;
+  if (needs_power_split(tab, dtype)) {
+    d.sb.E = take(power_split_bytes_E(tab, L));
+    d.sb.A = take(power_split_bytes_A(tab, L));
+  }
   if (w) *w = d;
   if (fl) *fl = d.flags;
   if (u0p) *u0p = d.u0;
@@ -1208,9 +1475,9 @@ tsk_status upload_start_vectors(uint64_t seed, int k, int L, int n, double* dst,
 tsk_status preload_twiddles(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype) {
   const cx<double>* t64 = nullptr;
   const cx<float>* t32 = nullptr;
-  TSK_TRY(get_tw<double>(ctx, tab->logb, &t64));
-  if (dtype == TSK_F32) TSK_TRY(get_tw<float>(ctx, tab->logb, &t32));
-  return TSK_OK;
+  if (tab->logb <= kLdsLogB) TSK_TRY(get_tw<double>(ctx, tab->logb, &t64));
+  if (dtype == TSK_F32 && tab->logb <= kLdsLogB + 1) TSK_TRY(get_tw<float>(ctx, tab->logb, &t32));
+  return preload_split_tables(ctx, tab->logb, needs_power_split(tab, dtype));
 }
 
 // Everything one decomposition enqueues: clear its flags (a fill kernel, so a

@@ -370,9 +370,9 @@ def test_argument_errors(ctx):
     h65, xi65 = tsk.hash_generate(0, 10, 256, 65)
     with pytest.raises(tsk.TskError, match="EINVAL"):
         tsk.Tables(ctx, h65, xi65, 256)              # B > 64
-    hb, xb = tsk.hash_generate(0, 10, 32768, 2)
+    hb, xb = tsk.hash_generate(0, 10, 131072, 2)
     with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
-        tsk.Tables(ctx, hb, xb, 32768)
+        tsk.Tables(ctx, hb, xb, 131072)
     hn, xn = tsk.hash_generate(0, 3000, 16384, 2)
     tabn = tsk.Tables(ctx, hn, xn, 16384)
     S64n, S32n = tsk.new_sketch(tabn, DEV)
