@@ -123,6 +123,17 @@ __device__ __forceinline__ cx<R> tw_load(__amdgpu_buffer_rsrc_t rs, unsigned vof
 
 constexpr int twid_len(int H, int NT) { return pass_table_len(H, NT) + H + 1; }
 
+// Radix of the last pass of the plan (the passes use fft_rmax, the last one
+// takes the remaining factor).
+constexpr int fft_last_radix(int N, int NT) {
+  int rad = 2;
+  for (int ns = 1; ns < N;) {
+    rad = pass_radix(N, ns, fft_rmax(N, NT));
+    ns *= rad;
+  }
+  return rad;
+}
+
 // ---- radix-R DFTs in registers (y_q = sum_r x_r W_R^{rq}, W_R = e^{-+2 pi i/R}) ----
 
 template <typename R, bool INV>
@@ -327,7 +338,7 @@ __device__ __forceinline__ void stockham_pass(const Soa<R>& buf,
 // next pass's twiddles are loaded before the current pass runs (their global
 // loads overlap its arithmetic, at the cost of registers); without PF each
 // pass loads its own at its start.
-template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, bool PF>
+template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, bool PF, bool SKIPLAST = false>
 __device__ __forceinline__ void fft_passes(
     const Soa<R>& buf, const Twid<R>& twp,
     const PassTw<R, (N / pass_radix(N, NS, RMAX) + NT - 1) / NT, pass_radix(N, NS, RMAX) - 1>& cur) {
@@ -348,18 +359,23 @@ __device__ __forceinline__ void fft_passes(
     load_pass_tw<R, N, RAD, NS, NT, TOFF>(own, twp, tid);
     stockham_pass<R, N, RAD, NS, NT, INV>(buf, own, tid);
   }
-  if constexpr (NS2 < N) fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, PF>(buf, twp, nxt);
+  // SKIPLAST: stop before the last pass (its inputs stay in the buffer).
+  if constexpr (NS2 < N && !(SKIPLAST && NS2 * RAD2 == N))
+    fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, PF, SKIPLAST>(buf, twp, nxt);
 }
 
 // Complex FFT of length N = 2^LOGN in LDS (SoA, padded); ends with a barrier.
-// PF as in fft_passes.
-template <typename R, int LOGN, int NT, bool INV, bool PF = true>
+// PF as in fft_passes.  With SKIPLAST the last pass is left out: for a last
+// pass of radix 2 the buffer then holds a[j] and b[j] = in[j + N/2], and
+// X[j] = a[j] + W_N^j b[j], X[j + N/2] = a[j] - W_N^j b[j] (conjugate twiddle
+// for INV), with W_N^j at pass_table_len(N, NT) - N/2 + j of the pass table.
+template <typename R, int LOGN, int NT, bool INV, bool PF = true, bool SKIPLAST = false>
 __device__ __forceinline__ void fft_soa(const Soa<R>& buf, const Twid<R>& tw) {
   constexpr int N = 1 << LOGN;
   constexpr int RMAX = fft_rmax(N, NT);
   constexpr int RAD = pass_radix(N, 1, RMAX);
   PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> first;  // the first pass has no twiddles
-  fft_passes<R, N, 1, NT, RMAX, INV, 0, PF>(buf, tw, first);
+  fft_passes<R, N, 1, NT, RMAX, INV, 0, PF, SKIPLAST>(buf, tw, first);
 }
 
 }  // namespace tsk

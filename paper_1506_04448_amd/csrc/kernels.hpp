@@ -255,9 +255,18 @@ __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict
       const int mm = e / cw, ii = e - mm * cw;
       const R x = stage[mm * CH + ii];
       int r = 0;
-      for (int j = 0; j < B; ++j) {
-        const R o = stage[j * CH + ii];
-        r += (o < x) || (o == x && j < mm);
+      if (B <= 16) {  // all loads issued together
+        R o[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) o[j] = j < B ? stage[j * CH + ii] : R(0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j < B) r += (o[j] < x) || (o[j] == x && j < mm);
+      } else {
+        for (int j = 0; j < B; ++j) {
+          const R o = stage[j * CH + ii];
+          r += (o < x) || (o == x && j < mm);
+        }
       }
       if (r == ra) selA[ii] = x;
       if (r == rb) selC[ii] = x;
@@ -265,7 +274,13 @@ __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict
     __syncthreads();
     for (int ii = threadIdx.x; ii < cw; ii += NT) {
       bool nan = false;
-      for (int j = 0; j < B; ++j) nan |= __builtin_isnan(stage[j * CH + ii]);
+      if (B <= 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j < B) nan |= __builtin_isnan(stage[j * CH + ii]);
+      } else {
+        for (int j = 0; j < B; ++j) nan |= __builtin_isnan(stage[j * CH + ii]);
+      }
       R med = (B & 1) ? selA[ii] : (selA[ii] + selC[ii]) * R(0.5);
       if (nan) med = R(__builtin_nan(""));
       u[c0 + ii] = med;
@@ -329,6 +344,11 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   // also owns k = H/2, which pairs with itself.
   constexpr int PK = (H / 2 + NT - 1) / NT;
   constexpr bool FULL = (H / 2) % NT == 0;
+  // With a last pass of radix 2, the forward transforms stop before it and
+  // the spectral products form X[k], X[H-k] from its inputs; the inverse stops
+  // before it and the read-off forms just the outputs it reads.
+  constexpr bool FUSE = fft_last_radix(H, NT) == 2 && H >= 64;
+  constexpr int TLAST = pass_table_len(H, NT) - H / 2;  // W_H^j, j < H/2, in the pass table
   extern __shared__ __align__(16) unsigned char lds[];
   const int n = a.n;
   const int B = a.B;
@@ -411,7 +431,7 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
       count_sketch<R>(a.hxs + tb + (size_t)(mode_j == 1 ? a.sa : a.sb) * n,
                       a.ord + tb + (size_t)(mode_j == 1 ? a.sa : a.sb) * n, n, NT, getu, store);
     __syncthreads();
-    fft_soa<R, LOGH, NT, false, false>(buf, tw);
+    fft_soa<R, LOGH, NT, false, false, FUSE>(buf, tw);
     // Opaque thread index: the pair indices are recomputed here rather than
     // kept live (or spilled) from the loads at the start.
     int ot = threadIdx.x;
@@ -420,15 +440,28 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
     for (int q = 0; q < PK; ++q) {
       const int k = ot + q * NT;
       if (!FULL && k >= H / 2) break;
-      const cx<R> w0 = wk(q);
+      cx<R> w0 = wk(q);
+      asm volatile("" : "+v"(w0.x), "+v"(w0.y));  // formed here, not hoisted out of the mode loop
       const cx<R> w1 = {-w0.x, w0.y};
-      const cx<R> Za = buf.get(k);
-      const cx<R> Zb = buf.get((H - k) & (H - 1));
+      cx<R> Za, Zb;
+      if constexpr (FUSE) {
+        const cx<R> wH = cmul(w0, w0);              // W_H^k = (W_b^k)^2
+        const cx<R> wH2 = {-wH.x, wH.y};            // W_H^(H/2-k)
+        Za = cadd(buf.get(k), cmul(wH, buf.get(k + H / 2)));
+        const int j2 = (H / 2 - k) & (H / 2 - 1);   // X[H-k] = X[j2 + H/2] for k > 0
+        const cx<R> Zc = csub(buf.get(j2), cmul(wH2, buf.get(j2 + H / 2)));
+        Zb = k == 0 ? Za : Zc;                      // X[H] is X[0]
+      } else {
+        Za = buf.get(k);
+        Zb = buf.get((H - k) & (H - 1));
+      }
       p0[q] = cmulc(p0[q], r2c_post(Za, Zb, w0));
       p1[q] = cmulc(p1[q], r2c_post(Zb, Za, w1));
+      // this pair finished before the next pair's loads
+      asm volatile("" : "+v"(p0[q].x), "+v"(p0[q].y), "+v"(p1[q].x), "+v"(p1[q].y) : : "memory");
     }
     if (tid == 0) {
-      const cx<R> Z = buf.get(H / 2);
+      const cx<R> Z = FUSE ? csub(buf.get(0), buf.get(H / 2)) : buf.get(H / 2);
       pmid = cmulc(pmid, r2c_post(Z, Z, cx<R>{R(0), R(-1)}));
     }
     __syncthreads();
@@ -447,7 +480,7 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   }
   if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, cx<R>{R(0), R(-1)}));
   __syncthreads();
-  fft_soa<R, LOGH, NT, true, false>(buf, tw);
+  fft_soa<R, LOGH, NT, true, false, FUSE>(buf, tw);
 
   const R scale = R(2) / R(b);
   // Read-off addresses formed here from opaque copies of the indices, so the
@@ -459,7 +492,16 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   double acc = 0.0;
   for (int i = orid; i < n; i += NT) {
     const uint32_t e = tab_lds ? stab[4 * n + i] : hx1[i];
-    const R val = load_packed(buf, e >> 1) * scale;
+    R val;
+    if constexpr (FUSE) {  // the skipped last inverse pass, for this output only
+      const uint32_t t = e >> 1, p = t >> 1;
+      const int j = (int)(p & (uint32_t)(H / 2 - 1));
+      const cx<R> c = cmulc(buf.get(j + H / 2), a.twg[TLAST + j]);
+      const cx<R> X = p < (uint32_t)(H / 2) ? cadd(buf.get(j), c) : csub(buf.get(j), c);
+      val = ((t & 1u) ? X.y : X.x) * scale;
+    } else {
+      val = load_packed(buf, e >> 1) * scale;
+    }
     const R v = (e & 1u) ? -val : val;
     Vrow[i] = v;
     acc += (double)u[i] * (double)v;
