@@ -74,6 +74,12 @@ struct Soa {
     re[q] = v.x;
     im[q] = v.y;
   }
+  // by padded position
+  __device__ __forceinline__ cx<R> at(int q) const { return {re[q], im[q]}; }
+  __device__ __forceinline__ void put_at(int q, cx<R> v) const {
+    re[q] = v.x;
+    im[q] = v.y;
+  }
 };
 
 // ---- twiddle tables ---------------------------------------------------------

@@ -135,6 +135,30 @@ __device__ __forceinline__ cx<R> c2r_pack(cx<R> Xk, cx<R> XHk, cx<R> Wk) {
   return {E.x - O.y, E.y + O.x};
 }
 
+// Both bins k and H-k of a real sequence's spectrum, twice over, from the
+// half-length transform Z of its even/odd packing: with c = conj Z[H-k],
+// e = Z[k] + c and o = (Z[k] - c) / i, 2 X[k] = e + W_b^k o and
+// 2 X[H-k] = conj(e - W_b^k o).  Returns 2 X[k] in xk and conj(2 X[H-k]) in xm.
+template <typename R>
+__device__ __forceinline__ void r2c_pair2(cx<R> Zk, cx<R> Zm, cx<R> w, cx<R>& xk, cx<R>& xm) {
+  const cx<R> e = {Zk.x + Zm.x, Zk.y - Zm.y};
+  const cx<R> o = {Zk.y + Zm.y, Zm.x - Zk.x};
+  const cx<R> t = cmul(w, o);
+  xk = cadd(e, t);
+  xm = csub(e, t);
+}
+
+// The packing Y of c2r_pack for both k and H-k, twice over: with
+// E = X[k] + conj X[H-k] and O = (X[k] - conj X[H-k]) conj(W_b^k),
+// 2 Y[k] = E + i O and 2 Y[H-k] = conj(E) + i conj(O).
+template <typename R>
+__device__ __forceinline__ void c2r_pair2(cx<R> Xk, cx<R> Xm, cx<R> w, cx<R>& yk, cx<R>& ym) {
+  const cx<R> E = {Xk.x + Xm.x, Xk.y - Xm.y};
+  const cx<R> O = cmulc(cx<R>{Xk.x - Xm.x, Xk.y + Xm.y}, w);
+  yk = {E.x - O.y, E.y + O.x};
+  ym = {E.x + O.y, O.x - E.y};
+}
+
 // Threads per work-group for a half-length H = 2^logh transform held in LDS:
 // eight complex values per thread (radix-8 passes), 64 to 1024 threads.
 template <typename R>
@@ -436,53 +460,63 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
     // kept live (or spilled) from the loads at the start.
     int ot = threadIdx.x;
     asm volatile("" : "+v"(ot));
+    // Bins k and H-k need Z[k] and Z[H-k]; fused, Z[k] comes from the inputs
+    // k, k + H/2 of the skipped pass and Z[H-k] from j, j + H/2, j = H/2 - k.
+    constexpr int M = FUSE ? H / 2 : H;
+    const int P0 = pidx(ot), Pm = pidx(NT - ot);
 #pragma unroll
     for (int q = 0; q < PK; ++q) {
       const int k = ot + q * NT;
       if (!FULL && k >= H / 2) break;
       cx<R> w0 = wk(q);
       asm volatile("" : "+v"(w0.x), "+v"(w0.y));  // formed here, not hoisted out of the mode loop
-      const cx<R> w1 = {-w0.x, w0.y};
+      // padded positions of k and of its mirror M - k (0 for k = 0)
+      const int pk = FULL ? P0 + poff(q * NT) : pidx(k);
+      int pm = FULL ? Pm + poff(M - NT - q * NT) : pidx((M - k) & (M - 1));
+      if (FULL && q == 0) pm = ot == 0 ? 0 : pm;
       cx<R> Za, Zb;
       if constexpr (FUSE) {
-        const cx<R> wH = cmul(w0, w0);              // W_H^k = (W_b^k)^2
-        const cx<R> wH2 = {-wH.x, wH.y};            // W_H^(H/2-k)
-        Za = cadd(buf.get(k), cmul(wH, buf.get(k + H / 2)));
-        const int j2 = (H / 2 - k) & (H / 2 - 1);   // X[H-k] = X[j2 + H/2] for k > 0
-        const cx<R> Zc = csub(buf.get(j2), cmul(wH2, buf.get(j2 + H / 2)));
-        Zb = k == 0 ? Za : Zc;                      // X[H] is X[0]
+        const cx<R> wH = cmul(w0, w0);  // W_H^k = (W_b^k)^2; W_H^(H/2-k) = -conj(W_H^k)
+        Za = cadd(buf.at(pk), cmul(wH, buf.at(pk + poff(H / 2))));
+        const cx<R> Zc = cadd(buf.at(pm), cmulc(buf.at(pm + poff(H / 2)), wH));
+        Zb = (q == 0 && k == 0) ? Za : Zc;  // X[H] is X[0]
       } else {
-        Za = buf.get(k);
-        Zb = buf.get((H - k) & (H - 1));
+        Za = buf.at(pk);
+        Zb = buf.at(pm);
       }
-      p0[q] = cmulc(p0[q], r2c_post(Za, Zb, w0));
-      p1[q] = cmulc(p1[q], r2c_post(Zb, Za, w1));
+      cx<R> xk, xm;
+      r2c_pair2(Za, Zb, w0, xk, xm);
+      p0[q] = cmulc(p0[q], xk);  // P[k] conj(2 X[k])
+      p1[q] = cmul(p1[q], xm);   // P[H-k] conj(2 X[H-k])
       // this pair finished before the next pair's loads
       asm volatile("" : "+v"(p0[q].x), "+v"(p0[q].y), "+v"(p1[q].x), "+v"(p1[q].y) : : "memory");
     }
-    if (tid == 0) {
+    if (tid == 0) {  // bin H/2: 2 X[H/2] = 2 conj(Z[H/2])
       const cx<R> Z = FUSE ? csub(buf.get(0), buf.get(H / 2)) : buf.get(H / 2);
-      pmid = cmulc(pmid, r2c_post(Z, Z, cx<R>{R(0), R(-1)}));
+      pmid = cscale(cmul(pmid, Z), R(2));
     }
     __syncthreads();
   }
-  // Half-length packing of the real inverse transform of P.
+  // Half-length packing of the real inverse transform of P (twice over).
   int ot = threadIdx.x;
   asm volatile("" : "+v"(ot));
+  const int P0 = pidx(ot), Pm = pidx(NT - ot);
 #pragma unroll
   for (int q = 0; q < PK; ++q) {
     const int k = ot + q * NT;
     if (!FULL && k >= H / 2) break;
     const cx<R> w0 = wk(q);
-    const cx<R> w1 = {-w0.x, w0.y};
-    buf.put(k, c2r_pack(p0[q], p1[q], w0));
-    if (k > 0) buf.put(H - k, c2r_pack(p1[q], p0[q], w1));
+    cx<R> yk, ym;
+    c2r_pair2(p0[q], p1[q], w0, yk, ym);
+    buf.put_at(FULL ? P0 + poff(q * NT) : pidx(k), yk);
+    if (k > 0) buf.put_at(FULL ? Pm + poff(H - NT - q * NT) : pidx(H - k), ym);
   }
-  if (tid == 0) buf.put(H / 2, c2r_pack(pmid, pmid, cx<R>{R(0), R(-1)}));
+  if (tid == 0) buf.put(H / 2, cscale(cconj(pmid), R(2)));
   __syncthreads();
   fft_soa<R, LOGH, NT, true, false, FUSE>(buf, tw);
 
-  const R scale = R(2) / R(b);
+  // Each forward product carried a factor 2 and the packing another.
+  const R scale = R(1) / R(4 * b);
   // Read-off addresses formed here from opaque copies of the indices, so the
   // compiler does not keep them live (or spill them) through the transforms.
   int om = m, otau = tau, orid = tid;

@@ -218,7 +218,7 @@ struct SplitMidArgs {
 
 __global__ __launch_bounds__(256) void k_power_split_mid(SplitMidArgs a) {
   const int m = blockIdx.x, vec = blockIdx.y;
-  const int M = a.M, b = a.b, H = 2 * M;
+  const int M = a.M, H = 2 * M;
   const cx<float>* E2 = a.E + (((size_t)vec * a.B + m) * 2 + 0) * 2 * (size_t)M;
   const cx<float>* E3 = a.E + (((size_t)vec * a.B + m) * 2 + 1) * 2 * (size_t)M;
   const cx<float>* S = a.S + (size_t)m * (H + 1);
