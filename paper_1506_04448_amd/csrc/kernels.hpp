@@ -245,20 +245,42 @@ __device__ __forceinline__ int median_chunk(int n, int B, int cap) {
   return n < c ? n : c;
 }
 
+// Sorts v[0..N) ascending in registers with Batcher's odd-even merge network
+// (63 compare-exchanges for N = 16); N a power of two, all indices fixed at
+// compile time.
+template <int N, typename R>
+__device__ __forceinline__ void sort_network(R (&v)[N]) {
+#pragma unroll
+  for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+    for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+      for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k && i + j + k < N; ++i)
+          if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+            const R lo = fmin(v[i + j], v[i + j + k]), hi = fmax(v[i + j], v[i + j + k]);
+            v[i + j] = lo;
+            v[i + j + k] = hi;
+          }
+}
+
 // ---------------------------------------------------------------------------
 // Median prologue: u = vbar / ||vbar||, vbar_i = med_m Vprev[tau][m][i], for
 // the n coordinates of one restart, into u[] (LDS or global).  Falls back to
 // Uprev[tau] when ||vbar|| is zero or not finite.  The median is the element
 // of rank (B-1)/2 (odd B) or the mean of ranks B/2-1 and B/2 (even B), ranks
-// breaking ties by sketch index; any NaN among the B values gives NaN.  Every
-// (coordinate, sketch) pair ranks its value in parallel and the two selected
-// ranks are written to LDS.  `stage` is LDS scratch of `cap` values; with
+// breaking ties by sketch index; any NaN among the B values gives NaN.  For
+// B <= 16 each thread sorts one coordinate's values with a network in
+// registers; otherwise every (coordinate, sketch) pair ranks its value in
+// parallel and the two selected ranks are written to LDS.  `stage` is LDS
+// scratch of `cap` values; with
 // `staged` the whole B x n block (one chunk) is already there, row m at m*n.
 // Returns true when the median vector was usable.
 // ---------------------------------------------------------------------------
 template <typename R, int NT>
-__device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict__ Uprev, int tau,
-                                int n, int B, R* u, R* stage, int cap, double* red, bool staged) {
+__device__ __forceinline__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict__ Uprev, int tau,
+                                                int n, int B, R* u, R* stage, int cap, double* red, bool staged) {
   const R* vb = Vprev + (size_t)tau * B * n;
   const int CH = median_chunk(n, B, cap);
   R* selA = stage + B * CH;
@@ -275,22 +297,39 @@ __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict
       }
       __syncthreads();
     }
+    if (B <= 16) {
+      // One coordinate per thread: its B values (padded with +inf) sorted by
+      // a network in registers; the order statistics are the same values the
+      // ranking below selects.
+      for (int ii = threadIdx.x; ii < cw; ii += NT) {
+        R v[16];
+        bool nan = false;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          v[j] = j < B ? stage[j * CH + ii] : R(__builtin_inf());
+          nan |= __builtin_isnan(v[j]);
+        }
+        sort_network(v);
+        R xa = v[0], xc = v[0];
+#pragma unroll
+        for (int j = 1; j < 16; ++j) {
+          xa = j == ra ? v[j] : xa;
+          xc = j == rb ? v[j] : xc;
+        }
+        R med = (B & 1) ? xa : (xa + xc) * R(0.5);
+        if (nan) med = R(__builtin_nan(""));
+        u[c0 + ii] = med;
+        ss += (double)med * (double)med;
+      }
+      continue;
+    }
     for (int e = threadIdx.x; e < B * cw; e += NT) {
       const int mm = e / cw, ii = e - mm * cw;
       const R x = stage[mm * CH + ii];
       int r = 0;
-      if (B <= 16) {  // all loads issued together
-        R o[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) o[j] = j < B ? stage[j * CH + ii] : R(0);
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < B) r += (o[j] < x) || (o[j] == x && j < mm);
-      } else {
-        for (int j = 0; j < B; ++j) {
-          const R o = stage[j * CH + ii];
-          r += (o < x) || (o == x && j < mm);
-        }
+      for (int j = 0; j < B; ++j) {
+        const R o = stage[j * CH + ii];
+        r += (o < x) || (o == x && j < mm);
       }
       if (r == ra) selA[ii] = x;
       if (r == rb) selC[ii] = x;
@@ -298,13 +337,7 @@ __device__ bool median_prologue(const R* __restrict__ Vprev, const R* __restrict
     __syncthreads();
     for (int ii = threadIdx.x; ii < cw; ii += NT) {
       bool nan = false;
-      if (B <= 16) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < B) nan |= __builtin_isnan(stage[j * CH + ii]);
-      } else {
-        for (int j = 0; j < B; ++j) nan |= __builtin_isnan(stage[j * CH + ii]);
-      }
+      for (int j = 0; j < B; ++j) nan |= __builtin_isnan(stage[j * CH + ii]);
       R med = (B & 1) ? selA[ii] : (selA[ii] + selC[ii]) * R(0.5);
       if (nan) med = R(__builtin_nan(""));
       u[c0 + ii] = med;
@@ -391,25 +424,8 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   const cx<R>* wkg = a.twg + pass_table_len(H, NT);
   const bool tab_lds = a.tab_lds != 0;
 
-  // One round of global loads up front: this sketch's spectrum values owned
-  // by the thread (they become the running products p0/p1), the twiddles
-  // W_b^tid and W_b^(q NT) (uniform), the table rows, and u or the previous
-  // step's estimates.  W_b^k for k = tid + q NT is formed as W_b^tid W_b^(q NT)
-  // when needed (two registers instead of 2 PK), W_b^(H-k) = -conj(W_b^k) and
-  // W_b^(H/2) = -i.
-  cx<R> p0[PK], p1[PK], pmid;
-  cx<R> wq[PK];
-#pragma unroll
-  for (int q = 0; q < PK; ++q) {
-    const int k = tid + q * NT;
-    wq[q] = wkg[q * NT];
-    if (!FULL && k >= H / 2) break;
-    p0[q] = Sm[k];
-    p1[q] = Sm[H - k];
-  }
-  const cx<R> wt = wkg[tid < H / 2 ? tid : 0];
-  auto wk = [&](int q) -> cx<R> { return q == 0 ? wt : cmul(wt, wq[q]); };
-  if (tid == 0) pmid = Sm[H / 2];
+  // Global loads in the order they are needed: the table rows and u, or the
+  // previous step's estimates for the median prologue, first.
   for (int e = tid; e < n; e += NT) {
     uint32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
     R uu = R(0);
@@ -432,6 +448,26 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   }
   const bool staged = PRE && median_chunk(n, B, 2 * PL) == n;
   if (staged) copy_to_lds<NT, 4>(re, a.Vprev + (size_t)tau * B * n, B * n);
+  // Then this sketch's spectrum values owned by the thread (they become the
+  // running products p0/p1) and the twiddles W_b^tid and W_b^(q NT)
+  // (uniform); issued after the loads above, they stay in flight through the
+  // prologue and the first count sketch (loads complete in issue order, so
+  // waiting for the earlier ones does not wait for these).  W_b^k for
+  // k = tid + q NT is formed as W_b^tid W_b^(q NT) when needed (two registers
+  // instead of 2 PK), W_b^(H-k) = -conj(W_b^k) and W_b^(H/2) = -i.
+  cx<R> p0[PK], p1[PK], pmid;
+  cx<R> wq[PK];
+#pragma unroll
+  for (int q = 0; q < PK; ++q) {
+    const int k = tid + q * NT;
+    wq[q] = wkg[q * NT];
+    if (!FULL && k >= H / 2) break;
+    p0[q] = Sm[k];
+    p1[q] = Sm[H - k];
+  }
+  const cx<R> wt = wkg[tid < H / 2 ? tid : 0];
+  auto wk = [&](int q) -> cx<R> { return q == 0 ? wt : cmul(wt, wq[q]); };
+  if (tid == 0) pmid = Sm[H / 2];
   const Twid<R> tw{a.twg, wkg};
   __syncthreads();  // staged tables, u or the estimates visible
 
