@@ -32,9 +32,13 @@ __device__ __forceinline__ double wave_down(double v, int o, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the work-group, returned to every thread.  `red` holds NT/64 doubles.
+// Sum over the work-group, returned to every thread.  `red` holds NT/64
+// doubles.  Each wave reduces its lanes; then every thread adds the wave sums
+// in the same fixed tree order, so all threads return the same value.  The
+// barrier in front keeps a previous call's readers of `red` safe.
 template <int NT>
 __device__ double block_sum(double v, double* red) {
+  constexpr int W = NT / 64;
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
 #pragma unroll
@@ -42,16 +46,14 @@ __device__ double block_sum(double v, double* red) {
   __syncthreads();
   if (lane == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x < 64) {
-    double s = (threadIdx.x < NT / 64) ? red[threadIdx.x] : 0.0;
+  double r[W];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += wave_down(s, o, lane);
-    if (threadIdx.x == 0) red[0] = s;
-  }
-  __syncthreads();
-  double s = red[0];
-  __syncthreads();
-  return s;
+  for (int i = 0; i < W; ++i) r[i] = red[i];
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < o; ++i) r[i] += r[i + o];
+  return r[0];
 }
 
 // Median of the values held by lanes 0..B-1 of a wave (B <= 64), returned to

@@ -84,6 +84,8 @@ struct tsk_ctx {
   std::vector<uint64_t> u0b_key;     // the same for batched decompositions
   std::vector<hipStream_t> fork;     // branch streams of batched graphs
   std::vector<hipEvent_t> fork_ev;   // one event per branch, plus the fork event
+  std::vector<hipStream_t> gfork;    // restart-group branches of one decomposition
+  std::vector<hipEvent_t> gfork_ev;
 };
 
 struct tsk_tables {
@@ -533,6 +535,8 @@ extern "C" void tsk_destroy(tsk_ctx_t c) {
   if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto s : c->fork) (void)hipStreamDestroy(s);
   for (auto e : c->fork_ev) (void)hipEventDestroy(e);
+  for (auto s : c->gfork) (void)hipStreamDestroy(s);
+  for (auto e : c->gfork_ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -1363,7 +1367,7 @@ template <typename R>
 tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, double* S64,
                              float* S32, int k, int L, int T, const double* u0, double* lam_out,
                              double* U_out, int32_t* tau_out, int32_t* flags, const DecompWs& w,
-                             bool plain, hipStream_t st) {
+                             bool plain, int groups, hipStream_t st) {
   const int n = tab->n, B = tab->B, b = tab->b;
   const int H1 = b / 2 + 1;
   const cx<double>* tw64 = nullptr;
@@ -1377,7 +1381,20 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
     TSK_TRY(check_launch("k_cvt"));
     int32_t* fl = flags + (size_t)c * L;
     R* ufin = nullptr;
-    if (!plain) {
+    if (!plain && groups > 1) {
+      // The restarts are independent until the selection: G groups of them
+      // run their T + 1 steps on parallel branches, so one group's launch
+      // tail overlaps the others' work.
+      TSK_HIP(hipEventRecord(ctx->gfork_ev[groups], st));
+      for (int g = 0; g < groups; ++g) {
+        const int t0 = (int)((long)L * g / groups), t1 = (int)((long)L * (g + 1) / groups);
+        hipStream_t s = ctx->gfork[g];
+        TSK_HIP(hipStreamWaitEvent(s, ctx->gfork_ev[groups], 0));
+        TSK_TRY(power_chain<R>(ctx, tab, spec, t1 - t0, t0, T, Ub, Vb, w.lam_per, fl, &ufin, s, &w.sb));
+        TSK_HIP(hipEventRecord(ctx->gfork_ev[g], s));
+        TSK_HIP(hipStreamWaitEvent(st, ctx->gfork_ev[g], 0));
+      }
+    } else if (!plain) {
       TSK_TRY(power_chain<R>(ctx, tab, spec, L, 0, T, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
     } else {
       for (int tau = 0; tau < L; ++tau)
@@ -1480,21 +1497,46 @@ tsk_status preload_twiddles(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype) {
   return preload_split_tables(ctx, tab->logb, needs_power_split(tab, dtype));
 }
 
+// Streams for `count` graph branches and count + 1 events (the last one forks).
+tsk_status ensure_branches(std::vector<hipStream_t>& streams, std::vector<hipEvent_t>& events, int count) {
+  while ((int)streams.size() < count) {
+    hipStream_t s = nullptr;
+    TSK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    streams.push_back(s);
+  }
+  while ((int)events.size() < count + 1) {
+    hipEvent_t e = nullptr;
+    TSK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    events.push_back(e);
+  }
+  return TSK_OK;
+}
+
+// Parallel restart groups of one decomposition.  Two halves of the restarts
+// on two branches measured fastest (their launches overlap each other's
+// start-up and tail; three or four branches gained less).  The split
+// transforms (b = 65536) keep one group: their buffers are indexed by restart
+// within a launch.
+int restart_groups(tsk_tables_t tab, tsk_dtype dtype, int L) {
+  if (needs_power_split(tab, dtype)) return 1;
+  return L >= 2 ? 2 : 1;
+}
+
 // Everything one decomposition enqueues: clear its flags (a fill kernel, so a
 // recorded graph holds no memset node), then the component loop.
 tsk_status decompose_all(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, double* S64, float* S32,
                          int k, int L, int T, const double* u0d, double* lam_out, double* U_out,
                          int32_t* tau_out, int32_t* flags, const DecompWs& w, bool plain,
-                         hipStream_t s) {
+                         int groups, hipStream_t s) {
   hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for((size_t)k * L, 256)), dim3(256), 0, s,
                      reinterpret_cast<unsigned*>(flags), 0u, (size_t)k * L);
   TSK_TRY(check_launch("k_fill_u32"));
   const void* spec = dtype == TSK_F32 ? (const void*)S32 : (const void*)S64;
   if (dtype == TSK_F32)
     return decompose_enqueue<float>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out,
-                                    flags, w, plain, s);
+                                    flags, w, plain, groups, s);
   return decompose_enqueue<double>(ctx, tab, spec, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out,
-                                   flags, w, plain, s);
+                                   flags, w, plain, groups, s);
 }
 
 GraphEntry* find_graph(tsk_ctx_t ctx, const std::vector<uint64_t>& key) {
@@ -1556,16 +1598,18 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
     u0d = u0_ws;
   }
   TSK_TRY(preload_twiddles(ctx, tab, dtype));  // uploads stay outside any capture
+  const int groups = restart_groups(tab, dtype, L);
+  if (!plain) TSK_TRY(ensure_branches(ctx->gfork, ctx->gfork_ev, groups));
   auto enqueue = [&](hipStream_t s) -> tsk_status {
     return decompose_all(ctx, tab, dtype, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out, flags, w,
-                         plain != 0, s);
+                         plain != 0, groups, s);
   };
   if (plain) return enqueue(st);
   std::vector<uint64_t> key = {0, (uint64_t)(uintptr_t)tab, (uint64_t)dtype, (uint64_t)(uintptr_t)S64,
                                (uint64_t)(uintptr_t)S32, (uint64_t)k, (uint64_t)L, (uint64_t)T,
                                (uint64_t)(uintptr_t)u0d, (uint64_t)(uintptr_t)lam_out,
                                (uint64_t)(uintptr_t)U_out, (uint64_t)(uintptr_t)tau_out,
-                               (uint64_t)(uintptr_t)flags, (uint64_t)(uintptr_t)base};
+                               (uint64_t)(uintptr_t)flags, (uint64_t)(uintptr_t)base, (uint64_t)groups};
   GraphEntry* ge = find_graph(ctx, key);
   if (!ge) TSK_TRY(record_graph(ctx, key, enqueue, &ge));
   TSK_HIP(hipGraphLaunch(ge->exec, st));
@@ -1628,16 +1672,7 @@ extern "C" tsk_status tsk_decompose_batched(tsk_ctx_t ctx, int ninst, const tsk_
   // Longest-first assignment of instances to at most 8 graph branches by
   // their sketch-update work k L (T+1) B b log2 b.
   const int nb = std::min(ninst, 8);
-  while ((int)ctx->fork.size() < nb) {
-    hipStream_t s = nullptr;
-    TSK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    ctx->fork.push_back(s);
-  }
-  while ((int)ctx->fork_ev.size() < nb + 1) {
-    hipEvent_t e = nullptr;
-    TSK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ctx->fork_ev.push_back(e);
-  }
+  TSK_TRY(ensure_branches(ctx->fork, ctx->fork_ev, nb));
   std::vector<int> order(ninst);
   std::vector<double> work(ninst);
   for (int i = 0; i < ninst; ++i) {
@@ -1671,7 +1706,7 @@ extern "C" tsk_status tsk_decompose_batched(tsk_ctx_t ctx, int ninst, const tsk_
       for (int i : branch[j]) {
         const tsk_problem& p = probs[i];
         TSK_TRY(decompose_all(ctx, p.tab, p.dtype, p.S64, p.S32, p.k, p.L, p.T, u0d[i], p.lam_out,
-                              p.U_out, p.tau_out, flags[i], w[i], false, s));
+                              p.U_out, p.tau_out, flags[i], w[i], false, 1, s));
       }
       TSK_HIP(hipEventRecord(ctx->fork_ev[j], s));
       TSK_HIP(hipStreamWaitEvent(cap, ctx->fork_ev[j], 0));
