@@ -109,8 +109,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> str:
     return "\n".join(out)
 
 
-def summarize_stats(stats_csv: str, top: int = 16) -> str:
-    """Per-kernel table of a rocprofv3 --stats kernel summary."""
+def summarize_stats(stats_csv: str, trace_csv: str = None, top: int = 16) -> str:
+    """Per-kernel table of a rocprofv3 --stats kernel summary; with the kernel
+    trace, the power kernels' launches split by grid (sketches x restarts)."""
     with open(stats_csv) as fh:
         rows = list(csv.DictReader(fh))
     out = ["# kernel | calls | average us | min us | max us | % of GPU time"]
@@ -118,6 +119,21 @@ def summarize_stats(stats_csv: str, top: int = 16) -> str:
         out.append(f"{r['Name'][:100]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                    f"{float(r['Percentage']):.2f}")
+    if trace_csv:
+        groups = {}
+        with open(trace_csv) as fh:
+            for r in csv.DictReader(fh):
+                if "k_power<" not in r["Kernel_Name"]:
+                    continue
+                grid = (int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]),
+                        int(r["Grid_Size_Y"]) // int(r["Workgroup_Size_Y"]))
+                key = (r["Kernel_Name"].split("(")[0].replace("void tsk::", ""), grid)
+                groups.setdefault(key, []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        out.append("# power kernel launches by grid (from the kernel trace)")
+        out.append("# kernel | grid (sketches x restarts) | calls | average us")
+        for (name, grid), d in sorted(groups.items()):
+            out.append(f"{name} | {grid[0]} x {grid[1]} | {len(d)} | {sum(d) / len(d):.2f}")
     return "\n".join(out)
 
 
@@ -413,13 +429,14 @@ def main():
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
-    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV")
+    ap.add_argument("--summarize-stats", nargs="+", metavar="CSV",
+                    help="kernel_stats.csv [kernel_trace.csv]")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(*args.summarize_pmc))
         return
     if args.summarize_stats:
-        print(summarize_stats(args.summarize_stats))
+        print(summarize_stats(*args.summarize_stats))
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "

@@ -333,10 +333,19 @@ tsk_status launch_c2r_t(const cx<double>* S64, double* s, const cx<double>* tw, 
     default: break;                                   \
   }
 
+// b <= 8192 (longer ones go through the sub-transform kernels).
 tsk_status launch_rank1(int logb, const tsk::Rank1Args& a, int B, int c, hipStream_t st) {
-#define CALL(L) launch_rank1_t<L>(a, B, c, st)
-  TSK_LOGB_SWITCH(logb, CALL)
-#undef CALL
+  switch (logb) {
+    case 6: return launch_rank1_t<6>(a, B, c, st);
+    case 7: return launch_rank1_t<7>(a, B, c, st);
+    case 8: return launch_rank1_t<8>(a, B, c, st);
+    case 9: return launch_rank1_t<9>(a, B, c, st);
+    case 10: return launch_rank1_t<10>(a, B, c, st);
+    case 11: return launch_rank1_t<11>(a, B, c, st);
+    case 12: return launch_rank1_t<12>(a, B, c, st);
+    case 13: return launch_rank1_t<13>(a, B, c, st);
+    default: break;
+  }
   return tsk::fail(TSK_EUNSUPPORTED, "rank-1 spectra: b=2^%d not built", logb);
 }
 tsk_status launch_r2c(int logb, const double* s, cx<double>* S64, cx<float>* S32,
@@ -363,6 +372,11 @@ int grid_for(size_t count, int threads) {
 
 int sub_R64(int logb) { return 1 << (logb - 1 - kSubLogM64); }
 
+// Rank-1 spectra through the sub-transform kernels: from b = 16384 on, where
+// one mode's transform per work-group (three per sketch) beats one
+// work-group doing all three in sequence.
+bool rank1_split_path(int logb) { return logb >= kLdsLogB; }
+
 // Sub-transform buffer of the split rank-1 spectra of c vectors.
 size_t rank1_split_bytes(tsk_tables_t tab, int c) {
   return (size_t)c * tab->B * 3 * sub_R64(tab->logb) * ((size_t)1 << kSubLogM64) * sizeof(cx<double>);
@@ -370,7 +384,7 @@ size_t rank1_split_bytes(tsk_tables_t tab, int c) {
 
 // Tables the split paths read, uploaded outside any graph capture.
 tsk_status preload_split_tables(tsk_ctx_t ctx, int logb, bool fp32_power) {
-  if (logb <= kLdsLogB) return TSK_OK;
+  if (!rank1_split_path(logb)) return TSK_OK;
   const cx<double>* t64 = nullptr;
   const cx<double>* w64 = nullptr;
   TSK_TRY(get_tw<double>(ctx, kSubLogM64 + 1, &t64, tsk::threads_for_h<double>(kSubLogM64)));
@@ -416,7 +430,7 @@ tsk_status rank1_split(tsk_ctx_t ctx, tsk_tables_t tab, const tsk::Rank1Args& a,
 
 tsk_status launch_rank1_any(tsk_ctx_t ctx, tsk_tables_t tab, const tsk::Rank1Args& a, int c, void* Ebuf,
                             hipStream_t st) {
-  if (tab->logb <= kLdsLogB) return launch_rank1(tab->logb, a, tab->B, c, st);
+  if (!rank1_split_path(tab->logb)) return launch_rank1(tab->logb, a, tab->B, c, st);
   return rank1_split(ctx, tab, a, c, Ebuf, st);
 }
 
@@ -743,7 +757,8 @@ tsk_status rank1_update(tsk_ctx_t ctx, tsk_tables_t tab, const double* lam, cons
   void* prod = nullptr;
   TSK_TRY(ws_get(ctx, WS_PROD, (size_t)std::min(chunk, c) * per_vec, &prod));
   void* ebuf = nullptr;
-  if (tab->logb > kLdsLogB) TSK_TRY(ws_get(ctx, WS_SPLITP, rank1_split_bytes(tab, std::min(chunk, c)), &ebuf));
+  if (rank1_split_path(tab->logb))
+    TSK_TRY(ws_get(ctx, WS_SPLITP, rank1_split_bytes(tab, std::min(chunk, c)), &ebuf));
   for (int r0 = 0; r0 < c; r0 += chunk) {
     const int cc = std::min(chunk, c - r0);
     tsk::Rank1Args a;
@@ -1337,7 +1352,7 @@ struct DecompWs {
   double* lam64;   // [B]
   void* prod;      // cx<double>[B][b/2+1]
   double* u0;      // [k][L][n] generated start vectors (when caller passes none)
-  void* esplit;    // split rank-1 sub-transforms (b > 16384)
+  void* esplit;    // split rank-1 sub-transforms (b >= 16384)
   SplitBufs sb;    // split FP32 power steps (b = 65536)
 };
 
@@ -1470,7 +1485,7 @@ size_t decomp_ws_layout(char* base, tsk_tables_t tab, tsk_dtype dtype, int k, in
   d.prod = take(B * H1 * 16);
   d.flags = flags ? (int32_t*)take((size_t)k * L * 4) : nullptr;
   d.u0 = u0 ? (double*)take((size_t)k * L * n * 8) : nullptr;
-  d.esplit = tab->logb > kLdsLogB ? take(rank1_split_bytes(tab, 1)) : nullptr;
+  d.esplit = rank1_split_path(tab->logb) ? take(rank1_split_bytes(tab, 1)) : nullptr;
   if (needs_power_split(tab, dtype)) {
     d.sb.E = take(power_split_bytes_E(tab, L));
     d.sb.A = take(power_split_bytes_A(tab, L));
