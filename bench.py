@@ -303,6 +303,86 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
     }
 
 
+# Table 5 of the paper (sketched robust tensor power method on the n = 1000
+# full-rank synthetic tensors, top 10 eigenvectors): squared residual and
+# wrong vectors for log2(b) = 12..16, keyed by (sigma, B).  Printed for
+# comparison next to the measured rows; the paper's times are CPU minutes.
+TABLE5 = {
+    (0.01, 20): ([.40, .19, .10, .09, .08], [8, 6, 3, 0, 0]),
+    (0.01, 30): ([.26, .10, .09, .08, .07], [7, 5, 2, 0, 0]),
+    (0.01, 40): ([.17, .10, .08, .08, .07], [7, 4, 0, 0, 0]),
+    (0.1, 20): ([.52, 3.1, .21, .18, .17], [8, 7, 4, 0, 0]),
+    (0.1, 30): ([4.0, .24, .19, .17, .16], [7, 5, 3, 0, 0]),
+    (0.1, 40): ([.30, .22, .18, .17, .16], [7, 4, 0, 0, 0]),
+}
+
+
+def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 14, 15, 16)):
+    """The paper's accuracy table on its own synthetic tensors: n = 1000,
+    full rank with lam_i = 1/i (normalised), symmetric noise with
+    E||E||^2 = sigma; top k = 10 eigenvectors, L = T = 30, FP32 power steps.
+    For every (sigma, B, b): dense build of the B sketches from the 4 GB
+    tensor, Algorithm 1, then the squared residual ||T - sum lam_i v_i^3||^2
+    (FP64 contractions of the dense tensor) and the wrong vectors against the
+    true top 10 (||v - v_hat||^2 > 0.1)."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    from paper_1506_04448_amd.workloads import full_rank_tensor
+    n, k, L, T = 1000, 10, 30, 30
+    rows = []
+    t_gen = 0.0
+    for sigma in sigmas:
+        t0 = time.perf_counter()
+        X = full_rank_tensor(n, sigma, seed=5, device=dev)
+        torch.cuda.synchronize()
+        t_gen += time.perf_counter() - t0
+        Tt = X.T
+        nrm2 = 0.0
+        for i0 in range(0, n, 100):
+            nrm2 += float((Tt[i0:i0 + 100].double() ** 2).sum())
+        for B in Bs:
+            for logb in logbs:
+                b = 1 << logb
+                h, xi = tsk.hash_generate(100 + B + logb, n, b, B)
+                tab = tsk.Tables(ctx, h, xi, b)
+                S64, S32 = tsk.new_sketch(tab, dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tsk.sketch_build_dense(ctx, tab, Tt, S64, S32)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F32, seed=7)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                Ud = U.double()
+                tuuu = torch.zeros(k, dtype=torch.float64, device=dev)
+                for i0 in range(0, n, 100):
+                    Y = Tt[i0:i0 + 100].double().reshape(-1, n) @ Ud.T          # [(i,j)][r]
+                    Y = Y.view(-1, n, k)                                          # [i][j][r]
+                    tuuu += torch.einsum("ijr,jr,ir->r", Y, Ud.T, Ud.T[i0:i0 + 100])
+                G = (Ud @ Ud.T) ** 3
+                lamd = lam.double()
+                res = nrm2 - 2.0 * float(lamd @ tuuu) + float(lamd @ G @ lamd)
+                wrong = wrong_vectors(X.V[:k], U.cpu().numpy())
+                ref = TABLE5.get((sigma, B))
+                j = logbs.index(logb)
+                rows.append({"sigma": sigma, "B": B, "log2b": logb, "residual": res, "wrong": int(wrong),
+                             "paper_residual": ref[0][j] if ref else None,
+                             "paper_wrong": ref[1][j] if ref else None,
+                             "build_ms": 1e3 * (t1 - t0), "decompose_ms": 1e3 * (t2 - t1)})
+                print(f"x1 sigma={sigma} B={B} log2b={logb}: residual {res:.3f} "
+                      f"(paper {rows[-1]['paper_residual']}), wrong {wrong} "
+                      f"(paper {rows[-1]['paper_wrong']}), decompose {rows[-1]['decompose_ms']:.1f} ms",
+                      file=sys.stderr, flush=True)
+                tab.close()
+                del S64, S32
+        del X, Tt
+        torch.cuda.empty_cache()
+    return {"workload": ("paper's synthetic tensors: n=1000 full rank, lam_i=1/i normalised, symmetric "
+                         "noise E||E||^2=sigma; top 10, L=T=30, FP32 power steps"),
+            "tensor_generation_s": t_gen, "rows": rows}
+
+
 def c5_autograd(ctx, dev, steps: int = 20):
     """Gradient extensions at the shapes of the differentiation workload:
     n=1000, k=100 planted orthonormal components (lam ~ U[1,2]), b=65536,
@@ -425,6 +505,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the LDA document-build leg")
     ap.add_argument("--c4-docs", type=int, default=500000, help="documents in the LDA corpus")
     ap.add_argument("--no-c5", action="store_true", help="skip the gradient-extension leg")
+    ap.add_argument("--no-x1", action="store_true", help="skip the paper's synthetic accuracy table")
     ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
@@ -554,6 +635,7 @@ def main():
     c3 = None if args.no_c3 else c3_batched(ctx, dev)
     c4 = None if args.no_c4 else c4_docs(ctx, dev, args.c4_docs)
     c5 = None if args.no_c5 else c5_autograd(ctx, dev)
+    x1 = None if args.no_x1 else x1_synthetic(ctx, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -595,6 +677,7 @@ def main():
         "batched_instances": c3,
         "lda_documents": c4,
         "gradients": c5,
+        "paper_table5": x1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

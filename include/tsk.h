@@ -93,6 +93,9 @@ tsk_status tsk_init_vectors(uint64_t seed, int comp, int L, int n, double* u0_ho
 tsk_status tsk_tables_create(tsk_ctx_t ctx, int n, int b, int B,
                              const uint32_t* h_host, const int8_t* xi_host,
                              tsk_tables_t* out);
+/* Waits for the device, frees the tables and drops the context's recorded
+ * decomposition graphs (they hold table addresses).  The context must still
+ * be alive. */
 void tsk_tables_destroy(tsk_tables_t tab);
 
 /* ---- Sketch construction -------------------------------------------------
@@ -167,6 +170,19 @@ tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
                             const double* S64, const float* S32, int L,
                             const void* U_in, void* U_out, void* V, int32_t* flags,
                             void* stream);
+
+/* The median and normalisation of a power step on given per-sketch estimates
+ * (Algorithm 1): vbar_i = med_m V[tau][m][i] (odd B: rank (B-1)/2; even B: the
+ * mean of ranks B/2-1 and B/2; any NaN among the B values gives NaN), then
+ * U_out[tau] = vbar / ||vbar||, or U_in[tau] with flags[tau] |= 1 when
+ * ||vbar|| is zero or not finite.  V: [L][B][n], U_in, U_out: [L][n], all
+ * device, float for TSK_F32 and double for TSK_F64 (U_out may not alias V or
+ * U_in); flags: nullable int32[L], device.  1 <= B <= 64 by sorting networks,
+ * larger B by ranking.  Errors: TSK_EINVAL (null, L, n or B < 1, alias,
+ * dtype). */
+tsk_status tsk_median_normalize(tsk_ctx_t ctx, tsk_dtype dtype, int L, int n, int B,
+                                const void* V, const void* U_in, void* U_out,
+                                int32_t* flags, void* stream);
 
 /* Per-sketch estimates of T(I,u,u) for L vectors (Proposition 1), without
  * the median: V[tau][m][i] = xi1(i) sbar[h1(i)],

@@ -60,6 +60,7 @@ _SIGS = {
     "tsk_sketch_export": ([_P, _I, _I, _P, _P, _P], _I),
     "tsk_sketch_deflate": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
+    "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_uuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_contract_tiuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P], _I),
     "tsk_decompose": ([_P, _P, _I, _P, _P, _I, _I, _I, _P, _U64, _P, _P, _P, _P, _I, _P], _I),
@@ -292,6 +293,23 @@ def power_update(ctx, tab, U_in, S64=None, S32=None, U_out=None, V=None, flags=N
     _check("tsk_power_update", lib().tsk_power_update(
         ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U_in), _ptr(U_out), _ptr(V),
         _ptr(flags), _stream(stream)))
+    return U_out
+
+
+def median_normalize(ctx, V, U_in, U_out=None, flags=None, stream=None):
+    """Median over the B sketches of V [L][B][n] and normalisation; U_in [L][n]
+    is the fallback for a zero or non-finite median vector."""
+    import torch
+    dt, tdt = _vdtype(V.dtype)
+    L, B, n = V.shape
+    _tensor(V, "V", tdt, (L, B, n))
+    _tensor(U_in, "U_in", tdt, (L, n))
+    if U_out is None:
+        U_out = torch.empty_like(U_in)
+    _tensor(U_out, "U_out", tdt, (L, n))
+    _tensor(flags, "flags", torch.int32, (L,), allow_none=True)
+    _check("tsk_median_normalize", lib().tsk_median_normalize(
+        ctx.handle, dt, L, n, B, _ptr(V), _ptr(U_in), _ptr(U_out), _ptr(flags), _stream(stream)))
     return U_out
 
 

@@ -267,6 +267,30 @@ __device__ __forceinline__ void sort_network(R (&v)[N]) {
           }
 }
 
+// Median of B <= N values get(0..B-1) by the network in registers (padded
+// with +inf): the element of rank (B-1)/2, or for even B the mean of ranks
+// B/2-1 and B/2; any NaN among them gives NaN.
+template <int N, typename R, typename Get>
+__device__ __forceinline__ R network_median(Get get, int B) {
+  R v[N];
+  bool nan = false;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    v[j] = j < B ? get(j) : R(__builtin_inf());
+    nan |= __builtin_isnan(v[j]);
+  }
+  sort_network(v);
+  const int ra = (B - 1) / 2, rb = B / 2;
+  R xa = v[0], xc = v[0];
+#pragma unroll
+  for (int j = 1; j < N; ++j) {
+    xa = j == ra ? v[j] : xa;
+    xc = j == rb ? v[j] : xc;
+  }
+  const R med = (B & 1) ? xa : (xa + xc) * R(0.5);
+  return nan ? R(__builtin_nan("")) : med;
+}
+
 // ---------------------------------------------------------------------------
 // Median prologue: u = vbar / ||vbar||, vbar_i = med_m Vprev[tau][m][i], for
 // the n coordinates of one restart, into u[] (LDS or global).  Falls back to
@@ -304,22 +328,7 @@ __device__ __forceinline__ bool median_prologue(const R* __restrict__ Vprev, con
       // a network in registers; the order statistics are the same values the
       // ranking below selects.
       for (int ii = threadIdx.x; ii < cw; ii += NT) {
-        R v[16];
-        bool nan = false;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          v[j] = j < B ? stage[j * CH + ii] : R(__builtin_inf());
-          nan |= __builtin_isnan(v[j]);
-        }
-        sort_network(v);
-        R xa = v[0], xc = v[0];
-#pragma unroll
-        for (int j = 1; j < 16; ++j) {
-          xa = j == ra ? v[j] : xa;
-          xc = j == rb ? v[j] : xc;
-        }
-        R med = (B & 1) ? xa : (xa + xc) * R(0.5);
-        if (nan) med = R(__builtin_nan(""));
+        const R med = network_median<16, R>([&](int j) { return stage[j * CH + ii]; }, B);
         u[c0 + ii] = med;
         ss += (double)med * (double)med;
       }
@@ -584,15 +593,43 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   }
 }
 
-// u_out[tau] = normalised median of V[tau] (fallback u_in, flag), grid = L.
+// Threads of the median kernel: the 64-value network holds 64 values per
+// thread in registers (FP64: 128 VGPRs, so one wave per SIMD).
 template <typename R>
-__global__ __launch_bounds__(256) void k_median_norm(const R* V, const R* Uin, R* Uout,
-                                                     int32_t* flags, int n, int B) {
+constexpr int median_threads() { return sizeof(R) == 8 ? 256 : 512; }
+
+// u_out[tau] = normalised median of V[tau] (fallback u_in, flag), grid = L,
+// median_threads<R>() threads.  For B <= 64 each thread takes whole coordinates: its B values
+// straight from global memory (coalesced across threads for each m) into a
+// sorting network; larger B goes through the ranking prologue.
+template <typename R>
+__global__ __launch_bounds__(median_threads<R>()) void k_median_norm(const R* V, const R* Uin, R* Uout,
+                                                                     int32_t* flags, int n, int B) {
+  constexpr int NT = median_threads<R>();
   __shared__ __align__(16) R stage[4096];
-  __shared__ double red[4];
+  __shared__ double red[NT / 64];
   const int tau = blockIdx.x;
-  R* u = Uout + (size_t)tau * n;  // the prologue writes u in place
-  const bool ok = median_prologue<R, 256>(V, Uin, tau, n, B, u, stage, 4096, red, false);
+  R* u = Uout + (size_t)tau * n;  // written in place, then normalised
+  bool ok;
+  if (B <= 64) {
+    const R* Vt = V + (size_t)tau * B * n;
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+      auto get = [&](int j) { return Vt[(size_t)j * n + i]; };
+      const R med = B <= 16   ? network_median<16, R>(get, B)
+                    : B <= 32 ? network_median<32, R>(get, B)
+                              : network_median<64, R>(get, B);
+      u[i] = med;
+      ss += (double)med * (double)med;
+    }
+    const double nrm = sqrt(block_sum<NT>(ss, red));
+    ok = nrm > 0.0 && nrm < __builtin_inf();
+    const R inv = ok ? R(1.0 / nrm) : R(0);
+    const R* up = Uin + (size_t)tau * n;
+    for (int i = threadIdx.x; i < n; i += NT) u[i] = ok ? u[i] * inv : up[i];  // own coordinates
+  } else {
+    ok = median_prologue<R, NT>(V, Uin, tau, n, B, u, stage, 4096, red, false);
+  }
   if (threadIdx.x == 0 && !ok && flags) flags[tau] |= 1;
 }
 

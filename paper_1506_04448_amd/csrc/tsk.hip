@@ -270,10 +270,37 @@ tsk_status power_lds_plan(int logb, int n, size_t* bytes, int* tab) {
   return TSK_OK;
 }
 
+template <typename R>
+tsk_status median_norm_launch(const R* V, const R* Uin, R* Uout, int32_t* flags, int L, int n, int B,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((tsk::k_median_norm<R>), dim3(L), dim3(tsk::median_threads<R>()), 0, st, V, Uin, Uout, flags, n,
+                     B);
+  return check_launch("k_median_norm");
+}
+
+// The median of the previous step runs as the power kernel's prologue when it
+// is cheap there (B <= 16 values per coordinate, at most two coordinates per
+// thread, all of them staged in the sequence buffer at once): every one of the
+// B work-groups of a restart repeats it.  Otherwise it is a launch of its own,
+// once per restart, before a power launch that reads the medians.
+template <typename R, int LOGB>
+bool fused_median(int n, int B) {
+  constexpr int NT = tsk::power_threads<R>(LOGB - 1);
+  const long staged = 2L * tsk::padded_len(1 << (LOGB - 1));
+  return B <= 16 && n <= 2 * NT && (long)n * (B + 2) <= staged;
+}
+
 template <typename R, int LOGB>
 tsk_status launch_power_t(tsk::PowerArgs<R> a, int B, int nrest, hipStream_t st) {
   size_t lds = 0;
   TSK_TRY(power_lds_plan<R>(LOGB, a.n, &lds, &a.tab_lds));
+  if (a.prefix && !fused_median<R, LOGB>(a.n, B)) {
+    const size_t on = (size_t)a.tau0 * a.n, obn = on * B;
+    TSK_TRY(median_norm_launch<R>(a.Vprev + obn, a.Uprev + on, a.Ucur + on,
+                                  a.flags ? a.flags + a.tau0 : nullptr, nrest, a.n, B, st));
+    a.prefix = 0;
+    a.Uprev = a.Ucur;
+  }
   if (a.prefix) return launch_power_v<R, LOGB, true>(a, lds, B, nrest, st);
   return launch_power_v<R, LOGB, false>(a, lds, B, nrest, st);
 }
@@ -617,6 +644,9 @@ extern "C" void tsk_tables_destroy(tsk_tables_t t) {
   if (!t) return;
   (void)hipSetDevice(t->ctx->device);
   (void)hipDeviceSynchronize();
+  // Recorded graphs hold this table's device addresses; a later table could
+  // reuse the handle's address and match their keys.
+  clear_graphs(t->ctx);
   (void)hipFree(t->hx);
   delete t;
 }
@@ -816,12 +846,6 @@ extern "C" tsk_status tsk_sketch_deflate(tsk_ctx_t ctx, tsk_tables_t tab, const 
 
 namespace {
 
-template <typename R>
-tsk_status median_norm_launch(const R* V, const R* Uin, R* Uout, int32_t* flags, int L, int n, int B,
-                              hipStream_t st) {
-  hipLaunchKernelGGL((tsk::k_median_norm<R>), dim3(L), dim3(256), 0, st, V, Uin, Uout, flags, n, B);
-  return check_launch("k_median_norm");
-}
 
 // FP32 power step at b = 65536 through the split transforms (large.hpp); the
 // median of the previous step (prefix) is a launch of its own here.
@@ -981,6 +1005,25 @@ extern "C" tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
                                nullptr, (double*)vbuf, nullptr, S(stream)));
   return median_norm_launch<double>((const double*)vbuf, (const double*)U_in, (double*)U_out, flags,
                                     L, n, B, S(stream));
+}
+
+extern "C" tsk_status tsk_median_normalize(tsk_ctx_t ctx, tsk_dtype dtype, int L, int n, int B,
+                                           const void* V, const void* U_in, void* U_out,
+                                           int32_t* flags, void* stream) {
+  if (!ctx || !V || !U_in || !U_out)
+    return tsk::fail(TSK_EINVAL, "tsk_median_normalize: null argument");
+  if (L < 1 || n < 1 || B < 1)
+    return tsk::fail(TSK_EINVAL, "tsk_median_normalize: L=%d, n=%d, B=%d must be >= 1", L, n, B);
+  if (dtype != TSK_F32 && dtype != TSK_F64)
+    return tsk::fail(TSK_EINVAL, "tsk_median_normalize: dtype %d", (int)dtype);
+  if (U_out == V || U_out == U_in)
+    return tsk::fail(TSK_EINVAL, "tsk_median_normalize: U_out aliases V or U_in");
+  TSK_TRY(set_device(ctx));
+  if (dtype == TSK_F32)
+    return median_norm_launch<float>((const float*)V, (const float*)U_in, (float*)U_out, flags, L, n, B,
+                                     S(stream));
+  return median_norm_launch<double>((const double*)V, (const double*)U_in, (double*)U_out, flags, L, n,
+                                    B, S(stream));
 }
 
 extern "C" tsk_status tsk_contract_tiuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,

@@ -176,3 +176,57 @@ def population_whitening(Phi: np.ndarray, alpha: np.ndarray) -> np.ndarray:
     A = Phi * np.sqrt(alpha / (a0 * (a0 + 1.0)))
     U, s, _ = np.linalg.svd(A, full_matrices=False)
     return U / s
+
+
+@dataclasses.dataclass
+class FullRankTensor:
+    T: object              # torch float32 [n][n][n] on the requested device
+    lam: np.ndarray        # [n] float64 weights after normalisation (descending)
+    V: np.ndarray          # [n][n] float64 orthonormal basis (rows)
+    sigma: float
+
+
+def full_rank_tensor(n: int, sigma: float, seed: int, device="cpu", chunk: int = 50) -> FullRankTensor:
+    """The synthetic tensors of the paper's accuracy table (Section 5.1,
+    Table 5): T = normalize(sum_{i<=n} lam_i v_i^{(x)3}) + E with a random
+    orthonormal basis {v_i} (QR of a seeded Gaussian n x n matrix), lam_i = 1/i
+    before normalisation, the signal scaled to unit Frobenius norm (exact:
+    ||sum lam_i v_i^{(x)3}||_F^2 = sum lam_i^2 for an orthonormal basis), and a
+    symmetric Gaussian E drawn for i<=j<=k and copied to every permutation of
+    the indices, with variance sigma/n^3 per entry so that E||E||_F^2 = sigma.
+
+    Built with torch on `device` (the n = 1000 tensor takes 4 GB in FP32): the
+    signal slab by slab as an FP64 matrix product, the noise from a seeded
+    torch generator on that device, gathered at the sorted index triples.
+    """
+    import torch
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = 1.0 / np.arange(1, n + 1, dtype=np.float64)
+    lam /= np.linalg.norm(lam)
+    dev = torch.device(device)
+    Qd = torch.from_numpy(Q).to(dev)
+    QlT = (Qd * torch.from_numpy(lam).to(dev)).T.contiguous()   # [r][k]: lam_r q_k,r
+    T = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    G = torch.randn((n, n, n), generator=gen, dtype=torch.float32, device=dev)
+    G.mul_(float(np.sqrt(sigma / float(n) ** 3)))
+    Gf = G.view(-1)
+    jj = torch.arange(n, device=dev).view(n, 1).expand(n, n)
+    kk = torch.arange(n, device=dev).view(1, n).expand(n, n)
+    for i0 in range(0, n, chunk):
+        i1 = min(n, i0 + chunk)
+        # signal: T[i, j, k] = sum_r q_ir q_jr lam_r q_kr
+        A = (Qd[i0:i1, None, :] * Qd[None, :, :]).reshape((i1 - i0) * n, n)
+        T[i0:i1] = (A @ QlT).view(i1 - i0, n, n).to(torch.float32)
+        # noise: E[i, j, k] = G[sorted(i, j, k)]
+        ii = torch.arange(i0, i1, device=dev).view(-1, 1, 1).expand(i1 - i0, n, n)
+        j = jj.unsqueeze(0).expand(i1 - i0, n, n)
+        k = kk.unsqueeze(0).expand(i1 - i0, n, n)
+        lo = torch.minimum(torch.minimum(ii, j), k)
+        hi = torch.maximum(torch.maximum(ii, j), k)
+        mid = ii + j + k - lo - hi
+        T[i0:i1] += Gf[(lo * n + mid) * n + hi]
+    del G, Gf
+    return FullRankTensor(T=T, lam=lam, V=np.ascontiguousarray(Q.T), sigma=sigma)

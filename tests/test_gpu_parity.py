@@ -285,6 +285,40 @@ def test_plain_path_equals_batched(ctx):
         np.testing.assert_array_equal(a, c)
 
 
+def test_recreated_tables_do_not_replay_old_graphs(ctx):
+    """Decompositions on tables created after others were destroyed (handles
+    and sketch buffers may reuse addresses) match a fresh context's result."""
+    n, k, L, T = 40, 2, 6, 6
+    P = planted_tensor(n, 2, noise=0.01, seed=8, dtype=np.float32)
+    Td = torch.from_numpy(P.T).to(DEV)
+    results = {}
+    for b, B in ((1024, 3), (2048, 4), (1024, 3)):
+        h, xi = tsk.hash_generate(9, n, b, B)
+        tab = tsk.Tables(ctx, h, xi, b)
+        S64, S32 = tsk.new_sketch(tab, DEV)
+        tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+        lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F64, seed=4)
+        results.setdefault((b, B), []).append((lam.cpu().numpy(), U.cpu().numpy()))
+        tab.close()
+        del S64, S32
+    c2 = tsk.Context(0)
+    try:
+        for (b, B), got in results.items():
+            h, xi = tsk.hash_generate(9, n, b, B)
+            tab = tsk.Tables(c2, h, xi, b)
+            S64, S32 = tsk.new_sketch(tab, DEV)
+            tsk.sketch_build_dense(c2, tab, Td, S64, S32)
+            lam, U, _, _ = tsk.decompose(c2, tab, S64, S32, k, L, T, dtype=tsk.F64, seed=4)
+            for lam_g, U_g in got:
+                # FP64 builds add in any order: equal to rounding
+                assert np.allclose(lam_g, lam.cpu().numpy(), rtol=1e-10, atol=0)
+                assert np.allclose(U_g, U.cpu().numpy(), rtol=0, atol=1e-9)
+            tab.close()
+    finally:
+        torch.cuda.synchronize()
+        c2.close()
+
+
 def test_graph_replay_is_stable(ctx):
     n, k, b, B, L, T = 64, 3, 4096, 5, 12, 10
     P = planted_tensor(n, 3, noise=0.02, seed=6, dtype=np.float32)
@@ -389,3 +423,67 @@ def test_argument_errors(ctx):
     assert st == -1                                            # aliasing in/out
     with pytest.raises(tsk.TskError, match="EINVAL"):
         tsk.decompose(ctx, tab16, S64, S32, 11, 2, 2)          # k > n
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 15, 16, 17, 20, 31, 32, 33, 40, 63, 64, 65, 80])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_median_normalize_matches_oracle(ctx, B, dtype):
+    """Median over sketches and normalisation (Algorithm 1) on given estimates:
+    values from a small set (many ties), a NaN coordinate, an all-zero restart
+    (fallback and flag), n across one and several coordinates per thread."""
+    print(f"median B={B} {dtype}", flush=True)
+    rng = np.random.default_rng(B)
+    for n in (1, 7, 300, 1500):
+        L = 4
+        V = rng.integers(-3, 4, size=(L, B, n)).astype(np.float64) * 0.25
+        V[1] += rng.standard_normal((B, n)) * 1e-3            # mostly distinct
+        if n > 3:
+            V[2, rng.integers(0, B), 3] = np.nan                 # NaN -> NaN coordinate -> fallback
+        V[3] = 0.0                                               # zero median -> fallback
+        U_in = rng.standard_normal((L, n))
+        if dtype == torch.float32:
+            V = V.astype(np.float32).astype(np.float64)
+            U_in = U_in.astype(np.float32).astype(np.float64)
+        Vd = torch.from_numpy(V).to(device=DEV, dtype=dtype)
+        Ud = torch.from_numpy(U_in).to(device=DEV, dtype=dtype)
+        flags = torch.zeros(L, dtype=torch.int32, device=DEV)
+        out = tsk.median_normalize(ctx, Vd, Ud, flags=flags).cpu().numpy()
+        vbar = oracle.contract.median(V, axis=1)
+        tol = 1e-6 if dtype == torch.float32 else 1e-14
+        for tau in range(L):
+            nrm = np.linalg.norm(vbar[tau])
+            if nrm > 0 and np.isfinite(nrm):
+                assert flags[tau].item() == 0
+                np.testing.assert_allclose(out[tau], vbar[tau] / nrm, rtol=0, atol=tol)
+            else:
+                assert flags[tau].item() == 1
+                np.testing.assert_array_equal(out[tau], U_in[tau])
+
+
+@pytest.mark.parametrize("B,dtype,T,tol", [(20, tsk.F64, 6, 1e-12), (40, tsk.F32, 25, 1e-5)])
+def test_decompose_with_separate_median_launch(ctx, B, dtype, T, tol):
+    """B > 16: the median of each step is a launch of its own inside the graph
+    (not the power kernel's prologue); whole of Algorithm 1 against the oracle
+    (FP32: the converged first component)."""
+    print(f"decompose separate median B={B}", flush=True)
+    n, k, b, L = 30, 2, 512, 5
+    P = planted_tensor(n, 2, noise=0.01, seed=11)
+    tab, h, xi = _tables(ctx, 12, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    u0 = np.stack([oracle.start_vectors_spec(3, c, L, n) for c in range(k)])
+    if dtype == tsk.F32:
+        u0 = u0.astype(np.float32).astype(np.float64)
+    lam, U, tau, flags = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=dtype,
+                                       u0=torch.from_numpy(u0).to(DEV))
+    S_time = _oracle_sketches(P.T, h, xi, b)
+    if dtype == tsk.F64:
+        ref = oracle.rtpm_sketched(S_time, h, xi, k, L, T, u0)
+        assert rel(lam.cpu().numpy(), ref.lam) < tol
+        assert rel(U.cpu().numpy(), ref.U) < tol
+        np.testing.assert_array_equal(flags.cpu().numpy(), ref.flags)
+    else:
+        # FP32 steps: the first component against the oracle's (later ones follow from it)
+        ref = oracle.rtpm_sketched(S_time, h, xi, 1, L, T, u0[:1])
+        assert abs(lam.cpu().numpy()[0] - ref.lam[0]) <= tol * abs(ref.lam[0])
+        assert rel(U.cpu().numpy()[0], ref.U[0]) < 10 * tol
