@@ -20,6 +20,10 @@ The gradients of the sketched T(u,u,u) estimate and of the sketched CP loss
 injective-hash reduction to the dense gradient.  The whitened LDA moment of
 Appendix D (``lda``) is pinned by brute force over word positions, by the
 closed forms of the population moments and by the explicit V^3 route.
+Fast ALS (``als``, Appendix C) is pinned by the injective-hash reduction of
+the two-vector estimate to the exact contraction, by its unbiasedness over
+all sign (and, tiny case, hash) draws, and by exact ALS recovering an exactly
+low-rank tensor.
 Parity unpinned: the full sketched power method beyond those pins (the paper
 prints no worked example to compare against).
 """
@@ -30,7 +34,7 @@ from .sketch import (count_sketch, sketch_dense, circular_convolution,
 from .contract import (median, power_update_sketch, power_update_direct,
                        tuuu_sketch, tuuu_direct, power_update, contract_uuu)
 from .rtpm import rtpm_sketched, rtpm_dense, RtpmResult
-from . import gradients, lda
+from . import gradients, lda, als
 from .dense import (dense_Tuuu, dense_TIuu, residual_dense, residual_factored,
                     wrong_vectors)
 
@@ -41,5 +45,5 @@ __all__ = [
     "median", "power_update_sketch", "power_update_direct", "tuuu_sketch",
     "tuuu_direct", "power_update", "contract_uuu",
     "rtpm_sketched", "rtpm_dense", "RtpmResult",
-    "gradients", "lda", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
+    "gradients", "lda", "als", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
 ]
