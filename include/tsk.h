@@ -200,6 +200,36 @@ tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
                             const double* S64, const float* S32, int L, const void* U,
                             double* lam_med, double* lam_per, void* stream);
 
+/* ---- Fast ALS (Appendix C, Algorithm 2) -----------------------------------
+ * Two-vector contraction (Proposition 1 with the two count sketches of
+ * different vectors): per sketch m, with a = (rd+1) mod 3, c = (rd+2) mod 3,
+ *   sbar = F^-1( S^(m) o conj F(s_a X[r]) o conj F(s_c Y[r]) ),
+ *   V[r][m][i] = xi_rd(i) sbar[h_rd(i)],
+ * the estimate of T contracted with X[r] in mode a and Y[r] in mode c, read
+ * off in mode rd (rd = 0: T(I, x, y)).  X, Y: [L][n], V: [L][B][n], device,
+ * float for TSK_F32 (reads S32) and double for TSK_F64 (reads S64).  b up to
+ * 32768 (FP32) or 16384 (FP64).  Errors: TSK_EINVAL (null, rd, L),
+ * TSK_EUNSUPPORTED (b). */
+tsk_status tsk_contract_two(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                            const double* S64, const float* S32, int rd, int L,
+                            const void* X, const void* Y, void* V, void* stream);
+
+/* Algorithm 2 for a rank-k CP model (factors held as rows: F[f][r] is column
+ * r of A, B, C for f = 0, 1, 2): T sweeps, each updating A, B, C in turn by
+ *   A = G^+ Vbar,  Vbar[r] = med_m V[r][m] (tsk_contract_two, rd = 0),
+ *   G = (B B^T) o (C C^T)  (k x k, pseudo-inverse over eigenvalues
+ *   > 1e-12 of the largest), lambda_r = ||A[r]||, A[r] /= lambda_r,
+ * and B, C likewise with the modes rotated (the update equation of
+ * Appendix C; the printed Algorithm 2 omits the pseudo-inverse, which is the
+ * identity for orthonormal factors).  Power-kernel precision as dtype; the
+ * factors, G and the update in FP64.  F0: double[3][k][n] initial factors;
+ * F_out: double[3][k][n] (may equal F0); lam_out: double[k] from the last (C)
+ * update; all device.  1 <= k <= 64, T >= 1, b as tsk_contract_two.
+ * Errors: TSK_EINVAL, TSK_EUNSUPPORTED (b). */
+tsk_status tsk_als(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const double* S64,
+                   const float* S32, int k, int T, const double* F0, double* lam_out,
+                   double* F_out, void* stream);
+
 /* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
  * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the
  * T(u,u,u) estimate of Eq. (3), and its gradient.  Each count sketch is linear

@@ -61,6 +61,8 @@ _SIGS = {
     "tsk_sketch_deflate": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
+    "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
+    "tsk_als": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
     "tsk_contract_uuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_contract_tiuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P], _I),
     "tsk_decompose": ([_P, _P, _I, _P, _P, _I, _I, _I, _P, _U64, _P, _P, _P, _P, _I, _P], _I),
@@ -311,6 +313,40 @@ def median_normalize(ctx, V, U_in, U_out=None, flags=None, stream=None):
     _check("tsk_median_normalize", lib().tsk_median_normalize(
         ctx.handle, dt, L, n, B, _ptr(V), _ptr(U_in), _ptr(U_out), _ptr(flags), _stream(stream)))
     return U_out
+
+
+def contract_two(ctx, tab, X, Y, rd=0, S64=None, S32=None, V=None, stream=None):
+    """Per-sketch estimates V [L][B][n] of T contracted with X[r] in mode
+    (rd+1)%3 and Y[r] in mode (rd+2)%3, read off in mode rd (Proposition 1
+    with two different vectors)."""
+    import torch
+    dt, tdt = _vdtype(X.dtype)
+    L = X.shape[0]
+    _tensor(X, "X", tdt, (L, tab.n))
+    _tensor(Y, "Y", tdt, (L, tab.n))
+    _spectra(tab, dt, S64, S32)
+    if V is None:
+        V = torch.empty((L, tab.B, tab.n), dtype=tdt, device=X.device)
+    _tensor(V, "V", tdt, (L, tab.B, tab.n))
+    _check("tsk_contract_two", lib().tsk_contract_two(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), rd, L, _ptr(X), _ptr(Y), _ptr(V),
+        _stream(stream)))
+    return V
+
+
+def als(ctx, tab, F0, T, dtype=None, S64=None, S32=None, stream=None):
+    """Fast ALS (Algorithm 2 with the update equation's pseudo-inverse) from
+    the float64 initial factors F0 [3][k][n] (rows); returns (lam [k], F [3][k][n])."""
+    import torch
+    dtype = F32 if dtype is None else dtype
+    k = F0.shape[1]
+    _tensor(F0, "F0", torch.float64, (3, k, tab.n))
+    _spectra(tab, dtype, S64, S32)
+    F = torch.empty_like(F0)
+    lam = torch.empty(k, dtype=torch.float64, device=F0.device)
+    _check("tsk_als", lib().tsk_als(ctx.handle, tab.handle, dtype, _ptr(S64), _ptr(S32), k, T, _ptr(F0),
+                                    _ptr(lam), _ptr(F), _stream(stream)))
+    return lam, F
 
 
 def contract_tiuu(ctx, tab, U, S64=None, S32=None, V=None, stream=None):

@@ -386,6 +386,8 @@ struct PowerArgs {
   const cx<R>* S;       // [B][H+1]
   const cx<R>* twg;     // [twid_len(H, NT)]
   const R* Uprev;       // [L][n]
+  const R* Uy;          // [L][n] or null: the second count sketch's vector (two-vector
+                        // contraction; not with PRE or mode 1)
   const R* Vprev;       // [L][B][n]   (PRE)
   R* Ucur;              // [L][n]      (PRE, written by m == 0)
   int32_t* flags;       // [L]         (PRE, nullable)
@@ -494,6 +496,13 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
 #pragma unroll 1
   for (int mode_j = 1; mode_j <= 2; ++mode_j) {
+    if (!PRE && a.Uy && mode_j == 2) {
+      // two-vector contraction: the second count sketch takes y (u is not
+      // read again: mode 0 has no lambda read-off)
+      int oe = threadIdx.x, ot2 = tau;
+      asm volatile("" : "+v"(oe), "+s"(ot2));
+      for (int e = oe; e < n; e += NT) u[e] = a.Uy[(size_t)ot2 * n + e];
+    }
     zero_lds<NT>(re, 2 * PL * (int)sizeof(R));
     __syncthreads();
     if (tab_lds)
@@ -631,6 +640,169 @@ __global__ __launch_bounds__(median_threads<R>()) void k_median_norm(const R* V,
     ok = median_prologue<R, NT>(V, Uin, tau, n, B, u, stage, 4096, red, false);
   }
   if (threadIdx.x == 0 && !ok && flags) flags[tau] |= 1;
+}
+
+// ---------------------------------------------------------------------------
+// Fast ALS (Appendix C, Algorithm 2): the update of one factor from the
+// median estimates Vbar[r] of T(I, x_r, y_r) and the other two factors X, Y
+// (rows r = 0..k-1):  A = G^+ Vbar,  G = (X X^T) o (Y Y^T),  lambda_r = ||A_r||,
+// A_r /= lambda_r.
+
+// Vbar[r][i] = med_m V[r][m][i] (no normalisation), FP64 out; grid = k rows,
+// median_threads<R>() threads.  B <= 64 by sorting networks, else by ranks.
+template <typename R>
+__global__ __launch_bounds__(median_threads<R>()) void k_median_rows(const R* V, double* Vbar, int n, int B) {
+  constexpr int NT = median_threads<R>();
+  const int r = blockIdx.x;
+  const R* Vr = V + (size_t)r * B * n;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    auto get = [&](int j) { return Vr[(size_t)j * n + i]; };
+    R med;
+    if (B <= 16) {
+      med = network_median<16, R>(get, B);
+    } else if (B <= 32) {
+      med = network_median<32, R>(get, B);
+    } else if (B <= 64) {
+      med = network_median<64, R>(get, B);
+    } else {
+      const int ra = (B - 1) / 2, rb = B / 2;
+      R xa = R(0), xc = R(0);
+      bool nan = false;
+      for (int mm = 0; mm < B; ++mm) {
+        const R x = get(mm);
+        nan |= __builtin_isnan(x);
+        int rank = 0;
+        for (int j = 0; j < B; ++j) {
+          const R o = get(j);
+          rank += (o < x) || (o == x && j < mm);
+        }
+        if (rank == ra) xa = x;
+        if (rank == rb) xc = x;
+      }
+      med = nan ? R(__builtin_nan("")) : ((B & 1) ? xa : (xa + xc) * R(0.5));
+    }
+    Vbar[(size_t)r * n + i] = (double)med;
+  }
+}
+
+// G[r][s] = (x_r . x_s)(y_r . y_s), FP64; grid = (k, k), 256 threads; fixed
+// reduction order, so G is exactly symmetric.
+__global__ __launch_bounds__(256) void k_als_gram(const double* X, const double* Y, double* G, int n, int k) {
+  __shared__ double red[4];
+  const int r = blockIdx.x, c = blockIdx.y;
+  const int lo = min(r, c), hi = max(r, c);
+  double sx = 0.0, sy = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    sx += X[(size_t)lo * n + i] * X[(size_t)hi * n + i];
+    sy += Y[(size_t)lo * n + i] * Y[(size_t)hi * n + i];
+  }
+  const double gx = block_sum<256>(sx, red);
+  const double gy = block_sum<256>(sy, red);
+  if (threadIdx.x == 0) G[(size_t)r * k + c] = gx * gy;
+}
+
+// P = G^+ for a symmetric k x k G (k <= 64), one work-group of 256 threads:
+// cyclic Jacobi rotations to G = E diag(d) E^T, then P = E diag(1/d) E^T over
+// the eigenvalues d > 1e-12 max|d| (the others dropped).  Sweeps stop when
+// the off-diagonal mass is below 1e-30 of the total, at most 60.
+__global__ __launch_bounds__(256) void k_als_pinv(const double* G, double* P, int k) {
+  __shared__ double A[64 * 64];
+  __shared__ double E[64 * 64];
+  __shared__ double rot[2];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * k; e += 256) {
+    A[e] = G[e];
+    E[e] = (e / k == e % k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < k * k; e += 256) {
+      const double v = A[e] * A[e];
+      tot += v;
+      if (e / k != e % k) off += v;
+    }
+    off = block_sum<256>(off, red);
+    tot = block_sum<256>(tot, red);
+    if (!(off > 1e-30 * tot)) break;  // uniform: every thread has the same sums
+    for (int p = 0; p < k - 1; ++p) {
+      for (int q = p + 1; q < k; ++q) {
+        if (tid == 0) {
+          const double apq = A[p * k + q];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            const double theta = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+          rot[0] = c;
+          rot[1] = s;
+        }
+        __syncthreads();
+        const double c = rot[0], s = rot[1];
+        if (s != 0.0) {
+          // A <- J^T A J: columns p, q, then rows p, q; E <- E J
+          if (tid < k) {
+            const double ap = A[tid * k + p], aq = A[tid * k + q];
+            A[tid * k + p] = c * ap - s * aq;
+            A[tid * k + q] = s * ap + c * aq;
+            const double ep = E[tid * k + p], eq = E[tid * k + q];
+            E[tid * k + p] = c * ep - s * eq;
+            E[tid * k + q] = s * ep + c * eq;
+          }
+          __syncthreads();
+          if (tid < k) {
+            const double ap = A[p * k + tid], aq = A[q * k + tid];
+            A[p * k + tid] = c * ap - s * aq;
+            A[q * k + tid] = s * ap + c * aq;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  double dmax = 0.0;
+  for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(A[j * k + j]));
+  for (int e = tid; e < k * k; e += 256) {
+    const int r = e / k, c = e % k;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double d = A[j * k + j];
+      if (fabs(d) > 1e-12 * dmax) acc += E[r * k + j] * E[c * k + j] / d;
+    }
+    P[e] = acc;
+  }
+}
+
+// A[r][i] = sum_s P[r][s] Vbar[s][i]; grid = (ceil(n / 256), k).
+__global__ __launch_bounds__(256) void k_als_apply(const double* P, const double* Vbar, double* A, int n, int k) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int s2 = 0; s2 < k; ++s2) acc += P[(size_t)r * k + s2] * Vbar[(size_t)s2 * n + i];
+  A[(size_t)r * n + i] = acc;
+}
+
+// lambda_r = ||A_r||, A_r /= lambda_r (rows of zero norm stay), and the
+// factor in the power kernel's precision; grid = k, 256 threads.
+template <typename R>
+__global__ __launch_bounds__(256) void k_als_normalize(double* A, R* Ar, double* lam, int n) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  double* row = A + (size_t)r * n;
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) ss += row[i] * row[i];
+  const double nrm = sqrt(block_sum<256>(ss, red));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = row[i] * inv;
+    row[i] = v;
+    Ar[(size_t)r * n + i] = (R)v;
+  }
+  if (threadIdx.x == 0) lam[r] = nrm;
 }
 
 // lam_med[tau] = med_m lam_per[tau][m]; one wave per restart.

@@ -101,7 +101,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -917,8 +917,11 @@ template <typename R>
 tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0,
                         int prefix, int mode, const R* Uprev, const R* Vprev, R* Ucur,
                         int32_t* flags, R* V, double* lam_per, hipStream_t st, int perm = 0,
-                        const SplitBufs* sb = nullptr) {
+                        const SplitBufs* sb = nullptr, const R* Uy = nullptr) {
   if (tab->logb > kLdsLogB + 1 || (sizeof(R) == 8 && tab->logb > kLdsLogB)) {
+    if (Uy)
+      return tsk::fail(TSK_EUNSUPPORTED, "two-vector contraction: b <= %d in this precision (b=%d)",
+                       1 << (sizeof(R) == 4 ? kLdsLogB + 1 : kLdsLogB), tab->b);
     if constexpr (sizeof(R) == 4)
       return power_split(ctx, tab, reinterpret_cast<const cx<float>*>(spec), nrest, tau0, prefix, mode, Uprev,
                          Vprev, Ucur, flags, V, lam_per, st, perm, sb);
@@ -935,6 +938,7 @@ tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int n
   a.S = reinterpret_cast<const cx<R>*>(spec);
   a.twg = tw;
   a.Uprev = Uprev;
+  a.Uy = Uy;
   a.Vprev = Vprev;
   a.Ucur = Ucur;
   a.flags = flags;
@@ -1040,6 +1044,96 @@ extern "C" tsk_status tsk_contract_tiuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dty
                                (float*)V, nullptr, S(stream), 0, &sb);
   return power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)U, nullptr, nullptr, nullptr,
                               (double*)V, nullptr, S(stream));
+}
+
+extern "C" tsk_status tsk_contract_two(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                       const double* S64, const float* S32, int rd, int L,
+                                       const void* X, const void* Y, void* V, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_contract_two"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_contract_two"));
+  if (!X || !Y || !V) return tsk::fail(TSK_EINVAL, "tsk_contract_two: null X, Y or V");
+  if (rd < 0 || rd > 2) return tsk::fail(TSK_EINVAL, "tsk_contract_two: rd=%d outside [0,2]", rd);
+  TSK_TRY(set_device(ctx));
+  if (dtype == TSK_F32)
+    return power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)X, nullptr, nullptr, nullptr,
+                               (float*)V, nullptr, S(stream), rd, nullptr, (const float*)Y);
+  return power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)X, nullptr, nullptr, nullptr,
+                              (double*)V, nullptr, S(stream), rd, nullptr, (const double*)Y);
+}
+
+namespace {
+
+// Algorithm 2 for k factors: T sweeps of the A, B, C updates.
+template <typename R>
+tsk_status als_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int k, int T, double* lam_out,
+                       double* F, char* ws, hipStream_t st) {
+  const int n = tab->n, B = tab->B;
+  const size_t kn = (size_t)k * n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = ws + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  R* Fr = (R*)take(3 * kn * sizeof(R));
+  R* V = (R*)take(kn * B * sizeof(R));
+  double* Vbar = (double*)take(kn * 8);
+  double* G = (double*)take((size_t)k * k * 8);
+  double* P = (double*)take((size_t)k * k * 8);
+  hipLaunchKernelGGL(tsk::k_cvt<R>, dim3(grid_for(3 * kn, 256)), dim3(256), 0, st, (const double*)F, Fr,
+                     3 * kn);
+  TSK_TRY(check_launch("k_cvt"));
+  for (int t = 0; t < T; ++t) {
+    for (int rd = 0; rd < 3; ++rd) {
+      const int ix = (rd + 1) % 3, iy = (rd + 2) % 3;
+      TSK_TRY(power_launch<R>(ctx, tab, spec, k, 0, 0, 0, Fr + ix * kn, nullptr, nullptr, nullptr, V,
+                              nullptr, st, rd, nullptr, Fr + iy * kn));
+      hipLaunchKernelGGL(tsk::k_median_rows<R>, dim3(k), dim3(tsk::median_threads<R>()), 0, st,
+                         (const R*)V, Vbar, n, B);
+      TSK_TRY(check_launch("k_median_rows"));
+      hipLaunchKernelGGL(tsk::k_als_gram, dim3(k, k), dim3(256), 0, st, (const double*)(F + ix * kn),
+                         (const double*)(F + iy * kn), G, n, k);
+      TSK_TRY(check_launch("k_als_gram"));
+      hipLaunchKernelGGL(tsk::k_als_pinv, dim3(1), dim3(256), 0, st, (const double*)G, P, k);
+      TSK_TRY(check_launch("k_als_pinv"));
+      hipLaunchKernelGGL(tsk::k_als_apply, dim3((n + 255) / 256, k), dim3(256), 0, st, (const double*)P,
+                         (const double*)Vbar, F + rd * kn, n, k);
+      TSK_TRY(check_launch("k_als_apply"));
+      hipLaunchKernelGGL(tsk::k_als_normalize<R>, dim3(k), dim3(256), 0, st, F + rd * kn, Fr + rd * kn,
+                         lam_out, n);
+      TSK_TRY(check_launch("k_als_normalize"));
+    }
+  }
+  return TSK_OK;
+}
+
+size_t als_ws_bytes(tsk_tables_t tab, tsk_dtype dtype, int k) {
+  const size_t kn = (size_t)k * tab->n, es = dtype == TSK_F32 ? 4 : 8;
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return r(3 * kn * es) + r(kn * tab->B * es) + r(kn * 8) + 2 * r((size_t)k * k * 8);
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_als(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const double* S64,
+                              const float* S32, int k, int T, const double* F0, double* lam_out,
+                              double* F_out, void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_als"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, k, "tsk_als"));
+  if (!F0 || !lam_out || !F_out) return tsk::fail(TSK_EINVAL, "tsk_als: null F0, lam_out or F_out");
+  if (k < 1 || k > 64) return tsk::fail(TSK_EINVAL, "tsk_als: k=%d outside [1,64]", k);
+  if (T < 1) return tsk::fail(TSK_EINVAL, "tsk_als: T=%d < 1", T);
+  if (tab->logb > (dtype == TSK_F32 ? kLdsLogB + 1 : kLdsLogB))
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_als: b=%d above the one-work-group transforms", tab->b);
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  void* ws = nullptr;
+  TSK_TRY(ws_get(ctx, WS_ALS, als_ws_bytes(tab, dtype, k), &ws));
+  if (F_out != F0)
+    TSK_HIP(hipMemcpyAsync(F_out, F0, (size_t)3 * k * tab->n * 8, hipMemcpyDeviceToDevice, st));
+  if (dtype == TSK_F32)
+    return als_enqueue<float>(ctx, tab, S32, k, T, lam_out, F_out, (char*)ws, st);
+  return als_enqueue<double>(ctx, tab, S64, k, T, lam_out, F_out, (char*)ws, st);
 }
 
 extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
