@@ -317,6 +317,18 @@ TABLE5 = {
 }
 
 
+# Table 7 of the paper (sketched ALS, same tensors, top 10, T = 30 sweeps):
+# squared residual and wrong vectors for log2(b) = 12..16, keyed by (sigma, B).
+TABLE7 = {
+    (0.01, 20): ([.71, .41, .25, .17, .12], [10, 9, 7, 6, 4]),
+    (0.01, 30): ([.50, .34, .21, .14, .11], [9, 8, 7, 5, 3]),
+    (0.01, 40): ([.46, .28, .17, .10, .07], [9, 8, 6, 5, 1]),
+    (0.1, 20): ([.88, .50, .35, .28, .23], [10, 8, 7, 6, 6]),
+    (0.1, 30): ([.78, .44, .30, .24, .21], [9, 8, 7, 5, 6]),
+    (0.1, 40): ([.56, .38, .28, .19, .16], [9, 8, 6, 4, 2]),
+}
+
+
 def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 14, 15, 16)):
     """The paper's accuracy table on its own synthetic tensors: n = 1000,
     full rank with lam_i = 1/i (normalised), symmetric noise with
@@ -351,6 +363,7 @@ def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 1
                 tsk.sketch_build_dense(ctx, tab, Tt, S64, S32)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
+                S32_als = S32.clone()        # the decomposition deflates S64/S32 in place
                 lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F32, seed=7)
                 torch.cuda.synchronize()
                 t2 = time.perf_counter()
@@ -374,13 +387,49 @@ def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 1
                       f"(paper {rows[-1]['paper_residual']}), wrong {wrong} "
                       f"(paper {rows[-1]['paper_wrong']}), decompose {rows[-1]['decompose_ms']:.1f} ms",
                       file=sys.stderr, flush=True)
+                rows[-1].update(x1_als_row(ctx, dev, tab, S32_als, Tt, X, nrm2, k, sigma, B, logbs.index(logb)))
                 tab.close()
-                del S64, S32
+                del S64, S32, S32_als
         del X, Tt
         torch.cuda.empty_cache()
     return {"workload": ("paper's synthetic tensors: n=1000 full rank, lam_i=1/i normalised, symmetric "
                          "noise E||E||^2=sigma; top 10, L=T=30, FP32 power steps"),
             "tensor_generation_s": t_gen, "rows": rows}
+
+
+def x1_als_row(ctx, dev, tab, S32, Tt, X, nrm2, k, sigma, B, j, T=30):
+    """Fast ALS (Algorithm 2) on the same sketches: k = 10 random Gaussian
+    start factors, T = 30 sweeps, FP32 power steps; residual of the CP model
+    and wrong vectors of A against the true top 10 (up to sign: ALS may put
+    the sign of a component on any two factors)."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    n = Tt.shape[0]
+    rng = np.random.default_rng(11)
+    F0 = torch.from_numpy(rng.standard_normal((3, k, n))).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, F = tsk.als(ctx, tab, F0, T, dtype=tsk.F32, S32=S32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    A, Bf, C = F[0], F[1], F[2]
+    tabc = torch.zeros(k, dtype=torch.float64, device=dev)
+    for i0 in range(0, n, 100):
+        Y = (Tt[i0:i0 + 100].double().reshape(-1, n) @ C.T).view(-1, n, k)   # [i][j][r]
+        tabc += torch.einsum("ijr,rj,ri->r", Y, Bf, A[:, i0:i0 + 100])
+    G = (A @ A.T) * (Bf @ Bf.T) * (C @ C.T)
+    res = nrm2 - 2.0 * float(lam @ tabc) + float(lam @ G @ lam)
+    Ah = A.cpu().numpy()
+    V = X.V[:k]
+    d2 = np.minimum(((V[:, None, :] - Ah[None]) ** 2).sum(-1), ((V[:, None, :] + Ah[None]) ** 2).sum(-1))
+    wrong = int(np.sum(d2.min(axis=1) > 0.1))
+    ref = TABLE7.get((sigma, B))
+    print(f"x1 als sigma={sigma} B={B}: residual {res:.3f} (paper {ref[0][j] if ref else None}), "
+          f"wrong {wrong} (paper {ref[1][j] if ref else None}), {1e3 * (t1 - t0):.1f} ms",
+          file=sys.stderr, flush=True)
+    return {"als_residual": res, "als_wrong": wrong, "als_ms": 1e3 * (t1 - t0),
+            "paper_als_residual": ref[0][j] if ref else None,
+            "paper_als_wrong": ref[1][j] if ref else None}
 
 
 def c5_autograd(ctx, dev, steps: int = 20):

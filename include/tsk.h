@@ -207,9 +207,8 @@ tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
  *   V[r][m][i] = xi_rd(i) sbar[h_rd(i)],
  * the estimate of T contracted with X[r] in mode a and Y[r] in mode c, read
  * off in mode rd (rd = 0: T(I, x, y)).  X, Y: [L][n], V: [L][B][n], device,
- * float for TSK_F32 (reads S32) and double for TSK_F64 (reads S64).  b up to
- * 32768 (FP32) or 16384 (FP64).  Errors: TSK_EINVAL (null, rd, L),
- * TSK_EUNSUPPORTED (b). */
+ * float for TSK_F32 (reads S32, any b) and double for TSK_F64 (reads S64,
+ * b <= 16384).  Errors: TSK_EINVAL (null, rd, L), TSK_EUNSUPPORTED (b). */
 tsk_status tsk_contract_two(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
                             const double* S64, const float* S32, int rd, int L,
                             const void* X, const void* Y, void* V, void* stream);

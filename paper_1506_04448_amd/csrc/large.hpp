@@ -29,6 +29,7 @@ struct SubCsArgs {
   int n, B, Rr, nmodes;
   int mode[3];
   const UIn* U;        // [nvec][n]
+  const UIn* U2;       // [nvec][n] or null: the vector of the second mode (two-vector contraction)
   const cx<R>* twM;    // pass table of the M-point transform
   cx<R>* E;
 };
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGM)) void k_sub_cs(SubCsArgs<R, 
   const int jj = blockIdx.z / a.Rr, r = blockIdx.z % a.Rr;
   const int n = a.n;
   const size_t tb = ((size_t)m * 3 + a.mode[jj]) * n;
-  const UIn* u = a.U + (size_t)vec * n;
+  const UIn* u = (jj == 1 && a.U2 ? a.U2 : a.U) + (size_t)vec * n;
   const unsigned Rr = (unsigned)a.Rr;
   for (int t = threadIdx.x; t < 2 * PL; t += NT) re[t] = R(0);
   __syncthreads();

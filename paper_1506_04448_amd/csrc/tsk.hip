@@ -445,6 +445,7 @@ tsk_status rank1_split(tsk_ctx_t ctx, tsk_tables_t tab, const tsk::Rank1Args& a,
   sa.mode[1] = 1;
   sa.mode[2] = 2;
   sa.U = a.U;
+  sa.U2 = nullptr;
   sa.twM = twM;
   sa.E = reinterpret_cast<cx<double>*>(Ebuf);
   hipLaunchKernelGGL((tsk::k_sub_cs<double, kSubLogM64, double>), dim3(tab->B, c, 3 * Rr),
@@ -852,7 +853,7 @@ namespace {
 tsk_status power_split(tsk_ctx_t ctx, tsk_tables_t tab, const cx<float>* spec, int nrest, int tau0,
                        int prefix, int mode, const float* Uprev, const float* Vprev, float* Ucur,
                        int32_t* flags, float* V, double* lam_per, hipStream_t st, int perm,
-                       const SplitBufs* sb) {
+                       const SplitBufs* sb, const float* Uy = nullptr) {
   if (!sb || !sb->E || !sb->A) return tsk::fail(TSK_EHIP, "internal: split power buffers missing");
   const int n = tab->n, B = tab->B, b = tab->b, M = 1 << kSubLogM32;
   const cx<float>* twM = nullptr;
@@ -877,6 +878,7 @@ tsk_status power_split(tsk_ctx_t ctx, tsk_tables_t tab, const cx<float>* spec, i
   a1.mode[1] = (perm + 2) % 3;
   a1.mode[2] = 0;
   a1.U = U;
+  a1.U2 = Uy ? Uy + on : nullptr;
   a1.twM = twM;
   a1.E = reinterpret_cast<cx<float>*>(sb->E);
   hipLaunchKernelGGL((tsk::k_sub_cs<float, kSubLogM32, float>), dim3(B, nrest, 4),
@@ -919,12 +921,9 @@ tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int n
                         int32_t* flags, R* V, double* lam_per, hipStream_t st, int perm = 0,
                         const SplitBufs* sb = nullptr, const R* Uy = nullptr) {
   if (tab->logb > kLdsLogB + 1 || (sizeof(R) == 8 && tab->logb > kLdsLogB)) {
-    if (Uy)
-      return tsk::fail(TSK_EUNSUPPORTED, "two-vector contraction: b <= %d in this precision (b=%d)",
-                       1 << (sizeof(R) == 4 ? kLdsLogB + 1 : kLdsLogB), tab->b);
     if constexpr (sizeof(R) == 4)
       return power_split(ctx, tab, reinterpret_cast<const cx<float>*>(spec), nrest, tau0, prefix, mode, Uprev,
-                         Vprev, Ucur, flags, V, lam_per, st, perm, sb);
+                         Vprev, Ucur, flags, V, lam_per, st, perm, sb, Uy);
     return tsk::fail(TSK_EUNSUPPORTED, "power step: FP64 supports b <= 16384 (b=%d)", tab->b);
   }
   const cx<R>* tw = nullptr;
@@ -1054,9 +1053,11 @@ extern "C" tsk_status tsk_contract_two(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
   if (!X || !Y || !V) return tsk::fail(TSK_EINVAL, "tsk_contract_two: null X, Y or V");
   if (rd < 0 || rd > 2) return tsk::fail(TSK_EINVAL, "tsk_contract_two: rd=%d outside [0,2]", rd);
   TSK_TRY(set_device(ctx));
+  SplitBufs sb;
+  TSK_TRY(eager_split_bufs(ctx, tab, dtype, L, &sb));
   if (dtype == TSK_F32)
     return power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)X, nullptr, nullptr, nullptr,
-                               (float*)V, nullptr, S(stream), rd, nullptr, (const float*)Y);
+                               (float*)V, nullptr, S(stream), rd, &sb, (const float*)Y);
   return power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)X, nullptr, nullptr, nullptr,
                               (double*)V, nullptr, S(stream), rd, nullptr, (const double*)Y);
 }
@@ -1066,7 +1067,7 @@ namespace {
 // Algorithm 2 for k factors: T sweeps of the A, B, C updates.
 template <typename R>
 tsk_status als_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int k, int T, double* lam_out,
-                       double* F, char* ws, hipStream_t st) {
+                       double* F, char* ws, const SplitBufs* sb, hipStream_t st) {
   const int n = tab->n, B = tab->B;
   const size_t kn = (size_t)k * n;
   size_t off = 0;
@@ -1087,7 +1088,7 @@ tsk_status als_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int k,
     for (int rd = 0; rd < 3; ++rd) {
       const int ix = (rd + 1) % 3, iy = (rd + 2) % 3;
       TSK_TRY(power_launch<R>(ctx, tab, spec, k, 0, 0, 0, Fr + ix * kn, nullptr, nullptr, nullptr, V,
-                              nullptr, st, rd, nullptr, Fr + iy * kn));
+                              nullptr, st, rd, sb, Fr + iy * kn));
       hipLaunchKernelGGL(tsk::k_median_rows<R>, dim3(k), dim3(tsk::median_threads<R>()), 0, st,
                          (const R*)V, Vbar, n, B);
       TSK_TRY(check_launch("k_median_rows"));
@@ -1123,17 +1124,19 @@ extern "C" tsk_status tsk_als(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, 
   if (!F0 || !lam_out || !F_out) return tsk::fail(TSK_EINVAL, "tsk_als: null F0, lam_out or F_out");
   if (k < 1 || k > 64) return tsk::fail(TSK_EINVAL, "tsk_als: k=%d outside [1,64]", k);
   if (T < 1) return tsk::fail(TSK_EINVAL, "tsk_als: T=%d < 1", T);
-  if (tab->logb > (dtype == TSK_F32 ? kLdsLogB + 1 : kLdsLogB))
-    return tsk::fail(TSK_EUNSUPPORTED, "tsk_als: b=%d above the one-work-group transforms", tab->b);
+  if (dtype == TSK_F64 && tab->logb > kLdsLogB)
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_als: FP64 power steps support b <= 16384 (b=%d)", tab->b);
   TSK_TRY(set_device(ctx));
   hipStream_t st = S(stream);
   void* ws = nullptr;
   TSK_TRY(ws_get(ctx, WS_ALS, als_ws_bytes(tab, dtype, k), &ws));
+  SplitBufs sb;
+  TSK_TRY(eager_split_bufs(ctx, tab, dtype, k, &sb));
   if (F_out != F0)
     TSK_HIP(hipMemcpyAsync(F_out, F0, (size_t)3 * k * tab->n * 8, hipMemcpyDeviceToDevice, st));
   if (dtype == TSK_F32)
-    return als_enqueue<float>(ctx, tab, S32, k, T, lam_out, F_out, (char*)ws, st);
-  return als_enqueue<double>(ctx, tab, S64, k, T, lam_out, F_out, (char*)ws, st);
+    return als_enqueue<float>(ctx, tab, S32, k, T, lam_out, F_out, (char*)ws, &sb, st);
+  return als_enqueue<double>(ctx, tab, S64, k, T, lam_out, F_out, (char*)ws, &sb, st);
 }
 
 extern "C" tsk_status tsk_contract_uuu(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,

@@ -51,6 +51,7 @@ def _setup(ctx, n, k, b, B, seed, dt=np.float64):
     (200, 16384, 4, 6, torch.float32, 1e-5),
     (90, 32768, 2, 3, torch.float32, 1e-5),
     (150, 8192, 3, 4, torch.float64, 1e-12),
+    (120, 65536, 2, 3, torch.float32, 1e-5),
 ])
 def test_contract_two_matches_oracle(ctx, n, b, B, L, dtype, tol):
     print(f"contract_two n={n} b={b} B={B} {dtype}", flush=True)
@@ -120,16 +121,28 @@ def test_als_recovers_planted_factors(ctx):
     np.testing.assert_allclose(np.sort(lam), np.sort(P.lam), rtol=0.05)
 
 
+def test_als_fp32_split_transforms_match_oracle(ctx):
+    """b = 65536: the power steps run through the split transforms."""
+    n, k, b, B = 50, 3, 65536, 2
+    P, tab, h, xi, S64, S32, S_time = _setup(ctx, n, k, b, B, 8, dt=np.float32)
+    rng = np.random.default_rng(8)
+    F0 = rng.standard_normal((3, k, n))
+    lam, F = tsk.als(ctx, tab, torch.from_numpy(F0).to(DEV), 2, dtype=tsk.F32, S32=S32)
+    ref = oals.als_sketched(S_time, h, xi, k, 2, F0)
+    assert rel(lam.cpu().numpy(), ref.lam) < 1e-4
+    assert rel(F.cpu().numpy(), ref.F) < 1e-4
+
+
 def test_als_argument_errors(ctx):
     h, xi = tsk.hash_generate(1, 10, 65536, 2)
     tab = tsk.Tables(ctx, h, xi, 65536)
     S64, S32 = tsk.new_sketch(tab, DEV)
     F0 = torch.zeros((3, 2, 10), dtype=torch.float64, device=DEV)
     with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
-        tsk.als(ctx, tab, F0, 1, dtype=tsk.F32, S32=S32)
-    X = torch.zeros((2, 10), dtype=torch.float32, device=DEV)
+        tsk.als(ctx, tab, F0, 1, dtype=tsk.F64, S64=S64)
+    X = torch.zeros((2, 10), dtype=torch.float64, device=DEV)
     with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
-        tsk.contract_two(ctx, tab, X, X, S32=S32)
+        tsk.contract_two(ctx, tab, X, X, S64=S64)
     tab.close()
     h, xi = tsk.hash_generate(1, 10, 256, 2)
     tab = tsk.Tables(ctx, h, xi, 256)
