@@ -23,7 +23,11 @@ closed forms of the population moments and by the explicit V^3 route.
 Fast ALS (``als``, Appendix C) is pinned by the injective-hash reduction of
 the two-vector estimate to the exact contraction, by its unbiasedness over
 all sign (and, tiny case, hash) draws, and by exact ALS recovering an exactly
-low-rank tensor.
+low-rank tensor.  The colliding-hash symmetric sketch (``symmetric``, Section
+3.3 and Appendix B) is pinned by the equality of its full and upper-triangle
+builds, exact unbiasedness of entry recovery and of both contractions over
+every sign draw (which also fixes the read-off weights), and the direct
+convolution route.
 Parity unpinned: the full sketched power method beyond those pins (the paper
 prints no worked example to compare against).
 """
@@ -34,7 +38,7 @@ from .sketch import (count_sketch, sketch_dense, circular_convolution,
 from .contract import (median, power_update_sketch, power_update_direct,
                        tuuu_sketch, tuuu_direct, power_update, contract_uuu)
 from .rtpm import rtpm_sketched, rtpm_dense, RtpmResult
-from . import gradients, lda, als
+from . import gradients, lda, als, symmetric
 from .dense import (dense_Tuuu, dense_TIuu, residual_dense, residual_factored,
                     wrong_vectors)
 
@@ -45,5 +49,5 @@ __all__ = [
     "median", "power_update_sketch", "power_update_direct", "tuuu_sketch",
     "tuuu_direct", "power_update", "contract_uuu",
     "rtpm_sketched", "rtpm_dense", "RtpmResult",
-    "gradients", "lda", "als", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
+    "gradients", "lda", "als", "symmetric", "dense_Tuuu", "dense_TIuu", "residual_dense", "residual_factored", "wrong_vectors",
 ]
