@@ -50,6 +50,7 @@ typedef enum { TSK_F32 = 0, TSK_F64 = 1 } tsk_dtype;
 
 typedef struct tsk_ctx* tsk_ctx_t;       /* per-device context + workspace  */
 typedef struct tsk_tables* tsk_tables_t; /* device copy of hash/sign tables */
+typedef struct tsk_sym_tables* tsk_sym_tables_t; /* colliding-hash tables (Section 3.3) */
 
 /* Library version string (static storage). */
 const char* tsk_version(void);
@@ -228,6 +229,55 @@ tsk_status tsk_contract_two(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
 tsk_status tsk_als(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const double* S64,
                    const float* S32, int k, int T, const double* F0, double* lam_out,
                    double* F_out, void* stream);
+
+/* ---- Colliding-hash symmetric sketches (Section 3.3, Eq. (5); Appendix B) --
+ * One hash h: [n] -> [b] and one sign sigma(i) = i^q(i), q in {0,1,2,3}, per
+ * sketch (h_host [B][n] in [0,b), q_host [B][n], host).  The sketch of a
+ * symmetric tensor
+ *   s(t) = sum over (h(i)+h(j)+h(k)) mod b == t of sigma(i) sigma(j) sigma(k) T_ijk
+ * is complex; it is kept in the time domain (s64 FP64, s32 FP32 copy,
+ * [B][b][2]) and as its full spectrum (S64, S32, [B][b][2]), all device,
+ * caller-owned.  b a power of two in [256, 16384].  Errors: TSK_EINVAL,
+ * TSK_EUNSUPPORTED (b). */
+tsk_status tsk_sym_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint32_t* h_host,
+                                 const uint8_t* q_host, tsk_sym_tables_t* out);
+void tsk_sym_tables_destroy(tsk_sym_tables_t tab);
+
+/* Dense build of Eq. (5) from the entries with i <= j <= k (each weighted by
+ * the number of distinct permutations of its index triple; for a symmetric
+ * tensor this is the sum over all entries), FP64 atomics (summation order
+ * varies between runs), then S64 = F(s64), S32 = (float)S64, s32 =
+ * (float)s64 (s32, S32 nullable).  T: [n][n][n] row-major, float or double
+ * by dtype.  accumulate != 0 adds to s64. */
+tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t tab, const void* T,
+                                      tsk_dtype dtype, double* s64, float* s32, double* S64,
+                                      float* S32, int accumulate, void* stream);
+
+/* Per-sketch estimates V[tau][m][i] = Re v_i of T(I,u,u) for L vectors
+ * (Appendix B read-off with weight 1/3 on all four terms; FP32):
+ *   v_i = (1/3) [ conj(s_i) (c1 + c2)[h_i] / 2 + conj(s_i^2) u_i c3[2h_i]
+ *                 + conj(s_i^3) u_i^2 s[3h_i] ],  s_i = sigma(i),
+ *   c1 + c2 = F^-1(S o (conj(U1)^2 + conj(U2))), c3 = F^-1(S o conj(U1)),
+ *   U1 = F(sum_{h(i)=t} s_i u_i), U2 = F(sum_{2h(i)=t} s_i^2 u_i^2).
+ * S32, s32: [B][b][2]; U: float [L][n]; V: float [L][B][n]; device.
+ * n at most about 2800 at b = 16384 (LDS).  Errors: TSK_EINVAL,
+ * TSK_EUNSUPPORTED. */
+tsk_status tsk_sym_contract_tiuu(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32,
+                                 const float* s32, int L, const float* U, float* V, void* stream);
+
+/* Algorithm 1 on symmetric sketches: per component, T power steps (FP32
+ * read-offs, median over sketches of Re v, normalisation; zero or
+ * non-finite medians keep the vector and set flags[c][tau]), selection by the
+ * median of u . Re v (lowest restart on ties), lambda_hat = med_m Re <s, s_X>
+ * in FP64 at the FP64-renormalised winner (s_X the sketch of the upper
+ * triangle of u^(x)3, Appendix B), and deflation of s64/s32/S64/S32 by
+ * lambda_hat (s_u * s_u * s_u).  u0: nullable double [k][L][n] (null: the
+ * start vectors of tsk_init_vectors(seed)); lam_out double[k]; U_out double
+ * [k][n]; tau_out, flags_out nullable int32 [k], [k][L]; device. */
+tsk_status tsk_sym_decompose(tsk_ctx_t ctx, tsk_sym_tables_t tab, double* s64, float* s32,
+                             double* S64, float* S32, int k, int L, int T, const double* u0,
+                             uint64_t seed, double* lam_out, double* U_out, int32_t* tau_out,
+                             int32_t* flags_out, void* stream);
 
 /* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
  * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the

@@ -62,6 +62,11 @@ _SIGS = {
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
+    "tsk_sym_tables_create": ([_P, _I, _I, _I, _P, _P, _P], _I),
+    "tsk_sym_tables_destroy": ([_P], None),
+    "tsk_sym_sketch_build_dense": ([_P, _P, _P, _I, _P, _P, _P, _P, _I, _P], _I),
+    "tsk_sym_contract_tiuu": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
+    "tsk_sym_decompose": ([_P, _P, _P, _P, _P, _P, _I, _I, _I, _P, ctypes.c_uint64, _P, _P, _P, _P, _P], _I),
     "tsk_als": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
     "tsk_contract_uuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_contract_tiuu": ([_P, _P, _I, _P, _P, _I, _P, _P, _P], _I),
@@ -194,6 +199,96 @@ class Tables:
             self.close()
         except Exception:
             pass
+
+
+class SymTables:
+    """Device copy of colliding-hash tables (h[B][n] in [0,b), q[B][n] in
+    {0,1,2,3}: sigma = i^q), Section 3.3."""
+
+    def __init__(self, ctx: Context, h: np.ndarray, q: np.ndarray, b: int):
+        h = np.ascontiguousarray(h, dtype=np.uint32)
+        q = np.ascontiguousarray(q, dtype=np.uint8)
+        if h.ndim != 2 or q.shape != h.shape:
+            raise ValueError("symmetric tables must be [B][n]")
+        self.B, self.n = h.shape
+        self.b = b
+        self.ctx = ctx
+        t = _P()
+        _check("tsk_sym_tables_create", lib().tsk_sym_tables_create(
+            ctx.handle, self.n, b, self.B, h.ctypes.data, q.ctypes.data, ctypes.byref(t)))
+        self.handle = t
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tsk_sym_tables_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def new_sym_sketch(tab: SymTables, device="cuda"):
+    """Allocate (s64, s32, S64, S32), each [B][b][2] (complex time domain and
+    spectrum, FP64 and FP32)."""
+    import torch
+    shp = (tab.B, tab.b, 2)
+    return (torch.zeros(shp, dtype=torch.float64, device=device), torch.zeros(shp, dtype=torch.float32, device=device),
+            torch.zeros(shp, dtype=torch.float64, device=device), torch.zeros(shp, dtype=torch.float32, device=device))
+
+
+def _symsk(tab, s64, s32, S64, S32):
+    import torch
+    shp = (tab.B, tab.b, 2)
+    _tensor(s64, "s64", torch.float64, shp)
+    _tensor(s32, "s32", torch.float32, shp)
+    _tensor(S64, "S64", torch.float64, shp)
+    _tensor(S32, "S32", torch.float32, shp)
+
+
+def sym_sketch_build_dense(ctx, tab, T, s64, s32, S64, S32, accumulate=False, stream=None):
+    """Eq. (5) sketches of the dense symmetric tensor T [n][n][n] (float32/64)."""
+    import torch
+    dt = F32 if T.dtype == torch.float32 else F64
+    _tensor(T, "T", torch.float32 if dt == F32 else torch.float64, (tab.n, tab.n, tab.n))
+    _symsk(tab, s64, s32, S64, S32)
+    _check("tsk_sym_sketch_build_dense", lib().tsk_sym_sketch_build_dense(
+        ctx.handle, tab.handle, _ptr(T), dt, _ptr(s64), _ptr(s32), _ptr(S64), _ptr(S32), int(bool(accumulate)),
+        _stream(stream)))
+
+
+def sym_contract_tiuu(ctx, tab, U, S32, s32, V=None, stream=None):
+    """Per-sketch Re T(I,u,u) estimates V [L][B][n] (float32) on symmetric sketches."""
+    import torch
+    L = U.shape[0]
+    _tensor(U, "U", torch.float32, (L, tab.n))
+    _tensor(S32, "S32", torch.float32, (tab.B, tab.b, 2))
+    _tensor(s32, "s32", torch.float32, (tab.B, tab.b, 2))
+    if V is None:
+        V = torch.empty((L, tab.B, tab.n), dtype=torch.float32, device=U.device)
+    _tensor(V, "V", torch.float32, (L, tab.B, tab.n))
+    _check("tsk_sym_contract_tiuu", lib().tsk_sym_contract_tiuu(
+        ctx.handle, tab.handle, _ptr(S32), _ptr(s32), L, _ptr(U), _ptr(V), _stream(stream)))
+    return V
+
+
+def sym_decompose(ctx, tab, s64, s32, S64, S32, k, L, T, u0=None, seed=0, stream=None):
+    """Algorithm 1 on symmetric sketches (deflated in place).
+    Returns (lam [k] f64, U [k][n] f64, tau [k] i32, flags [k][L] i32)."""
+    import torch
+    _symsk(tab, s64, s32, S64, S32)
+    _tensor(u0, "u0", torch.float64, (k, L, tab.n), allow_none=True)
+    dev = S64.device
+    lam = torch.empty((k,), dtype=torch.float64, device=dev)
+    U = torch.empty((k, tab.n), dtype=torch.float64, device=dev)
+    tau = torch.empty((k,), dtype=torch.int32, device=dev)
+    flags = torch.empty((k, L), dtype=torch.int32, device=dev)
+    _check("tsk_sym_decompose", lib().tsk_sym_decompose(
+        ctx.handle, tab.handle, _ptr(s64), _ptr(s32), _ptr(S64), _ptr(S32), k, L, T, _ptr(u0),
+        seed & (2 ** 64 - 1), _ptr(lam), _ptr(U), _ptr(tau), _ptr(flags), _stream(stream)))
+    return lam, U, tau, flags
 
 
 def new_sketch(tab: Tables, device="cuda"):

@@ -1,0 +1,322 @@
+// Colliding-hash symmetric tensor sketches (Section 3.3, Eq. (5)) and the
+// tensor power method on them (Appendix B).
+//
+// One hash h: [n] -> [b] and one complex sign sigma(i) = i^q(i), q in
+// {0, 1, 2, 3}, per sketch.  The sketch of a symmetric tensor,
+//   s(t) = sum over (h(i) + h(j) + h(k)) mod b == t of sigma(i) sigma(j) sigma(k) T_ijk,
+// is complex; it is built from the entries with i <= j <= k, each weighted by
+// the number of distinct permutations of its index triple (6, 3 or 1).  It is
+// kept in the time domain (the T(I,u,u) read-off takes s at 3h(i)) and as a
+// full complex spectrum of b points.
+//
+// T(I,u,u)_i is estimated by the read-off of Appendix B with weight 1/3 on all
+// four terms:
+//   v_i = (1/3) [ conj(sigma_i) (c_1 + c_2)[h_i] / 2 + conj(sigma_i^2) u_i c_3[2h_i]
+//                 + conj(sigma_i^3) u_i^2 s[3h_i] ],
+//   c_1 + c_2 = F^-1(S o (conj(U_1)^2 + conj(U_2))),  c_3 = F^-1(S o conj(U_1)),
+//   U_1 = F(s_u), s_u(t) = sum_{h(i)=t} sigma_i u_i,
+//   U_2 = F(s_2), s_2(t) = sum_{2h(i)=t} sigma_i^2 u_i^2   (positions mod b),
+// and the power step keeps Re v_i.  T(u,u,u) is u . Re v (the estimate
+// <s, s_X> of Appendix B equals it: sum_i u_i s_{Z_i} = 3 s_X).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace tsk {
+
+// Table words: (position << 2) | rotation, rotation = the power of i.
+__device__ __forceinline__ uint32_t sym_pos(uint32_t e) { return e >> 2; }
+__device__ __forceinline__ int sym_rot(uint32_t e) { return (int)(e & 3u); }
+
+// x * i^r
+template <typename R>
+__device__ __forceinline__ cx<R> rot(cx<R> x, int r) {
+  switch (r & 3) {
+    case 0: return x;
+    case 1: return {-x.y, x.x};
+    case 2: return {-x.x, -x.y};
+    default: return {x.y, -x.x};
+  }
+}
+
+// Deterministic complex count sketch from a table sorted by position (stable
+// by index): the entries sharing a bucket are summed by one thread in
+// increasing index order; store(bucket, sum).  Entry words carry the rotation
+// of sigma^p; getx(i) is the real value x_i (u_i, u_i^2, ...).
+template <typename R, typename GetX, typename Store>
+__device__ __forceinline__ void sym_count_sketch(const uint32_t* __restrict__ srt, const uint32_t* __restrict__ ord,
+                                                 int n, int nt, GetX getx, Store store) {
+  for (int p = threadIdx.x; p < n; p += nt) {
+    uint32_t e = srt[p];
+    const uint32_t bk = sym_pos(e);
+    if (p > 0 && sym_pos(srt[p - 1]) == bk) continue;
+    cx<R> acc = {R(0), R(0)};
+    int q = p;
+    while (true) {
+      acc = cadd(acc, rot(cx<R>{getx(ord[q]), R(0)}, sym_rot(e)));
+      if (++q >= n) break;
+      e = srt[q];
+      if (sym_pos(e) != bk) break;
+    }
+    store(bk, acc);
+  }
+}
+
+// ---- build ------------------------------------------------------------------
+
+// Dense symmetric build: grid (work-groups over index pairs, B), 256 threads;
+// wave w of work-group g takes the pairs (i <= j) numbered p = w + nwaves * g
+// + stride * r and adds, for k >= j, mult * T_ijk rotated by
+// q_i + q_j + q_k at bucket (h_i + h_j + h_k) mod b of s_time[m] (FP64
+// atomics: the summation order varies between runs).
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_sym_build(const TIn* __restrict__ T, const uint32_t* __restrict__ hq,
+                                                   int n, int b, double* s_time) {
+  const int m = blockIdx.y;
+  const uint32_t* tab = hq + (size_t)m * n;
+  double* out = s_time + (size_t)m * 2 * b;
+  const unsigned bmask = (unsigned)b - 1u;
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * 4;
+  const long long w0 = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long npairs = (long long)n * (n + 1) / 2;
+  for (long long p = w0; p < npairs; p += nw) {
+    // pair p -> (i, j), i <= j, by rows of the upper triangle counted from j
+    // (j = 0: 1 pair, j = 1: 2 pairs, ...): p = j (j + 1) / 2 + i
+    int j = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((long long)(j + 1) * (j + 2) / 2 <= p) ++j;
+    while ((long long)j * (j + 1) / 2 > p) --j;
+    const int i = (int)(p - (long long)j * (j + 1) / 2);
+    const uint32_t ei = tab[i], ej = tab[j];
+    const uint32_t hij = sym_pos(ei) + sym_pos(ej);
+    const int qij = sym_rot(ei) + sym_rot(ej);
+    const TIn* row = T + ((size_t)i * n + j) * n;
+    for (int k = j + lane; k < n; k += 64) {
+      const uint32_t ek = tab[k];
+      const double mult = (i == j) ? (j == k ? 1.0 : 3.0) : (j == k ? 3.0 : 6.0);
+      const double x = mult * (double)row[k];
+      const uint32_t t = (hij + sym_pos(ek)) & bmask;
+      const int r = (qij + sym_rot(ek)) & 3;
+      const double v = (r & 2) ? -x : x;
+      if (x != 0.0) atomicAdd(out + 2 * t + (r & 1), v);
+    }
+  }
+}
+
+// ---- FP64 complex transforms ------------------------------------------------
+
+// Complex FFT of rows of N = 2^LOGN points, one work-group per row:
+// out[row] = F(in[row]) (INV: the unnormalised inverse).  With DEC = 2 the
+// row is the decimated subsequence in[row / 2][2 s + row % 2] of a 2N-point
+// input (the two halves of a radix-2 split).
+template <int LOGN, bool INV, int DEC>
+__global__ __launch_bounds__(threads_for_h<double>(LOGN)) void k_c2c64(const cx<double>* in, cx<double>* out,
+                                                                         const cx<double>* tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NT = threads_for_h<double>(LOGN);
+  constexpr int PL = padded_len(N);
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* re = reinterpret_cast<double*>(lds);
+  const Soa<double> buf{re, re + PL};
+  const int row = blockIdx.x;
+  const cx<double>* src = in + (size_t)(row / DEC) * N * DEC;
+  const int par = row % DEC;
+  for (int s = threadIdx.x; s < N; s += NT) buf.put(s, src[(size_t)s * DEC + par]);
+  __syncthreads();
+  const Twid<double> twd{tw, nullptr};
+  fft_soa<double, LOGN, NT, INV>(buf, twd);
+  cx<double>* dst = out + (size_t)row * N;
+  for (int k = threadIdx.x; k < N; k += NT) dst[k] = buf.get(k);
+}
+
+// Radix-2 combination of the two half transforms E = rows 2r, O = rows 2r+1
+// (N points each) into the 2N-point transform of row r:
+// X[k] = E[k mod N] + W^k O[k mod N], W = e^{-2 pi i / 2N} (conjugate for INV);
+// W^k from the full-circle table of 2N points.  Optional FP32 copy.
+__global__ void k_c2c_combine(const cx<double>* half, cx<double>* out, cx<float>* out32, const cx<double>* wb,
+                              int N, int rows, int inv) {
+  const size_t total = (size_t)rows * 2 * N;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / (2 * N);
+    const int k = (int)(e % (2 * N));
+    const int km = k & (N - 1);
+    const cx<double> E = half[(2 * r) * N + km], O = half[(2 * r + 1) * N + km];
+    cx<double> w = wb[k];
+    if (inv) w.y = -w.y;
+    const cx<double> x = cadd(E, cmul(w, O));
+    out[e] = x;
+    if (out32) out32[e] = cx<float>{(float)x.x, (float)x.y};
+  }
+}
+
+// dst = (float) src, elementwise over complex values.
+__global__ void k_c64to32(const cx<double>* src, cx<float>* dst, size_t count) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = cx<float>{(float)src[e].x, (float)src[e].y};
+}
+
+// ---- power step (FP32) ----------------------------------------------------
+
+struct SymPowerArgs {
+  const uint32_t* hq;     // [B][n] (h << 2) | q
+  const uint32_t* srt1;   // [B][n] sorted (h << 2) | q
+  const uint32_t* ord1;   // [B][n]
+  const uint32_t* srt2;   // [B][n] sorted (2h mod b << 2) | 2q mod 4
+  const uint32_t* ord2;   // [B][n]
+  int n, B;
+  const cx<float>* S;     // [B][b] spectra
+  const cx<float>* s;     // [B][b] time-domain sketches
+  const cx<float>* tw;    // pass table of the b-point transform
+  const float* U;         // [L][n]
+  float* V;               // [L][B][n]  Re v
+  double* lam_per;        // [L][B] u . Re v (mode 1)
+  int mode;
+};
+
+// Threads of the symmetric power kernel: 16 points per thread, at least 64.
+constexpr int sym_threads(int logb) { return logb >= 10 ? (1 << (logb - 4)) : 64; }
+// Dynamic LDS: the b-point sequence (split re/im, padded), u and the partial
+// read-offs (n floats each).
+constexpr size_t sym_power_lds(int logb, int n) {
+  return align16(sizeof(float) * 2 * (size_t)padded_len(1 << logb)) + 2 * align16(sizeof(float) * (size_t)n);
+}
+
+template <int LOGB>
+__global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a) {
+  constexpr int b = 1 << LOGB;
+  constexpr int NT = sym_threads(LOGB);
+  constexpr int PL = padded_len(b);
+  constexpr int PK = (b + NT - 1) / NT;
+  extern __shared__ __align__(16) unsigned char lds[];
+  float* re = reinterpret_cast<float*>(lds);
+  const Soa<float> buf{re, re + PL};
+  float* u = reinterpret_cast<float*>(lds + align16(sizeof(float) * 2 * (size_t)PL));
+  float* vp = u + align16(sizeof(float) * (size_t)a.n) / sizeof(float);
+  const int n = a.n, B = a.B;
+  const int m = blockIdx.x, tau = blockIdx.y;
+  const size_t tb = (size_t)m * n;
+  const Twid<float> tw{a.tw, nullptr};
+  for (int e = threadIdx.x; e < n; e += NT) {
+    u[e] = a.U[(size_t)tau * n + e];
+    vp[e] = 0.f;
+  }
+  // U_1 = F(s_u), kept in registers for the products
+  for (int t = threadIdx.x; t < 2 * PL; t += NT) re[t] = 0.f;
+  __syncthreads();
+  auto put = [&](uint32_t t, cx<float> v) { buf.put((int)t, v); };
+  sym_count_sketch<float>(a.srt1 + tb, a.ord1 + tb, n, NT, [&](uint32_t i) { return u[i]; }, put);
+  __syncthreads();
+  fft_soa<float, LOGB, NT, false>(buf, tw);
+  cx<float> u1[PK];
+#pragma unroll
+  for (int q = 0; q < PK; ++q) {
+    const int k = threadIdx.x + q * NT;
+    u1[q] = k < b ? buf.get(k) : cx<float>{0.f, 0.f};
+  }
+  __syncthreads();
+  // U_2 = F(s_2)
+  for (int t = threadIdx.x; t < 2 * PL; t += NT) re[t] = 0.f;
+  __syncthreads();
+  sym_count_sketch<float>(a.srt2 + tb, a.ord2 + tb, n, NT, [&](uint32_t i) { return u[i] * u[i]; }, put);
+  __syncthreads();
+  fft_soa<float, LOGB, NT, false>(buf, tw);
+  // P_1 = S o (conj U_1^2 + conj U_2) in place; P_2 = S o conj U_1 kept
+  const cx<float>* Sm = a.S + (size_t)m * b;
+#pragma unroll
+  for (int q = 0; q < PK; ++q) {
+    const int k = threadIdx.x + q * NT;
+    if (k < b) {
+      const cx<float> sk = Sm[k];
+      const cx<float> c1 = cconj(u1[q]);
+      const cx<float> c2 = cconj(buf.get(k));
+      buf.put(k, cmul(sk, cadd(cmul(c1, c1), c2)));
+      u1[q] = cmul(sk, c1);
+    }
+  }
+  __syncthreads();
+  fft_soa<float, LOGB, NT, true>(buf, tw);
+  const float sc = 1.f / (float)b;
+  const uint32_t* hq = a.hq + tb;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const uint32_t e = hq[i];
+    const cx<float> c = rot(buf.get((int)sym_pos(e)), (4 - sym_rot(e)) & 3);  // conj(sigma) c12[h]
+    vp[i] = c.x * (sc / 6.f);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PK; ++q) {
+    const int k = threadIdx.x + q * NT;
+    if (k < b) buf.put(k, u1[q]);
+  }
+  __syncthreads();
+  fft_soa<float, LOGB, NT, true>(buf, tw);
+  const cx<float>* sm = a.s + (size_t)m * b;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const uint32_t e = hq[i];
+    const uint32_t h = sym_pos(e);
+    const int qq = sym_rot(e);
+    const float ui = u[i];
+    const cx<float> c3 = rot(buf.get((int)((2u * h) & (uint32_t)(b - 1))), (8 - 2 * qq) & 3);
+    const cx<float> s3 = rot(sm[(3u * h) & (uint32_t)(b - 1)], (12 - 3 * qq) & 3);
+    const float v = vp[i] + (ui * c3.x * sc + ui * ui * s3.x) * (1.f / 3.f);
+    a.V[((size_t)tau * B + m) * n + i] = v;
+    acc += (double)ui * (double)v;
+  }
+  if (a.mode == 1) {
+    __shared__ double red[NT / 64];
+    const double lam = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) a.lam_per[(size_t)tau * B + m] = lam;
+  }
+}
+
+// ---- lambda_hat and deflation (FP64) ---------------------------------------
+
+// cs[m][p-1] = the count sketch of u^p with sigma^p at p h mod b (p = 1, 2, 3),
+// complex, for the run heads of the sorted tables; the rows are zero on entry.
+// grid = (B, 3), 256 threads.
+__global__ __launch_bounds__(256) void k_sym_cs64(const uint32_t* srt, const uint32_t* ord, int n, int b, int B,
+                                                  const double* u, cx<double>* cs) {
+  const int m = blockIdx.x, p = blockIdx.y + 1;
+  const size_t tb = ((size_t)(p - 1) * B + m) * n;
+  cx<double>* row = cs + ((size_t)m * 3 + (p - 1)) * b;
+  sym_count_sketch<double>(srt + tb, ord + tb, n, 256,
+                           [&](uint32_t i) { const double x = u[i]; return p == 1 ? x : (p == 2 ? x * x : x * x * x); },
+                           [&](uint32_t t, cx<double> v) { row[t] = v; });
+}
+
+// Per sketch m: lam_per[m] = Re <s, s_X> = (1/b) Re sum_k S[k] conj(X[k]),
+// X = U_1^3 / 6 + U_2 U_1 / 2 + U_3 / 3, and cube[m][k] = U_1[k]^3 (the
+// spectrum of the full symmetric sketch of u^(x)3).  grid = B, 1024 threads.
+__global__ __launch_bounds__(1024) void k_sym_lam(const cx<double>* S, const cx<double>* Uf, int b,
+                                                  double* lam_per, cx<double>* cube) {
+  __shared__ double red[16];
+  const int m = blockIdx.x;
+  const cx<double>* U1 = Uf + (size_t)m * 3 * b;
+  const cx<double>* U2 = U1 + b;
+  const cx<double>* U3 = U2 + b;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < b; k += 1024) {
+    const cx<double> c3 = cmul(cmul(U1[k], U1[k]), U1[k]);
+    const cx<double> x = cadd(cadd(cscale(c3, 1.0 / 6.0), cscale(cmul(U2[k], U1[k]), 0.5)),
+                              cscale(U3[k], 1.0 / 3.0));
+    const cx<double> sk = S[(size_t)m * b + k];
+    acc += sk.x * x.x + sk.y * x.y;
+    cube[(size_t)m * b + k] = c3;
+  }
+  const double s = block_sum<1024>(acc, red);
+  if (threadIdx.x == 0) lam_per[m] = s / (double)b;
+}
+
+// X[e] -= lam * D[e] (complex), optional FP32 copy of X; scale applies to D.
+__global__ void k_sym_axpy(cx<double>* X, cx<float>* X32, const cx<double>* D, const double* lam, double scale,
+                           size_t count) {
+  const double l = *lam * scale;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    const cx<double> x = csub(X[e], cscale(D[e], l));
+    X[e] = x;
+    if (X32) X32[e] = cx<float>{(float)x.x, (float)x.y};
+  }
+}
+
+}  // namespace tsk

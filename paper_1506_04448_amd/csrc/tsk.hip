@@ -16,6 +16,7 @@
 #include "../../include/tsk.h"
 #include "kernels.hpp"
 #include "large.hpp"
+#include "symmetric.hpp"
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include "status.hpp"
@@ -96,12 +97,22 @@ struct tsk_tables {
   uint32_t* ord = nullptr;
 };
 
+// Colliding-hash tables: one (h, q) per index and sketch, plus the entries
+// sorted by p h mod b (stable by index) for p = 1, 2, 3.
+struct tsk_sym_tables {
+  tsk_ctx* ctx = nullptr;
+  int n = 0, b = 0, B = 0, logb = 0;
+  uint32_t* hq = nullptr;    // [B][n] (h << 2) | q
+  uint32_t* srt = nullptr;   // [3][B][n] (p h mod b << 2) | p q mod 4
+  uint32_t* ord = nullptr;   // [3][B][n]
+};
+
 namespace {
 
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -1887,5 +1898,325 @@ extern "C" tsk_status tsk_workspace_size(tsk_ctx_t ctx, int ninst, const tsk_pro
                               nullptr);
   }
   *bytes = total;
+  return TSK_OK;
+}
+
+// =============================================================================
+// Colliding-hash symmetric sketches (Section 3.3, Appendix B)
+// =============================================================================
+
+extern "C" tsk_status tsk_sym_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint32_t* h_host,
+                                            const uint8_t* q_host, tsk_sym_tables_t* out) {
+  if (!ctx || !h_host || !q_host || !out) return tsk::fail(TSK_EINVAL, "tsk_sym_tables_create: null argument");
+  if (n < 1 || n > 65535 || B < 1 || B > 64)
+    return tsk::fail(TSK_EINVAL, "tsk_sym_tables_create: n=%d, B=%d out of range", n, B);
+  if (b < 256 || b > 16384 || (b & (b - 1)))
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_sym_tables_create: b=%d (powers of two in [256, 16384])", b);
+  const size_t cnt = (size_t)B * n;
+  std::vector<uint32_t> hq(cnt), srt(3 * cnt), ord(3 * cnt);
+  for (size_t e = 0; e < cnt; ++e) {
+    if (h_host[e] >= (uint32_t)b || q_host[e] > 3)
+      return tsk::fail(TSK_EINVAL, "tsk_sym_tables_create: h or q out of range at %zu", e);
+    hq[e] = (h_host[e] << 2) | q_host[e];
+  }
+  std::vector<uint32_t> idx(n);
+  for (int p = 1; p <= 3; ++p)
+    for (int m = 0; m < B; ++m) {
+      const size_t base = (size_t)m * n, ob = ((size_t)(p - 1) * B + m) * n;
+      auto pos = [&](uint32_t i) { return (uint32_t)(((uint64_t)p * h_host[base + i]) & (uint32_t)(b - 1)); };
+      std::iota(idx.begin(), idx.end(), 0u);
+      std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return pos(x) < pos(y); });
+      for (int r = 0; r < n; ++r) {
+        const uint32_t i = idx[r];
+        srt[ob + r] = (pos(i) << 2) | ((uint32_t)(p * q_host[base + i]) & 3u);
+        ord[ob + r] = i;
+      }
+    }
+  TSK_TRY(set_device(ctx));
+  tsk_sym_tables* t = new tsk_sym_tables;
+  t->ctx = ctx;
+  t->n = n;
+  t->b = b;
+  t->B = B;
+  t->logb = 0;
+  while ((1 << t->logb) < b) ++t->logb;
+  if (hipMalloc(&t->hq, 7 * cnt * 4) != hipSuccess) {
+    delete t;
+    return tsk::fail(TSK_ENOMEM, "tsk_sym_tables_create: device allocation");
+  }
+  t->srt = t->hq + cnt;
+  t->ord = t->srt + 3 * cnt;
+  hipError_t e1 = hipMemcpy(t->hq, hq.data(), cnt * 4, hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(t->srt, srt.data(), 3 * cnt * 4, hipMemcpyHostToDevice);
+  hipError_t e3 = hipMemcpy(t->ord, ord.data(), 3 * cnt * 4, hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    (void)hipFree(t->hq);
+    delete t;
+    return tsk::fail(TSK_EHIP, "tsk_sym_tables_create: upload failed");
+  }
+  *out = t;
+  return TSK_OK;
+}
+
+extern "C" void tsk_sym_tables_destroy(tsk_sym_tables_t t) {
+  if (!t) return;
+  (void)hipSetDevice(t->ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(t->hq);
+  delete t;
+}
+
+namespace {
+
+tsk_status check_sym(tsk_sym_tables_t tab, tsk_ctx_t ctx, const char* fn) {
+  if (!ctx) return tsk::fail(TSK_EINVAL, "%s: null context", fn);
+  if (!tab) return tsk::fail(TSK_EINVAL, "%s: null tables", fn);
+  if (tab->ctx != ctx) return tsk::fail(TSK_EINVAL, "%s: tables belong to another context", fn);
+  return TSK_OK;
+}
+
+template <int LOGN, bool INV, int DEC>
+tsk_status launch_c2c64_t(tsk_ctx_t ctx, const cx<double>* in, cx<double>* out, int rows, hipStream_t st) {
+  constexpr int NT = tsk::threads_for_h<double>(LOGN);
+  const cx<double>* tw = nullptr;
+  TSK_TRY(get_tw<double>(ctx, LOGN + 1, &tw, NT));
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  const size_t lds = sizeof(double) * 2 * (size_t)tsk::padded_len(1 << LOGN);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_c2c64<LOGN, INV, DEC>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL((tsk::k_c2c64<LOGN, INV, DEC>), dim3(rows), dim3(NT), lds, st, in, out, tw);
+  return check_launch("k_c2c64");
+}
+
+// Complex FFT (unnormalised; inverse with conjugate twiddles) of `rows` rows
+// of b = 2^logb points, FP64, with an optional FP32 copy of the result:
+// one work-group per row up to 8192 points, a radix-2 split above.
+tsk_status fft64_rows(tsk_ctx_t ctx, int logb, const cx<double>* in, cx<double>* out, cx<float>* out32, int rows,
+                      bool inv, hipStream_t st) {
+  const size_t count = (size_t)rows << logb;
+  if (logb == 14) {
+    void* half = nullptr;
+    TSK_TRY(ws_get(ctx, WS_SYM, count * sizeof(cx<double>), &half));
+    const cx<double>* wb = nullptr;
+    TSK_TRY(get_wb<double>(ctx, 14, &wb));
+    cx<double>* hb = reinterpret_cast<cx<double>*>(half);
+    if (inv) TSK_TRY((launch_c2c64_t<13, true, 2>(ctx, in, hb, 2 * rows, st)));
+    else TSK_TRY((launch_c2c64_t<13, false, 2>(ctx, in, hb, 2 * rows, st)));
+    hipLaunchKernelGGL(tsk::k_c2c_combine, dim3(grid_for(count, 256)), dim3(256), 0, st, (const cx<double>*)hb,
+                       out, out32, wb, 1 << 13, rows, inv ? 1 : 0);
+    return check_launch("k_c2c_combine");
+  }
+#define TSK_C2C(L)                                                                                      \
+  case L:                                                                                               \
+    if (inv) TSK_TRY((launch_c2c64_t<L, true, 1>(ctx, in, out, rows, st)));                            \
+    else TSK_TRY((launch_c2c64_t<L, false, 1>(ctx, in, out, rows, st)));                               \
+    break;
+  switch (logb) {
+    TSK_C2C(8)
+    TSK_C2C(9)
+    TSK_C2C(10)
+    TSK_C2C(11)
+    TSK_C2C(12)
+    TSK_C2C(13)
+    default: return tsk::fail(TSK_EUNSUPPORTED, "symmetric sketches: b=2^%d", logb);
+  }
+#undef TSK_C2C
+  if (out32) {
+    hipLaunchKernelGGL(tsk::k_c64to32, dim3(grid_for(count, 256)), dim3(256), 0, st, (const cx<double>*)out,
+                       out32, count);
+    TSK_TRY(check_launch("k_c64to32"));
+  }
+  return TSK_OK;
+}
+
+template <int LOGB>
+tsk_status launch_sym_power_t(const tsk::SymPowerArgs& a, int L, hipStream_t st) {
+  constexpr int NT = tsk::sym_threads(LOGB);
+  const size_t lds = tsk::sym_power_lds(LOGB, a.n);
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_sym_power<LOGB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLds - 256)));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL((tsk::k_sym_power<LOGB>), dim3(a.B, L), dim3(NT), lds, st, a);
+  return check_launch("k_sym_power");
+}
+
+// The FP32 read-off of T(I,u,u) for L vectors on every sketch (mode 1: also
+// lam_per = u . Re v).
+tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, const float* s32, int L,
+                     const float* U, float* V, double* lam_per, int mode, hipStream_t st) {
+  if (tsk::sym_power_lds(tab->logb, tab->n) > kMaxLds - 256)
+    return tsk::fail(TSK_EUNSUPPORTED, "symmetric power step: n=%d too large for b=%d", tab->n, tab->b);
+  const cx<float>* tw = nullptr;
+  TSK_TRY(get_tw<float>(ctx, tab->logb + 1, &tw, tsk::sym_threads(tab->logb)));
+  tsk::SymPowerArgs a;
+  const size_t cnt = (size_t)tab->B * tab->n;
+  a.hq = tab->hq;
+  a.srt1 = tab->srt;
+  a.ord1 = tab->ord;
+  a.srt2 = tab->srt + cnt;
+  a.ord2 = tab->ord + cnt;
+  a.n = tab->n;
+  a.B = tab->B;
+  a.S = reinterpret_cast<const cx<float>*>(S32);
+  a.s = reinterpret_cast<const cx<float>*>(s32);
+  a.tw = tw;
+  a.U = U;
+  a.V = V;
+  a.lam_per = lam_per;
+  a.mode = mode;
+  switch (tab->logb) {
+    case 8: return launch_sym_power_t<8>(a, L, st);
+    case 9: return launch_sym_power_t<9>(a, L, st);
+    case 10: return launch_sym_power_t<10>(a, L, st);
+    case 11: return launch_sym_power_t<11>(a, L, st);
+    case 12: return launch_sym_power_t<12>(a, L, st);
+    case 13: return launch_sym_power_t<13>(a, L, st);
+    case 14: return launch_sym_power_t<14>(a, L, st);
+    default: break;
+  }
+  return tsk::fail(TSK_EUNSUPPORTED, "symmetric power step: b=%d", tab->b);
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t tab, const void* T,
+                                                 tsk_dtype dtype, double* s64, float* s32, double* S64,
+                                                 float* S32, int accumulate, void* stream) {
+  TSK_TRY(check_sym(tab, ctx, "tsk_sym_sketch_build_dense"));
+  if (!T || !s64 || !S64) return tsk::fail(TSK_EINVAL, "tsk_sym_sketch_build_dense: null T, s64 or S64");
+  if (dtype != TSK_F32 && dtype != TSK_F64) return tsk::fail(TSK_EINVAL, "tsk_sym_sketch_build_dense: dtype");
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  const int n = tab->n, b = tab->b, B = tab->B;
+  const size_t cplx = (size_t)B * b;
+  if (!accumulate) {
+    hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for(4 * cplx, 256)), dim3(256), 0, st,
+                       reinterpret_cast<unsigned*>(s64), 0u, 4 * cplx);
+    TSK_TRY(check_launch("k_fill_u32"));
+  }
+  const long long pairs = (long long)n * (n + 1) / 2;
+  const int gx = (int)std::max(1LL, std::min(2048LL, (pairs + 3) / 4));
+  if (dtype == TSK_F32)
+    hipLaunchKernelGGL(tsk::k_sym_build<float>, dim3(gx, B), dim3(256), 0, st, (const float*)T, tab->hq, n, b, s64);
+  else
+    hipLaunchKernelGGL(tsk::k_sym_build<double>, dim3(gx, B), dim3(256), 0, st, (const double*)T, tab->hq, n, b,
+                       s64);
+  TSK_TRY(check_launch("k_sym_build"));
+  if (s32) {
+    hipLaunchKernelGGL(tsk::k_c64to32, dim3(grid_for(cplx, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const cx<double>*>(s64), reinterpret_cast<cx<float>*>(s32), cplx);
+    TSK_TRY(check_launch("k_c64to32"));
+  }
+  return fft64_rows(ctx, tab->logb, reinterpret_cast<const cx<double>*>(s64), reinterpret_cast<cx<double>*>(S64),
+                    reinterpret_cast<cx<float>*>(S32), B, false, st);
+}
+
+extern "C" tsk_status tsk_sym_contract_tiuu(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32,
+                                            const float* s32, int L, const float* U, float* V, void* stream) {
+  TSK_TRY(check_sym(tab, ctx, "tsk_sym_contract_tiuu"));
+  if (!S32 || !s32 || !U || !V) return tsk::fail(TSK_EINVAL, "tsk_sym_contract_tiuu: null argument");
+  if (L < 1 || L > 65535) return tsk::fail(TSK_EINVAL, "tsk_sym_contract_tiuu: L=%d", L);
+  TSK_TRY(set_device(ctx));
+  return sym_power(ctx, tab, S32, s32, L, U, V, nullptr, 0, S(stream));
+}
+
+extern "C" tsk_status tsk_sym_decompose(tsk_ctx_t ctx, tsk_sym_tables_t tab, double* s64, float* s32,
+                                        double* S64, float* S32, int k, int L, int T, const double* u0,
+                                        uint64_t seed, double* lam_out, double* U_out, int32_t* tau_out,
+                                        int32_t* flags_out, void* stream) {
+  TSK_TRY(check_sym(tab, ctx, "tsk_sym_decompose"));
+  if (!s64 || !s32 || !S64 || !S32 || !lam_out || !U_out)
+    return tsk::fail(TSK_EINVAL, "tsk_sym_decompose: null argument");
+  if (k < 1 || k > tab->n) return tsk::fail(TSK_EINVAL, "tsk_sym_decompose: k=%d outside [1,n]", k);
+  if (L < 1 || L > 65535 || T < 1) return tsk::fail(TSK_EINVAL, "tsk_sym_decompose: L=%d, T=%d", L, T);
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  const int n = tab->n, b = tab->b, B = tab->B;
+  const size_t cplx = (size_t)B * b;
+  // workspace: U0/U1 [L][n] f32, V [L][B][n] f32, lam_per [L][B], lam_med [L],
+  // u_hat [n], lam64 [B], cs [B][3][b] c64 (count sketches, then spectra),
+  // cube [B][b] c64, tmp [B][b] c64, u0 [k][L][n] f64, flags [k][L]
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t szU = r((size_t)L * n * 4), szV = r((size_t)L * B * n * 4);
+  const size_t szLP = r((size_t)L * B * 8), szLM = r((size_t)L * 8), szUH = r((size_t)n * 8), szL64 = r((size_t)B * 8);
+  const size_t szCS = r(3 * cplx * 16), szC = r(cplx * 16), szU0 = u0 ? 0 : r((size_t)k * L * n * 8);
+  const size_t szF = flags_out ? 0 : r((size_t)k * L * 4);
+  const size_t total = 2 * szU + szV + szLP + szLM + szUH + szL64 + szCS + 3 * szC + szU0 + szF;
+  void* base = nullptr;
+  TSK_TRY(ws_get(ctx, WS_U, total, &base));
+  char* p = (char*)base;
+  auto take = [&](size_t sz) { char* q = p; p += sz; return q; };
+  float* Ub[2] = {(float*)take(szU), (float*)take(szU)};
+  float* V = (float*)take(szV);
+  double* lam_per = (double*)take(szLP);
+  double* lam_med = (double*)take(szLM);
+  double* u_hat = (double*)take(szUH);
+  double* lam64 = (double*)take(szL64);
+  cx<double>* cs = (cx<double>*)take(szCS);
+  cx<double>* Uf = (cx<double>*)take(szCS);
+  cx<double>* cube = (cx<double>*)take(szC);
+  cx<double>* tmp = (cx<double>*)take(szC);
+  const double* u0d = u0;
+  if (!u0) {
+    double* u0w = (double*)take(szU0);
+    TSK_TRY(upload_start_vectors(seed, k, L, n, u0w, st));
+    u0d = u0w;
+  }
+  int32_t* flags = flags_out ? flags_out : (int32_t*)take(szF);
+  hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for((size_t)k * L, 256)), dim3(256), 0, st,
+                     reinterpret_cast<unsigned*>(flags), 0u, (size_t)k * L);
+  TSK_TRY(check_launch("k_fill_u32"));
+  const size_t LN = (size_t)L * n;
+  for (int c = 0; c < k; ++c) {
+    hipLaunchKernelGGL(tsk::k_cvt<float>, dim3(grid_for(LN, 256)), dim3(256), 0, st, u0d + (size_t)c * LN, Ub[0],
+                       LN);
+    TSK_TRY(check_launch("k_cvt"));
+    int cu = 0;
+    for (int t = 0; t < T; ++t) {
+      TSK_TRY(sym_power(ctx, tab, S32, s32, L, Ub[cu], V, nullptr, 0, st));
+      TSK_TRY(median_norm_launch<float>(V, Ub[cu], Ub[cu ^ 1], flags + (size_t)c * L, L, n, B, st));
+      cu ^= 1;
+    }
+    TSK_TRY(sym_power(ctx, tab, S32, s32, L, Ub[cu], V, lam_per, 1, st));
+    TSK_TRY(lam_median_launch(lam_per, lam_med, L, B, st));
+    hipLaunchKernelGGL(tsk::k_select<float>, dim3(1), dim3(256), 0, st, (const double*)lam_med, L,
+                       (const float*)Ub[cu], n, u_hat, U_out + (size_t)c * n, tau_out ? tau_out + c : nullptr);
+    TSK_TRY(check_launch("k_select"));
+    // lambda_hat = med_m Re <s, s_X(u_hat)> in FP64, then deflation by
+    // lambda_hat (s_u * s_u * s_u) in both domains
+    hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for(12 * cplx, 256)), dim3(256), 0, st,
+                       reinterpret_cast<unsigned*>(cs), 0u, 12 * cplx);
+    TSK_TRY(check_launch("k_fill_u32"));
+    hipLaunchKernelGGL(tsk::k_sym_cs64, dim3(B, 3), dim3(256), 0, st, tab->srt, tab->ord, n, b, B,
+                       (const double*)u_hat, cs);
+    TSK_TRY(check_launch("k_sym_cs64"));
+    TSK_TRY(fft64_rows(ctx, tab->logb, cs, Uf, nullptr, 3 * B, false, st));
+    hipLaunchKernelGGL(tsk::k_sym_lam, dim3(B), dim3(1024), 0, st, (const cx<double>*)S64, (const cx<double>*)Uf,
+                       b, lam64, cube);
+    TSK_TRY(check_launch("k_sym_lam"));
+    hipLaunchKernelGGL(tsk::k_median_scalar, dim3(1), dim3(64), 0, st, (const double*)lam64, B, lam_out + c);
+    TSK_TRY(check_launch("k_median_scalar"));
+    hipLaunchKernelGGL(tsk::k_sym_axpy, dim3(grid_for(cplx, 256)), dim3(256), 0, st,
+                       reinterpret_cast<cx<double>*>(S64), reinterpret_cast<cx<float>*>(S32),
+                       (const cx<double>*)cube, (const double*)(lam_out + c), 1.0, cplx);
+    TSK_TRY(check_launch("k_sym_axpy"));
+    TSK_TRY(fft64_rows(ctx, tab->logb, cube, tmp, nullptr, B, true, st));
+    hipLaunchKernelGGL(tsk::k_sym_axpy, dim3(grid_for(cplx, 256)), dim3(256), 0, st,
+                       reinterpret_cast<cx<double>*>(s64), reinterpret_cast<cx<float>*>(s32), (const cx<double>*)tmp,
+                       (const double*)(lam_out + c), 1.0 / (double)b, cplx);
+    TSK_TRY(check_launch("k_sym_axpy"));
+  }
   return TSK_OK;
 }

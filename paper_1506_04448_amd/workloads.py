@@ -230,3 +230,12 @@ def full_rank_tensor(n: int, sigma: float, seed: int, device="cpu", chunk: int =
         T[i0:i1] += Gf[(lo * n + mid) * n + hi]
     del G, Gf
     return FullRankTensor(T=T, lam=lam, V=np.ascontiguousarray(Q.T), sigma=sigma)
+
+
+def sym_tables(seed: int, n: int, b: int, B: int):
+    """Colliding-hash tables for B sketches: h [B][n] uniform on [0, b) and
+    q [B][n] uniform on {0, 1, 2, 3} (the sign is i^q), from numpy."""
+    rng = np.random.default_rng(seed)
+    h = rng.integers(0, b, size=(B, n), dtype=np.uint32)
+    q = rng.integers(0, 4, size=(B, n)).astype(np.uint8)
+    return h, q

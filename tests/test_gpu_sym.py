@@ -1,0 +1,133 @@
+"""Parity of the colliding-hash symmetric sketches (Section 3.3, Eq. (5);
+Appendix B) with the oracle, through the C ABI: the dense build (time domain
+and spectrum, including the radix-2 split at b = 16384), the FP32 T(I,u,u)
+read-off, and Algorithm 1 on symmetric sketches.
+
+Bars: FP64 sketches and spectra 1e-12 normwise relative; FP32 read-offs 1e-5;
+the FP32 decomposition's converged first component 1e-5 (lambda) / 1e-4 (u).
+Inputs: seeded planted symmetric tensors with symmetric noise; seeded tables.
+"""
+import numpy as np
+import pytest
+
+from oracle import symmetric as osym
+from paper_1506_04448_amd.workloads import planted_tensor, sym_tables
+
+torch = pytest.importorskip("torch")
+import paper_1506_04448_amd as tsk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, ref):
+    d = np.linalg.norm(ref)
+    return np.linalg.norm(np.asarray(a) - ref) / (d if d > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tsk.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _c(x):
+    x = x.cpu().numpy()
+    return x[..., 0] + 1j * x[..., 1]
+
+
+@pytest.mark.parametrize("n,b,B,dt", [(7, 256, 3, np.float64), (40, 1024, 2, np.float64),
+                                      (60, 8192, 2, np.float32), (50, 16384, 2, np.float64)])
+def test_sym_build_matches_eq5(ctx, n, b, B, dt):
+    print(f"sym build n={n} b={b} B={B}", flush=True)
+    P = planted_tensor(n, 3, noise=0.05, seed=n, dtype=dt)
+    h, q = sym_tables(n + b, n, b, B)
+    tab = tsk.SymTables(ctx, h, q, b)
+    s64, s32, S64, S32 = tsk.new_sym_sketch(tab, DEV)
+    tsk.sym_sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), s64, s32, S64, S32)
+    got_s, got_S = _c(s64), _c(S64)
+    for m in range(B):
+        ref = osym.sym_sketch_dense(P.T.astype(np.float64), h[m], q[m], b)
+        assert rel(got_s[m], ref) < 1e-12
+        assert rel(got_S[m], np.fft.fft(ref)) < 1e-12
+    np.testing.assert_array_equal(S32.cpu().numpy(), S64.cpu().numpy().astype(np.float32))
+    np.testing.assert_array_equal(s32.cpu().numpy(), s64.cpu().numpy().astype(np.float32))
+    tab.close()
+
+
+@pytest.mark.parametrize("n,b,B,L", [(9, 256, 3, 2), (100, 2048, 3, 4), (200, 16384, 2, 3), (1000, 8192, 2, 2)])
+def test_sym_tiuu_matches_appendix_b(ctx, n, b, B, L):
+    print(f"sym tiuu n={n} b={b}", flush=True)
+    rng = np.random.default_rng(n)
+    P = planted_tensor(n, 3, noise=0.05, seed=n + 1) if n <= 200 else None
+    h, q = sym_tables(n, n, b, B)
+    tab = tsk.SymTables(ctx, h, q, b)
+    s64, s32, S64, S32 = tsk.new_sym_sketch(tab, DEV)
+    if P is not None:
+        tsk.sym_sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), s64, s32, S64, S32)
+        s_ref = [osym.sym_sketch_dense(P.T, h[m], q[m], b) for m in range(B)]
+    else:
+        # n = 1000: a random complex sketch stands in for a built one (the read-off is linear in it)
+        s_ref = [rng.standard_normal(b) + 1j * rng.standard_normal(b) for m in range(B)]
+        st = np.stack(s_ref)
+        s64.copy_(torch.from_numpy(np.stack([st.real, st.imag], -1)).to(DEV))
+        Sf = np.fft.fft(st, axis=-1)
+        S64.copy_(torch.from_numpy(np.stack([Sf.real, Sf.imag], -1)).to(DEV))
+        s32.copy_(s64.float())
+        S32.copy_(S64.float())
+    U = rng.standard_normal((L, n))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    U = U.astype(np.float32).astype(np.float64)
+    V = tsk.sym_contract_tiuu(ctx, tab, torch.from_numpy(U).to(DEV, torch.float32), S32, s32).cpu().numpy()
+    s32_np = _c(s32).astype(np.complex128)
+    for m in range(B):
+        for t in range(L):
+            # the kernel reads the FP32 copies: compare with the oracle on those values
+            ref = np.real(osym.sym_tiuu(s32_np[m], h[m], q[m], U[t]))
+            assert rel(V[t, m], ref) < 1e-5, (m, t, rel(V[t, m], ref))
+    tab.close()
+
+
+def test_sym_decompose_matches_oracle_and_recovers(ctx):
+    print("sym decompose", flush=True)
+    n, k, b, B, L, T = 40, 3, 2048, 5, 6, 25
+    P = planted_tensor(n, k, noise=0.01, seed=21, lam_range=(1.0, 3.0))
+    h, q = sym_tables(21, n, b, B)
+    tab = tsk.SymTables(ctx, h, q, b)
+    s64, s32, S64, S32 = tsk.new_sym_sketch(tab, DEV)
+    tsk.sym_sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), s64, s32, S64, S32)
+    rng = np.random.default_rng(5)
+    u0 = rng.standard_normal((k, L, n))
+    u0 /= np.linalg.norm(u0, axis=2, keepdims=True)
+    u0 = u0.astype(np.float32).astype(np.float64)
+    lam, U, tau, flags = tsk.sym_decompose(ctx, tab, s64, s32, S64, S32, k, L, T,
+                                           u0=torch.from_numpy(u0).to(DEV))
+    S_ref = np.stack([osym.sym_sketch_dense(P.T, h[m], q[m], b) for m in range(B)])
+    ref = osym.rtpm_symmetric(S_ref, h, q, 1, L, T, u0[:1])
+    lam, U = lam.cpu().numpy(), U.cpu().numpy()
+    assert abs(lam[0] - ref.lam[0]) <= 1e-5 * abs(ref.lam[0])
+    assert rel(U[0], ref.U[0]) < 1e-4
+    import oracle
+    assert oracle.wrong_vectors(P.V, U) == 0
+    # sketched eigenvalue estimates at b = 2048, B = 5 (the method's accuracy, not parity)
+    np.testing.assert_allclose(np.sort(lam), np.sort(P.lam), rtol=0.1)
+    tab.close()
+
+
+def test_sym_argument_errors(ctx):
+    h, q = sym_tables(1, 10, 256, 2)
+    with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
+        tsk.SymTables(ctx, sym_tables(1, 10, 32768, 2)[0], sym_tables(1, 10, 32768, 2)[1], 32768)
+    bad = q.copy()
+    bad[0, 0] = 4
+    with pytest.raises(tsk.TskError, match="out of range"):
+        tsk.SymTables(ctx, h, bad, 256)
+    h2, q2 = sym_tables(2, 4000, 16384, 1)
+    tab = tsk.SymTables(ctx, h2, q2, 16384)
+    s64, s32, S64, S32 = tsk.new_sym_sketch(tab, DEV)
+    with pytest.raises(tsk.TskError, match="too large"):
+        tsk.sym_contract_tiuu(ctx, tab, torch.zeros((1, 4000), dtype=torch.float32, device=DEV), S32, s32)
+    tab.close()
