@@ -388,6 +388,8 @@ def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 1
                       f"(paper {rows[-1]['paper_wrong']}), decompose {rows[-1]['decompose_ms']:.1f} ms",
                       file=sys.stderr, flush=True)
                 rows[-1].update(x1_als_row(ctx, dev, tab, S32_als, Tt, X, nrm2, k, sigma, B, logbs.index(logb)))
+                if logb <= 14:   # colliding-hash sketches: complex transforms of b <= 16384
+                    rows[-1].update(x1_sym_row(ctx, dev, Tt, X, nrm2, k, L, T, B, b, logb))
                 tab.close()
                 del S64, S32, S32_als
         del X, Tt
@@ -395,6 +397,39 @@ def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 1
     return {"workload": ("paper's synthetic tensors: n=1000 full rank, lam_i=1/i normalised, symmetric "
                          "noise E||E||^2=sigma; top 10, L=T=30, FP32 power steps"),
             "tensor_generation_s": t_gen, "rows": rows}
+
+
+def x1_sym_row(ctx, dev, Tt, X, nrm2, k, L, T, B, b, logb):
+    """Algorithm 1 on colliding-hash symmetric sketches (Section 3.3) of the
+    same tensor: build from the i <= j <= k entries, FP32 read-offs."""
+    import torch
+    import paper_1506_04448_amd as tsk
+    from paper_1506_04448_amd.workloads import sym_tables
+    n = Tt.shape[0]
+    h, q = sym_tables(200 + B + logb, n, b, B)
+    tab = tsk.SymTables(ctx, h, q, b)
+    s64, s32, S64, S32 = tsk.new_sym_sketch(tab, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tsk.sym_sketch_build_dense(ctx, tab, Tt, s64, s32, S64, S32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lam, U, _, _ = tsk.sym_decompose(ctx, tab, s64, s32, S64, S32, k, L, T, seed=7)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    Ud = U.double()
+    tuuu = torch.zeros(k, dtype=torch.float64, device=dev)
+    for i0 in range(0, n, 100):
+        Y = (Tt[i0:i0 + 100].double().reshape(-1, n) @ Ud.T).view(-1, n, k)
+        tuuu += torch.einsum("ijr,jr,ir->r", Y, Ud.T, Ud.T[i0:i0 + 100])
+    G = (Ud @ Ud.T) ** 3
+    res = nrm2 - 2.0 * float(lam @ tuuu) + float(lam @ G @ lam)
+    wrong = wrong_vectors(X.V[:k], U.cpu().numpy())
+    print(f"x1 sym B={B} log2b={logb}: residual {res:.3f}, wrong {wrong}, build {1e3 * (t1 - t0):.0f} ms, "
+          f"decompose {1e3 * (t2 - t1):.1f} ms", file=sys.stderr, flush=True)
+    tab.close()
+    return {"sym_residual": res, "sym_wrong": int(wrong), "sym_build_ms": 1e3 * (t1 - t0),
+            "sym_decompose_ms": 1e3 * (t2 - t1)}
 
 
 def x1_als_row(ctx, dev, tab, S32, Tt, X, nrm2, k, sigma, B, j, T=30):

@@ -2153,10 +2153,11 @@ extern "C" tsk_status tsk_sym_decompose(tsk_ctx_t ctx, tsk_sym_tables_t tab, dou
   const size_t szLP = r((size_t)L * B * 8), szLM = r((size_t)L * 8), szUH = r((size_t)n * 8), szL64 = r((size_t)B * 8);
   const size_t szCS = r(3 * cplx * 16), szC = r(cplx * 16), szU0 = u0 ? 0 : r((size_t)k * L * n * 8);
   const size_t szF = flags_out ? 0 : r((size_t)k * L * 4);
-  const size_t total = 2 * szU + szV + szLP + szLM + szUH + szL64 + szCS + 3 * szC + szU0 + szF;
+  const size_t total = 2 * szU + szV + szLP + szLM + szUH + szL64 + 2 * szCS + 2 * szC + szU0 + szF;
   void* base = nullptr;
   TSK_TRY(ws_get(ctx, WS_U, total, &base));
   char* p = (char*)base;
+  char* const end = p + total;
   auto take = [&](size_t sz) { char* q = p; p += sz; return q; };
   float* Ub[2] = {(float*)take(szU), (float*)take(szU)};
   float* V = (float*)take(szV);
@@ -2168,13 +2169,14 @@ extern "C" tsk_status tsk_sym_decompose(tsk_ctx_t ctx, tsk_sym_tables_t tab, dou
   cx<double>* Uf = (cx<double>*)take(szCS);
   cx<double>* cube = (cx<double>*)take(szC);
   cx<double>* tmp = (cx<double>*)take(szC);
+  double* u0w = u0 ? nullptr : (double*)take(szU0);
+  int32_t* flags = flags_out ? flags_out : (int32_t*)take(szF);
+  if (p > end) return tsk::fail(TSK_EHIP, "internal: symmetric decomposition workspace layout");
   const double* u0d = u0;
   if (!u0) {
-    double* u0w = (double*)take(szU0);
     TSK_TRY(upload_start_vectors(seed, k, L, n, u0w, st));
     u0d = u0w;
   }
-  int32_t* flags = flags_out ? flags_out : (int32_t*)take(szF);
   hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for((size_t)k * L, 256)), dim3(256), 0, st,
                      reinterpret_cast<unsigned*>(flags), 0u, (size_t)k * L);
   TSK_TRY(check_launch("k_fill_u32"));
