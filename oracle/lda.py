@@ -179,3 +179,56 @@ def sketch_docs(corpus, W: np.ndarray, alpha0: float, h, xi, b: int) -> np.ndarr
     """The B sketches of M3(W, W, W) by Eq. (1) over the explicit K^3 tensor."""
     T = whitened_m3(corpus, W, alpha0)
     return np.stack([sketch_dense(T, h[m], xi[m], b) for m in range(h.shape[0])])
+
+
+# ---- Fast spectral LDA (Appendix D, Algorithm 3): whitening and recovery ----
+
+def empirical_m2(corpus, alpha0: float) -> np.ndarray:
+    """M2 of Eq. (moment2) from the averaged document estimates (V x V)."""
+    docs = list(_docs(corpus))
+    E2 = np.mean([doc_second_moment(n) for n, _ in docs], axis=0)
+    M1 = np.mean([n / m for n, m in docs], axis=0)
+    return combine_m2(E2, M1, alpha0)
+
+
+def whitening_exact(M2: np.ndarray, K: int):
+    """W = U_K diag(1/sqrt(sigma_K)) from the K largest-magnitude eigenpairs of
+    the symmetric M2 (its truncated SVD); returns (W, sigma)."""
+    d, E = np.linalg.eigh(M2)
+    order = np.argsort(-np.abs(d), kind="stable")[:K]
+    sig = np.abs(d[order])
+    return E[:, order] / np.sqrt(sig), sig
+
+
+def orth_gram(Y: np.ndarray, rel: float = 1e-12) -> np.ndarray:
+    """Orthonormal basis of range(Y) through the eigenpairs of Y^T Y:
+    Q = Y E diag(1/sqrt(d)) (columns with d <= rel max d dropped to zero)."""
+    d, E = np.linalg.eigh(Y.T @ Y)
+    keep = d > rel * d.max()
+    Q = np.zeros_like(Y)
+    Q[:, keep] = (Y @ E[:, keep]) / np.sqrt(d[keep])
+    return Q
+
+
+def whitening_subspace(M2: np.ndarray, Omega: np.ndarray, iters: int):
+    """The randomized truncated SVD the library runs: Y = M2 Omega; `iters`
+    rounds of Q = orth(Y), Y = M2 Q; then Q = orth(Y), B = Q^T M2 Q and
+    W = Q E_B diag(1/sqrt|d_B|) over B's eigenpairs by decreasing |d|."""
+    Y = M2 @ Omega
+    for _ in range(iters):
+        Y = M2 @ orth_gram(Y)
+    Q = orth_gram(Y)
+    Bm = Q.T @ (M2 @ Q)
+    Bm = (Bm + Bm.T) / 2
+    d, E = np.linalg.eigh(Bm)
+    order = np.argsort(-np.abs(d), kind="stable")
+    sig = np.abs(d[order])
+    return (Q @ E[:, order]) / np.sqrt(sig), sig
+
+
+def recover(lam: np.ndarray, V: np.ndarray, W: np.ndarray, alpha0: float):
+    """Algorithm 3's output: alpha_i = 4 alpha0 (alpha0 + 1) / ((alpha0 + 2)^2 lam_i^2)
+    and mu_i = (alpha0 + 2)/2 lam_i (W^+)^T v_i; V [k][K] rows, W [V][K]."""
+    alpha = 4.0 * alpha0 * (alpha0 + 1.0) / ((alpha0 + 2.0) ** 2 * lam ** 2)
+    mu = (alpha0 + 2.0) / 2.0 * lam[:, None] * (np.linalg.pinv(W).T @ V.T).T
+    return alpha, mu
