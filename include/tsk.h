@@ -279,6 +279,34 @@ tsk_status tsk_sym_decompose(tsk_ctx_t ctx, tsk_sym_tables_t tab, double* s64, f
                              uint64_t seed, double* lam_out, double* U_out, int32_t* tau_out,
                              int32_t* flags_out, void* stream);
 
+/* ---- Fast spectral LDA (Appendix D, Algorithm 3) ---------------------------
+ * Whitening from the empirical second moment (Eq. (moment2)):
+ *   M2 = (1/D) sum_d (n_d n_d^T - diag n_d)/(m_d (m_d - 1)) - alpha0/(alpha0+1) M1 M1^T
+ * over the documents with at least three words (M1 the mean of n_d/m_d),
+ * never formed: a randomized truncated SVD by subspace iteration,
+ *   Y = M2 Omega; `iters` times { Q = orth(Y); Y = M2 Q }; Q = orth(Y);
+ *   B = Q^T M2 Q = E diag(d) E^T;  W = Q E diag(1/sqrt|d|), sigma = |d|,
+ * columns by decreasing |d| (orth: Q = Y E_G diag(1/sqrt(d_G)) from the
+ * eigenpairs of Y^T Y).  Then W^T M2 W = I on the captured subspace.
+ * CSR counts as tsk_sketch_build_docs; Omega: double [V][K] start block
+ * (drawn by the caller, e.g. Gaussian); W_out double [V][K]; sigma_out
+ * double [K]; device.  1 <= K <= 100, K <= V.  Errors: TSK_EINVAL. */
+tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const int32_t* col,
+                          const int32_t* cnt, int D, int V, int K, double alpha0,
+                          const double* Omega, int iters, double* W_out, double* sigma_out,
+                          void* stream);
+
+/* Algorithm 3's output from the CP decomposition (lam [k], U [k][K] rows
+ * v_i) of M3(W, W, W):
+ *   alpha_i = 4 alpha0 (alpha0 + 1) / ((alpha0 + 2)^2 lam_i^2),
+ *   mu_i = (alpha0 + 2)/2 lam_i (W^+)^T v_i,  (W^+)^T = W (W^T W)^+,
+ * the pseudo-inverse over eigenvalues above 1e-12 of the largest.  W double
+ * [V][K]; lam double [k]; U double [k][K]; alpha_out double [k]; mu_out
+ * double [k][V]; device.  1 <= K <= 100.  Errors: TSK_EINVAL. */
+tsk_status tsk_lda_recover(tsk_ctx_t ctx, int V, int K, int k, double alpha0, const double* W,
+                           const double* lam, const double* U, double* alpha_out, double* mu_out,
+                           void* stream);
+
 /* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
  * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the
  * T(u,u,u) estimate of Eq. (3), and its gradient.  Each count sketch is linear

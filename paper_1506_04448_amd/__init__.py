@@ -63,6 +63,8 @@ _SIGS = {
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
     "tsk_sym_tables_create": ([_P, _I, _I, _I, _P, _P, _P], _I),
+    "tsk_lda_whiten": ([_P, _P, _P, _P, _I, _I, _I, ctypes.c_double, _P, _I, _P, _P, _P], _I),
+    "tsk_lda_recover": ([_P, _I, _I, _I, ctypes.c_double, _P, _P, _P, _P, _P, _P], _I),
     "tsk_sym_tables_destroy": ([_P], None),
     "tsk_sym_sketch_build_dense": ([_P, _P, _P, _I, _P, _P, _P, _P, _I, _P], _I),
     "tsk_sym_contract_tiuu": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
@@ -289,6 +291,37 @@ def sym_decompose(ctx, tab, s64, s32, S64, S32, k, L, T, u0=None, seed=0, stream
         ctx.handle, tab.handle, _ptr(s64), _ptr(s32), _ptr(S64), _ptr(S32), k, L, T, _ptr(u0),
         seed & (2 ** 64 - 1), _ptr(lam), _ptr(U), _ptr(tau), _ptr(flags), _stream(stream)))
     return lam, U, tau, flags
+
+
+def lda_whiten(ctx, rowptr, col, cnt, D, V, K, alpha0, Omega, iters=4, stream=None):
+    """Whitening of the empirical M2 (Algorithm 3) by randomized subspace
+    iteration from the float64 block Omega [V][K]; returns (W [V][K], sigma [K])."""
+    import torch
+    for t, name in ((rowptr, "rowptr"), (col, "col"), (cnt, "cnt")):
+        _tensor(t, name, torch.int32)
+    _tensor(Omega, "Omega", torch.float64, (V, K))
+    W = torch.empty((V, K), dtype=torch.float64, device=Omega.device)
+    sig = torch.empty((K,), dtype=torch.float64, device=Omega.device)
+    _check("tsk_lda_whiten", lib().tsk_lda_whiten(
+        ctx.handle, _ptr(rowptr), _ptr(col), _ptr(cnt), D, V, K, float(alpha0), _ptr(Omega), iters, _ptr(W),
+        _ptr(sig), _stream(stream)))
+    return W, sig
+
+
+def lda_recover(ctx, W, lam, U, alpha0, stream=None):
+    """Algorithm 3's alpha [k] and topic vectors mu [k][V] from the CP
+    decomposition (lam [k], U [k][K]) of M3(W, W, W)."""
+    import torch
+    V, K = W.shape
+    k = lam.shape[0]
+    _tensor(W, "W", torch.float64, (V, K))
+    _tensor(lam, "lam", torch.float64, (k,))
+    _tensor(U, "U", torch.float64, (k, K))
+    alpha = torch.empty((k,), dtype=torch.float64, device=W.device)
+    mu = torch.empty((k, V), dtype=torch.float64, device=W.device)
+    _check("tsk_lda_recover", lib().tsk_lda_recover(
+        ctx.handle, V, K, k, float(alpha0), _ptr(W), _ptr(lam), _ptr(U), _ptr(alpha), _ptr(mu), _stream(stream)))
+    return alpha, mu
 
 
 def new_sketch(tab: Tables, device="cuda"):

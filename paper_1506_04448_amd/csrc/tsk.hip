@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "large.hpp"
 #include "symmetric.hpp"
+#include "spectral.hpp"
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include "status.hpp"
@@ -112,7 +113,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -2221,4 +2222,156 @@ extern "C" tsk_status tsk_sym_decompose(tsk_ctx_t ctx, tsk_sym_tables_t tab, dou
     TSK_TRY(check_launch("k_sym_axpy"));
   }
   return TSK_OK;
+}
+
+// =============================================================================
+// Fast spectral LDA (Appendix D, Algorithm 3): whitening and recovery
+// =============================================================================
+
+namespace {
+
+tsk_status jacobi_eig(const double* G, int k, double* E, double* d, hipStream_t st) {
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_jacobi_eig),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 100 * 100 * 8));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL(tsk::k_jacobi_eig, dim3(1), dim3(256), (size_t)2 * k * k * 8, st, G, k, E, d);
+  return check_launch("k_jacobi_eig");
+}
+
+}  // namespace
+
+extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const int32_t* col, const int32_t* cnt,
+                                     int D, int V, int K, double alpha0, const double* Omega, int iters,
+                                     double* W_out, double* sigma_out, void* stream) {
+  if (!ctx || !rowptr || !Omega || !W_out || !sigma_out)
+    return tsk::fail(TSK_EINVAL, "tsk_lda_whiten: null argument");
+  if (K < 1 || K > 100 || V < K || D < 1 || iters < 0 || iters > 1000)
+    return tsk::fail(TSK_EINVAL, "tsk_lda_whiten: K=%d (1..100, <= V=%d), D=%d, iters=%d", K, V, D, iters);
+  if (!(alpha0 >= 0.0) || alpha0 > 1e300)
+    return tsk::fail(TSK_EINVAL, "tsk_lda_whiten: alpha0=%g must be finite and >= 0", alpha0);
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  int32_t nnz = 0;
+  TSK_HIP(hipMemcpyAsync(&nnz, rowptr + D, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TSK_HIP(hipStreamSynchronize(st));
+  if (nnz < 0) return tsk::fail(TSK_EINVAL, "tsk_lda_whiten: rowptr[D]=%d < 0", nnz);
+  if (nnz > 0 && (!col || !cnt)) return tsk::fail(TSK_EINVAL, "tsk_lda_whiten: null col or cnt");
+  const int G = std::max(1, std::min(1024, (D + 255) / 256));
+  const int per_q = (D + G - 1) / G;
+  size_t sort_tmp = 0;
+  TSK_HIP(rocprim::radix_sort_pairs(nullptr, sort_tmp, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                    (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)std::max(nnz, 1), 0, 32,
+                                    st));
+  size_t off = 0;
+  std::vector<size_t> offs;
+  auto take = [&](size_t bytes) {
+    offs.push_back(off);
+    off += (bytes + 255) & ~(size_t)255;
+  };
+  const size_t VK = (size_t)V * K;
+  take((size_t)D * K * 8);          // 0 P
+  take((size_t)D * 8);              // 1 cd
+  take((size_t)D * 8);              // 2 cpd
+  take((size_t)D * 8);              // 3 invm
+  take((size_t)G * (K + 1) * 8);    // 4 q partials
+  take((size_t)K * 8);              // 5 q
+  take(8);                          // 6 D_eff
+  take((size_t)nnz * 4 + 4);        // 7 rowof
+  take((size_t)nnz * 4 + 4);        // 8 iota
+  take((size_t)nnz * 4 + 4);        // 9 sorted word ids
+  take((size_t)nnz * 4 + 4);        // 10 sorted nonzero index
+  take(sort_tmp);                   // 11 sort scratch
+  take((size_t)(V + 1) * 4);        // 12 colptr
+  take(VK * 8);                     // 13 Y
+  take(VK * 8);                     // 14 Q
+  take((size_t)K * K * 8);          // 15 Gram
+  take((size_t)K * K * 8);          // 16 eigenvectors
+  take((size_t)K * 8);              // 17 eigenvalues
+  void* base = nullptr;
+  TSK_TRY(ws_get(ctx, WS_LDA, off, &base));
+  auto at = [&](int i) { return reinterpret_cast<char*>(base) + offs[i]; };
+  double* P = (double*)at(0);
+  double *cd = (double*)at(1), *cpd = (double*)at(2), *invm = (double*)at(3);
+  double *qpart = (double*)at(4), *q = (double*)at(5), *deff = (double*)at(6);
+  int32_t *rowof = (int32_t*)at(7), *iota = (int32_t*)at(8), *skeys = (int32_t*)at(9);
+  int32_t *svals = (int32_t*)at(10), *colptr = (int32_t*)at(12);
+  double *Y = (double*)at(13), *Q = (double*)at(14), *Gm = (double*)at(15), *E = (double*)at(16);
+  double* dv = (double*)at(17);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(tsk::k_rowof, dim3(grid_for((size_t)D, 256)), dim3(256), 0, st, rowptr, D, rowof, iota);
+    TSK_TRY(check_launch("k_rowof"));
+    size_t tmp = sort_tmp;
+    TSK_HIP(rocprim::radix_sort_pairs(at(11), tmp, col, skeys, (const int32_t*)iota, svals, (size_t)nnz, 0, 32,
+                                      st));
+  }
+  hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
+                     (const int32_t*)skeys, nnz, V, colptr);
+  TSK_TRY(check_launch("k_col_bounds"));
+  // Yout = M2 X
+  auto apply = [&](const double* X, double* Yout) -> tsk_status {
+    hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min(D, 8192)), dim3(128), 0, st, rowptr, col, cnt, D,
+                       K, X, P, cd, cpd, invm);
+    TSK_TRY(check_launch("k_doc_project"));
+    hipLaunchKernelGGL(tsk::k_doc_q_partial<double>, dim3(G), dim3(128), 0, st, (const double*)P,
+                       (const double*)invm, D, K, per_q, qpart);
+    hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
+    TSK_TRY(check_launch("k_doc_q"));
+    hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)svals,
+                       (const int32_t*)colptr, (const int32_t*)rowof, cnt, (const double*)P, (const double*)cpd,
+                       (const double*)invm, X, (const double*)q, (const double*)deff, alpha0, V, K, Yout);
+    return check_launch("k_lda_m2_apply");
+  };
+  // Q = orth(Yin)
+  auto orth = [&](const double* Yin, double* Qout) -> tsk_status {
+    hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, Yin, Yin, Gm, V, K);
+    TSK_TRY(check_launch("k_gram2"));
+    TSK_TRY(jacobi_eig(Gm, K, E, dv, st));
+    hipLaunchKernelGGL(tsk::k_orth_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, Yin, (const double*)E,
+                       (const double*)dv, Qout, V, K);
+    return check_launch("k_orth_apply");
+  };
+  TSK_TRY(apply(Omega, Y));
+  for (int it = 0; it < iters; ++it) {
+    TSK_TRY(orth(Y, Q));
+    TSK_TRY(apply(Q, Y));
+  }
+  TSK_TRY(orth(Y, Q));
+  TSK_TRY(apply(Q, Y));
+  hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, (const double*)Q, (const double*)Y, Gm, V, K);
+  TSK_TRY(check_launch("k_gram2"));
+  TSK_TRY(jacobi_eig(Gm, K, E, dv, st));
+  hipLaunchKernelGGL(tsk::k_whiten_out, dim3(std::min(V, 8192)), dim3(128), 0, st, (const double*)Q,
+                     (const double*)E, (const double*)dv, W_out, sigma_out, V, K);
+  return check_launch("k_whiten_out");
+}
+
+extern "C" tsk_status tsk_lda_recover(tsk_ctx_t ctx, int V, int K, int k, double alpha0, const double* W,
+                                      const double* lam, const double* U, double* alpha_out, double* mu_out,
+                                      void* stream) {
+  if (!ctx || !W || !lam || !U || !alpha_out || !mu_out) return tsk::fail(TSK_EINVAL, "tsk_lda_recover: null argument");
+  if (K < 1 || K > 100 || V < 1 || k < 1) return tsk::fail(TSK_EINVAL, "tsk_lda_recover: V=%d, K=%d, k=%d", V, K, k);
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  void* base = nullptr;
+  const size_t kk = ((size_t)K * K * 8 + 255) & ~(size_t)255, kv = ((size_t)K * 8 + 255) & ~(size_t)255;
+  const size_t tv = ((size_t)k * K * 8 + 255) & ~(size_t)255;
+  TSK_TRY(ws_get(ctx, WS_LDAR, 2 * kk + kv + tv, &base));
+  double* Gm = (double*)base;
+  double* E = (double*)((char*)base + kk);
+  double* dv = (double*)((char*)base + 2 * kk);
+  double* t = (double*)((char*)base + 2 * kk + kv);
+  hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, W, W, Gm, V, K);
+  TSK_TRY(check_launch("k_gram2"));
+  TSK_TRY(jacobi_eig(Gm, K, E, dv, st));
+  hipLaunchKernelGGL(tsk::k_lda_tvec, dim3(k), dim3(128), 0, st, (const double*)E, (const double*)dv, U, K, t);
+  TSK_TRY(check_launch("k_lda_tvec"));
+  hipLaunchKernelGGL(tsk::k_lda_mu, dim3((V + 255) / 256, k), dim3(256), 0, st, W, (const double*)t, lam, alpha0, V,
+                     K, mu_out, alpha_out);
+  return check_launch("k_lda_mu");
 }

@@ -1,0 +1,106 @@
+"""Parity of the fast spectral LDA pieces (Appendix D, Algorithm 3) with the
+oracle, through the C ABI: whitening of the empirical M2 by randomized
+subspace iteration, recovery of alpha and the topics, and the whole pipeline
+(whitening, document build, decomposition, recovery) on a synthetic corpus.
+
+Bars: whitening against the oracle's identical iteration 1e-9 (sigma, and
+W W^T which is free of the eigenvectors' signs); against the exact truncated
+eigendecomposition 1e-6 after 40 rounds; recovery 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import lda as olda
+from paper_1506_04448_amd.workloads import lda_corpus
+
+torch = pytest.importorskip("torch")
+import paper_1506_04448_amd as tsk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tsk.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _dev(C):
+    return (torch.from_numpy(C.rowptr.astype(np.int32)).to(DEV),
+            torch.from_numpy(C.col.astype(np.int32)).to(DEV),
+            torch.from_numpy(C.cnt.astype(np.int32)).to(DEV))
+
+
+@pytest.mark.parametrize("D,V,K,L", [(400, 60, 5, 40.0), (300, 150, 12, 25.0)])
+def test_whitening_matches_oracle(ctx, D, V, K, L):
+    print(f"whiten D={D} V={V} K={K}", flush=True)
+    C = lda_corpus(D=D, V=V, K=K, seed=D + V, mean_len=L, min_len=1, alpha=0.3)
+    a0 = float(C.alpha.sum())
+    M2 = olda.empirical_m2(C, a0)
+    Om = np.random.default_rng(K).standard_normal((V, K))
+    rp, col, cnt = _dev(C)
+    W, sig = tsk.lda_whiten(ctx, rp, col, cnt, D, V, K, a0, torch.from_numpy(Om).to(DEV), iters=8)
+    W, sig = W.cpu().numpy(), sig.cpu().numpy()
+    Wr, sr = olda.whitening_subspace(M2, Om, 8)
+    np.testing.assert_allclose(sig, sr, rtol=1e-9)
+    P, Pr = W @ W.T, Wr @ Wr.T
+    assert np.abs(P - Pr).max() <= 1e-9 * np.abs(Pr).max()
+    W40, s40 = tsk.lda_whiten(ctx, rp, col, cnt, D, V, K, a0, torch.from_numpy(Om).to(DEV), iters=40)
+    We, se = olda.whitening_exact(M2, K)
+    np.testing.assert_allclose(s40.cpu().numpy(), se, rtol=1e-6)
+    P40 = W40.cpu().numpy() @ W40.cpu().numpy().T
+    assert np.abs(P40 - We @ We.T).max() <= 1e-6 * np.abs(We @ We.T).max()
+
+
+def test_recovery_matches_oracle(ctx):
+    rng = np.random.default_rng(3)
+    V, K, k = 500, 9, 6
+    W = rng.standard_normal((V, K))
+    lam = rng.uniform(0.5, 3.0, k)
+    U = rng.standard_normal((k, K))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    a0 = 1.7
+    alpha, mu = tsk.lda_recover(ctx, torch.from_numpy(W).to(DEV), torch.from_numpy(lam).to(DEV),
+                                torch.from_numpy(U).to(DEV), a0)
+    ra, rmu = olda.recover(lam, U, W, a0)
+    np.testing.assert_allclose(alpha.cpu().numpy(), ra, rtol=1e-12)
+    np.testing.assert_allclose(mu.cpu().numpy(), rmu, rtol=0, atol=1e-10 * np.abs(rmu).max())
+
+
+def test_spectral_lda_pipeline_recovers_topics(ctx):
+    """Algorithm 3 end to end on a synthetic corpus: whitening from the data,
+    sketches of M3(W,W,W), Algorithm 1, recovery; every true topic has a
+    recovered topic vector close to it."""
+    D, V, K = 20000, 200, 6
+    C = lda_corpus(D=D, V=V, K=K, seed=11, mean_len=60.0, beta=0.05, alpha=0.2)
+    a0 = float(C.alpha.sum())
+    rp, col, cnt = _dev(C)
+    Om = torch.from_numpy(np.random.default_rng(1).standard_normal((V, K))).to(DEV)
+    W, sig = tsk.lda_whiten(ctx, rp, col, cnt, D, V, K, a0, Om, iters=6)
+    b, B = 4096, 8
+    h, xi = tsk.hash_generate(5, K, b, B)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_docs(ctx, tab, rp, col, cnt, V, W, a0, S64, S32)
+    lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, K, 30, 30, dtype=tsk.F64, seed=3)
+    alpha, mu = tsk.lda_recover(ctx, W, lam, U, a0)
+    mu = mu.cpu().numpy()
+    Phi = C.Phi.T
+    # cosine similarity of every true topic with its best recovered topic
+    cos = (Phi / np.linalg.norm(Phi, axis=1, keepdims=True)) @ (mu / np.linalg.norm(mu, axis=1, keepdims=True)).T
+    assert np.all(cos.max(axis=1) > 0.9), cos.max(axis=1)
+    tab.close()
+
+
+def test_lda_argument_errors(ctx):
+    z = torch.zeros(3, dtype=torch.int32, device=DEV)
+    Om = torch.zeros((10, 101), dtype=torch.float64, device=DEV)
+    with pytest.raises(tsk.TskError, match="K=101"):
+        tsk.lda_whiten(ctx, z, z, z, 2, 10, 101, 1.0, Om)
+    Om = torch.zeros((10, 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(tsk.TskError, match="alpha0"):
+        tsk.lda_whiten(ctx, z, z, z, 2, 10, 3, -1.0, Om)
