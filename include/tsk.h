@@ -245,10 +245,11 @@ void tsk_sym_tables_destroy(tsk_sym_tables_t tab);
 
 /* Dense build of Eq. (5) from the entries with i <= j <= k (each weighted by
  * the number of distinct permutations of its index triple; for a symmetric
- * tensor this is the sum over all entries), FP64 atomics (summation order
- * varies between runs), then S64 = F(s64), S32 = (float)S64, s32 =
- * (float)s64 (s32, S32 nullable).  T: [n][n][n] row-major, float or double
- * by dtype.  accumulate != 0 adds to s64. */
+ * tensor this is the sum over all entries), accumulated in 64-bit fixed point
+ * (a power-of-two scale from max |T|; repeated builds are bit-identical),
+ * then S64 = F(s64), S32 = (float)S64, s32 = (float)s64 (s32, S32
+ * nullable).  T: [n][n][n] row-major, float or double by dtype.
+ * accumulate != 0 adds to s64.  A non-finite entry makes the sketch NaN. */
 tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t tab, const void* T,
                                       tsk_dtype dtype, double* s64, float* s32, double* S64,
                                       float* S32, int accumulate, void* stream);

@@ -2092,6 +2092,74 @@ tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, cons
 
 }  // namespace
 
+namespace {
+
+// The fixed-point LDS build of the symmetric sketches into s64 (written, or
+// added to with accumulate): the plan of the asymmetric dense build with
+// 2b real bins per sketch and the index pairs i <= j.
+template <typename TIn>
+tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, double* s64, int accumulate,
+                          hipStream_t st) {
+  const int n = tab->n, b = tab->b, B = tab->B;
+  const int b2 = 2 * b;
+  const int nrange = b2 > 16384 ? b2 / 16384 : 1;
+  const int br = b2 / nrange;
+  int lbr = 0;
+  while ((1 << lbr) < br) ++lbr;
+  const int Bv = B * nrange;
+  const size_t per_sketch = (size_t)br * 8 + (size_t)4 * n;
+  if (per_sketch > (size_t)kBuildPoolLarge * 8)
+    return tsk::fail(TSK_EUNSUPPORTED, "symmetric build: b=%d, n=%d exceed one CU's LDS", b, n);
+  const bool small = (size_t)Bv * per_sketch <= (size_t)kBuildPoolSmall * 8;
+  const size_t pool = (size_t)(small ? kBuildPoolSmall : kBuildPoolLarge) * 8;
+  int G = nrange > 1 ? 1 : (int)std::min<size_t>((size_t)B, pool / per_sketch);
+  const int ngroups = (Bv + G - 1) / G;
+  G = (Bv + ngroups - 1) / ngroups;
+  const long long npairs = (long long)n * (n + 1) / 2;
+  const int slots = 32 * (small ? 2 : 1);
+  const int nslab = (int)std::min<long long>(std::max<long long>(1, npairs / 8), 8LL * std::max(1, slots / ngroups));
+  void* partial = nullptr;
+  void* stime = nullptr;
+  void* amax = nullptr;
+  TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * br * sizeof(double), &partial));
+  TSK_TRY(ws_get(ctx, WS_STIME, (size_t)B * b2 * sizeof(double), &stime));
+  TSK_TRY(ws_get(ctx, WS_AMAX, sizeof(unsigned long long), &amax));
+  hipLaunchKernelGGL(tsk::k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(amax), 0u, (size_t)2);
+  TSK_TRY(check_launch("k_fill_u32"));
+  const size_t cnt = (size_t)n * n * n;
+  hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3((int)std::min<size_t>(1024, (cnt + 1023) / 1024)), dim3(256), 0, st,
+                     T, cnt, reinterpret_cast<unsigned long long*>(amax));
+  TSK_TRY(check_launch("k_absmax"));
+  tsk::SymBuildArgs<TIn> a;
+  a.T = T;
+  a.n = n;
+  a.b = b;
+  a.B = B;
+  a.G = G;
+  a.nrange = nrange;
+  a.lbr = lbr;
+  a.hq = tab->hq;
+  a.npairs = npairs;
+  a.nslab = nslab;
+  a.ngroups = ngroups;
+  a.absmax = reinterpret_cast<const unsigned long long*>(amax);
+  a.partial = reinterpret_cast<double*>(partial);
+  const int nblk = 8 * ngroups * ((nslab + 7) / 8);
+  if (small)
+    hipLaunchKernelGGL((tsk::k_sym_build<TIn, kBuildPoolSmall>), dim3(nblk), dim3(1024), 0, st, a);
+  else
+    hipLaunchKernelGGL((tsk::k_sym_build<TIn, kBuildPoolLarge>), dim3(nblk), dim3(1024), 0, st, a);
+  TSK_TRY(check_launch("k_sym_build"));
+  hipLaunchKernelGGL(tsk::k_build_reduce, dim3(grid_for((size_t)B * b2, 256)), dim3(256), 0, st,
+                     (const double*)partial, (double*)stime, b2, B, G, nslab, nrange, lbr);
+  TSK_TRY(check_launch("k_build_reduce"));
+  hipLaunchKernelGGL(tsk::k_add64, dim3(grid_for((size_t)B * b2, 256)), dim3(256), 0, st, s64,
+                     (const double*)stime, (size_t)B * b2, accumulate ? 1 : 0);
+  return check_launch("k_add64");
+}
+
+}  // namespace
+
 extern "C" tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t tab, const void* T,
                                                  tsk_dtype dtype, double* s64, float* s32, double* S64,
                                                  float* S32, int accumulate, void* stream) {
@@ -2102,19 +2170,9 @@ extern "C" tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t
   hipStream_t st = S(stream);
   const int n = tab->n, b = tab->b, B = tab->B;
   const size_t cplx = (size_t)B * b;
-  if (!accumulate) {
-    hipLaunchKernelGGL(tsk::k_fill_u32, dim3(grid_for(4 * cplx, 256)), dim3(256), 0, st,
-                       reinterpret_cast<unsigned*>(s64), 0u, 4 * cplx);
-    TSK_TRY(check_launch("k_fill_u32"));
-  }
-  const long long pairs = (long long)n * (n + 1) / 2;
-  const int gx = (int)std::max(1LL, std::min(2048LL, (pairs + 3) / 4));
-  if (dtype == TSK_F32)
-    hipLaunchKernelGGL(tsk::k_sym_build<float>, dim3(gx, B), dim3(256), 0, st, (const float*)T, tab->hq, n, b, s64);
-  else
-    hipLaunchKernelGGL(tsk::k_sym_build<double>, dim3(gx, B), dim3(256), 0, st, (const double*)T, tab->hq, n, b,
-                       s64);
-  TSK_TRY(check_launch("k_sym_build"));
+  (void)n;
+  if (dtype == TSK_F32) TSK_TRY(sym_build_impl<float>(ctx, tab, (const float*)T, s64, accumulate, st));
+  else TSK_TRY(sym_build_impl<double>(ctx, tab, (const double*)T, s64, accumulate, st));
   if (s32) {
     hipLaunchKernelGGL(tsk::k_c64to32, dim3(grid_for(cplx, 256)), dim3(256), 0, st,
                        reinterpret_cast<const cx<double>*>(s64), reinterpret_cast<cx<float>*>(s32), cplx);
