@@ -58,6 +58,23 @@ def test_sym_build_matches_eq5(ctx, n, b, B, dt):
     tab.close()
 
 
+def test_sym_build_is_deterministic_and_accumulates(ctx):
+    n, b, B = 70, 8192, 3
+    P = planted_tensor(n, 3, noise=0.05, seed=4, dtype=np.float32)
+    h, q = sym_tables(4, n, b, B)
+    tab = tsk.SymTables(ctx, h, q, b)
+    Td = torch.from_numpy(P.T).to(DEV)
+    s1 = tsk.new_sym_sketch(tab, DEV)
+    s2 = tsk.new_sym_sketch(tab, DEV)
+    tsk.sym_sketch_build_dense(ctx, tab, Td, *s1)
+    tsk.sym_sketch_build_dense(ctx, tab, Td, *s2)
+    for x, y in zip(s1, s2):
+        assert torch.equal(x, y)
+    tsk.sym_sketch_build_dense(ctx, tab, Td, *s2, accumulate=True)
+    assert torch.equal(s2[0], 2 * s1[0])
+    tab.close()
+
+
 @pytest.mark.parametrize("n,b,B,L", [(9, 256, 3, 2), (100, 2048, 3, 4), (200, 16384, 2, 3), (1000, 8192, 2, 2)])
 def test_sym_tiuu_matches_appendix_b(ctx, n, b, B, L):
     print(f"sym tiuu n={n} b={b}", flush=True)
