@@ -104,8 +104,12 @@ void tsk_tables_destroy(tsk_tables_t tab);
  * xi1(i) xi2(j) xi3(k) T_ijk, for every m; then S64 = F(s) and S32 = (float)S64.
  * T: [n][n][n] row-major, float (TSK_F32) or double (TSK_F64), n = tables' n.
  * accumulate != 0 adds to S64 instead of overwriting it (the sketch is linear
- * in T, Section 3.1).  FP32 input is accumulated in FP32 inside a work-group
- * and summed across work-groups in FP64. */
+ * in T, Section 3.1).  Each work-group sums its share of T in 64-bit fixed
+ * point (scaled from max |T| so that nothing overflows; repeated builds are
+ * bit-identical) and the shares are summed in FP64.  A non-finite entry of T
+ * makes every bucket NaN.  The first dense build with a table set also makes
+ * its per-fibre offsets (4 B n^2 bytes of device memory, held until
+ * tsk_tables_destroy) and waits for its stream once. */
 tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, const void* T,
                                   tsk_dtype dtype, double* S64, float* S32,
                                   int accumulate, void* stream);

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft.hpp"
 
 namespace tsk {
@@ -986,69 +988,162 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_c2r64(const
 }
 
 // ---------------------------------------------------------------------------
-// Dense build, Eq. (1).  Work-group (slab, group): the G sketches of `group`
-// accumulate a contiguous slab of (i, j) fibres of T in LDS bins, then write
-// the bins as one FP64 partial sum.  Each wave takes two fibres T[i][j][:] at
-// a time with its lanes along k (coalesced reads); the fibre offsets
-// h1(i) + h2(j) are wave-uniform.
+// Dense build, Eq. (1).  Work-group (slab, group): the G <= 2 sketches of
+// `group` accumulate a contiguous slab of (i, j) fibres of T in LDS bins,
+// then write the bins as one FP64 partial sum.  A wave takes four fibres
+// T[i][j][:] at a time with its lanes along k in chunks of 64 (coalesced
+// reads) and loads the next four while it scatters the current ones.  The
+// offsets and signs of the fibres' first two modes come precomputed
+// (k_fibre_offsets) and those of the third mode stay in registers, so every
+// load of the loop is a buffer load from loop-invariant lane offsets.
 //
 // Bins are 64-bit fixed point: integer LDS atomics are an order of magnitude
 // faster than floating-point ones on this chip, and integer sums do not
-// depend on the order of the adds.  Each work-group scales its slab by 2^F
-// with F chosen from the slab's largest |T| and element count so that no bin
-// can overflow; a slab with a non-finite entry writes NaN partials.
+// depend on the order of the adds.  Each work-group scales its slab by 2^F,
+// with F chosen from max |T| and the slab's element count so that no bin can
+// overflow and no scaled entry reaches 2^50; a tensor with a non-finite
+// entry writes NaN partials.
 // ---------------------------------------------------------------------------
+constexpr int kBuildMaxG = 2;
+
 template <typename TIn>
 struct BuildArgs {
   const TIn* T;
   int n, b, B, G;
   int nrange, lbr;            // bucket ranges per sketch, log2 of their length
   const uint32_t* hx;         // [B][3][n]
-  long long pairs_per_slab;
+  const uint32_t* ef;         // [B][efs] fibre offsets, k_fibre_offsets
+  long long efs;              // row length of ef (>= n^2 + 4, multiple of 4)
+  long long pairs_per_slab;   // multiple of 4
   int nslab, ngroups;
-  const unsigned long long* absmax;  // bits of max |T| (a non-negative double)
+  const unsigned long long* absmax;  // [nabs] per-block max |T| of k_absmax
+  int nabs;
   double* partial;            // [ngroups][nslab][G][b]
 };
 
-// *out = bits of max |T| over `count` entries (non-negative doubles compare
-// like their bit patterns; NaN and Inf compare above every finite value).
-// *out must start at 0.
+// A table entry (h << 1 | sign bit) as the byte offset of a 64-bit bin with
+// the sign in bit 31: the sum of three such values is the bin's byte offset
+// before the modulo (below 2^21) with the product of the signs in bit 31.
+__device__ __forceinline__ uint32_t bin_code(uint32_t e) { return ((e >> 1) << 3) | (e << 31); }
+
+// ef[m][i n + j] = code of h1(i) + code of h2(j) for sketch m; the padding
+// entries are zero.
+__global__ void k_fibre_offsets(const uint32_t* __restrict__ hx, int n, int B, long long efs,
+                                uint32_t* __restrict__ ef) {
+  const long long nn = (long long)n * n;
+  const long long total = (long long)B * efs;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(e / efs);
+    const long long p = e - (long long)m * efs;
+    uint32_t v = 0;
+    if (p < nn) {
+      const int i = (int)(p / n), j = (int)(p - (long long)i * n);
+      const uint32_t* hm = hx + (size_t)m * 3 * n;
+      v = bin_code(hm[i]) + bin_code(hm[n + j]);
+    }
+    ef[e] = v;
+  }
+}
+
+// out[blockIdx.x] = max |T| over this block's share of the `count` entries,
+// as the bits of a non-negative double (Inf when the share holds a NaN or an
+// Inf).  No atomics: the consumers reduce the per-block values themselves.
 template <typename TIn>
 __global__ __launch_bounds__(256) void k_absmax(const TIn* __restrict__ T, size_t count,
                                                 unsigned long long* out) {
   double m = 0.0;
   bool bad = false;
-  const size_t stride = (size_t)gridDim.x * 256;
-  size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  for (; e + 3 * stride < count; e += 4 * stride) {
-    const double x0 = fabs((double)T[e]), x1 = fabs((double)T[e + stride]);
-    const double x2 = fabs((double)T[e + 2 * stride]), x3 = fabs((double)T[e + 3 * stride]);
-    bad |= !(x0 < __builtin_inf()) || !(x1 < __builtin_inf()) || !(x2 < __builtin_inf()) ||
-           !(x3 < __builtin_inf());
-    m = fmax(fmax(m, x0), fmax(fmax(x1, x2), x3));
-  }
-  for (; e < count; e += stride) {
-    const double x = fabs((double)T[e]);
+  auto take = [&](double x) {
+    x = fabs(x);
     bad |= !(x < __builtin_inf());
     m = fmax(m, x);
+  };
+  const size_t stride = (size_t)gridDim.x * 256;
+  const size_t first = (size_t)blockIdx.x * 256 + threadIdx.x;
+  size_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(T) & 15) == 0) {
+    // 16-byte loads, four in flight per thread
+    constexpr int W = 16 / (int)sizeof(TIn);
+    using V = typename std::conditional<sizeof(TIn) == 4, float4, double2>::type;
+    const V* Tv = reinterpret_cast<const V*>(T);
+    const size_t nv = count / W;
+    auto take_v = [&](const V& v) {
+      if constexpr (sizeof(TIn) == 4) {
+        take(v.x); take(v.y); take(v.z); take(v.w);
+      } else {
+        take(v.x); take(v.y);
+      }
+    };
+    size_t e = first;
+    for (; e + 3 * stride < nv; e += 4 * stride) {
+      const V a0 = Tv[e], a1 = Tv[e + stride], a2 = Tv[e + 2 * stride], a3 = Tv[e + 3 * stride];
+      take_v(a0); take_v(a1); take_v(a2); take_v(a3);
+    }
+    for (; e < nv; e += stride) take_v(Tv[e]);
+    done = nv * W;
   }
+  for (size_t e = done + first; e < count; e += stride) take((double)T[e]);
   if (bad) m = __builtin_inf();
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o));
   __shared__ double wm[4];
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double r = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
-    atomicMax(out, (unsigned long long)__double_as_longlong(r));
-  }
+  if (threadIdx.x == 0)
+    out[blockIdx.x] = (unsigned long long)__double_as_longlong(fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3])));
 }
 
-// One static pool of POOL 64-bit words: the G sketches' bins (G*b) followed by
-// the three modes' table entries of those sketches ([G][3][n] 32-bit words).
-template <typename TIn, int POOL>
+// The largest of the np per-block values of k_absmax, in every thread of
+// the work-group (red: 16 words of LDS; contains a barrier).
+__device__ inline double reduce_absmax(const unsigned long long* p, int np, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v = fmax(v, __longlong_as_double((long long)p[i]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+  return v;
+}
+
+// Fixed-point scale exponent F of a slab of `count` entries with max |T| = m:
+// count * m * 2^F < 2^62 (no bin overflows) and m * 2^F <= 2^50 (the
+// rounding below is exact), clamped to where 2^F is a normal double.
+__device__ inline int fixed_scale(double m, long long count) {
+  int e2 = 0, em = 0;
+  (void)frexp(m * (double)count * 2.0, &e2);
+  (void)frexp(m, &em);
+  return m > 0.0 ? max(-1000, min(1000, min(62 - e2, 50 - em))) : 0;
+}
+
+// round(x * 2^F) as a 64-bit two's-complement integer for |x * 2^F| <= 2^50:
+// adding 1.5 * 2^52 rounds the product to an integer (ties to even, as
+// rint) and leaves it in the low mantissa bits; the constant's low word is
+// zero, so removing it touches only the high word.
+__device__ __forceinline__ unsigned long long to_fixed(double x, double up) {
+  const double d = fma(x, up, 6755399441055744.0);
+  const uint32_t lo = (uint32_t)__double2loint(d);
+  const uint32_t hi = (uint32_t)__double2hiint(d) - 0x43380000u;
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// x with its sign flipped where bit 31 of s is set
+__device__ __forceinline__ double signed_in(float x, uint32_t s) {
+  return (double)__uint_as_float(__float_as_uint(x) ^ (s & 0x80000000u));
+}
+__device__ __forceinline__ double signed_in(double x, uint32_t s) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  return __longlong_as_double((long long)(u ^ ((unsigned long long)(s & 0x80000000u) << 32)));
+}
+
+// One static pool of POOL 64-bit words holds the G sketches' bins (G*b).
+// SPLIT: the sketch is longer than one bucket range (then G = 1).
+template <typename TIn, int POOL, bool SPLIT>
 __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   __shared__ __align__(16) unsigned long long pool[POOL];
+  __shared__ double red[16];
   const int n = a.n, b = a.b, G = a.G;
   // Work-groups of one slab (all groups) are numbered consecutively within
   // one XCD (block ids are dealt round-robin over the 8 XCDs), so the slab's
@@ -1065,77 +1160,117 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   const int br = 1 << a.lbr;
   const int sk0 = g0 / a.nrange, rq = g0 % a.nrange;
   unsigned long long* bins = pool;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(pool + (size_t)G * br);
   const int tid = threadIdx.x;
   for (int t = tid; t < G * br; t += blockDim.x) bins[t] = 0ull;
-  for (int t = tid; t < Gc * 3 * n; t += blockDim.x) tab[t] = a.hx[(size_t)sk0 * 3 * n + t];
 
   const long long npairs = (long long)n * n;
   const long long p0 = (long long)slab * a.pairs_per_slab;
   const long long p1 = min(npairs, p0 + a.pairs_per_slab);
-  // Scale 2^F: |bin| <= (entries in the slab) * max|T| * 2^F < 2^62, with F
-  // kept where 2^F is a normal double.
-  const double m = __longlong_as_double((long long)*a.absmax);
+  const double m = reduce_absmax(a.absmax, a.nabs, red);  // contains a barrier
   const bool bad = !(m < __builtin_inf());
-  int e2 = 0;
-  (void)frexp(m * (double)((p1 - p0) * n) * 2.0, &e2);
-  const int F = (m > 0.0 && !bad) ? max(-1000, min(1000, 62 - e2)) : 0;
+  const int F = bad ? 0 : fixed_scale(m, (p1 - p0) * n);
   const double up = ldexp(1.0, F), down = ldexp(1.0, -F);
   __syncthreads();
 
   if (!bad) {
     const int lane = tid & 63;
     const int nw = blockDim.x >> 6;
-    const unsigned bmask = (unsigned)b - 1u;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-    constexpr int NF = 4;  // fibres per wave iteration
-    for (long long q0 = p0 + NF * wv; q0 < p1; q0 += NF * nw) {
-      const int nf = (int)min((long long)NF, p1 - q0);
-      const TIn* f0 = a.T + q0 * n;
-      int ii[NF], jj[NF];
-      ii[0] = (int)(q0 / n);
-      jj[0] = (int)(q0 - (long long)ii[0] * n);
+    constexpr int NF = 4;   // fibres per item
+    constexpr int NC = 4;   // chunks of 64 lanes along k per item
+    constexpr int GM = kBuildMaxG;
+    constexpr unsigned SZ = sizeof(TIn);
+    const uint32_t pmask = ((uint32_t)b - 1u) << 3;
+    const uint32_t lmask = ((uint32_t)br - 1u) << 3;
+    const long long step = (long long)NF * nw;
+    const __amdgpu_buffer_rsrc_t efr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(a.ef + (size_t)sk0 * a.efs), 0, (int)(Gc * a.efs * 4), kBufferWord3);
+    // The item of fibres q .. q+3: their ef words (per sketch) and entries.
+    struct Item {
+      uint32_t ef[GM][NF];
+      TIn x[NF][NC];
+    };
+    for (int kb = 0; kb < n; kb += 64 * NC) {
+      unsigned voff[NC];
+      bool kin[NC];
+      uint32_t e3[GM][NC];
 #pragma unroll
-      for (int f = 1; f < NF; ++f) {
-        const bool wrap = jj[f - 1] + 1 == n;
-        ii[f] = wrap ? ii[f - 1] + 1 : ii[f - 1];
-        jj[f] = wrap ? 0 : jj[f - 1] + 1;
+      for (int c = 0; c < NC; ++c) {
+        const int k = kb + 64 * c + lane;
+        kin[c] = k < n;
+        voff[c] = (unsigned)min(k, n - 1) * SZ;
+#pragma unroll
+        for (int g = 0; g < GM; ++g)
+          e3[g][c] = g < Gc ? bin_code(a.hx[((size_t)(sk0 + g) * 3 + 2) * n + min(k, n - 1)]) : 0u;
       }
-      for (int kb = 0; kb < n; kb += 128) {
-        // every load of this block of the fibres before the atomics
-        long long x[NF][2];
+      // Every variable offset is a lane offset, which the buffer range check
+      // covers: a fibre past the slab gets a resource of zero bytes.
+      auto load = [&](long long q, Item& it) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int k = kb + lane + 64 * c;
-            x[f][c] = (f < nf && k < n) ? __double2ll_rn((double)f0[(size_t)f * n + k] * up) : 0ll;
+        for (int g = 0; g < GM; ++g) {
+          if (g < Gc) {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b128(
+                efr, (unsigned)((g * a.efs + min(q, a.efs - NF)) * 4), 0u, 0);
+            it.ef[g][0] = w[0];
+            it.ef[g][1] = w[1];
+            it.ef[g][2] = w[2];
+            it.ef[g][3] = w[3];
           }
-        for (int g = 0; g < Gc; ++g) {
-          const uint32_t* tg = tab + g * 3 * n;
-          unsigned long long* bg = bins + (size_t)g * br;
-          uint32_t off[NF];  // (h1(i) + h2(j)) << 1 | sign bit, per fibre
+        }
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            const uint32_t ea = tg[ii[f]], eb = tg[n + jj[f]];
-            off[f] = (((ea >> 1) + (eb >> 1)) << 1) | ((ea ^ eb) & 1u);
+        for (int f = 0; f < NF; ++f) {
+          const bool live = q + f < p1;
+          const __amdgpu_buffer_rsrc_t tr = __builtin_amdgcn_make_buffer_rsrc(
+              const_cast<TIn*>(a.T) + (size_t)(live ? q + f : 0) * n, 0, live ? (int)(n * SZ) : 0,
+              kBufferWord3);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            if constexpr (sizeof(TIn) == 4)
+              it.x[f][c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(tr, voff[c], 0u, 0));
+            else
+              it.x[f][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(tr, voff[c], 0u, 0));
           }
+        }
+      };
+      long long q0 = p0 + NF * wv;
+      Item cur;
+      load(q0, cur);
+      while (q0 < p1) {
+        const long long qn = q0 + step;
+        Item nxt;
+        load(qn, nxt);
+        const int nf = (int)min((long long)NF, p1 - q0);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int k = kb + lane + 64 * c;
-            if (k < n) {
-              const uint32_t e3 = tg[2 * n + k];
+        for (int g = 0; g < GM; ++g) {
+          if (g < Gc) {
+            const uint32_t gbase = SPLIT ? 0u : (uint32_t)g * (uint32_t)br * 8u;
 #pragma unroll
-              for (int f = 0; f < NF; ++f) {
-                if (f < nf) {
-                  const uint32_t t = ((off[f] >> 1) + (e3 >> 1)) & bmask;
-                  const long long v = ((off[f] ^ e3) & 1u) ? -x[f][c] : x[f][c];
-                  if ((int)(t >> a.lbr) == rq) atomicAdd(&bg[t & (unsigned)(br - 1)], (unsigned long long)v);
+            for (int c = 0; c < NC; ++c) {
+              if (kin[c]) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                  if (f < nf) {
+                    const uint32_t sg = cur.ef[g][f] + e3[g][c];
+                    const unsigned long long v = to_fixed(signed_in(cur.x[f][c], sg), up);
+                    const uint32_t t8 = sg & pmask;
+                    if (SPLIT) {
+                      if ((int)(t8 >> (a.lbr + 3)) == rq)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(
+                                      reinterpret_cast<unsigned char*>(bins) + (t8 & lmask)),
+                                  v);
+                    } else {
+                      atomicAdd(reinterpret_cast<unsigned long long*>(
+                                    reinterpret_cast<unsigned char*>(bins) + (t8 | gbase)),
+                                v);
+                    }
+                  }
                 }
               }
             }
           }
         }
+        cur = nxt;
+        q0 = qn;
       }
     }
   }

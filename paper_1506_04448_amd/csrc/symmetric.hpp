@@ -80,7 +80,8 @@ struct SymBuildArgs {
   const uint32_t* hq;         // [B][n]
   long long npairs;
   int nslab, ngroups;
-  const unsigned long long* absmax;
+  const unsigned long long* absmax;  // [nabs] per-block max |T| of k_absmax
+  int nabs;
   double* partial;            // [ngroups][nslab][G][2^lbr]
 };
 
@@ -104,7 +105,8 @@ __global__ __launch_bounds__(1024) void k_sym_build(SymBuildArgs<TIn> a) {
   for (int t = tid; t < Gc * n; t += blockDim.x) tab[t] = a.hq[(size_t)sk0 * n + t];
   // scale 2^F: |bin| <= 6 max|T| (entries of the slab) 2^F < 2^62
   const long long pairs_here = (a.npairs - slab + a.nslab - 1) / a.nslab;
-  const double m = __longlong_as_double((long long)*a.absmax);
+  __shared__ double red[16];
+  const double m = reduce_absmax(a.absmax, a.nabs, red);
   const bool bad = !(m < __builtin_inf());
   int e2 = 0;
   (void)frexp(m * 6.0 * (double)(pairs_here * n) * 2.0, &e2);

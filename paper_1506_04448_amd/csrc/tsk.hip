@@ -53,6 +53,7 @@ constexpr int kMaxLogB = 16;
 // are split by residue into sub-transforms of 2^kSubLogM64 points (large.hpp).
 constexpr int kLdsLogB = 14;
 constexpr int kSubLogM64 = 13;
+constexpr int kSubLogM64Mid = 11;  // forward FP64 transforms at b = 16384
 constexpr int kSubLogM32 = 14;     // FP32 power steps at b = 65536
 
 int ilog2_exact(int b) {
@@ -96,6 +97,10 @@ struct tsk_tables {
   uint32_t* hx = nullptr;
   uint32_t* hxs = nullptr;
   uint32_t* ord = nullptr;
+  // Bin offsets of the first two modes per (i, j) fibre and sketch, made by
+  // the first dense build ([B][efs] words).
+  uint32_t* ef = nullptr;
+  long long efs = 0;
 };
 
 // Colliding-hash tables: one (h, q) per index and sketch, plus the entries
@@ -477,20 +482,28 @@ tsk_status launch_rank1_any(tsk_ctx_t ctx, tsk_tables_t tab, const tsk::Rank1Arg
 // Time domain -> half spectrum (FP64) at any supported b.
 tsk_status r2c_any(tsk_ctx_t ctx, int logb, const double* s, cx<double>* S64, cx<float>* S32, int acc,
                    int B, hipStream_t st) {
-  if (logb <= kLdsLogB) {
+  if (logb < kLdsLogB) {
     const cx<double>* tw = nullptr;
     TSK_TRY(get_tw<double>(ctx, logb, &tw));
     return launch_r2c(logb, s, S64, S32, tw, acc, B, st);
   }
-  const int Rr = sub_R64(logb), M = 1 << kSubLogM64, b = 1 << logb;
+  // At b = 16384 the transform still fits one work-group, but B work-groups
+  // leave the chip idle: four sub-transforms per sketch finish sooner.
+  const int logm = logb > kLdsLogB ? kSubLogM64 : kSubLogM64Mid;
+  const int Rr = 1 << (logb - 1 - logm), M = 1 << logm, b = 1 << logb;
+  const int nt = tsk::threads_for_h<double>(logm);
   const cx<double>* twM = nullptr;
   const cx<double>* Wb = nullptr;
-  TSK_TRY(get_tw<double>(ctx, kSubLogM64 + 1, &twM, tsk::threads_for_h<double>(kSubLogM64)));
+  TSK_TRY(get_tw<double>(ctx, logm + 1, &twM, nt));
   TSK_TRY(get_wb<double>(ctx, logb, &Wb));
   void* E = nullptr;
   TSK_TRY(ws_get(ctx, WS_SPLITP, (size_t)B * Rr * M * sizeof(cx<double>), &E));
-  hipLaunchKernelGGL((tsk::k_sub_gather64<kSubLogM64>), dim3(B, Rr),
-                     dim3(tsk::threads_for_h<double>(kSubLogM64)), 0, st, s, b, Rr, twM, (cx<double>*)E);
+  if (logm == kSubLogM64)
+    hipLaunchKernelGGL((tsk::k_sub_gather64<kSubLogM64>), dim3(B, Rr), dim3(nt), 0, st, s, b, Rr, twM,
+                       (cx<double>*)E);
+  else
+    hipLaunchKernelGGL((tsk::k_sub_gather64<kSubLogM64Mid>), dim3(B, Rr), dim3(nt), 0, st, s, b, Rr, twM,
+                       (cx<double>*)E);
   TSK_TRY(check_launch("k_sub_gather64"));
   hipLaunchKernelGGL(tsk::k_combine_r2c, dim3(grid_for((size_t)B * (b / 2 + 1), 256)), dim3(256), 0, st,
                      (const cx<double>*)E, B, b, M, Rr, Wb, acc, S64, S32);
@@ -661,6 +674,7 @@ extern "C" void tsk_tables_destroy(tsk_tables_t t) {
   // reuse the handle's address and match their keys.
   clear_graphs(t->ctx);
   (void)hipFree(t->hx);
+  if (t->ef) (void)hipFree(t->ef);
   delete t;
 }
 
@@ -675,6 +689,11 @@ namespace {
 constexpr int kBuildPoolLarge = (159 * 1024) / 8;  // leaves room for the reduction scratch
 constexpr int kBuildPoolSmall = (20 * 1024) / 8;
 
+// Blocks of the max |T| pass: about 16 KB of T per block, at most 512.
+int absmax_blocks(size_t count) {
+  return (int)std::max<size_t>(1, std::min<size_t>(512, (count + 4095) / 4096));
+}
+
 template <typename TIn>
 tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipStream_t st,
                             double** s_time_out) {
@@ -686,37 +705,54 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   int lbr = 0;
   while ((1 << lbr) < br) ++lbr;
   const int Bv = B * nrange;                                  // (sketch, range) pairs
-  const size_t per_sketch = (size_t)br * 8 + (size_t)12 * n;  // bins + 3 table words
-  if (per_sketch > (size_t)kBuildPoolLarge * 8)
-    return tsk::fail(TSK_EUNSUPPORTED, "dense build: b=%d, n=%d exceed one CU's LDS", b, n);
-  const bool small = (size_t)Bv * per_sketch <= (size_t)kBuildPoolSmall * 8;
-  const size_t pool = (size_t)(small ? kBuildPoolSmall : kBuildPoolLarge) * 8;
-  int G = nrange > 1 ? 1 : (int)std::min<size_t>((size_t)B, pool / per_sketch);
+  const size_t per_sketch = (size_t)br * 8;  // 64-bit bins
+  int G = nrange > 1 ? 1
+                     : (int)std::min<size_t>({(size_t)B, (size_t)tsk::kBuildMaxG,
+                                              (size_t)kBuildPoolLarge * 8 / per_sketch});
   const int ngroups = (Bv + G - 1) / G;
   G = (Bv + ngroups - 1) / ngroups;  // balance the groups
+  const bool small = (size_t)G * per_sketch <= (size_t)kBuildPoolSmall * 8;
   const long long npairs = (long long)n * n;
   // Slabs come in multiples of 8 (one per XCD lane of the grid mapping), as
   // many as fill each XCD's 32 CUs in one round (one work-group per CU with
   // the large pool, two with the small one), never slabs of fewer than 8
-  // fibres.
+  // fibres; slab lengths are multiples of 4 fibres (the kernel's items).
   const int slots = 32 * (small ? 2 : 1);
   int nslab = (int)std::min<long long>(std::max<long long>(1, npairs / 8),
                                        8LL * std::max(1, slots / ngroups));
-  const long long pps = (npairs + nslab - 1) / nslab;
+  long long pps = (npairs + nslab - 1) / nslab;
+  pps = (pps + 3) / 4 * 4;
   nslab = (int)((npairs + pps - 1) / pps);
+  // Offsets of the first two modes per fibre and sketch: made once per table
+  // set, on the first dense build, and complete before that call returns (a
+  // later build may run on another stream).
+  const long long efs = (npairs + 4 + 3) / 4 * 4;
+  if ((size_t)G * efs * 4 > (size_t)0x7fffffff)
+    return tsk::fail(TSK_EUNSUPPORTED, "dense build: n=%d too large", n);
+  if (!tab->ef) {
+    void* d = nullptr;
+    TSK_HIP(hipMalloc(&d, (size_t)B * efs * sizeof(uint32_t)));
+    hipLaunchKernelGGL(tsk::k_fibre_offsets, dim3(grid_for((size_t)B * efs, 256)), dim3(256), 0, st, tab->hx, n,
+                       B, efs, reinterpret_cast<uint32_t*>(d));
+    if (check_launch("k_fibre_offsets") != TSK_OK || hipStreamSynchronize(st) != hipSuccess) {
+      (void)hipFree(d);
+      return tsk::fail(TSK_EHIP, "dense build: fibre offsets failed");
+    }
+    tab->ef = reinterpret_cast<uint32_t*>(d);
+    tab->efs = efs;
+  }
+  const void* efb = tab->ef;
   void* partial = nullptr;
   void* stime = nullptr;
   void* amax = nullptr;
   TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * br * sizeof(double), &partial));
   TSK_TRY(ws_get(ctx, WS_STIME, (size_t)B * b * sizeof(double), &stime));
-  TSK_TRY(ws_get(ctx, WS_AMAX, sizeof(unsigned long long), &amax));
-  // max |T| for the fixed-point scale (a fill kernel clears the slot)
-  hipLaunchKernelGGL(tsk::k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(amax), 0u,
-                     (size_t)2);
-  TSK_TRY(check_launch("k_fill_u32"));
+  // per-block max |T| for the fixed-point scale (reduced by the build)
   const size_t cnt = (size_t)n * n * n;
-  hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3((int)std::min<size_t>(1024, (cnt + 1023) / 1024)),
-                     dim3(256), 0, st, T, cnt, reinterpret_cast<unsigned long long*>(amax));
+  const int nabs = absmax_blocks(cnt);
+  TSK_TRY(ws_get(ctx, WS_AMAX, (size_t)nabs * sizeof(unsigned long long), &amax));
+  hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3(nabs), dim3(256), 0, st, T, cnt,
+                     reinterpret_cast<unsigned long long*>(amax));
   TSK_TRY(check_launch("k_absmax"));
   tsk::BuildArgs<TIn> a;
   a.T = T;
@@ -727,17 +763,22 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   a.nrange = nrange;
   a.lbr = lbr;
   a.hx = tab->hx;
+  a.ef = reinterpret_cast<const uint32_t*>(efb);
+  a.efs = efs;
   a.pairs_per_slab = pps;
   a.nslab = nslab;
   a.ngroups = ngroups;
   a.absmax = reinterpret_cast<const unsigned long long*>(amax);
+  a.nabs = nabs;
   a.partial = reinterpret_cast<double*>(partial);
   // 1-D grid: 8 XCD lanes x ngroups x ceil(nslab / 8) (see the kernel).
   const int nblk = 8 * ngroups * ((nslab + 7) / 8);
   if (small)
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolSmall>), dim3(nblk), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolSmall, false>), dim3(nblk), dim3(1024), 0, st, a);
+  else if (nrange > 1)
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge, true>), dim3(nblk), dim3(1024), 0, st, a);
   else
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge>), dim3(nblk), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge, false>), dim3(nblk), dim3(1024), 0, st, a);
   TSK_TRY(check_launch("k_build_dense"));
   hipLaunchKernelGGL(tsk::k_build_reduce, dim3(grid_for((size_t)B * b, 256)), dim3(256), 0, st,
                      (const double*)partial, (double*)stime, b, B, G, nslab, nrange, lbr);
@@ -2123,12 +2164,11 @@ tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, dou
   void* amax = nullptr;
   TSK_TRY(ws_get(ctx, WS_PARTIAL, (size_t)ngroups * nslab * G * br * sizeof(double), &partial));
   TSK_TRY(ws_get(ctx, WS_STIME, (size_t)B * b2 * sizeof(double), &stime));
-  TSK_TRY(ws_get(ctx, WS_AMAX, sizeof(unsigned long long), &amax));
-  hipLaunchKernelGGL(tsk::k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(amax), 0u, (size_t)2);
-  TSK_TRY(check_launch("k_fill_u32"));
   const size_t cnt = (size_t)n * n * n;
-  hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3((int)std::min<size_t>(1024, (cnt + 1023) / 1024)), dim3(256), 0, st,
-                     T, cnt, reinterpret_cast<unsigned long long*>(amax));
+  const int nabs = absmax_blocks(cnt);
+  TSK_TRY(ws_get(ctx, WS_AMAX, (size_t)nabs * sizeof(unsigned long long), &amax));
+  hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3(nabs), dim3(256), 0, st, T, cnt,
+                     reinterpret_cast<unsigned long long*>(amax));
   TSK_TRY(check_launch("k_absmax"));
   tsk::SymBuildArgs<TIn> a;
   a.T = T;
@@ -2143,6 +2183,7 @@ tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, dou
   a.nslab = nslab;
   a.ngroups = ngroups;
   a.absmax = reinterpret_cast<const unsigned long long*>(amax);
+  a.nabs = nabs;
   a.partial = reinterpret_cast<double*>(partial);
   const int nblk = 8 * ngroups * ((nslab + 7) / 8);
   if (small)
