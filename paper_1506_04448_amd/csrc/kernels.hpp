@@ -1010,21 +1010,39 @@ template <typename TIn>
 struct BuildArgs {
   const TIn* T;
   int n, b, B, G;
-  int nrange, lbr;            // bucket ranges per sketch, log2 of their length
-  const uint32_t* hx;         // [B][3][n]
-  const uint32_t* ef;         // [B][efs] fibre offsets, k_fibre_offsets
-  long long efs;              // row length of ef (>= n^2 + 4, multiple of 4)
-  long long pairs_per_slab;   // multiple of 4
+  int nrange, lbr;            // bin ranges per sketch, log2 of their length
+  const uint32_t* t3;         // third-mode table words of sketch m at t3 + m * t3s
+  int t3s;
+  const uint32_t* ef;         // [B][efs] codes of the fibres' first two modes
+  long long efs;              // row length of ef (>= nfib + 4, multiple of 4)
+  long long nfib;             // fibres: n^2, or the n(n+1)/2 pairs i <= j (SYM)
+  long long pairs_per_slab;   // fibres per slab, a multiple of 4
   int nslab, ngroups;
   const unsigned long long* absmax;  // [nabs] per-block max |T| of k_absmax
   int nabs;
-  double* partial;            // [ngroups][nslab][G][b]
+  double* partial;            // [ngroups][nslab][G][bins]
 };
 
 // A table entry (h << 1 | sign bit) as the byte offset of a 64-bit bin with
 // the sign in bit 31: the sum of three such values is the bin's byte offset
 // before the modulo (below 2^21) with the product of the signs in bit 31.
 __device__ __forceinline__ uint32_t bin_code(uint32_t e) { return ((e >> 1) << 3) | (e << 31); }
+
+// Colliding-hash table word (h << 2 | rotation q) as a code whose sums over
+// three indices carry the summed positions from bit 4 and the summed
+// rotations (at most 9) in bits 0-3: the complex bucket t = positions mod b
+// is stored as real bins 2t (real part) and 2t + 1 (imaginary part), so a
+// rotation r puts the value in bin 2t + (r & 1) with sign (-1)^(r >> 1).
+__device__ __forceinline__ uint32_t sym_code(uint32_t e) { return ((e >> 2) << 4) | (e & 3u); }
+
+// Pair p = j (j + 1) / 2 + i, i <= j.
+__device__ inline void pair_of(long long p, int& i, int& j) {
+  int jj = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while ((long long)(jj + 1) * (jj + 2) / 2 <= p) ++jj;
+  while ((long long)jj * (jj + 1) / 2 > p) --jj;
+  j = jj;
+  i = (int)(p - (long long)jj * (jj + 1) / 2);
+}
 
 // ef[m][i n + j] = code of h1(i) + code of h2(j) for sketch m; the padding
 // entries are zero.
@@ -1138,9 +1156,33 @@ __device__ __forceinline__ double signed_in(double x, uint32_t s) {
   return __longlong_as_double((long long)(u ^ ((unsigned long long)(s & 0x80000000u) << 32)));
 }
 
-// One static pool of POOL 64-bit words holds the G sketches' bins (G*b).
-// SPLIT: the sketch is longer than one bucket range (then G = 1).
-template <typename TIn, int POOL, bool SPLIT>
+// ef[m][p] = sym_code(h(i)) + sym_code(h(j)) for pair p = (i, j) of sketch m
+// (hq: [B][n] colliding-hash words); the padding entries are zero.
+__global__ void k_pair_codes(const uint32_t* __restrict__ hq, int n, int B, long long efs,
+                             uint32_t* __restrict__ ef) {
+  const long long np = (long long)n * (n + 1) / 2;
+  const long long total = (long long)B * efs;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(e / efs);
+    const long long p = e - (long long)m * efs;
+    uint32_t v = 0;
+    if (p < np) {
+      int i, j;
+      pair_of(p, i, j);
+      v = sym_code(hq[(size_t)m * n + i]) + sym_code(hq[(size_t)m * n + j]);
+    }
+    ef[e] = v;
+  }
+}
+
+// One static pool of POOL 64-bit words holds the G sketches' bins.
+// SPLIT: a sketch has more bins than one range (then G = 1).
+// SYM: colliding-hash sketches of a symmetric tensor (Section 3.3, Eq. (5)):
+// the fibres are T[i][j][:] for the pairs i <= j, weighted 2 when i < j (the
+// sum over all index triples), each sketch has 2b real bins (sym_code), and
+// the sign of an entry is (-1)^(r >> 1) for its summed rotation r.
+template <typename TIn, int POOL, bool SPLIT, bool SYM>
 __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   __shared__ __align__(16) unsigned long long pool[POOL];
   __shared__ double red[16];
@@ -1153,7 +1195,7 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   const int slab = (r / a.ngroups) * 8 + xcd;
   const int grp = r % a.ngroups;
   if (slab >= a.nslab) return;  // padding blocks of the XCD mapping
-  // Work-group `grp` holds the bins of G consecutive (sketch, bucket range)
+  // Work-group `grp` holds the bins of G consecutive (sketch, bin range)
   // pairs; with more than one range per sketch G is 1.
   const int g0 = grp * G;
   const int Gc = min(G, a.B * a.nrange - g0);
@@ -1163,12 +1205,11 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   const int tid = threadIdx.x;
   for (int t = tid; t < G * br; t += blockDim.x) bins[t] = 0ull;
 
-  const long long npairs = (long long)n * n;
   const long long p0 = (long long)slab * a.pairs_per_slab;
-  const long long p1 = min(npairs, p0 + a.pairs_per_slab);
+  const long long p1 = min(a.nfib, p0 + a.pairs_per_slab);
   const double m = reduce_absmax(a.absmax, a.nabs, red);  // contains a barrier
   const bool bad = !(m < __builtin_inf());
-  const int F = bad ? 0 : fixed_scale(m, (p1 - p0) * n);
+  const int F = bad ? 0 : fixed_scale(SYM ? 2.0 * m : m, (p1 - p0) * n);
   const double up = ldexp(1.0, F), down = ldexp(1.0, -F);
   __syncthreads();
 
@@ -1180,15 +1221,17 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
     constexpr int NC = 4;   // chunks of 64 lanes along k per item
     constexpr int GM = kBuildMaxG;
     constexpr unsigned SZ = sizeof(TIn);
-    const uint32_t pmask = ((uint32_t)b - 1u) << 3;
+    const uint32_t pmask = ((uint32_t)b - 1u) << (SYM ? 4 : 3);
     const uint32_t lmask = ((uint32_t)br - 1u) << 3;
     const long long step = (long long)NF * nw;
     const __amdgpu_buffer_rsrc_t efr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t*>(a.ef + (size_t)sk0 * a.efs), 0, (int)(Gc * a.efs * 4), kBufferWord3);
-    // The item of fibres q .. q+3: their ef words (per sketch) and entries.
+    // The item of fibres q .. q+3: their ef words (per sketch), entries and
+    // (SYM) which of them are diagonal pairs.
     struct Item {
       uint32_t ef[GM][NF];
       TIn x[NF][NC];
+      uint32_t diag;
     };
     for (int kb = 0; kb < n; kb += 64 * NC) {
       unsigned voff[NC];
@@ -1200,8 +1243,14 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
         kin[c] = k < n;
         voff[c] = (unsigned)min(k, n - 1) * SZ;
 #pragma unroll
-        for (int g = 0; g < GM; ++g)
-          e3[g][c] = g < Gc ? bin_code(a.hx[((size_t)(sk0 + g) * 3 + 2) * n + min(k, n - 1)]) : 0u;
+        for (int g = 0; g < GM; ++g) {
+          if (g < Gc) {
+            const uint32_t w = a.t3[(size_t)(sk0 + g) * a.t3s + min(k, n - 1)];
+            e3[g][c] = SYM ? sym_code(w) : bin_code(w);
+          } else {
+            e3[g][c] = 0u;
+          }
+        }
       }
       // Every variable offset is a lane offset, which the buffer range check
       // covers: a fibre past the slab gets a resource of zero bytes.
@@ -1217,11 +1266,23 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
             it.ef[g][3] = w[3];
           }
         }
+        int pi = 0, pj = 0;
+        if (SYM) pair_of(min(q, a.nfib - 1), pi, pj);
+        it.diag = 0u;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           const bool live = q + f < p1;
+          long long row = q + f;
+          if (SYM) {
+            row = (long long)pi * n + pj;
+            it.diag |= (pi == pj ? 1u : 0u) << f;
+            if (++pi > pj) {
+              ++pj;
+              pi = 0;
+            }
+          }
           const __amdgpu_buffer_rsrc_t tr = __builtin_amdgcn_make_buffer_rsrc(
-              const_cast<TIn*>(a.T) + (size_t)(live ? q + f : 0) * n, 0, live ? (int)(n * SZ) : 0,
+              const_cast<TIn*>(a.T) + (size_t)(live ? row : 0) * n, 0, live ? (int)(n * SZ) : 0,
               kBufferWord3);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
@@ -1245,22 +1306,25 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
           if (g < Gc) {
             const uint32_t gbase = SPLIT ? 0u : (uint32_t)g * (uint32_t)br * 8u;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              if (kin[c]) {
+            for (int f = 0; f < NF; ++f) {
+              if (f < nf) {
+                // off-diagonal pairs stand for (i, j) and (j, i)
+                const double upf = (SYM && !((cur.diag >> f) & 1u)) ? 2.0 * up : up;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                  if (f < nf) {
+                for (int c = 0; c < NC; ++c) {
+                  if (kin[c]) {
                     const uint32_t sg = cur.ef[g][f] + e3[g][c];
-                    const unsigned long long v = to_fixed(signed_in(cur.x[f][c], sg), up);
-                    const uint32_t t8 = sg & pmask;
+                    const uint32_t off = SYM ? ((sg & pmask) | ((sg & 1u) << 3)) : (sg & pmask);
+                    const unsigned long long v =
+                        to_fixed(signed_in(cur.x[f][c], SYM ? (sg << 30) : sg), upf);
                     if (SPLIT) {
-                      if ((int)(t8 >> (a.lbr + 3)) == rq)
+                      if ((int)(off >> (a.lbr + 3)) == rq)
                         atomicAdd(reinterpret_cast<unsigned long long*>(
-                                      reinterpret_cast<unsigned char*>(bins) + (t8 & lmask)),
+                                      reinterpret_cast<unsigned char*>(bins) + (off & lmask)),
                                   v);
                     } else {
                       atomicAdd(reinterpret_cast<unsigned long long*>(
-                                    reinterpret_cast<unsigned char*>(bins) + (t8 | gbase)),
+                                    reinterpret_cast<unsigned char*>(bins) + (off | gbase)),
                                 v);
                     }
                   }

@@ -64,87 +64,7 @@ __device__ __forceinline__ void sym_count_sketch(const uint32_t* __restrict__ sr
 
 // ---- build ------------------------------------------------------------------
 
-// Dense symmetric build in 64-bit fixed point (LDS atomics, so the sums do
-// not depend on the order of the additions).  The complex sketch of b
-// buckets is handled as 2b real bins (bin 2t + r mod 2 with sign (-1)^(r / 2)
-// for rotation r, i.e. interleaved re/im), split into bucket ranges of at
-// most 16384 bins.  Work-group (slab, group) holds the bins of G (sketch,
-// range) pairs; slab s takes the index pairs i <= j numbered s, s + nslab,
-// s + 2 nslab, ... (pair p = j (j + 1)/2 + i), and for each the entries
-// k >= j, weighted by the number of distinct permutations of (i, j, k).
-template <typename TIn>
-struct SymBuildArgs {
-  const TIn* T;
-  int n, b, B, G;
-  int nrange, lbr;            // ranges of the 2b bins per sketch, log2 of their length
-  const uint32_t* hq;         // [B][n]
-  long long npairs;
-  int nslab, ngroups;
-  const unsigned long long* absmax;  // [nabs] per-block max |T| of k_absmax
-  int nabs;
-  double* partial;            // [ngroups][nslab][G][2^lbr]
-};
-
-template <typename TIn, int POOL>
-__global__ __launch_bounds__(1024) void k_sym_build(SymBuildArgs<TIn> a) {
-  __shared__ __align__(16) unsigned long long pool[POOL];
-  const int n = a.n, b = a.b, G = a.G;
-  const int lin = blockIdx.x;
-  const int xcd = lin & 7, rr = lin >> 3;
-  const int slab = (rr / a.ngroups) * 8 + xcd;   // one slab's groups on one XCD (shared L2)
-  const int grp = rr % a.ngroups;
-  if (slab >= a.nslab) return;
-  const int g0 = grp * G;
-  const int Gc = min(G, a.B * a.nrange - g0);
-  const int br = 1 << a.lbr;
-  const int sk0 = g0 / a.nrange, rq = g0 % a.nrange;
-  unsigned long long* bins = pool;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(pool + (size_t)G * br);
-  const int tid = threadIdx.x;
-  for (int t = tid; t < G * br; t += blockDim.x) bins[t] = 0ull;
-  for (int t = tid; t < Gc * n; t += blockDim.x) tab[t] = a.hq[(size_t)sk0 * n + t];
-  // scale 2^F: |bin| <= 6 max|T| (entries of the slab) 2^F < 2^62
-  const long long pairs_here = (a.npairs - slab + a.nslab - 1) / a.nslab;
-  __shared__ double red[16];
-  const double m = reduce_absmax(a.absmax, a.nabs, red);
-  const bool bad = !(m < __builtin_inf());
-  int e2 = 0;
-  (void)frexp(m * 6.0 * (double)(pairs_here * n) * 2.0, &e2);
-  const int F = (m > 0.0 && !bad) ? max(-1000, min(1000, 62 - e2)) : 0;
-  const double up = ldexp(1.0, F), down = ldexp(1.0, -F);
-  __syncthreads();
-  if (!bad) {
-    const int lane = tid & 63;
-    const int nw = blockDim.x >> 6;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const unsigned bmask = (unsigned)b - 1u;
-    for (long long p = slab + (long long)a.nslab * wv; p < a.npairs; p += (long long)a.nslab * nw) {
-      int j = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-      while ((long long)(j + 1) * (j + 2) / 2 <= p) ++j;
-      while ((long long)j * (j + 1) / 2 > p) --j;
-      const int i = (int)(p - (long long)j * (j + 1) / 2);
-      const TIn* row = a.T + ((size_t)i * n + j) * n;
-      for (int k = j + lane; k < n; k += 64) {
-        const double mult = (i == j) ? (j == k ? 1.0 : 3.0) : (j == k ? 3.0 : 6.0);
-        const long long x = __double2ll_rn((double)row[k] * mult * up);
-        for (int g = 0; g < Gc; ++g) {
-          const uint32_t* tg = tab + g * n;
-          const uint32_t ei = tg[i], ej = tg[j], ek = tg[k];
-          const uint32_t t = (sym_pos(ei) + sym_pos(ej) + sym_pos(ek)) & bmask;
-          const int r = (sym_rot(ei) + sym_rot(ej) + sym_rot(ek)) & 3;
-          const uint32_t bin = 2u * t + (uint32_t)(r & 1);
-          if ((int)(bin >> a.lbr) == rq)
-            atomicAdd(&bins[(size_t)g * br + (bin & (uint32_t)(br - 1))],
-                      (unsigned long long)((r & 2) ? -x : x));
-        }
-      }
-    }
-  }
-  __syncthreads();
-  double* out = a.partial + ((size_t)grp * a.nslab + slab) * (size_t)G * br;
-  for (int t = tid; t < Gc * br; t += blockDim.x)
-    out[t] = bad ? __builtin_nan("") : (double)(long long)bins[t] * down;
-}
+// The dense symmetric build is k_build_dense<..., SYM = true> (kernels.hpp).
 
 // dst = src (+ dst when acc), doubles.
 __global__ void k_add64(double* dst, const double* src, size_t count, int acc) {

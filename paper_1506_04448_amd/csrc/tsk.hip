@@ -111,6 +111,7 @@ struct tsk_sym_tables {
   uint32_t* hq = nullptr;    // [B][n] (h << 2) | q
   uint32_t* srt = nullptr;   // [3][B][n] (p h mod b << 2) | p q mod 4
   uint32_t* ord = nullptr;   // [3][B][n]
+  uint32_t* ef = nullptr;    // [B][pairs + pad] pair codes, made by the first build
 };
 
 namespace {
@@ -689,6 +690,38 @@ namespace {
 constexpr int kBuildPoolLarge = (159 * 1024) / 8;  // leaves room for the reduction scratch
 constexpr int kBuildPoolSmall = (20 * 1024) / 8;
 
+template <typename TIn, bool SYM>
+tsk_status launch_build(bool small, bool split, int nblk, const tsk::BuildArgs<TIn>& a, hipStream_t st) {
+  if (small)
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolSmall, false, SYM>), dim3(nblk), dim3(1024), 0, st, a);
+  else if (split)
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge, true, SYM>), dim3(nblk), dim3(1024), 0, st, a);
+  else
+    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge, false, SYM>), dim3(nblk), dim3(1024), 0, st, a);
+  return check_launch("k_build_dense");
+}
+
+// Slabs of the dense build: a multiple of 8 (one per XCD lane of the grid
+// mapping), never slabs of fewer than 8 fibres; the fewest whose
+// work-groups (ngroups per slab) fill 90% of the rounds they take (one
+// work-group per CU with the large pool, two with the small one), else the
+// count that fills them best.
+int pick_nslab(long long nfib, int ngroups, bool small) {
+  const long long per_round = 256LL * (small ? 2 : 1);
+  int best = 8;
+  double best_fill = -1.0;
+  for (int ns = 8; ns <= 1024 && (ns == 8 || nfib / ns >= 8); ns += 8) {
+    const long long w = (long long)ns * ngroups;
+    const double fill = (double)w / (double)(per_round * ((w + per_round - 1) / per_round));
+    if (fill > best_fill + 1e-9) {
+      best_fill = fill;
+      best = ns;
+    }
+    if (fill >= 0.9) break;
+  }
+  return (int)std::min<long long>(best, std::max<long long>(1, nfib));
+}
+
 // Blocks of the max |T| pass: about 16 KB of T per block, at most 512.
 int absmax_blocks(size_t count) {
   return (int)std::max<size_t>(1, std::min<size_t>(512, (count + 4095) / 4096));
@@ -717,9 +750,7 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   // many as fill each XCD's 32 CUs in one round (one work-group per CU with
   // the large pool, two with the small one), never slabs of fewer than 8
   // fibres; slab lengths are multiples of 4 fibres (the kernel's items).
-  const int slots = 32 * (small ? 2 : 1);
-  int nslab = (int)std::min<long long>(std::max<long long>(1, npairs / 8),
-                                       8LL * std::max(1, slots / ngroups));
+  int nslab = pick_nslab(npairs, ngroups, small);
   long long pps = (npairs + nslab - 1) / nslab;
   pps = (pps + 3) / 4 * 4;
   nslab = (int)((npairs + pps - 1) / pps);
@@ -762,9 +793,11 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   a.G = G;
   a.nrange = nrange;
   a.lbr = lbr;
-  a.hx = tab->hx;
+  a.t3 = tab->hx + 2 * n;
+  a.t3s = 3 * n;
   a.ef = reinterpret_cast<const uint32_t*>(efb);
   a.efs = efs;
+  a.nfib = npairs;
   a.pairs_per_slab = pps;
   a.nslab = nslab;
   a.ngroups = ngroups;
@@ -773,13 +806,7 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
   a.partial = reinterpret_cast<double*>(partial);
   // 1-D grid: 8 XCD lanes x ngroups x ceil(nslab / 8) (see the kernel).
   const int nblk = 8 * ngroups * ((nslab + 7) / 8);
-  if (small)
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolSmall, false>), dim3(nblk), dim3(1024), 0, st, a);
-  else if (nrange > 1)
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge, true>), dim3(nblk), dim3(1024), 0, st, a);
-  else
-    hipLaunchKernelGGL((tsk::k_build_dense<TIn, kBuildPoolLarge, false>), dim3(nblk), dim3(1024), 0, st, a);
-  TSK_TRY(check_launch("k_build_dense"));
+  TSK_TRY((launch_build<TIn, false>(small, nrange > 1, nblk, a, st)));
   hipLaunchKernelGGL(tsk::k_build_reduce, dim3(grid_for((size_t)B * b, 256)), dim3(256), 0, st,
                      (const double*)partial, (double*)stime, b, B, G, nslab, nrange, lbr);
   TSK_TRY(check_launch("k_build_reduce"));
@@ -2005,6 +2032,7 @@ extern "C" void tsk_sym_tables_destroy(tsk_sym_tables_t t) {
   (void)hipSetDevice(t->ctx->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(t->hq);
+  if (t->ef) (void)hipFree(t->ef);
   delete t;
 }
 
@@ -2136,8 +2164,8 @@ tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, cons
 namespace {
 
 // The fixed-point LDS build of the symmetric sketches into s64 (written, or
-// added to with accumulate): the plan of the asymmetric dense build with
-// 2b real bins per sketch and the index pairs i <= j.
+// added to with accumulate): the dense build's kernel with the pairs i <= j
+// as fibres and 2b real bins per sketch.
 template <typename TIn>
 tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, double* s64, int accumulate,
                           hipStream_t st) {
@@ -2148,17 +2176,33 @@ tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, dou
   int lbr = 0;
   while ((1 << lbr) < br) ++lbr;
   const int Bv = B * nrange;
-  const size_t per_sketch = (size_t)br * 8 + (size_t)4 * n;
-  if (per_sketch > (size_t)kBuildPoolLarge * 8)
-    return tsk::fail(TSK_EUNSUPPORTED, "symmetric build: b=%d, n=%d exceed one CU's LDS", b, n);
-  const bool small = (size_t)Bv * per_sketch <= (size_t)kBuildPoolSmall * 8;
-  const size_t pool = (size_t)(small ? kBuildPoolSmall : kBuildPoolLarge) * 8;
-  int G = nrange > 1 ? 1 : (int)std::min<size_t>((size_t)B, pool / per_sketch);
+  const size_t per_sketch = (size_t)br * 8;
+  int G = nrange > 1 ? 1
+                     : (int)std::min<size_t>({(size_t)B, (size_t)tsk::kBuildMaxG,
+                                              (size_t)kBuildPoolLarge * 8 / per_sketch});
   const int ngroups = (Bv + G - 1) / G;
   G = (Bv + ngroups - 1) / ngroups;
+  const bool small = (size_t)G * per_sketch <= (size_t)kBuildPoolSmall * 8;
   const long long npairs = (long long)n * (n + 1) / 2;
-  const int slots = 32 * (small ? 2 : 1);
-  const int nslab = (int)std::min<long long>(std::max<long long>(1, npairs / 8), 8LL * std::max(1, slots / ngroups));
+  int nslab = pick_nslab(npairs, ngroups, small);
+  long long pps = (npairs + nslab - 1) / nslab;
+  pps = (pps + 3) / 4 * 4;
+  nslab = (int)((npairs + pps - 1) / pps);
+  // codes of the pairs per sketch, made once per table set (see the dense build)
+  const long long efs = (npairs + 4 + 3) / 4 * 4;
+  if ((size_t)G * efs * 4 > (size_t)0x7fffffff)
+    return tsk::fail(TSK_EUNSUPPORTED, "symmetric build: n=%d too large", n);
+  if (!tab->ef) {
+    void* d = nullptr;
+    TSK_HIP(hipMalloc(&d, (size_t)B * efs * sizeof(uint32_t)));
+    hipLaunchKernelGGL(tsk::k_pair_codes, dim3(grid_for((size_t)B * efs, 256)), dim3(256), 0, st, tab->hq, n, B,
+                       efs, reinterpret_cast<uint32_t*>(d));
+    if (check_launch("k_pair_codes") != TSK_OK || hipStreamSynchronize(st) != hipSuccess) {
+      (void)hipFree(d);
+      return tsk::fail(TSK_EHIP, "symmetric build: pair codes failed");
+    }
+    tab->ef = reinterpret_cast<uint32_t*>(d);
+  }
   void* partial = nullptr;
   void* stime = nullptr;
   void* amax = nullptr;
@@ -2170,7 +2214,7 @@ tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, dou
   hipLaunchKernelGGL(tsk::k_absmax<TIn>, dim3(nabs), dim3(256), 0, st, T, cnt,
                      reinterpret_cast<unsigned long long*>(amax));
   TSK_TRY(check_launch("k_absmax"));
-  tsk::SymBuildArgs<TIn> a;
+  tsk::BuildArgs<TIn> a;
   a.T = T;
   a.n = n;
   a.b = b;
@@ -2178,19 +2222,19 @@ tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, dou
   a.G = G;
   a.nrange = nrange;
   a.lbr = lbr;
-  a.hq = tab->hq;
-  a.npairs = npairs;
+  a.t3 = tab->hq;
+  a.t3s = n;
+  a.ef = tab->ef;
+  a.efs = efs;
+  a.nfib = npairs;
+  a.pairs_per_slab = pps;
   a.nslab = nslab;
   a.ngroups = ngroups;
   a.absmax = reinterpret_cast<const unsigned long long*>(amax);
   a.nabs = nabs;
   a.partial = reinterpret_cast<double*>(partial);
   const int nblk = 8 * ngroups * ((nslab + 7) / 8);
-  if (small)
-    hipLaunchKernelGGL((tsk::k_sym_build<TIn, kBuildPoolSmall>), dim3(nblk), dim3(1024), 0, st, a);
-  else
-    hipLaunchKernelGGL((tsk::k_sym_build<TIn, kBuildPoolLarge>), dim3(nblk), dim3(1024), 0, st, a);
-  TSK_TRY(check_launch("k_sym_build"));
+  TSK_TRY((launch_build<TIn, true>(small, nrange > 1, nblk, a, st)));
   hipLaunchKernelGGL(tsk::k_build_reduce, dim3(grid_for((size_t)B * b2, 256)), dim3(256), 0, st,
                      (const double*)partial, (double*)stime, b2, B, G, nslab, nrange, lbr);
   TSK_TRY(check_launch("k_build_reduce"));
