@@ -13,9 +13,10 @@
 
 namespace tsk {
 
+// W_b^x for any integer x (b a power of two: x mod b is x & (b - 1))
 template <typename R>
 __device__ __forceinline__ cx<R> wfull(const cx<R>* Wb, int b, long long x) {
-  return Wb[(int)(((x % b) + b) % b)];
+  return Wb[(int)(x & (long long)(b - 1))];
 }
 
 // Forward sub-transforms of count sketches restricted to one residue class of
@@ -136,19 +137,25 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGM)) void k_sub_gather64(co
 }
 
 // Half spectrum from the sub-transforms E[m][r][M]: S64 (+)= X, S32 = (float) S64.
+// One thread per bin pair (k, H-k), k <= H/2: both recombined values serve
+// both outputs.
 __global__ void k_combine_r2c(const cx<double>* E, int B, int b, int M, int Rr, const cx<double>* Wb,
                               int accumulate, cx<double>* S64, cx<float>* S32) {
   const int H = b / 2;
-  const size_t total = (size_t)B * (H + 1);
+  const size_t total = (size_t)B * (H / 2 + 1);
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
-    const int m = (int)(e / (H + 1)), k = (int)(e % (H + 1));
+    const int m = (int)(e / (H / 2 + 1)), k = (int)(e % (H / 2 + 1));
     const cx<double>* Em = E + (size_t)m * Rr * M;
-    cx<double> X = r2c_post(recombine(Em, M, Rr, Wb, b, k % H), recombine(Em, M, Rr, Wb, b, (H - k) % H),
-                            Wb[k]);
-    if (accumulate) X = cadd(X, S64[e]);
-    S64[e] = X;
-    if (S32) S32[e] = cx<float>{(float)X.x, (float)X.y};
+    const cx<double> Za = recombine(Em, M, Rr, Wb, b, k), Zb = recombine(Em, M, Rr, Wb, b, (H - k) % H);
+    const size_t base = (size_t)m * (H + 1);
+    auto put = [&](int kk, cx<double> X) {
+      if (accumulate) X = cadd(X, S64[base + kk]);
+      S64[base + kk] = X;
+      if (S32) S32[base + kk] = cx<float>{(float)X.x, (float)X.y};
+    };
+    put(k, r2c_post(Za, Zb, Wb[k]));
+    if (H - k != k) put(H - k, r2c_post(Zb, Za, Wb[H - k]));
   }
 }
 
