@@ -247,13 +247,16 @@ tsk_status tsk_sym_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint3
                                  const uint8_t* q_host, tsk_sym_tables_t* out);
 void tsk_sym_tables_destroy(tsk_sym_tables_t tab);
 
-/* Dense build of Eq. (5) from the entries with i <= j <= k (each weighted by
- * the number of distinct permutations of its index triple; for a symmetric
- * tensor this is the sum over all entries), accumulated in 64-bit fixed point
- * (a power-of-two scale from max |T|; repeated builds are bit-identical),
- * then S64 = F(s64), S32 = (float)S64, s32 = (float)s64 (s32, S32
- * nullable).  T: [n][n][n] row-major, float or double by dtype.
- * accumulate != 0 adds to s64.  A non-finite entry makes the sketch NaN. */
+/* Dense build of Eq. (5) from the fibres T[i][j][:] with i <= j (weighted 2
+ * when i < j; for a tensor symmetric in its first two indices this is the
+ * sum over all entries, and only those fibres are read), accumulated in
+ * 64-bit fixed point (a power-of-two scale from max |T|; repeated builds are
+ * bit-identical), then S64 = F(s64), S32 = (float)S64, s32 = (float)s64
+ * (s32, S32 nullable).  T: [n][n][n] row-major, float or double by dtype.
+ * accumulate != 0 adds to s64.  A non-finite entry makes the sketch NaN.
+ * The first build with a table set also makes its per-pair codes (2 B n^2
+ * bytes of device memory, held until tsk_sym_tables_destroy) and waits for
+ * its stream once. */
 tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t tab, const void* T,
                                       tsk_dtype dtype, double* s64, float* s32, double* S64,
                                       float* S32, int accumulate, void* stream);
