@@ -1724,6 +1724,10 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
   constexpr int PL = padded_len(H);
   constexpr int PK = (H / 2 + NT - 1) / NT;
   constexpr int PKP = (PK + NPART - 1) / NPART;
+  // With a last pass of radix 2 the transforms stop before it and the bins
+  // are formed from its inputs: Z[k] = A[k] + W_H^k A[k + H/2] and, for
+  // j = H/2 - k, Z[H-k] = A[j] + conj(W_H^k) A[j + H/2], W_H^k = (W_b^k)^2.
+  constexpr bool FUSE = fft_last_radix(H, NT) == 2 && H >= 64;
   extern __shared__ __align__(16) unsigned char lds[];
   R* re = reinterpret_cast<R*>(lds);
   R* im = re + PL;
@@ -1755,8 +1759,21 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
     auto store = [&](uint32_t t, R v) { store_packed(buf, t, v); };
     count_sketch<R>(stab + (2 * j) * n, stab + (2 * j + 1) * n, n, NT, getu, store);
     __syncthreads();
-    fft_soa<R, LOGH, NT, false, false>(buf, tw);
+    fft_soa<R, LOGH, NT, false, false, FUSE>(buf, tw);
   };
+  // Z[k] and Z[H-k] for 0 <= k < H/2 (Z[H] = Z[0]), and Z[H/2]
+  auto zpair = [&](int k, cx<R>& Za, cx<R>& Zb) {
+    if constexpr (FUSE) {
+      const cx<R> w = tw.w(k);
+      const cx<R> wH = cmul(w, w);
+      Za = cadd(buf.get(k), cmul(wH, buf.get(k + H / 2)));
+      Zb = k == 0 ? Za : cadd(buf.get(H / 2 - k), cmulc(buf.get(H - k), wH));
+    } else {
+      Za = buf.get(k);
+      Zb = buf.get((H - k) & (H - 1));
+    }
+  };
+  auto zmid = [&]() -> cx<R> { return FUSE ? csub(buf.get(0), buf.get(H / 2)) : buf.get(H / 2); };
   // owned bin pair (k, H-k) of slot s in round `part`; k < H/2 when valid
   auto bin_k = [&](int part, int s) -> int {
     int t = threadIdx.x;
@@ -1791,13 +1808,13 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
         for (int s = 0; s < PKP; ++s) {
           const int k = bin_k(part, s);
           if (k >= H / 2) break;
-          const cx<R> Za = buf.get(k);
-          const cx<R> Zb = buf.get((H - k) & (H - 1));
+          cx<R> Za, Zb;
+          zpair(k, Za, Zb);
           F0[s] = r2c_post(Za, Zb, tw.w(k));
           F1[s] = r2c_post(Zb, Za, tw.w(H - k));
         }
         if (tid == 0 && part == 0) {
-          const cx<R> Z = buf.get(H / 2);
+          const cx<R> Z = zmid();
           Fm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
         }
         __syncthreads();
@@ -1808,13 +1825,13 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
           for (int s = 0; s < PKP; ++s) {
             const int k = bin_k(part, s);
             if (k >= H / 2) break;
-            const cx<R> Za = buf.get(k);
-            const cx<R> Zb = buf.get((H - k) & (H - 1));
+            cx<R> Za, Zb;
+            zpair(k, Za, Zb);
             G0[s] = r2c_post(Za, Zb, tw.w(k));
             G1[s] = r2c_post(Zb, Za, tw.w(H - k));
           }
           if (tid == 0 && part == 0) {
-            const cx<R> Z = buf.get(H / 2);
+            const cx<R> Z = zmid();
             Gm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
           }
           __syncthreads();
