@@ -58,6 +58,27 @@ def test_sym_build_matches_eq5(ctx, n, b, B, dt):
     tab.close()
 
 
+@pytest.mark.parametrize("n,b,B,dt", [(30, 512, 3, np.float32), (24, 8192, 2, np.float32),
+                                      (45, 16384, 2, np.float64)])
+def test_sym_build_of_integer_tensor_is_exact(ctx, n, b, B, dt):
+    """A symmetric tensor of small integers makes every bucket sum exact on both
+    sides: the time-domain sketch must equal Eq. (5) exactly (codes, rotations,
+    pair weights and bin ranges)."""
+    import itertools
+    print(f"sym exact build n={n} b={b} B={B}", flush=True)
+    rng = np.random.default_rng(n + b)
+    A = rng.integers(-3, 4, size=(n, n, n))
+    T = sum(np.transpose(A, p) for p in itertools.permutations(range(3))).astype(dt)
+    h, q = sym_tables(n * b, n, b, B)
+    tab = tsk.SymTables(ctx, h, q, b)
+    s64, s32, S64, S32 = tsk.new_sym_sketch(tab, DEV)
+    tsk.sym_sketch_build_dense(ctx, tab, torch.from_numpy(T).to(DEV), s64, s32, S64, S32)
+    got = _c(s64)
+    for m in range(B):
+        np.testing.assert_array_equal(got[m], osym.sym_sketch_dense(T.astype(np.float64), h[m], q[m], b))
+    tab.close()
+
+
 def test_sym_build_is_deterministic_and_accumulates(ctx):
     n, b, B = 70, 8192, 3
     P = planted_tensor(n, 3, noise=0.05, seed=4, dtype=np.float32)
