@@ -232,23 +232,36 @@ __global__ __launch_bounds__(256) void k_power_split_mid(SplitMidArgs a) {
   const cx<float>* S = a.S + (size_t)m * (H + 1);
   cx<float>* A0 = a.A + (((size_t)vec * a.B + m) * 2 + 0) * (size_t)M;
   cx<float>* A1 = A0 + M;
-  auto Z = [&](const cx<float>* E, int k) -> cx<float> {  // k in [0, H)
-    const int km = k % M;
-    const cx<float> w = a.Wb[2 * km];                       // W_H^km
-    const cx<float> t = cmul(w, E[M + km]);
-    return k < M ? cadd(E[km], t) : csub(E[km], t);
-  };
-  auto P = [&](int k) -> cx<float> {  // k in [0, H]
-    const int ka = k % H, kb = (H - k) % H;
-    const cx<float> X2 = r2c_post(Z(E2, ka), Z(E2, kb), a.Wb[k]);
-    const cx<float> X3 = r2c_post(Z(E3, ka), Z(E3, kb), a.Wb[k]);
-    return cmulc(cmulc(S[k], X2), X3);
+  // Z[km] and Z[km + M] from the two sub-transforms (W_H^km E_1[km] added or
+  // subtracted), km < M.
+  auto zpair = [&](const cx<float>* E, int km, cx<float>& lo, cx<float>& hi) {
+    const cx<float> t = cmul(a.Wb[2 * km], E[M + km]);
+    lo = cadd(E[km], t);
+    hi = csub(E[km], t);
   };
   auto Y = [&](int k, cx<float> Pk, cx<float> PHk) -> cx<float> { return c2r_pack(Pk, PHk, a.Wb[k]); };
   for (int kp = blockIdx.z * blockDim.x + threadIdx.x; kp <= M / 2; kp += gridDim.z * blockDim.x) {
-    // P at k', H - k', M - k', M + k'
-    const cx<float> Pa = P(kp), Pd = P(H - kp);
-    const cx<float> Pb = P(M - kp), Pc = P(M + kp);
+    // The quad k', H - k', M - k', M + k' needs Z at those four bins, which
+    // come from the sub-transform bins k' and M - k' (mod M).
+    const int km2 = (M - kp) % M;
+    cx<float> P[4];  // at k', H - k', M - k', M + k'
+    const cx<float>* Es[2] = {E2, E3};
+    cx<float> X[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cx<float> a0, a1, b0, b1;
+      zpair(Es[j], kp, a0, a1);    // Z[k'], Z[M + k']
+      zpair(Es[j], km2, b0, b1);   // Z[M - k'], Z[H - k'] (k' > 0); Z[0], Z[M] (k' = 0)
+      const cx<float> zk = a0, zMk = kp ? b0 : b1, zHk = kp ? b1 : b0, zMpk = a1;
+      X[j][0] = r2c_post(zk, zHk, a.Wb[kp]);
+      X[j][1] = r2c_post(zHk, zk, a.Wb[H - kp]);
+      X[j][2] = r2c_post(zMk, zMpk, a.Wb[M - kp]);
+      X[j][3] = r2c_post(zMpk, zMk, a.Wb[M + kp]);
+    }
+    const int ks[4] = {kp, H - kp, M - kp, M + kp};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[q] = cmulc(cmulc(S[ks[q]], X[0][q]), X[1][q]);
+    const cx<float> Pa = P[0], Pd = P[1], Pb = P[2], Pc = P[3];
     const cx<float> Ya = Y(kp, Pa, Pd);              // Y[k']
     const cx<float> Yc = Y(M + kp, Pc, Pb);          // Y[M + k']
     A0[kp] = cadd(Ya, Yc);
