@@ -6,8 +6,9 @@
                   modes permuted) of the median's sketch.
 ``SketchedCPLoss`` (1/B) sum_m ||s^(m)(T) - sum_i lam_i s^(m)(u_i^(x)3)||^2, the
                   CP least-squares objective measured through the sketches
-                  (linearity of Section 3.1); its backward recomputes the FP64
-                  residual spectra and reads the gradients off them.
+                  (linearity of Section 3.1); when gradients are wanted the
+                  forward reads them off the same FP64 residual spectra and
+                  the backward scales them.
 ``refine_adam``   torch.optim.Adam on (lam, U) of that loss, e.g. from the
                   output of the robust tensor power method.
 
@@ -54,20 +55,21 @@ class SketchedTuuu(torch.autograd.Function):
 class SketchedCPLoss(torch.autograd.Function):
     @staticmethod
     def forward(fctx, lam, U, sk: SketchHandle):
-        loss, _, _ = cp_loss(sk.ctx, sk.tab, sk.S64, lam.detach().contiguous(),
-                             U.detach().contiguous(), grads=False)
-        fctx.sk = sk
-        fctx.save_for_backward(lam, U)
+        # The gradients are linear in the upstream gradient (a scalar), so when
+        # they are wanted the one library call that forms the FP64 residual
+        # spectra returns them with the loss, and the backward only scales them.
+        want = any(fctx.needs_input_grad[:2])
+        loss, g_lam, g_U = cp_loss(sk.ctx, sk.tab, sk.S64, lam.detach().contiguous(),
+                                   U.detach().contiguous(), grads=want)
+        if want:
+            fctx.save_for_backward(g_lam, g_U)
         return loss
 
     @staticmethod
     def backward(fctx, grad_loss):
-        lam, U = fctx.saved_tensors
-        sk = fctx.sk
-        scale = grad_loss.reshape(1).to(U.dtype).contiguous()
-        _, g_lam, g_U = cp_loss(sk.ctx, sk.tab, sk.S64, lam.detach().contiguous(),
-                                U.detach().contiguous(), scale=scale, grads=True)
-        return g_lam, g_U, None
+        g_lam, g_U = fctx.saved_tensors
+        scale = grad_loss.to(g_U.dtype)
+        return g_lam * scale, g_U * scale, None
 
 
 def tuuu(U: torch.Tensor, sk: SketchHandle) -> torch.Tensor:

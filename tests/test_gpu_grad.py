@@ -128,6 +128,19 @@ def test_autograd_functions_gradcheck_and_oracle(ctx):
                                     eps=1e-6, atol=1e-6, rtol=1e-5)
     Uv = torch.tensor(rng.standard_normal((L, n)), device=DEV, requires_grad=True)
     assert torch.autograd.gradcheck(lambda c: tag.tuuu(c, sk), (Uv,), eps=1e-6, atol=1e-6, rtol=1e-5)
+    # the CP loss's backward is its gradient times the upstream gradient
+    c = 0.37
+    lam.grad = None
+    U.grad = None
+    (c * tag.sketched_cp_loss(lam, U, sk)).backward()
+    _, rg_lam, rg_U = G.cp_loss_grad(S_time, h, xi, lam.detach().cpu().numpy(), U.detach().cpu().numpy())
+    assert rel(lam.grad.cpu().numpy(), c * rg_lam) < 1e-12
+    assert rel(U.grad.cpu().numpy(), c * rg_U) < 1e-12
+    # no gradient wanted: the forward returns the loss alone
+    with torch.no_grad():
+        l0 = tag.sketched_cp_loss(lam, U, sk)
+    assert abs(float(l0) - G.cp_loss(S_time, h, xi, lam.detach().cpu().numpy(), U.detach().cpu().numpy())) \
+        <= 1e-12 * abs(float(l0))
     # the backward pass equals the oracle gradient with the upstream weights
     w = torch.tensor(rng.standard_normal(L), device=DEV)
     (tag.tuuu(Uv, sk) * w).sum().backward()
