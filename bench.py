@@ -299,7 +299,9 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
     Wdat, _ = tsk.lda_whiten(ctx, rp, col, cnt, D, V, K, alpha0, Om, iters=4)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tsk.sketch_build_docs(ctx, tab, rp, col, cnt, V, Wdat, alpha0, S64, S32)
+    # the document build takes W in FP32, as above (the power steps that follow are FP32);
+    # whitening and recovery stay in FP64
+    tsk.sketch_build_docs(ctx, tab, rp, col, cnt, V, Wdat.float(), alpha0, S64, S32)
     lam2, U2, _, _ = tsk.decompose(ctx, tab, S64, S32, K, L, T, dtype=tsk.F32, seed=3)
     alpha_hat, mu = tsk.lda_recover(ctx, Wdat, lam2, U2, alpha0)
     torch.cuda.synchronize()
