@@ -1634,34 +1634,65 @@ __global__ void k_col_bounds(const int32_t* skeys, int nnz, int V, int32_t* colp
   }
 }
 
+// sdoc[e], scnt[e]: document and count of the e-th nonzero in word order
+// (svals: the nonzeros sorted by word, stable in document order), so that
+// the per-word kernels read them without a chain of dependent loads.
+__global__ void k_sorted_entries(const int32_t* svals, const int32_t* rowof, const int32_t* cnt, int nnz,
+                                 int32_t* sdoc, int32_t* scnt) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) {
+    const int idx = svals[e];
+    sdoc[e] = rowof[idx];
+    scnt[e] = cnt[idx];
+  }
+}
+
 // Per-word sums over the documents containing the word (in document order):
 // R_i = sum_d c_d n_di p_d, g_i = sum_d c_d n_di, g'_i = sum_d c'_d n_di.
 template <typename R>
-__global__ __launch_bounds__(256) void k_word_accum(const int32_t* svals, const int32_t* colptr,
-                                                    const int32_t* rowof, const int32_t* cnt,
-                                                    const R* P, const double* cd, const double* cpd,
-                                                    int V, int K, R* Rw, double* g, double* gp) {
-  for (int i = blockIdx.x; i < V; i += gridDim.x) {
-    const int lo = colptr[i], hi = colptr[i + 1];
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-      double acc = 0.0;
-      for (int e = lo; e < hi; ++e) {
-        const int idx = svals[e];
-        const int d = rowof[idx];
-        acc += cd[d] * (double)cnt[idx] * (double)P[(size_t)d * K + k];
+__global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const int32_t* scnt,
+                                                    const int32_t* colptr, const R* P, const double* cd,
+                                                    const double* cpd, int V, int K, R* Rw, double* g,
+                                                    double* gp) {
+  // sdoc, scnt: document and count of each nonzero in word order, so four
+  // documents per step keep four rows of P in flight (four partial sums)
+  for (int w = blockIdx.x; w < V; w += gridDim.x) {
+    const int lo = colptr[w], hi = colptr[w + 1];
+    for (int kb = 0; kb < K; kb += blockDim.x) {
+      const int k = kb + threadIdx.x;
+      const int kc = k < K ? k : K - 1;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0}, ga = 0.0, gc = 0.0;
+      int e = lo;
+      for (; e + 4 <= hi; e += 4) {
+        int d[4];
+        double n[4], p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          d[u] = sdoc[e + u];
+          n[u] = (double)scnt[e + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] = (double)P[(size_t)d[u] * K + kc];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double c = cd[d[u]];
+          acc[u] += c * n[u] * p[u];
+          ga += c * n[u];
+          gc += cpd[d[u]] * n[u];
+        }
       }
-      Rw[(size_t)i * K + k] = (R)acc;
-    }
-    if (threadIdx.x == 0) {
-      double a = 0.0, c = 0.0;
-      for (int e = lo; e < hi; ++e) {
-        const int idx = svals[e];
-        const int d = rowof[idx];
-        a += cd[d] * (double)cnt[idx];
-        c += cpd[d] * (double)cnt[idx];
+      for (; e < hi; ++e) {
+        const int d = sdoc[e];
+        const double n = (double)scnt[e];
+        const double c = cd[d];
+        acc[0] += c * n * (double)P[(size_t)d * K + kc];
+        ga += c * n;
+        gc += cpd[d] * n;
       }
-      g[i] = a;
-      gp[i] = c;
+      if (k < K) Rw[(size_t)w * K + k] = (R)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+      if (kb == 0 && threadIdx.x == 0) {
+        g[w] = ga;
+        gp[w] = gc;
+      }
     }
   }
 }

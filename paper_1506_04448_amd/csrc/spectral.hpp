@@ -16,28 +16,45 @@
 
 namespace tsk {
 
-// Y = M2 X (rows w, K <= 128 columns); grid over words, 128 threads.
-__global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* svals, const int32_t* colptr,
-                                                      const int32_t* rowof, const int32_t* cnt, const double* P,
-                                                      const double* cpd, const double* invm, const double* X,
-                                                      const double* q, const double* deff, double alpha0, int V,
-                                                      int K, double* Y) {
+// Y = M2 X (rows w, K <= 128 columns); grid over words, 128 threads.  Four
+// documents per step, with four partial sums, keep four rows of P in flight.
+__global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const int32_t* scnt,
+                                                      const int32_t* colptr, const double* P, const double* cpd,
+                                                      const double* invm, const double* X, const double* q,
+                                                      const double* deff, double alpha0, int V, int K, double* Y) {
   const double Dk = deff[0];
   const double inv = Dk > 0.0 ? 1.0 / Dk : 0.0;
   const double a = alpha0 / (alpha0 + 1.0);
+  const int k = threadIdx.x;
+  const int kc = k < K ? k : 0;  // lanes past K read column 0 and discard it
   for (int w = blockIdx.x; w < V; w += gridDim.x) {
     const int lo = colptr[w], hi = colptr[w + 1];
-    const int k = threadIdx.x;
-    const double xw = k < K ? X[(size_t)w * K + k] : 0.0;
-    double acc = 0.0, m1 = 0.0;
-    for (int e = lo; e < hi; ++e) {
-      const int idx = svals[e];
-      const int d = rowof[idx];
-      const double n = (double)cnt[idx];
-      m1 += invm[d] * n;
-      if (k < K) acc += cpd[d] * n * (P[(size_t)d * K + k] - xw);
+    const double xw = X[(size_t)w * K + kc];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, m1 = 0.0;
+    int e = lo;
+    for (; e + 4 <= hi; e += 4) {
+      int d[4];
+      double n[4], p[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        d[u] = sdoc[e + u];
+        n[u] = (double)scnt[e + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = P[(size_t)d[u] * K + kc];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        m1 += invm[d[u]] * n[u];
+        acc[u] += cpd[d[u]] * n[u] * (p[u] - xw);
+      }
     }
-    if (k < K) Y[(size_t)w * K + k] = acc * inv - a * (m1 * inv) * q[k];
+    for (; e < hi; ++e) {
+      const int d = sdoc[e];
+      const double n = (double)scnt[e];
+      m1 += invm[d] * n;
+      acc[0] += cpd[d] * n * (P[(size_t)d * K + kc] - xw);
+    }
+    if (k < K) Y[(size_t)w * K + k] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * inv - a * (m1 * inv) * q[k];
   }
 }
 

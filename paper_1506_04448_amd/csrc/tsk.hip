@@ -1375,8 +1375,16 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
                      (const int32_t*)skeys, nnz, V, colptr);
   TSK_TRY(check_launch("k_col_bounds"));
-  hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)svals,
-                     (const int32_t*)colptr, (const int32_t*)rowof, cnt, (const R*)P, (const double*)cd,
+  // documents and counts of the nonzeros in word order (the sort's input
+  // values and the sorted keys are no longer needed: their buffers take them)
+  int32_t *sdoc = iota, *scnt = skeys;
+  if (nnz > 0) {
+    hipLaunchKernelGGL(tsk::k_sorted_entries, dim3(grid_for((size_t)nnz, 256)), dim3(256), 0, st,
+                       (const int32_t*)svals, (const int32_t*)rowof, cnt, nnz, sdoc, scnt);
+    TSK_TRY(check_launch("k_sorted_entries"));
+  }
+  hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)sdoc,
+                     (const int32_t*)scnt, (const int32_t*)colptr, (const R*)P, (const double*)cd,
                      (const double*)cpd, V, K, Rw, g, gp);
   TSK_TRY(check_launch("k_word_accum"));
   TSK_TRY(launch_mode_spectra<R>(logb, tab, q, tw, Qs, st));
@@ -2436,6 +2444,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   take((size_t)K * K * 8);          // 15 Gram
   take((size_t)K * K * 8);          // 16 eigenvectors
   take((size_t)K * 8);              // 17 eigenvalues
+  take((size_t)nnz * 4 + 4);        // 18 counts in word order
   void* base = nullptr;
   TSK_TRY(ws_get(ctx, WS_LDA, off, &base));
   auto at = [&](int i) { return reinterpret_cast<char*>(base) + offs[i]; };
@@ -2456,6 +2465,14 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
                      (const int32_t*)skeys, nnz, V, colptr);
   TSK_TRY(check_launch("k_col_bounds"));
+  // documents and counts of the nonzeros in word order (the sort's input
+  // values are no longer needed: their buffer takes the documents)
+  int32_t *sdoc = iota, *scnt = (int32_t*)at(18);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(tsk::k_sorted_entries, dim3(grid_for((size_t)nnz, 256)), dim3(256), 0, st,
+                       (const int32_t*)svals, (const int32_t*)rowof, cnt, nnz, sdoc, scnt);
+    TSK_TRY(check_launch("k_sorted_entries"));
+  }
   // Yout = M2 X
   auto apply = [&](const double* X, double* Yout) -> tsk_status {
     hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min(D, 8192)), dim3(128), 0, st, rowptr, col, cnt, D,
@@ -2465,8 +2482,8 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
                        (const double*)invm, D, K, per_q, qpart);
     hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
     TSK_TRY(check_launch("k_doc_q"));
-    hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)svals,
-                       (const int32_t*)colptr, (const int32_t*)rowof, cnt, (const double*)P, (const double*)cpd,
+    hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)sdoc,
+                       (const int32_t*)scnt, (const int32_t*)colptr, (const double*)P, (const double*)cpd,
                        (const double*)invm, X, (const double*)q, (const double*)deff, alpha0, V, K, Yout);
     return check_launch("k_lda_m2_apply");
   };
