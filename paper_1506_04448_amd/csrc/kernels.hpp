@@ -703,21 +703,19 @@ __global__ __launch_bounds__(256) void k_als_gram(const double* X, const double*
   if (threadIdx.x == 0) G[(size_t)r * k + c] = gx * gy;
 }
 
-// P = G^+ for a symmetric k x k G (k <= 64), one work-group of 256 threads:
-// cyclic Jacobi rotations to G = E diag(d) E^T, then P = E diag(1/d) E^T over
-// the eigenvalues d > 1e-12 max|d| (the others dropped).  Sweeps stop when
-// the off-diagonal mass is below 1e-30 of the total, at most 60.
-__global__ __launch_bounds__(256) void k_als_pinv(const double* G, double* P, int k) {
-  __shared__ double A[64 * 64];
-  __shared__ double E[64 * 64];
-  __shared__ double rot[2];
-  __shared__ double red[4];
+// Jacobi sweeps on the symmetric k x k matrix A (k <= 128, row-major in
+// LDS), accumulating the rotations into E (LDS, the identity on entry), by
+// the 256 threads of a work-group: the round-robin order, every round
+// rotating k/2 disjoint index pairs at once (player 0 fixed, the others
+// moving round a circle; a dummy player when k is odd), until the
+// off-diagonal mass is below 1e-30 of the total (at most 60 sweeps).  On
+// return A is diagonal to that accuracy: A = E diag E^T of the input.
+__device__ inline void jacobi_sweeps(double* A, double* E, int k, double* red) {
+  __shared__ double rc[64], rs[64];
+  __shared__ int rp[64], rq[64];
   const int tid = threadIdx.x;
-  for (int e = tid; e < k * k; e += 256) {
-    A[e] = G[e];
-    E[e] = (e / k == e % k) ? 1.0 : 0.0;
-  }
-  __syncthreads();
+  const int m = k + (k & 1);  // players
+  const int np = m / 2;       // pairs per round
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < k * k; e += 256) {
@@ -728,43 +726,74 @@ __global__ __launch_bounds__(256) void k_als_pinv(const double* G, double* P, in
     off = block_sum<256>(off, red);
     tot = block_sum<256>(tot, red);
     if (!(off > 1e-30 * tot)) break;  // uniform: every thread has the same sums
-    for (int p = 0; p < k - 1; ++p) {
-      for (int q = p + 1; q < k; ++q) {
-        if (tid == 0) {
+    for (int round = 0; round + 1 < m; ++round) {
+      if (tid < np) {
+        const int a = tid == 0 ? 0 : (round + tid) % (m - 1) + 1;
+        const int b = tid == 0 ? round % (m - 1) + 1 : (round - tid + m - 1) % (m - 1) + 1;
+        const int p = min(a, b), q = max(a, b);
+        double c = 1.0, s = 0.0;
+        if (q < k) {
           const double apq = A[p * k + q];
-          double c = 1.0, s = 0.0;
           if (apq != 0.0) {
             const double theta = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
             const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
           }
-          rot[0] = c;
-          rot[1] = s;
         }
-        __syncthreads();
-        const double c = rot[0], s = rot[1];
-        if (s != 0.0) {
-          // A <- J^T A J: columns p, q, then rows p, q; E <- E J
-          if (tid < k) {
-            const double ap = A[tid * k + p], aq = A[tid * k + q];
-            A[tid * k + p] = c * ap - s * aq;
-            A[tid * k + q] = s * ap + c * aq;
-            const double ep = E[tid * k + p], eq = E[tid * k + q];
-            E[tid * k + p] = c * ep - s * eq;
-            E[tid * k + q] = s * ep + c * eq;
-          }
-          __syncthreads();
-          if (tid < k) {
-            const double ap = A[p * k + tid], aq = A[q * k + tid];
-            A[p * k + tid] = c * ap - s * aq;
-            A[q * k + tid] = s * ap + c * aq;
-          }
-        }
-        __syncthreads();
+        rp[tid] = p;
+        rq[tid] = q;
+        rc[tid] = c;
+        rs[tid] = s;
       }
+      __syncthreads();
+      // A <- J^T A J: columns p, q of A and of E, every pair at once ...
+      for (int e = tid; e < np * k; e += 256) {
+        const int i = e / k, r = e - i * k;
+        const double s = rs[i];
+        if (s != 0.0) {
+          const double c = rc[i];
+          const int p = rp[i], q = rq[i];
+          const double ap = A[r * k + p], aq = A[r * k + q];
+          A[r * k + p] = c * ap - s * aq;
+          A[r * k + q] = s * ap + c * aq;
+          const double ep = E[r * k + p], eq = E[r * k + q];
+          E[r * k + p] = c * ep - s * eq;
+          E[r * k + q] = s * ep + c * eq;
+        }
+      }
+      __syncthreads();
+      // ... then rows p, q of A
+      for (int e = tid; e < np * k; e += 256) {
+        const int i = e / k, r = e - i * k;
+        const double s = rs[i];
+        if (s != 0.0) {
+          const double c = rc[i];
+          const int p = rp[i], q = rq[i];
+          const double ap = A[p * k + r], aq = A[q * k + r];
+          A[p * k + r] = c * ap - s * aq;
+          A[q * k + r] = s * ap + c * aq;
+        }
+      }
+      __syncthreads();
     }
   }
+}
+
+// P = G^+ for a symmetric k x k G (k <= 64), one work-group of 256 threads:
+// Jacobi sweeps to G = E diag(d) E^T, then P = E diag(1/d) E^T over the
+// eigenvalues d > 1e-12 max|d| (the others dropped).
+__global__ __launch_bounds__(256) void k_als_pinv(const double* G, double* P, int k) {
+  __shared__ double A[64 * 64];
+  __shared__ double E[64 * 64];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * k; e += 256) {
+    A[e] = G[e];
+    E[e] = (e / k == e % k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi_sweeps(A, E, k, red);
   double dmax = 0.0;
   for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(A[j * k + j]));
   for (int e = tid; e < k * k; e += 256) {

@@ -70,17 +70,12 @@ __global__ __launch_bounds__(256) void k_gram2(const double* X, const double* Y,
 
 // Eigenpairs of the symmetric part of the k x k matrix G (k <= 100), one
 // work-group of 256 threads with the matrix and the eigenvectors in dynamic
-// LDS: Jacobi sweeps in the round-robin order, every round rotating k/2
-// disjoint index pairs at once (player 0 fixed, the others moving round a
-// circle; a dummy player when k is odd), until the off-diagonal mass is below
-// 1e-30 of the total (at most 60 sweeps).  E[r][j] is component r of
-// eigenvector j, d[j] its eigenvalue.
+// LDS (jacobi_sweeps).  E[r][j] is component r of eigenvector j, d[j] its
+// eigenvalue.
 __global__ __launch_bounds__(256) void k_jacobi_eig(const double* G, int k, double* E, double* d) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* A = reinterpret_cast<double*>(lds);
   double* Ev = A + (size_t)k * k;
-  __shared__ double rc[64], rs[64];
-  __shared__ int rp[64], rq[64];
   __shared__ double red[4];
   const int tid = threadIdx.x;
   for (int e = tid; e < k * k; e += 256) {
@@ -89,70 +84,7 @@ __global__ __launch_bounds__(256) void k_jacobi_eig(const double* G, int k, doub
     Ev[e] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int m = k + (k & 1);  // players
-  const int np = m / 2;       // pairs per round
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < k * k; e += 256) {
-      const double v = A[e] * A[e];
-      tot += v;
-      if (e / k != e % k) off += v;
-    }
-    off = block_sum<256>(off, red);
-    tot = block_sum<256>(tot, red);
-    if (!(off > 1e-30 * tot)) break;
-    for (int round = 0; round + 1 < m; ++round) {
-      if (tid < np) {
-        const int a = tid == 0 ? 0 : (round + tid) % (m - 1) + 1;
-        const int b = tid == 0 ? round % (m - 1) + 1 : (round - tid + m - 1) % (m - 1) + 1;
-        const int p = min(a, b), q = max(a, b);
-        double c = 1.0, s = 0.0;
-        if (q < k) {
-          const double apq = A[p * k + q];
-          if (apq != 0.0) {
-            const double theta = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-          }
-        }
-        rp[tid] = p;
-        rq[tid] = q;
-        rc[tid] = c;
-        rs[tid] = s;
-      }
-      __syncthreads();
-      // columns p, q of A and of the eigenvectors, every pair at once
-      for (int e = tid; e < np * k; e += 256) {
-        const int i = e / k, r = e - i * k;
-        const double s = rs[i];
-        if (s != 0.0) {
-          const double c = rc[i];
-          const int p = rp[i], q = rq[i];
-          const double ap = A[r * k + p], aq = A[r * k + q];
-          A[r * k + p] = c * ap - s * aq;
-          A[r * k + q] = s * ap + c * aq;
-          const double ep = Ev[r * k + p], eq = Ev[r * k + q];
-          Ev[r * k + p] = c * ep - s * eq;
-          Ev[r * k + q] = s * ep + c * eq;
-        }
-      }
-      __syncthreads();
-      // then rows p, q of A
-      for (int e = tid; e < np * k; e += 256) {
-        const int i = e / k, r = e - i * k;
-        const double s = rs[i];
-        if (s != 0.0) {
-          const double c = rc[i];
-          const int p = rp[i], q = rq[i];
-          const double ap = A[p * k + r], aq = A[q * k + r];
-          A[p * k + r] = c * ap - s * aq;
-          A[q * k + r] = s * ap + c * aq;
-        }
-      }
-      __syncthreads();
-    }
-  }
+  jacobi_sweeps(A, Ev, k, red);
   for (int e = tid; e < k * k; e += 256) E[e] = Ev[e];
   for (int j = tid; j < k; j += 256) d[j] = A[j * k + j];
 }
