@@ -136,6 +136,7 @@ struct SymPowerArgs {
   const cx<float>* S;     // [B][b] spectra
   const cx<float>* s;     // [B][b] time-domain sketches
   const cx<float>* tw;    // pass table of the b-point transform
+  const cx<float>* tw2;   // pass table of the b/2-point transform
   const float* U;         // [L][n]
   float* V;               // [L][B][n]  Re v
   double* lam_per;        // [L][B] u . Re v (mode 1)
@@ -183,23 +184,32 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
     u1[q] = k < b ? buf.get(k) : cx<float>{0.f, 0.f};
   }
   __syncthreads();
-  // U_2 = F(s_2)
+  // U_2 = F(s_2): s_2 sits on the even positions 2h mod b only, so U_2 is the
+  // b/2-point transform E of its even samples, repeated: U_2[k] = E[k mod b/2]
+  constexpr int H = b / 2;
+  constexpr int PH = PK / 2;  // the thread's bins below b/2 (NT divides b/2)
+  const Twid<float> tw2{a.tw2, nullptr};
   for (int t = threadIdx.x; t < 2 * PL; t += NT) re[t] = 0.f;
   __syncthreads();
-  sym_count_sketch<float>(a.srt2 + tb, a.ord2 + tb, n, NT, [&](uint32_t i) { return u[i] * u[i]; }, put);
+  auto put2 = [&](uint32_t t, cx<float> v) { buf.put((int)(t >> 1), v); };
+  sym_count_sketch<float>(a.srt2 + tb, a.ord2 + tb, n, NT, [&](uint32_t i) { return u[i] * u[i]; }, put2);
   __syncthreads();
-  fft_soa<float, LOGB, NT, false>(buf, tw);
-  // P_1 = S o (conj U_1^2 + conj U_2) in place; P_2 = S o conj U_1 kept
+  fft_soa<float, LOGB - 1, NT, false>(buf, tw2);
+  // P_1 = S o (conj U_1^2 + conj U_2) in place at bins k and k + b/2, which
+  // share E[k] (each thread writes only the position it read and one above
+  // b/2); P_2 = S o conj U_1 kept
   const cx<float>* Sm = a.S + (size_t)m * b;
 #pragma unroll
-  for (int q = 0; q < PK; ++q) {
+  for (int q = 0; q < PH; ++q) {
     const int k = threadIdx.x + q * NT;
-    if (k < b) {
-      const cx<float> sk = Sm[k];
-      const cx<float> c1 = cconj(u1[q]);
-      const cx<float> c2 = cconj(buf.get(k));
-      buf.put(k, cmul(sk, cadd(cmul(c1, c1), c2)));
-      u1[q] = cmul(sk, c1);
+    const cx<float> c2 = cconj(buf.get(k));
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int qq = q + half * PH, kk = k + half * H;
+      const cx<float> sk = Sm[kk];
+      const cx<float> c1 = cconj(u1[qq]);
+      buf.put(kk, cmul(sk, cadd(cmul(c1, c1), c2)));
+      u1[qq] = cmul(sk, c1);
     }
   }
   __syncthreads();
@@ -212,13 +222,12 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
     vp[i] = c.x * (sc / 6.f);
   }
   __syncthreads();
+  // c_3 is read at even positions only: c_3[2t] is the b/2-point inverse
+  // transform of the folded spectrum P_2[k] + P_2[k + b/2]
 #pragma unroll
-  for (int q = 0; q < PK; ++q) {
-    const int k = threadIdx.x + q * NT;
-    if (k < b) buf.put(k, u1[q]);
-  }
+  for (int q = 0; q < PH; ++q) buf.put(threadIdx.x + q * NT, cadd(u1[q], u1[q + PH]));
   __syncthreads();
-  fft_soa<float, LOGB, NT, true>(buf, tw);
+  fft_soa<float, LOGB - 1, NT, true>(buf, tw2);
   const cx<float>* sm = a.s + (size_t)m * b;
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) {
@@ -226,7 +235,7 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
     const uint32_t h = sym_pos(e);
     const int qq = sym_rot(e);
     const float ui = u[i];
-    const cx<float> c3 = rot(buf.get((int)((2u * h) & (uint32_t)(b - 1))), (8 - 2 * qq) & 3);
+    const cx<float> c3 = rot(buf.get((int)(h & (uint32_t)(H - 1))), (8 - 2 * qq) & 3);  // c_3[2h mod b]
     const cx<float> s3 = rot(sm[(3u * h) & (uint32_t)(b - 1)], (12 - 3 * qq) & 3);
     const float v = vp[i] + (ui * c3.x * sc + ui * ui * s3.x) * (1.f / 3.f);
     a.V[((size_t)tau * B + m) * n + i] = v;

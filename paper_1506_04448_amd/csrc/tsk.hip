@@ -2137,7 +2137,9 @@ tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, cons
   if (tsk::sym_power_lds(tab->logb, tab->n) > kMaxLds - 256)
     return tsk::fail(TSK_EUNSUPPORTED, "symmetric power step: n=%d too large for b=%d", tab->n, tab->b);
   const cx<float>* tw = nullptr;
+  const cx<float>* tw2 = nullptr;
   TSK_TRY(get_tw<float>(ctx, tab->logb + 1, &tw, tsk::sym_threads(tab->logb)));
+  TSK_TRY(get_tw<float>(ctx, tab->logb, &tw2, tsk::sym_threads(tab->logb)));
   tsk::SymPowerArgs a;
   const size_t cnt = (size_t)tab->B * tab->n;
   a.hq = tab->hq;
@@ -2150,6 +2152,7 @@ tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, cons
   a.S = reinterpret_cast<const cx<float>*>(S32);
   a.s = reinterpret_cast<const cx<float>*>(s32);
   a.tw = tw;
+  a.tw2 = tw2;
   a.U = U;
   a.V = V;
   a.lam_per = lam_per;
