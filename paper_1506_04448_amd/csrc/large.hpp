@@ -91,18 +91,23 @@ __global__ __launch_bounds__(1024) void k_combine_rank1(const cx<double>* E, int
   cx<double>* out = prod + ((size_t)vec * B + m) * (H + 1);
   const cx<double>* S = S64 ? S64 + (size_t)m * (H + 1) : nullptr;
   double acc = 0.0;
-  for (int k = threadIdx.x; k <= H; k += 1024) {
-    cx<double> p = {1.0, 0.0};
+  // one thread per bin pair (k, H - k), k <= H/2: both bins use the same two
+  // recombined values of each mode
+  for (int k = threadIdx.x; k <= H / 2; k += 1024) {
+    const int kh = H - k;
+    cx<double> p = {1.0, 0.0}, ph = {1.0, 0.0};
     for (int j = 0; j < 3; ++j) {
       const cx<double>* Ej = Ev + (size_t)j * Rr * M;
-      const cx<double> Za = recombine(Ej, M, Rr, Wb, b, k % H);
-      const cx<double> Zb = recombine(Ej, M, Rr, Wb, b, (H - k) % H);
+      const cx<double> Za = recombine(Ej, M, Rr, Wb, b, k);
+      const cx<double> Zb = recombine(Ej, M, Rr, Wb, b, kh % H);
       p = cmul(p, r2c_post(Za, Zb, Wb[k]));
+      ph = cmul(ph, r2c_post(Zb, Za, Wb[kh]));
     }
     out[k] = p;
+    if (kh != k) out[kh] = ph;
     if (S) {
-      const double w = (k == 0 || k == H) ? 1.0 : 2.0;
-      acc += w * (S[k].x * p.x + S[k].y * p.y);
+      acc += (k == 0 ? 1.0 : 2.0) * (S[k].x * p.x + S[k].y * p.y);
+      if (kh != k) acc += (kh == H ? 1.0 : 2.0) * (S[kh].x * ph.x + S[kh].y * ph.y);
     }
   }
   if (lam_per) {
