@@ -56,6 +56,24 @@ def test_whitening_matches_oracle(ctx, D, V, K, L):
     assert np.abs(P40 - We @ We.T).max() <= 1e-6 * np.abs(We @ We.T).max()
 
 
+def test_whitening_at_the_largest_k_matches_the_same_iteration(ctx):
+    """K = 100 (the largest the eigensolver takes, 50 rotations per round): the
+    GPU subspace iteration equals the oracle's on the same start block."""
+    D, V, K = 3000, 240, 100
+    print(f"whiten D={D} V={V} K={K}", flush=True)
+    C = lda_corpus(D=D, V=V, K=K, seed=D + V, mean_len=60.0, min_len=1, alpha=0.3)
+    a0 = float(C.alpha.sum())
+    M2 = olda.empirical_m2(C, a0)
+    Om = np.random.default_rng(K).standard_normal((V, K))
+    rp, col, cnt = _dev(C)
+    W, sig = tsk.lda_whiten(ctx, rp, col, cnt, D, V, K, a0, torch.from_numpy(Om).to(DEV), iters=8)
+    W, sig = W.cpu().numpy(), sig.cpu().numpy()
+    Wr, sr = olda.whitening_subspace(M2, Om, 8)
+    np.testing.assert_allclose(sig, sr, rtol=1e-9)
+    P, Pr = W @ W.T, Wr @ Wr.T
+    assert np.abs(P - Pr).max() <= 1e-9 * np.abs(Pr).max()
+
+
 def test_recovery_matches_oracle(ctx):
     rng = np.random.default_rng(3)
     V, K, k = 500, 9, 6
