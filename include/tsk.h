@@ -21,11 +21,13 @@
  *     (interleaved re, im), for each of the B independent sketches:
  *       S64 : double[B][b/2+1][2]  master copy (FP64)
  *       S32 : float [B][b/2+1][2]  working copy used by the FP32 power method
- *   - Limits: 1 <= n <= 65535, b a power of two with 64 <= b <= 16384,
- *     1 <= B <= 64, 1 <= L <= 65535, T >= 1, 1 <= k <= n.  A power step
- *     also needs its work-group's LDS (the half spectrum, twiddles and the
- *     n-vector) to fit one CU; requests outside the built kernel limits
- *     return TSK_EUNSUPPORTED.
+ *   - Limits: 1 <= n <= 65535, b a power of two with 64 <= b <= 65536,
+ *     1 <= B <= 64, 1 <= L <= 65535, T >= 1, 1 <= k <= n.  FP64 power
+ *     steps and the document build stop at b = 16384.  A power step at
+ *     b <= 32768 also needs its work-group's LDS (the half spectrum and the
+ *     n-vector) to fit one CU, which bounds n (19348 in FP64 at b = 1024,
+ *     23252 in FP32 at b = 16384); requests outside the built kernel
+ *     limits return TSK_EUNSUPPORTED.
  */
 #ifndef TSK_H
 #define TSK_H

@@ -89,20 +89,34 @@ constexpr int fft_rmax(int N, int NT) {
   return (N / NT) >= 16 ? 16 : ((N / NT) >= 8 ? 8 : ((N / NT) >= 4 ? 4 : 2));
 }
 constexpr int pass_radix(int N, int NS, int RMAX) { return (N / NS) >= RMAX ? RMAX : N / NS; }
+// Number of passes of the plan from stride NS on.
+constexpr int passes_from(int N, int NS, int RMAX) {
+  int c = 0;
+  for (int ns = NS; ns < N; ns *= pass_radix(N, ns, RMAX)) ++c;
+  return c;
+}
+// Stride of the pass that has `left` passes after it (0: the last pass).
+constexpr int pass_stride(int N, int NT, int left) {
+  int ns = 1;
+  while (passes_from(N, ns, fft_rmax(N, NT)) > left + 1) ns *= pass_radix(N, ns, fft_rmax(N, NT));
+  return ns;
+}
 
 // Per-pass twiddle table: for every pass with stride NS > 1 and radix R, the
 // entries W_{NS R}^{r k} for r = 1..R-1 and k < NS, stored at
 // [pass offset + (r-1) NS + k], so the lanes of a wave read consecutive
-// entries.  Built on the host in FP64 and rounded once.
-constexpr int pass_table_len(int N, int NT) {
+// entries.  Built on the host in FP64 and rounded once.  pass_table_off is
+// the offset of the pass with stride NS.
+constexpr int pass_table_off(int N, int NT, int NS) {
   int len = 0;
-  for (int ns = 1; ns < N;) {
+  for (int ns = 1; ns < NS;) {
     const int rad = pass_radix(N, ns, fft_rmax(N, NT));
     if (ns > 1) len += (rad - 1) * ns;
     ns *= rad;
   }
   return len;
 }
+constexpr int pass_table_len(int N, int NT) { return pass_table_off(N, NT, N); }
 
 // Twiddles of one real transform of length b = 2H through an H-point complex
 // transform: the pass table of the H-point FFT followed by W_b^k, k = 0..H.
@@ -344,7 +358,7 @@ __device__ __forceinline__ void stockham_pass(const Soa<R>& buf,
 // next pass's twiddles are loaded before the current pass runs (their global
 // loads overlap its arithmetic, at the cost of registers); without PF each
 // pass loads its own at its start.
-template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, bool PF, bool SKIPLAST = false>
+template <typename R, int N, int NS, int NT, int RMAX, bool INV, int TOFF, bool PF, int SKIP = 0>
 __device__ __forceinline__ void fft_passes(
     const Soa<R>& buf, const Twid<R>& twp,
     const PassTw<R, (N / pass_radix(N, NS, RMAX) + NT - 1) / NT, pass_radix(N, NS, RMAX) - 1>& cur) {
@@ -365,23 +379,35 @@ __device__ __forceinline__ void fft_passes(
     load_pass_tw<R, N, RAD, NS, NT, TOFF>(own, twp, tid);
     stockham_pass<R, N, RAD, NS, NT, INV>(buf, own, tid);
   }
-  // SKIPLAST: stop before the last pass (its inputs stay in the buffer).
-  if constexpr (NS2 < N && !(SKIPLAST && NS2 * RAD2 == N))
-    fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, PF, SKIPLAST>(buf, twp, nxt);
+  // SKIP: the last SKIP passes are left out (their inputs stay in the buffer).
+  if constexpr (NS2 < N && passes_from(N, NS2, RMAX) > SKIP)
+    fft_passes<R, N, NS2, NT, RMAX, INV, TOFF2, PF, SKIP>(buf, twp, nxt);
 }
 
 // Complex FFT of length N = 2^LOGN in LDS (SoA, padded); ends with a barrier.
-// PF as in fft_passes.  With SKIPLAST the last pass is left out: for a last
+// PF as in fft_passes.  SKIP = 1 leaves the last pass out: for a last
 // pass of radix 2 the buffer then holds a[j] and b[j] = in[j + N/2], and
 // X[j] = a[j] + W_N^j b[j], X[j + N/2] = a[j] - W_N^j b[j] (conjugate twiddle
 // for INV), with W_N^j at pass_table_len(N, NT) - N/2 + j of the pass table.
-template <typename R, int LOGN, int NT, bool INV, bool PF = true, bool SKIPLAST = false>
+template <typename R, int LOGN, int NT, bool INV, bool PF = true, int SKIP = 0>
 __device__ __forceinline__ void fft_soa(const Soa<R>& buf, const Twid<R>& tw) {
   constexpr int N = 1 << LOGN;
   constexpr int RMAX = fft_rmax(N, NT);
   constexpr int RAD = pass_radix(N, 1, RMAX);
+  static_assert(passes_from(N, 1, RMAX) > SKIP, "at least one pass runs");
   PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> first;  // the first pass has no twiddles
-  fft_passes<R, N, 1, NT, RMAX, INV, 0, PF, SKIPLAST>(buf, tw, first);
+  fft_passes<R, N, 1, NT, RMAX, INV, 0, PF, SKIP>(buf, tw, first);
+}
+
+// The passes of the same transform from stride NS on (each loads its own
+// twiddles), leaving the last SKIP out; ends with a barrier.
+template <typename R, int LOGN, int NT, bool INV, int NS, int SKIP = 0>
+__device__ __forceinline__ void fft_soa_from(const Soa<R>& buf, const Twid<R>& tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int RMAX = fft_rmax(N, NT);
+  constexpr int RAD = pass_radix(N, NS, RMAX);
+  PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> none;  // unused without PF
+  fft_passes<R, N, NS, NT, RMAX, INV, pass_table_off(N, NT, NS), false, SKIP>(buf, tw, none);
 }
 
 }  // namespace tsk

@@ -571,7 +571,22 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   }
   if (tid == 0) buf.put(H / 2, cscale(cconj(pmid), R(2)));
   __syncthreads();
-  fft_soa<R, LOGH, NT, true, false, FUSE>(buf, tw);
+  // For n small against H the inverse also leaves out the pass before the
+  // last (radix R3, stride NS3).  Its inputs are the NS3-point transforms D_g
+  // of the subsequences g + 2 R3 t (g < 2 R3, D_g at g NS3 + k), so each
+  // output the read-off needs is z[p] = sum_g W_H^{-g p} D_g[p mod NS3]:
+  // 2 R3 terms per output instead of the whole pass.
+  constexpr int RMX = fft_rmax(H, NT);
+  constexpr bool PRUNABLE = FUSE && passes_from(H, 1, RMX) >= 3;
+  constexpr int NS3 = pass_stride(H, NT, 1);
+  constexpr int R3 = pass_radix(H, NS3, RMX);
+  const bool prune = PRUNABLE && n * R3 <= H;
+  if constexpr (PRUNABLE) {
+    fft_soa<R, LOGH, NT, true, false, 2>(buf, tw);
+    if (!prune) fft_soa_from<R, LOGH, NT, true, NS3, 1>(buf, tw);
+  } else {
+    fft_soa<R, LOGH, NT, true, false, FUSE>(buf, tw);
+  }
 
   // Each forward product carried a factor 2 and the packing another.
   const R scale = R(1) / R(4 * b);
@@ -585,11 +600,48 @@ __global__ __launch_bounds__(power_threads<R>(LOGB - 1), power_waves<R>(LOGB - 1
   for (int i = orid; i < n; i += NT) {
     const uint32_t e = tab_lds ? stab[4 * n + i] : hx1[i];
     R val;
-    if constexpr (FUSE) {  // the skipped last inverse pass, for this output only
+    if constexpr (FUSE) {  // the skipped last inverse pass(es), for this output only
       const uint32_t t = e >> 1, p = t >> 1;
       const int j = (int)(p & (uint32_t)(H / 2 - 1));
-      const cx<R> c = cmulc(buf.get(j + H / 2), a.twg[TLAST + j]);
-      const cx<R> X = p < (uint32_t)(H / 2) ? cadd(buf.get(j), c) : csub(buf.get(j), c);
+      const cx<R> W = a.twg[TLAST + j];  // W_H^j; W_H^{-p} = +-conj(W)
+      cx<R> E0, E1;
+      if (PRUNABLE && prune) {
+        // E_c = sum_r (W_H^{-2p})^r D_{c+2r}[k], two-level Horner (groups of
+        // RI terms), so no term passes through more than a few roundings.
+        constexpr int RI = R3 >= 4 ? 4 : R3;
+        const int k = (int)(p & (uint32_t)(NS3 - 1));
+        const int pk = pidx(k);
+        auto d = [&](int g) -> cx<R> {
+          return buf.at(NS3 % 64 == 0 ? pk + poff(g * NS3) : pidx(g * NS3 + k));
+        };
+        auto mad = [](cx<R> x, cx<R> w, cx<R> y) -> cx<R> {
+          return {x.x * w.x - x.y * w.y + y.x, x.x * w.y + x.y * w.x + y.y};
+        };
+        const cx<R> w2 = cconj(cmul(W, W));
+        cx<R> wo = w2;
+#pragma unroll
+        for (int s2 = 1; s2 < RI; s2 *= 2) wo = cmul(wo, wo);
+        cx<R> E[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          cx<R> acc{R(0), R(0)};
+#pragma unroll
+          for (int r1 = R3 / RI - 1; r1 >= 0; --r1) {
+            cx<R> in = d(c + 2 * (r1 * RI + RI - 1));
+#pragma unroll
+            for (int r0 = RI - 2; r0 >= 0; --r0) in = mad(in, w2, d(c + 2 * (r1 * RI + r0)));
+            acc = r1 == R3 / RI - 1 ? in : mad(acc, wo, in);
+          }
+          E[c] = acc;
+        }
+        E0 = E[0];
+        E1 = E[1];
+      } else {
+        E0 = buf.get(j);
+        E1 = buf.get(j + H / 2);
+      }
+      const cx<R> c = cmulc(E1, W);
+      const cx<R> X = p < (uint32_t)(H / 2) ? cadd(E0, c) : csub(E0, c);
       val = ((t & 1u) ? X.y : X.x) * scale;
     } else {
       val = load_packed(buf, e >> 1) * scale;

@@ -243,6 +243,58 @@ def test_factor_build_matches_eq2(ctx, n, k, b, B):
         assert rel(got[m], ref) < 1e-12, (m, rel(got[m], ref))
 
 
+def _factor_sketches(ctx, seed, n, k, b, B):
+    """Factor build (Eq. (2)) of a random rank-k tensor on the GPU and in the oracle."""
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(1, 10, k)
+    A = rng.standard_normal((k, n))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    tab, h, xi = _tables(ctx, seed, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_factors(ctx, tab, torch.from_numpy(lam).to(DEV), torch.from_numpy(A).to(DEV),
+                             S64, S32)
+    S_time = np.stack([oracle.sketch_factors(lam, A, h[m], xi[m], b) for m in range(B)])
+    return tab, h, xi, S64, S32, S_time
+
+
+# The largest n a power step takes: n = 65535 through the split transforms
+# (b = 65536); below that the work-group's LDS (half spectrum and u) bounds n,
+# exactly at 19348 (FP64, b = 1024) and 23252 (FP32, b = 16384).
+@pytest.mark.parametrize("b,dtype,tol,n_max", [(1024, torch.float64, 1e-12, 19348),
+                                                (16384, torch.float32, 1e-5, 23252),
+                                                (65536, torch.float32, 1e-5, 65535)])
+def test_largest_n_factor_build_and_power_step(ctx, b, dtype, tol, n_max):
+    """n = 65535 (the largest dimension the tables take) through the factor build, then one
+    power step (Prop. 1 per sketch, the median and normalisation) at the largest n it
+    supports, far above what one work-group stages for a fused median; one more
+    coordinate is refused."""
+    B, L = 3, 2
+    print(f"largest n b={b} {dtype} n_max={n_max}", flush=True)
+    tab, h, xi, S64, S32, S_time = _factor_sketches(ctx, b + 7, 65535, 3, b, B)
+    assert rel(_time_sketch(ctx, tab, S64), S_time) < 1e-12
+    if n_max < 65535:
+        tab, h, xi, S64, S32, S_time = _factor_sketches(ctx, b + 8, n_max, 3, b, B)
+        t2, _, _ = _tables(ctx, 3, n_max + 1, b, B)
+        S64b, S32b = tsk.new_sketch(t2, DEV)
+        with pytest.raises(tsk.TskError, match="LDS"):
+            tsk.power_update(ctx, t2, torch.zeros((L, n_max + 1), dtype=dtype, device=DEV),
+                             S64=S64b, S32=S32b)
+    rng = np.random.default_rng(b)
+    U = rng.standard_normal((L, n_max))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    if dtype == torch.float32:
+        U = U.astype(np.float32).astype(np.float64)
+    V = torch.empty((L, B, n_max), dtype=dtype, device=DEV)
+    Uo = tsk.power_update(ctx, tab, torch.from_numpy(U).to(device=DEV, dtype=dtype),
+                          S64=S64, S32=S32, V=V)
+    Vr, Ur, _ = oracle.power_update(S_time, h, xi, U)
+    Vg = V.cpu().numpy()
+    for tau in range(L):
+        for m in range(B):
+            assert rel(Vg[tau, m], Vr[tau, m]) < tol, (tau, m, rel(Vg[tau, m], Vr[tau, m]))
+    assert rel(Uo.cpu().numpy(), Ur) < tol
+
+
 # ----------------------------------------------------------------------------- decompose
 
 def test_decompose_fp64_small_config(ctx):
