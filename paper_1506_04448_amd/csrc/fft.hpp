@@ -19,6 +19,8 @@
 // carries no 1/N factor.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 namespace tsk {
@@ -399,15 +401,94 @@ __device__ __forceinline__ void fft_soa(const Soa<R>& buf, const Twid<R>& tw) {
   fft_passes<R, N, 1, NT, RMAX, INV, 0, PF, SKIP>(buf, tw, first);
 }
 
-// The passes of the same transform from stride NS on (each loads its own
-// twiddles), leaving the last SKIP out; ends with a barrier.
-template <typename R, int LOGN, int NT, bool INV, int NS, int SKIP = 0>
+// The passes of the same transform from stride NS on (NS > 1), leaving the
+// last SKIP out; ends with a barrier.  PF as in fft_passes.
+template <typename R, int LOGN, int NT, bool INV, int NS, int SKIP = 0, bool PF = false>
 __device__ __forceinline__ void fft_soa_from(const Soa<R>& buf, const Twid<R>& tw) {
   constexpr int N = 1 << LOGN;
   constexpr int RMAX = fft_rmax(N, NT);
   constexpr int RAD = pass_radix(N, NS, RMAX);
-  PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> none;  // unused without PF
-  fft_passes<R, N, NS, NT, RMAX, INV, pass_table_off(N, NT, NS), false, SKIP>(buf, tw, none);
+  constexpr int TOFF = pass_table_off(N, NT, NS);
+  static_assert(NS > 1 && passes_from(N, NS, RMAX) > SKIP, "at least one twiddled pass runs");
+  PassTw<R, (N / RAD + NT - 1) / NT, RAD - 1> cur;  // read only with PF
+  if constexpr (PF) load_pass_tw<R, N, RAD, NS, NT, TOFF>(cur, tw, (int)threadIdx.x);
+  fft_passes<R, N, NS, NT, RMAX, INV, TOFF, PF, SKIP>(buf, tw, cur);
+}
+
+// Output p of an inverse N-point transform run without its last two passes
+// (fft_soa with SKIP = 2).  Before those passes group g < G = N / NS3 of the
+// buffer holds the NS3-point transform D_g of the inputs congruent to g
+// modulo G (D_g[k] at g NS3 + k), so z[p] = sum_g W_N^{-g p} D_g[p mod NS3].
+// The sum is a Horner scheme in base 4 (base 2 at the top when G is not a
+// power of 4) whose level l uses W_N^{-4^l p}, each read from the last
+// pass's twiddle row (W_N^j, j < NSL) times a power of W_RL, so every term
+// passes through a few roundings per level only.  `pass` is the pass table.
+template <typename R, int LOGN, int NT>
+__device__ __forceinline__ cx<R> inverse_output_from_groups(const Soa<R>& buf, const cx<R>* pass, int p) {
+  constexpr int N = 1 << LOGN;
+  constexpr int RMAX = fft_rmax(N, NT);
+  static_assert(passes_from(N, 1, RMAX) >= 3, "two passes left out and at least one run");
+  constexpr int NS3 = pass_stride(N, NT, 1);
+  constexpr int NSL = pass_stride(N, NT, 0);
+  constexpr int RL = N / NSL;
+  constexpr int G = N / NS3;
+  static_assert(RL == 2 || RL == 4, "last pass of radix 2 or 4");
+  const cx<R>* wrow = pass + pass_table_off(N, NT, NSL);  // W_N^j, j < NSL
+  // W_N^{-j} for any j: the row entry of j mod NSL times W_RL^{-(j / NSL)}.
+  auto wneg = [&](int j) -> cx<R> {
+    const cx<R> t = wrow[j & (NSL - 1)];
+    const int q = (j / NSL) & (RL - 1);
+    cx<R> w{t.x, -t.y};  // conj
+    if constexpr (RL == 2) {
+      if (q) w = {-w.x, -w.y};
+    } else {  // times i^q
+      if (q & 1) w = {-w.y, w.x};
+      if (q & 2) w = {-w.x, -w.y};
+    }
+    return w;
+  };
+  auto mad = [](cx<R> x, cx<R> w, cx<R> y) -> cx<R> {
+    return {x.x * w.x - x.y * w.y + y.x, x.x * w.y + x.y * w.x + y.y};
+  };
+  const int k = p & (NS3 - 1);
+  const int pk = pidx(k);
+  auto d = [&](int g) -> cx<R> {
+    return buf.at(NS3 % 64 == 0 ? pk + poff(g * NS3) : pidx(g * NS3 + k));
+  };
+  constexpr int L4 = [] { int l = 0; for (int g = G; g >= 4; g /= 4) ++l; return l; }();  // levels of 4
+  constexpr bool TOP2 = (1 << (2 * L4)) != G;  // one more level of 2
+  cx<R> wl[L4 + 1];
+#pragma unroll
+  for (int l = 0; l < L4 + (TOP2 ? 1 : 0); ++l) wl[l] = wneg((int)(((unsigned)p << (2 * l)) & (unsigned)(N - 1)));
+  // sum_{j < 4^(LVL+1)} w^j d(base + j), with wl[LVL] = w^(4^LVL)
+  auto level = [&](auto&& self, auto lvl, int base) -> cx<R> {
+    constexpr int LVL = decltype(lvl)::value;
+    cx<R> acc;
+#pragma unroll
+    for (int c = 3; c >= 0; --c) {
+      cx<R> x;
+      if constexpr (LVL == 0)
+        x = d(base + c);
+      else
+        x = self(self, std::integral_constant<int, LVL - 1>{}, base + c * (1 << (2 * LVL)));
+      acc = c == 3 ? x : mad(acc, wl[LVL], x);
+    }
+    return acc;
+  };
+  if constexpr (!TOP2) {
+    return level(level, std::integral_constant<int, L4 - 1>{}, 0);
+  } else {
+    constexpr int HALF = G / 2;
+    cx<R> lo, hi;
+    if constexpr (L4 == 0) {
+      lo = d(0);
+      hi = d(1);
+    } else {
+      lo = level(level, std::integral_constant<int, L4 - 1>{}, 0);
+      hi = level(level, std::integral_constant<int, L4 - 1>{}, HALF);
+    }
+    return mad(hi, wl[L4], lo);  // wl[L4] = w^(4^L4) = w^HALF
+  }
 }
 
 }  // namespace tsk

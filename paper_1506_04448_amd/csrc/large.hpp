@@ -301,8 +301,19 @@ __global__ __launch_bounds__(threads_for_h<float>(LOGM)) void k_power_split_out(
   for (int k = threadIdx.x; k < M; k += NT) buf.put(k, src[k]);
   __syncthreads();
   const Twid<float> tw{a.twM, nullptr};
-  fft_soa<float, LOGM, NT, true>(buf, tw);
   const int n = a.n;
+  // With n small against M the transform leaves out its last two passes and
+  // the read-off forms each output it needs from the groups before them.
+  constexpr int RMX = fft_rmax(M, NT);
+  constexpr bool PRUNABLE = passes_from(M, 1, RMX) >= 3;
+  constexpr int NS3 = pass_stride(M, NT, 1);
+  const bool prune = PRUNABLE && n * pass_radix(M, NS3, RMX) <= M;
+  if constexpr (PRUNABLE) {
+    fft_soa<float, LOGM, NT, true, true, 2>(buf, tw);
+    if (!prune) fft_soa_from<float, LOGM, NT, true, NS3, 0, true>(buf, tw);
+  } else {
+    fft_soa<float, LOGM, NT, true>(buf, tw);
+  }
   const uint32_t* hx1 = a.hx + ((size_t)m * 3 + a.rd) * n;
   float* Vrow = a.V + ((size_t)vec * a.B + m) * n;
   const float scale = 2.0f / (float)a.b;
@@ -310,8 +321,15 @@ __global__ __launch_bounds__(threads_for_h<float>(LOGM)) void k_power_split_out(
     const uint32_t e = hx1[i];
     const uint32_t t = e >> 1, p = t >> 1;
     if ((int)(p & 1u) != r) continue;
-    const int q = pidx((int)(p >> 1));
-    const float val = ((t & 1u) ? im[q] : re[q]) * scale;
+    float val;
+    if (PRUNABLE && prune) {
+      const cx<float> z = inverse_output_from_groups<float, LOGM, NT>(buf, a.twM, (int)(p >> 1));
+      val = (t & 1u) ? z.y : z.x;
+    } else {
+      const int q = pidx((int)(p >> 1));
+      val = (t & 1u) ? im[q] : re[q];
+    }
+    val *= scale;
     Vrow[i] = (e & 1u) ? -val : val;
   }
 }
