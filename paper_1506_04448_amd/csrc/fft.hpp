@@ -415,6 +415,12 @@ __device__ __forceinline__ void fft_soa_from(const Soa<R>& buf, const Twid<R>& t
   fft_passes<R, N, NS, NT, RMAX, INV, TOFF, PF, SKIP>(buf, tw, cur);
 }
 
+// Whether inverse_output_from_groups applies to the plan of an N-point
+// transform run by NT threads: at least three passes, the last of radix 2 or 4.
+constexpr bool output_from_groups_ok(int N, int NT) {
+  return passes_from(N, 1, fft_rmax(N, NT)) >= 3 && (fft_last_radix(N, NT) == 2 || fft_last_radix(N, NT) == 4);
+}
+
 // Output p of an inverse N-point transform run without its last two passes
 // (fft_soa with SKIP = 2).  Before those passes group g < G = N / NS3 of the
 // buffer holds the NS3-point transform D_g of the inputs congruent to g
@@ -426,13 +432,11 @@ __device__ __forceinline__ void fft_soa_from(const Soa<R>& buf, const Twid<R>& t
 template <typename R, int LOGN, int NT>
 __device__ __forceinline__ cx<R> inverse_output_from_groups(const Soa<R>& buf, const cx<R>* pass, int p) {
   constexpr int N = 1 << LOGN;
-  constexpr int RMAX = fft_rmax(N, NT);
-  static_assert(passes_from(N, 1, RMAX) >= 3, "two passes left out and at least one run");
+  static_assert(output_from_groups_ok(N, NT), "three passes or more, the last of radix 2 or 4");
   constexpr int NS3 = pass_stride(N, NT, 1);
   constexpr int NSL = pass_stride(N, NT, 0);
   constexpr int RL = N / NSL;
   constexpr int G = N / NS3;
-  static_assert(RL == 2 || RL == 4, "last pass of radix 2 or 4");
   const cx<R>* wrow = pass + pass_table_off(N, NT, NSL);  // W_N^j, j < NSL
   // W_N^{-j} for any j: the row entry of j mod NSL times W_RL^{-(j / NSL)}.
   auto wneg = [&](int j) -> cx<R> {

@@ -305,7 +305,7 @@ __global__ __launch_bounds__(threads_for_h<float>(LOGM)) void k_power_split_out(
   // With n small against M the transform leaves out its last two passes and
   // the read-off forms each output it needs from the groups before them.
   constexpr int RMX = fft_rmax(M, NT);
-  constexpr bool PRUNABLE = passes_from(M, 1, RMX) >= 3;
+  constexpr bool PRUNABLE = output_from_groups_ok(M, NT);
   constexpr int NS3 = pass_stride(M, NT, 1);
   const bool prune = PRUNABLE && n * pass_radix(M, NS3, RMX) <= M;
   if constexpr (PRUNABLE) {

@@ -213,12 +213,30 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
     }
   }
   __syncthreads();
-  fft_soa<float, LOGB, NT, true>(buf, tw);
+  // With n small against b both inverses leave out their last two passes and
+  // the read-offs form the outputs they need from the groups before them.
+  constexpr bool PR1 = output_from_groups_ok(b, NT) && LOGB < 14, PR2 = output_from_groups_ok(H, NT);
+  constexpr int NS1 = pass_stride(b, NT, 1), NS2 = pass_stride(H, NT, 1);
+  const bool prune1 = PR1 && n * pass_radix(b, NS1, fft_rmax(b, NT)) <= b;
+  const bool prune2 = PR2 && n * pass_radix(H, NS2, fft_rmax(H, NT)) <= H;
+  if constexpr (PR1) {
+    fft_soa<float, LOGB, NT, true, true, 2>(buf, tw);
+    if (!prune1) fft_soa_from<float, LOGB, NT, true, NS1, 0, true>(buf, tw);
+  } else {
+    fft_soa<float, LOGB, NT, true>(buf, tw);
+  }
   const float sc = 1.f / (float)b;
   const uint32_t* hq = a.hq + tb;
   for (int i = threadIdx.x; i < n; i += NT) {
     const uint32_t e = hq[i];
-    const cx<float> c = rot(buf.get((int)sym_pos(e)), (4 - sym_rot(e)) & 3);  // conj(sigma) c12[h]
+    cx<float> c12;
+    if constexpr (PR1) {
+      c12 = prune1 ? inverse_output_from_groups<float, LOGB, NT>(buf, a.tw, (int)sym_pos(e))
+                   : buf.get((int)sym_pos(e));
+    } else {
+      c12 = buf.get((int)sym_pos(e));
+    }
+    const cx<float> c = rot(c12, (4 - sym_rot(e)) & 3);  // conj(sigma) c12[h]
     vp[i] = c.x * (sc / 6.f);
   }
   __syncthreads();
@@ -227,7 +245,12 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
 #pragma unroll
   for (int q = 0; q < PH; ++q) buf.put(threadIdx.x + q * NT, cadd(u1[q], u1[q + PH]));
   __syncthreads();
-  fft_soa<float, LOGB - 1, NT, true>(buf, tw2);
+  if constexpr (PR2) {
+    fft_soa<float, LOGB - 1, NT, true, true, 2>(buf, tw2);
+    if (!prune2) fft_soa_from<float, LOGB - 1, NT, true, NS2, 0, true>(buf, tw2);
+  } else {
+    fft_soa<float, LOGB - 1, NT, true>(buf, tw2);
+  }
   const cx<float>* sm = a.s + (size_t)m * b;
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) {
@@ -235,7 +258,14 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
     const uint32_t h = sym_pos(e);
     const int qq = sym_rot(e);
     const float ui = u[i];
-    const cx<float> c3 = rot(buf.get((int)(h & (uint32_t)(H - 1))), (8 - 2 * qq) & 3);  // c_3[2h mod b]
+    const int ph = (int)(h & (uint32_t)(H - 1));
+    cx<float> c3e;
+    if constexpr (PR2) {
+      c3e = prune2 ? inverse_output_from_groups<float, LOGB - 1, NT>(buf, a.tw2, ph) : buf.get(ph);
+    } else {
+      c3e = buf.get(ph);
+    }
+    const cx<float> c3 = rot(c3e, (8 - 2 * qq) & 3);  // c_3[2h mod b]
     const cx<float> s3 = rot(sm[(3u * h) & (uint32_t)(b - 1)], (12 - 3 * qq) & 3);
     const float v = vp[i] + (ui * c3.x * sc + ui * ui * s3.x) * (1.f / 3.f);
     a.V[((size_t)tau * B + m) * n + i] = v;
