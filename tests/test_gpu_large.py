@@ -90,10 +90,12 @@ def test_split_factor_build_and_deflate(ctx, b):
         assert rel(got[m], ref) < 1e-12
 
 
-@pytest.mark.parametrize("b", [32768, 65536])
-def test_large_power_update_and_uuu(ctx, b):
-    print(f"large power b={b}", flush=True)
-    n, B, L = 200, 4, 3
+# n = 1024 and 1025 at b = 65536 sit on both sides of the bound below which the
+# inverse sub-transforms leave out their last two passes.
+@pytest.mark.parametrize("b,n", [(32768, 200), (65536, 200), (65536, 1024), (65536, 1025)])
+def test_large_power_update_and_uuu(ctx, b, n):
+    print(f"large power b={b} n={n}", flush=True)
+    B, L = 4, 3
     rng = np.random.default_rng(b + 1)
     h, xi = tsk.hash_generate(6, n, b, B)
     tab = tsk.Tables(ctx, h, xi, b)

@@ -167,9 +167,12 @@ def test_power_update_matches_prop1(ctx, n, b, B, L, dtype, tol):
     (200, 16384, 10, 50, torch.float32, 1e-5),
     (50, 16384, 3, 4, torch.float64, 1e-12),
     (2000, 4096, 8, 3, torch.float32, 1e-5),
+    (512, 16384, 2, 3, torch.float32, 1e-5),
+    (513, 16384, 2, 3, torch.float32, 1e-5),
 ])
 def test_contract_tiuu_per_sketch(ctx, n, b, B, L, dtype, tol):
-    """Proposition 1 per sketch, no median (the launch the benchmark times)."""
+    """Proposition 1 per sketch, no median (the launch the benchmark times); n = 512 and 513
+    sit on both sides of the bound below which the inverse leaves out its last two passes."""
     print(f"tiuu n={n} b={b} B={B} L={L} {dtype}", flush=True)
     rng = np.random.default_rng(12)
     tab, h, xi = _tables(ctx, 13, n, b, B)

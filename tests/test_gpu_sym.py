@@ -96,7 +96,11 @@ def test_sym_build_is_deterministic_and_accumulates(ctx):
     tab.close()
 
 
-@pytest.mark.parametrize("n,b,B,L", [(9, 256, 3, 2), (100, 2048, 3, 4), (200, 16384, 2, 3), (1000, 8192, 2, 2)])
+# The shapes cover both inverses with and without the read-off from the groups
+# before their last two passes (n small against b), including 32 groups
+# (b = 8192, n <= 512) and the ragged n just above and below that bound.
+@pytest.mark.parametrize("n,b,B,L", [(9, 256, 3, 2), (100, 2048, 3, 4), (200, 16384, 2, 3), (1000, 8192, 2, 2),
+                                     (200, 8192, 3, 3), (512, 8192, 2, 2), (513, 8192, 2, 2)])
 def test_sym_tiuu_matches_appendix_b(ctx, n, b, B, L):
     print(f"sym tiuu n={n} b={b}", flush=True)
     rng = np.random.default_rng(n)
@@ -108,7 +112,7 @@ def test_sym_tiuu_matches_appendix_b(ctx, n, b, B, L):
         tsk.sym_sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), s64, s32, S64, S32)
         s_ref = [osym.sym_sketch_dense(P.T, h[m], q[m], b) for m in range(B)]
     else:
-        # n = 1000: a random complex sketch stands in for a built one (the read-off is linear in it)
+        # n > 200: a random complex sketch stands in for a built one (the read-off is linear in it)
         s_ref = [rng.standard_normal(b) + 1j * rng.standard_normal(b) for m in range(B)]
         st = np.stack(s_ref)
         s64.copy_(torch.from_numpy(np.stack([st.real, st.imag], -1)).to(DEV))
