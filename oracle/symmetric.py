@@ -174,6 +174,7 @@ class SymResult:
     tau: np.ndarray
     flags: np.ndarray
     S: np.ndarray
+    lam_tau: np.ndarray = None   # [k][L] selection values of each component's restarts
 
 
 def rtpm_symmetric(S: np.ndarray, h, q, k: int, L: int, T: int, u0: np.ndarray) -> SymResult:
@@ -187,6 +188,7 @@ def rtpm_symmetric(S: np.ndarray, h, q, k: int, L: int, T: int, u0: np.ndarray) 
     lam_out, U_out = np.zeros(k), np.zeros((k, n))
     tau_out = np.zeros(k, dtype=np.int64)
     flags = np.zeros((k, L), dtype=np.int32)
+    lam_tau_out = np.zeros((k, L))
     for c in range(k):
         U = np.array(u0[c], dtype=np.float64, copy=True)
         for _ in range(T):
@@ -203,4 +205,5 @@ def rtpm_symmetric(S: np.ndarray, h, q, k: int, L: int, T: int, u0: np.ndarray) 
             s1 = sym_count_sketch(u_hat, h[m], q[m], b, 1)
             S[m] -= lam_hat * cconv(cconv(s1, s1), s1)
         lam_out[c], U_out[c], tau_out[c] = lam_hat, u_hat, tau
-    return SymResult(lam=lam_out, U=U_out, tau=tau_out, flags=flags, S=S)
+        lam_tau_out[c] = lam_tau
+    return SymResult(lam=lam_out, U=U_out, tau=tau_out, flags=flags, S=S, lam_tau=lam_tau_out)

@@ -150,6 +150,10 @@ tsk_status ws_get(tsk_ctx* c, int id, size_t bytes, void** out) {
     TSK_HIP(hipMemset(d.p, 0, nb));
     TSK_HIP(hipDeviceSynchronize());
     d.bytes = nb;
+    // A new buffer may reuse a freed address: start vectors cached under an
+    // address are uploaded again.
+    c->u0_key.clear();
+    c->u0b_key.clear();
   }
   *out = d.p;
   return TSK_OK;
@@ -1822,14 +1826,17 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
   TSK_TRY(set_device(ctx));
   hipStream_t st = S(stream);
   const int n = tab->n;
-  const size_t bytes = decomp_ws_layout(nullptr, tab, dtype, k, L, !flags_out, !u0, nullptr, nullptr,
+  const size_t bytes = decomp_ws_layout(nullptr, tab, dtype, k, L, !flags_out, false, nullptr, nullptr,
                                         nullptr);
+  // Generated start vectors live in a slot of their own: other entry points
+  // (the symmetric decomposition) lay their scratch over WS_U.
+  double* u0_ws = nullptr;
+  if (!u0) TSK_TRY(ws_get(ctx, WS_U0, (size_t)k * L * n * 8, (void**)&u0_ws));
   void* base = nullptr;
   TSK_TRY(ws_get(ctx, WS_U, bytes, &base));
   DecompWs w;
   int32_t* fl_ws = nullptr;
-  double* u0_ws = nullptr;
-  decomp_ws_layout((char*)base, tab, dtype, k, L, !flags_out, !u0, &w, &fl_ws, &u0_ws);
+  decomp_ws_layout((char*)base, tab, dtype, k, L, !flags_out, false, &w, &fl_ws, nullptr);
   int32_t* flags = flags_out ? flags_out : fl_ws;
   const double* u0d = u0;
   if (!u0d) {

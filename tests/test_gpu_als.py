@@ -3,8 +3,11 @@ C ABI: the two-vector contraction in all three read-off modes, single ALS
 sweeps and whole runs (FP64 and FP32 power steps), a singular Gram matrix
 (pseudo-inverse), recovery of planted factors, argument errors.
 
-Bars: FP64 contractions 1e-12 normwise relative; FP64 ALS 1e-9; FP32
-contractions 1e-5; FP32 ALS 1e-4 after a few sweeps.
+Bars: FP64 contractions 1e-12 normwise relative, FP32 ones 1e-5.  An ALS
+update solves with the k x k Gram matrix G = (X X^T) o (Y Y^T), which
+multiplies the relative error of its inputs by up to cond(G); whole runs are
+held to 1e-12 (FP64) and 1e-5 (FP32) times the largest cond(G) of the
+oracle's run (printed with the observed error).
 Inputs: seeded planted symmetric tensors with noise, random start factors.
 """
 import numpy as np
@@ -16,15 +19,38 @@ from paper_1506_04448_amd.workloads import planted_tensor
 
 torch = pytest.importorskip("torch")
 import paper_1506_04448_amd as tsk  # noqa: E402
+from parity_rules import rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 
 
-def rel(a, ref):
-    d = np.linalg.norm(ref)
-    return np.linalg.norm(np.asarray(a) - ref) / (d if d > 0 else 1.0)
+def gram_conditioning(S_time, h, xi, k, T, F0):
+    """Largest cond(G) over the updates of the oracle's ALS run (the same
+    iteration as oracle.als.als_sketched, stepped update by update here to
+    read each G)."""
+    F = np.array(F0, dtype=np.float64, copy=True)
+    B = S_time.shape[0]
+    kmax = 1.0
+    for _ in range(T):
+        for rd in range(3):
+            X, Y = F[(rd + 1) % 3], F[(rd + 2) % 3]
+            G = (X @ X.T) * (Y @ Y.T)
+            ev = np.abs(np.linalg.eigvalsh(G))
+            keep = ev > 1e-12 * ev.max()
+            kmax = max(kmax, float(ev[keep].max() / ev[keep].min()))
+            V = np.stack([oals.contract_two(S_time[m], h[m], xi[m], X, Y, rd) for m in range(B)], axis=1)
+            _, F[rd] = oals.als_update(oracle.median(V, axis=1), X, Y)
+    return kmax
+
+
+def check_als(lam, F, ref, base, kappa, label):
+    el, ef = rel(lam, ref.lam), rel(F, ref.F)
+    bar = base * kappa
+    print(f"{label}: lambda rel err {el:.2e}, factors rel err {ef:.2e}, max cond(G) {kappa:.1f}, "
+          f"bar {bar:.1e}", flush=True)
+    assert el < bar and ef < bar, (el, ef, bar)
 
 
 @pytest.fixture(scope="module")
@@ -80,8 +106,8 @@ def test_als_sweeps_fp64_match_oracle(ctx, B):
     for T in (1, 6):
         lam, F = tsk.als(ctx, tab, torch.from_numpy(F0).to(DEV), T, dtype=tsk.F64, S64=S64)
         ref = oals.als_sketched(S_time, h, xi, k, T, F0)
-        assert rel(lam.cpu().numpy(), ref.lam) < 1e-9
-        assert rel(F.cpu().numpy(), ref.F) < 1e-9
+        check_als(lam.cpu().numpy(), F.cpu().numpy(), ref, 1e-12,
+                  gram_conditioning(S_time, h, xi, k, T, F0), f"als fp64 B={B} T={T}")
 
 
 def test_als_fp32_matches_oracle(ctx):
@@ -91,8 +117,8 @@ def test_als_fp32_matches_oracle(ctx):
     F0 = rng.standard_normal((3, k, n))
     lam, F = tsk.als(ctx, tab, torch.from_numpy(F0).to(DEV), 3, dtype=tsk.F32, S32=S32)
     ref = oals.als_sketched(S_time, h, xi, k, 3, F0)
-    assert rel(lam.cpu().numpy(), ref.lam) < 1e-4
-    assert rel(F.cpu().numpy(), ref.F) < 1e-4
+    check_als(lam.cpu().numpy(), F.cpu().numpy(), ref, 1e-5,
+              gram_conditioning(S_time, h, xi, k, 3, F0), "als fp32 b=16384")
 
 
 def test_als_singular_gram_uses_pseudo_inverse(ctx):
@@ -105,8 +131,8 @@ def test_als_singular_gram_uses_pseudo_inverse(ctx):
     F0[:, 2] = F0[:, 1]
     lam, F = tsk.als(ctx, tab, torch.from_numpy(F0).to(DEV), 1, dtype=tsk.F64, S64=S64)
     ref = oals.als_sketched(S_time, h, xi, k, 1, F0)
-    assert rel(lam.cpu().numpy(), ref.lam) < 1e-8
-    assert rel(F.cpu().numpy(), ref.F) < 1e-8
+    check_als(lam.cpu().numpy(), F.cpu().numpy(), ref, 1e-12,
+              gram_conditioning(S_time, h, xi, k, 1, F0), "als singular Gram")
 
 
 def test_als_recovers_planted_factors(ctx):
@@ -129,8 +155,8 @@ def test_als_fp32_split_transforms_match_oracle(ctx):
     F0 = rng.standard_normal((3, k, n))
     lam, F = tsk.als(ctx, tab, torch.from_numpy(F0).to(DEV), 2, dtype=tsk.F32, S32=S32)
     ref = oals.als_sketched(S_time, h, xi, k, 2, F0)
-    assert rel(lam.cpu().numpy(), ref.lam) < 1e-4
-    assert rel(F.cpu().numpy(), ref.F) < 1e-4
+    check_als(lam.cpu().numpy(), F.cpu().numpy(), ref, 1e-5,
+              gram_conditioning(S_time, h, xi, k, 2, F0), "als fp32 b=65536")
 
 
 def test_als_argument_errors(ctx):

@@ -15,15 +15,11 @@ from paper_1506_04448_amd.workloads import lda_corpus
 
 torch = pytest.importorskip("torch")
 import paper_1506_04448_amd as tsk  # noqa: E402
+from parity_rules import rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-
-
-def rel(a, ref):
-    d = np.linalg.norm(ref)
-    return np.linalg.norm(np.asarray(a) - ref) / (d if d > 0 else 1.0)
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +40,10 @@ def _dev(C):
                                             (200, 60, 7, 12.0, 256, 3, np.float64),
                                             (400, 200, 20, 30.0, 16384, 3, np.float32),
                                             (30, 300, 100, 12.0, 4096, 2, np.float32),
-                                            (150, 80, 9, 6.0, 8192, 2, np.float64)])
+                                            (150, 80, 9, 6.0, 8192, 2, np.float64),
+                                            # the LDA workload's sketch shape: K = 100, b = 16384, B = 8
+                                            (12, 300, 100, 40.0, 16384, 8, np.float32),
+                                            (12, 300, 100, 40.0, 16384, 8, np.float64)])
 def test_docs_build_matches_oracle(ctx, D, V, K, L, b, B, dt):
     print(f"docs D={D} V={V} K={K} b={b} B={B} {np.dtype(dt).name}", flush=True)
     C = lda_corpus(D=D, V=V, K=K, seed=D + V, mean_len=L, min_len=1)

@@ -14,17 +14,13 @@ from paper_1506_04448_amd.workloads import planted_tensor
 
 torch = pytest.importorskip("torch")
 import paper_1506_04448_amd as tsk  # noqa: E402
+from parity_rules import near_tie, rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 
 
-def rel(a, ref):
-    a = np.asarray(a)
-    ref = np.asarray(ref)
-    d = np.linalg.norm(ref)
-    return np.linalg.norm(a - ref) / (d if d > 0 else 1.0)
 
 
 @pytest.fixture(scope="module")
@@ -323,15 +319,49 @@ def test_decompose_fp64_small_config(ctx):
     assert rel(U2.cpu().numpy(), ref.U) < 1e-12
 
 
+def check_fp32_decomposition(ref, lam, U, S64_time, S_in, h, xi, b, label):
+    """Every component of an FP32 decomposition against the FP64 oracle's at
+    1e-5 (lambda relative, u normwise), stopping at the first near-tie (later
+    components then follow a different deflation); then the FP64 steps given
+    the GPU's own (lambda_hat, u_hat): lambda_hat = med_m <s^(m), s^(m)(u^3)>
+    on the sketches deflated by the GPU's earlier components, and the final
+    deflated sketches, both at 1e-12."""
+    k = lam.shape[0]
+    B = S_in.shape[0]
+    compared = 0
+    for c in range(k):
+        if near_tie(ref.lam_tau[c]):
+            print(f"{label}: component {c}: near-tie in the oracle's selection values, "
+                  f"components {c}..{k - 1} not compared", flush=True)
+            break
+        el = abs(lam[c] - ref.lam[c]) / abs(ref.lam[c])
+        eu = rel(U[c], ref.U[c])
+        print(f"{label}: component {c}: lambda rel err {el:.2e}, u rel err {eu:.2e}", flush=True)
+        assert el < 1e-5 and eu < 1e-5, (c, el, eu)
+        compared += 1
+    assert compared >= 1
+    S = np.array(S_in, dtype=np.float64, copy=True)
+    for c in range(k):
+        lam_c = float(oracle.median(np.array([oracle.tuuu_sketch(S[m], h[m], xi[m], U[c]) for m in range(B)]),
+                                   axis=0))
+        assert abs(lam[c] - lam_c) <= 1e-12 * max(abs(lam_c), 1e-300), (c, lam[c], lam_c)
+        for m in range(B):
+            S[m] -= lam[c] * oracle.sketch_rank1_fft(U[c], U[c], U[c], h[m], xi[m], b)
+    assert rel(S64_time, S) < 1e-12
+    return compared
+
+
 def test_decompose_fp32_full_size_c2(ctx):
-    """n=200 FP32 dense, k=10, b=16384, B=10, L=50, T=30 batched: the first two
-    components against the oracle (later ones depend only on these through the
-    deflation), all ten against the planted truth."""
+    """n=200 FP32 dense, k=10, b=16384, B=10, L=50, T=30 batched: all ten
+    components against the FP64 oracle (1e-5; near-ties reported, not failed),
+    lambda_hat and the deflated sketches given the GPU's vectors (1e-12), and all
+    ten against the planted truth."""
     n, k, b, B, L, T = 200, 10, 16384, 10, 50, 30
     P = planted_tensor(n, k, noise=0.05, seed=1, dtype=np.float32)
     tab, h, xi = _tables(ctx, 1, n, b, B)
     S64, S32 = tsk.new_sketch(tab, DEV)
     tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    S_built = _time_sketch(ctx, tab, S64)
     u0 = np.stack([oracle.start_vectors_spec(1, c, L, n) for c in range(k)])
     lam, U, tau, flags = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F32,
                                        u0=torch.from_numpy(u0).to(DEV))
@@ -340,11 +370,11 @@ def test_decompose_fp32_full_size_c2(ctx):
     # Theorem 1: each sketched estimate is off by O(||T||_F / sqrt(b)); allow 3x.
     tol = 3.0 * float(np.linalg.norm(P.T.astype(np.float64))) / np.sqrt(b)
     np.testing.assert_allclose(np.sort(lam), np.sort(P.lam), atol=tol)
-    kk = 2
     S_time = _oracle_sketches(P.T.astype(np.float64), h, xi, b)
-    ref = oracle.rtpm_sketched(S_time, h, xi, kk, L, T, u0[:kk])
-    assert np.abs(lam[:kk] - ref.lam).max() / np.abs(ref.lam).max() < 1e-5
-    assert rel(U[:kk], ref.U) < 1e-5
+    assert rel(S_built, S_time) < 1e-12
+    ref = oracle.rtpm_sketched(S_time, h, xi, k, L, T, u0)
+    n_cmp = check_fp32_decomposition(ref, lam, U, _time_sketch(ctx, tab, S64), S_built, h, xi, b, "C2")
+    assert n_cmp == k, f"only {n_cmp} of {k} components compared (near-tie)"
 
 
 def test_plain_path_equals_batched(ctx):
@@ -541,14 +571,14 @@ def test_median_normalize_matches_oracle(ctx, B, dtype):
 @pytest.mark.parametrize("B,dtype,T,tol", [(20, tsk.F64, 6, 1e-12), (40, tsk.F32, 25, 1e-5)])
 def test_decompose_with_separate_median_launch(ctx, B, dtype, T, tol):
     """B > 16: the median of each step is a launch of its own inside the graph
-    (not the power kernel's prologue); whole of Algorithm 1 against the oracle
-    (FP32: the converged first component)."""
+    (not the power kernel's prologue); whole of Algorithm 1 against the oracle."""
     print(f"decompose separate median B={B}", flush=True)
     n, k, b, L = 30, 2, 512, 5
     P = planted_tensor(n, 2, noise=0.01, seed=11)
     tab, h, xi = _tables(ctx, 12, n, b, B)
     S64, S32 = tsk.new_sketch(tab, DEV)
     tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    S_built = _time_sketch(ctx, tab, S64)
     u0 = np.stack([oracle.start_vectors_spec(3, c, L, n) for c in range(k)])
     if dtype == tsk.F32:
         u0 = u0.astype(np.float32).astype(np.float64)
@@ -561,7 +591,9 @@ def test_decompose_with_separate_median_launch(ctx, B, dtype, T, tol):
         assert rel(U.cpu().numpy(), ref.U) < tol
         np.testing.assert_array_equal(flags.cpu().numpy(), ref.flags)
     else:
-        # FP32 steps: the first component against the oracle's (later ones follow from it)
-        ref = oracle.rtpm_sketched(S_time, h, xi, 1, L, T, u0[:1])
-        assert abs(lam.cpu().numpy()[0] - ref.lam[0]) <= tol * abs(ref.lam[0])
-        assert rel(U.cpu().numpy()[0], ref.U[0]) < 10 * tol
+        # FP32 steps: every component at 1e-5 (near-ties reported), FP64 steps at 1e-12
+        ref = oracle.rtpm_sketched(S_time, h, xi, k, L, T, u0)
+        n_cmp = check_fp32_decomposition(ref, lam.cpu().numpy(), U.cpu().numpy(),
+                                         _time_sketch(ctx, tab, S64), S_built, h, xi, b,
+                                         f"separate median B={B}")
+        assert n_cmp == k

@@ -89,3 +89,72 @@ def test_injective_hash_separates_multisets():
     for i, j, k in itertools.combinations_with_replacement(range(n), 3):
         mult = 1 if i == j == k else (3 if (i == j or j == k) else 6)
         assert abs(s[h[i] + h[j] + h[k]] - mult * T[i, j, k]) < 1e-12
+
+
+def _multiset_injective_tables(n, B, rng):
+    """h(i) = 4^i: every multiset {i, j, k} has its own sum h_i + h_j + h_k (its
+    base-4 digits are the multiplicities), and with b > 3 h_max no sum wraps.
+    Signs are random 4th roots of unity, different per sketch."""
+    h = np.tile(4 ** np.arange(n), (B, 1))
+    q = rng.integers(0, 4, size=(B, n))
+    b = 1
+    while b <= 3 * int(h.max()):
+        b *= 2
+    return h, q, b
+
+
+def test_injective_hash_reduces_contractions_to_the_dense_ones():
+    rng = np.random.default_rng(6)
+    n = 5
+    T = _sym_tensor(n, rng)
+    h, q, b = _multiset_injective_tables(n, 2, rng)
+    u = rng.standard_normal(n)
+    for m in range(2):
+        s = sy.sym_sketch_dense(T, h[m], q[m], b)
+        np.testing.assert_allclose(sy.sym_tiuu(s, h[m], q[m], u), np.einsum("ijk,j,k->i", T, u, u),
+                                   rtol=0, atol=1e-12)
+        assert abs(sy.sym_tuuu(s, h[m], q[m], u) - np.einsum("ijk,i,j,k->", T, u, u, u)) < 1e-12
+
+
+def test_injective_hash_symmetric_rtpm_equals_dense_rtpm():
+    """With a multiset-injective hash every symmetric-sketch estimate is the
+    exact contraction, so Algorithm 1 on the sketches must retrace the dense
+    power method step by step: same (lambda_hat, u_hat) per component, and the
+    deflated sketches must be the symmetric sketches of the deflated tensor
+    T - sum_c lambda_c u_c^(x)3 (deflation by the full sketch s_u * s_u * s_u of
+    u^(x)3; the upper-triangle sketch s_X would leave other buckets)."""
+    import oracle
+    from paper_1506_04448_amd.workloads import planted_tensor
+    n, B, k, L, Titer = 5, 3, 3, 4, 15
+    rng = np.random.default_rng(8)
+    P = planted_tensor(n, k, noise=0.05, seed=7)
+    h, q, b = _multiset_injective_tables(n, B, rng)
+    S = np.stack([sy.sym_sketch_dense(P.T, h[m], q[m], b) for m in range(B)])
+    u0 = rng.standard_normal((k, L, n))
+    u0 /= np.linalg.norm(u0, axis=2, keepdims=True)
+    rs = sy.rtpm_symmetric(S, h, q, k, L, Titer, u0)
+    rd = oracle.rtpm_dense(P.T, k, L, Titer, u0)
+    np.testing.assert_allclose(rs.lam, rd.lam, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(rs.U, rd.U, rtol=0, atol=1e-11)
+    Tdef = P.T.copy()
+    for c in range(k):
+        Tdef -= rd.lam[c] * np.einsum("i,j,k->ijk", rd.U[c], rd.U[c], rd.U[c])
+    for m in range(B):
+        np.testing.assert_allclose(rs.S[m], sy.sym_sketch_dense(Tdef, h[m], q[m], b), rtol=0, atol=1e-11)
+
+
+def test_deflation_by_upper_triangle_sketch_would_fail_the_pin():
+    """The pin above separates the full sketch of u^(x)3 from the upper-triangle
+    sketch s_X: the two differ on buckets of repeated indices."""
+    rng = np.random.default_rng(9)
+    n = 4
+    h, q, b = _multiset_injective_tables(n, 1, rng)
+    u = rng.standard_normal(n)
+    s1 = sy.sym_count_sketch(u, h[0], q[0], b, 1)
+    s2 = sy.sym_count_sketch(u ** 2, h[0], q[0], b, 2)
+    s3 = sy.sym_count_sketch(u ** 3, h[0], q[0], b, 3)
+    full = sy.cconv(sy.cconv(s1, s1), s1)
+    upper = full / 6 + sy.cconv(s2, s1) / 2 + s3 / 3
+    ref = sy.sym_sketch_dense(np.einsum("i,j,k->ijk", u, u, u), h[0], q[0], b)
+    np.testing.assert_allclose(full, ref, rtol=0, atol=1e-12)
+    assert np.max(np.abs(upper - ref)) > 1e-3
