@@ -18,7 +18,8 @@ import numpy as np
 __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
-    "sketch_export", "sketch_deflate", "power_update", "contract_tiuu", "contract_uuu",
+    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "contract_tiuu",
+    "contract_uuu",
     "decompose", "contract_tuuu_grad", "cp_loss", "Problem", "decompose_batched",
     "workspace_size", "sketch_build_docs",
     "F32", "F64",
@@ -60,6 +61,7 @@ _SIGS = {
     "tsk_sketch_export": ([_P, _I, _I, _P, _P, _P], _I),
     "tsk_sketch_deflate": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
+    "tsk_power_update_noalloc": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
     "tsk_sym_tables_create": ([_P, _I, _I, _I, _P, _P, _P], _I),
@@ -423,6 +425,23 @@ def power_update(ctx, tab, U_in, S64=None, S32=None, U_out=None, V=None, flags=N
     _check("tsk_power_update", lib().tsk_power_update(
         ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U_in), _ptr(U_out), _ptr(V),
         _ptr(flags), _stream(stream)))
+    return U_out
+
+
+def power_update_noalloc(ctx, tab, U_in, U_out, S64=None, S32=None, flags=None, stream=None):
+    """The power step of ``power_update`` for callers that cannot allocate:
+    the library allocates nothing (its estimates live in a static per-GPU
+    array), so the caller passes the output ``U_out`` [L][n]."""
+    import torch
+    dt, tdt = _vdtype(U_in.dtype)
+    L = U_in.shape[0]
+    _tensor(U_in, "U_in", tdt, (L, tab.n))
+    _tensor(U_out, "U_out", tdt, (L, tab.n))
+    _tensor(flags, "flags", torch.int32, (L,), allow_none=True)
+    _spectra(tab, dt, S64, S32)
+    _check("tsk_power_update_noalloc", lib().tsk_power_update_noalloc(
+        ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U_in), _ptr(U_out), _ptr(flags),
+        _stream(stream)))
     return U_out
 
 

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -23,6 +24,13 @@
 #include "status.hpp"
 
 using tsk::cx;
+
+// Device memory of the allocation-free power step (tsk_power_update_noalloc):
+// per-sketch estimates and, at b = 65536, the split transforms' buffers.  Each
+// GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace tsk {
 char* last_error_buffer() {
@@ -89,6 +97,8 @@ struct tsk_ctx {
   std::vector<hipEvent_t> fork_ev;   // one event per branch, plus the fork event
   std::vector<hipStream_t> gfork;    // restart-group branches of one decomposition
   std::vector<hipEvent_t> gfork_ev;
+  void* scratch = nullptr;           // this device's address of `scratch` below
+  bool no_alloc = false;             // set while an allocation-free entry point runs
 };
 
 struct tsk_tables {
@@ -137,6 +147,8 @@ tsk_status ws_get(tsk_ctx* c, int id, size_t bytes, void** out) {
   DevBuf& d = c->ws[id];
   if (bytes == 0) bytes = 256;
   if (d.bytes < bytes) {
+    if (c->no_alloc)
+      return tsk::fail(TSK_EUNSUPPORTED, "allocation-free call would allocate a %zu-byte workspace", bytes);
     TSK_HIP(hipDeviceSynchronize());
     clear_graphs(c);
     if (d.p) TSK_HIP(hipFree(d.p));
@@ -185,6 +197,8 @@ tsk_status get_tw(tsk_ctx* c, int logb, const cx<R>** out, int nt = 0) {
   const int key = (logb << 16) | nt;
   auto it = mp.find(key);
   if (it == mp.end()) {
+    if (c->no_alloc)
+      return tsk::fail(TSK_EUNSUPPORTED, "allocation-free call would allocate the b=2^%d twiddle table", logb);
     const int b = 1 << logb, H = b / 2;
     const int NT = nt;
     const int rmax = tsk::fft_rmax(H, NT);
@@ -225,6 +239,8 @@ tsk_status get_wb(tsk_ctx* c, int logb, const cx<R>** out) {
   auto& mp = (sizeof(R) == 8) ? c->wb64 : c->wb32;
   auto it = mp.find(logb);
   if (it == mp.end()) {
+    if (c->no_alloc)
+      return tsk::fail(TSK_EUNSUPPORTED, "allocation-free call would allocate the b=2^%d root table", logb);
     const int b = 1 << logb;
     std::vector<cx<R>> h(b);
     for (int x = 0; x < b; ++x) {
@@ -565,6 +581,47 @@ tsk_status set_device(tsk_ctx_t ctx) {
   return TSK_OK;
 }
 
+// Device address of `scratch` on `device`, which must be current: looked up
+// once per device and kept.
+constexpr int kScratchDevices = 64;
+tsk_status scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kScratchDevices] = {};
+  if (device < 0 || device >= kScratchDevices)
+    return tsk::fail(TSK_EUNSUPPORTED, "device %d: scratch kept for devices below %d", device, kScratchDevices);
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return tsk::fail(TSK_EHIP, "scratch address on device %d: %s", device, hipGetErrorString(e));
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return TSK_OK;
+}
+
+// Twiddle tables of the power step at this b, so that later steps (and the
+// allocation-free one) find them made.
+tsk_status preload_power_tables(tsk_ctx_t ctx, int logb) {
+  if (logb <= kLdsLogB + 1) {
+    const cx<float>* t32 = nullptr;
+    TSK_TRY(get_tw<float>(ctx, logb, &t32));
+  }
+  if (logb <= kLdsLogB) {
+    const cx<double>* t64 = nullptr;
+    TSK_TRY(get_tw<double>(ctx, logb, &t64));
+  }
+  return preload_split_tables(ctx, logb, logb > kLdsLogB + 1);
+}
+
+// Marks a context as forbidden to allocate for the lifetime of the guard.
+struct NoAllocGuard {
+  tsk_ctx* c;
+  explicit NoAllocGuard(tsk_ctx* ctx) : c(ctx) { c->no_alloc = true; }
+  ~NoAllocGuard() { c->no_alloc = false; }
+};
+
 }  // namespace
 
 // =============================================================================
@@ -583,8 +640,11 @@ extern "C" tsk_status tsk_create(tsk_ctx_t* out, int device) {
   if (device < 0 || device >= count)
     return tsk::fail(TSK_EINVAL, "tsk_create: device %d out of range [0,%d)", device, count);
   TSK_HIP(hipSetDevice(device));
+  void* scr = nullptr;
+  TSK_TRY(scratch_address(device, &scr));
   tsk_ctx* c = new tsk_ctx();
   c->device = device;
+  c->scratch = scr;
   if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return tsk::fail(TSK_EHIP, "tsk_create: stream creation failed");
@@ -666,6 +726,12 @@ extern "C" tsk_status tsk_tables_create(tsk_ctx_t ctx, int n, int b, int B, cons
     (void)hipFree(p);
     delete t;
     return tsk::fail(TSK_EHIP, "tsk_tables_create: upload failed");
+  }
+  const tsk_status ps = preload_power_tables(ctx, logb);
+  if (ps != TSK_OK) {
+    (void)hipFree(p);
+    delete t;
+    return ps;
   }
   *out = t;
   return TSK_OK;
@@ -1082,6 +1148,50 @@ extern "C" tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtyp
   const int n = tab->n, B = tab->B;
   SplitBufs sb;
   TSK_TRY(eager_split_bufs(ctx, tab, dtype, L, &sb));
+  if (dtype == TSK_F32) {
+    TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U_in, nullptr, nullptr,
+                                nullptr, (float*)vbuf, nullptr, S(stream), 0, &sb));
+    return median_norm_launch<float>((const float*)vbuf, (const float*)U_in, (float*)U_out, flags, L,
+                                     n, B, S(stream));
+  }
+  TSK_TRY(power_launch<double>(ctx, tab, S64, L, 0, 0, 0, (const double*)U_in, nullptr, nullptr,
+                               nullptr, (double*)vbuf, nullptr, S(stream)));
+  return median_norm_launch<double>((const double*)vbuf, (const double*)U_in, (double*)U_out, flags,
+                                    L, n, B, S(stream));
+}
+
+extern "C" tsk_status tsk_power_update_noalloc(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
+                                               const double* S64, const float* S32, int L,
+                                               const void* U_in, void* U_out, int32_t* flags,
+                                               void* stream) {
+  TSK_TRY(check_tables(tab, ctx, "tsk_power_update_noalloc"));
+  TSK_TRY(check_power_args(tab, dtype, S64, S32, L, "tsk_power_update_noalloc"));
+  if (!U_in || !U_out) return tsk::fail(TSK_EINVAL, "tsk_power_update_noalloc: null vector buffer");
+  if (U_in == U_out) return tsk::fail(TSK_EINVAL, "tsk_power_update_noalloc: U_in and U_out alias");
+  if (!ctx->scratch) return tsk::fail(TSK_EHIP, "tsk_power_update_noalloc: no scratch address");
+  const int n = tab->n, B = tab->B;
+  const size_t es = dtype == TSK_F32 ? 4 : 8;
+  const size_t vbytes = ((size_t)L * B * n * es + 255) & ~(size_t)255;
+  size_t ebytes = 0, abytes = 0;
+  if (needs_power_split(tab, dtype)) {
+    ebytes = (power_split_bytes_E(tab, L) + 255) & ~(size_t)255;
+    abytes = power_split_bytes_A(tab, L);
+  }
+  const size_t need = vbytes + ebytes + abytes;
+  if (need > kScratchBytes)
+    return tsk::fail(TSK_EINVAL,
+                     "tsk_power_update_noalloc: L=%d, B=%d, n=%d, b=%d needs %zu bytes of scratch, more than "
+                     "its %zu; take fewer vectors per call or use tsk_power_update",
+                     L, B, n, tab->b, need, kScratchBytes);
+  TSK_TRY(set_device(ctx));
+  NoAllocGuard guard(ctx);
+  char* base = reinterpret_cast<char*>(ctx->scratch);
+  void* vbuf = base;
+  SplitBufs sb;
+  if (ebytes) {
+    sb.E = base + vbytes;
+    sb.A = base + vbytes + ebytes;
+  }
   if (dtype == TSK_F32) {
     TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U_in, nullptr, nullptr,
                                 nullptr, (float*)vbuf, nullptr, S(stream), 0, &sb));
