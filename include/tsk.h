@@ -66,6 +66,22 @@ const char* tsk_last_error(void);
 tsk_status tsk_create(tsk_ctx_t* out, int device);
 void tsk_destroy(tsk_ctx_t ctx);
 
+/* Launch-shape tuning.  Launch shapes come from fixed rules (mode 0, the
+ * default) or from a tuner the library runs on the caller's own data: the
+ * dense build's sketches per work-group and slab count (how the buckets are
+ * privatised in LDS and how the tensor is split), and the number of restart
+ * groups a decomposition runs on parallel graph branches (not at b = 65536 in
+ * FP32).  Mode 1: the first call of an uncached shape times every candidate
+ * (blocking on its stream; a decomposition times one-component runs on a copy
+ * of the sketch), keeps the fastest, and records it; mode 2: cached choices
+ * only, the rules elsewhere.  cache_path (host, nullable) names a text file,
+ * read now and rewritten after each new choice: one line per shape, the key
+ * (entry point, device name and CU count, precision, sizes) and the chosen
+ * integers.  A choice of build shape changes the rounding of the build within
+ * FP64 round-off; restart groups change no result bit.  Errors: TSK_EINVAL
+ * (null context, mode). */
+tsk_status tsk_tune_config(tsk_ctx_t ctx, int mode, const char* cache_path);
+
 /* ---- Randomness (host only, no device work) ------------------------------
  * Hash and sign tables h_j^(m): [n] -> [b], xi_j^(m): [n] -> {+1,-1} for
  * sketch m < B and mode j in {0,1,2} (Algorithm 1, initialisation; the tensor
@@ -140,11 +156,13 @@ tsk_status tsk_sketch_build_factors(tsk_ctx_t ctx, tsk_tables_t tab, const doubl
  * and cost six per word.  Every rank-1 term is sketched by Eq. (2).
  *   rowptr: int32[D+1], col: int32[nnz] word ids in [0, V) (unique within a
  *   document), cnt: int32[nnz] counts >= 1 -- CSR, device.
- *   W: [V][K] in wdtype (TSK_F32 or TSK_F64; the transforms run in that
- *   precision, the sums over documents in FP64), K = the tables' n.
+ *   W: [V][K] in wdtype (TSK_F32 or TSK_F64; the projections p = W^T n, on
+ *   the matrix cores, and the transforms run in that precision, the sums over
+ *   documents in FP64), K = the tables' n.
  *   accumulate != 0 adds to S64.  The call reads rowptr[D] back to the host.
  * Errors: TSK_EINVAL (null, D < 1, V < 1, alpha0 < 0 or not finite, dtype),
- * TSK_EUNSUPPORTED (K too large for one work-group's LDS at this b). */
+ * TSK_EUNSUPPORTED (K above 128, or too large for one work-group's LDS at
+ * this b). */
 tsk_status tsk_sketch_build_docs(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowptr,
                                  const int32_t* col, const int32_t* cnt, int D, int V,
                                  const void* W, tsk_dtype wdtype, double alpha0, double* S64,
@@ -335,7 +353,7 @@ tsk_status tsk_lda_recover(tsk_ctx_t ctx, int V, int K, int k, double alpha0, co
                            const double* lam, const double* U, double* alpha_out, double* mu_out,
                            void* stream);
 
-/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
+/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
  * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the
  * T(u,u,u) estimate of Eq. (3), and its gradient.  Each count sketch is linear
  * in u, so

@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
-    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "contract_tiuu",
+    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "tune_config", "contract_tiuu",
     "contract_uuu",
     "decompose", "contract_tuuu_grad", "cp_loss", "Problem", "decompose_batched",
     "workspace_size", "sketch_build_docs",
@@ -62,6 +62,7 @@ _SIGS = {
     "tsk_sketch_deflate": ([_P, _P, _P, _P, _I, _P, _P, _P], _I),
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "tsk_power_update_noalloc": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
+    "tsk_tune_config": ([_P, _I, ctypes.c_char_p], _I),
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
     "tsk_sym_tables_create": ([_P, _I, _I, _I, _P, _P, _P], _I),
@@ -426,6 +427,15 @@ def power_update(ctx, tab, U_in, S64=None, S32=None, U_out=None, V=None, flags=N
         ctx.handle, tab.handle, dt, _ptr(S64), _ptr(S32), L, _ptr(U_in), _ptr(U_out), _ptr(V),
         _ptr(flags), _stream(stream)))
     return U_out
+
+
+def tune_config(ctx, mode, cache_path=None):
+    """Launch-shape tuning of the context: 0 fixed rules, 1 time the candidates
+    of each new shape on first use and record the fastest, 2 recorded choices
+    only; ``cache_path`` names the text file the choices are read from and
+    written to."""
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check("tsk_tune_config", lib().tsk_tune_config(ctx.handle, int(mode), path))
 
 
 def power_update_noalloc(ctx, tab, U_in, U_out, S64=None, S32=None, flags=None, stream=None):

@@ -1640,25 +1640,123 @@ __global__ __launch_bounds__(256) void k_cp_grad(const double* lam_per, const R*
 // term x (x) y (x) z is sketched as F(s1 x) F(s2 y) F(s3 z) (Eq. (2)).
 // ===========================================================================
 
-// p_d = W^T n_d and the document coefficients; one block per document.
+// Matrix-core steps of 16 x 16 x 4 (k = 4): lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; output v < 4 of lane l is D[row(l / 16, v)][l % 16], with
+// row = 4 (l / 16) + v in FP32 and (l / 16) + 4 v in FP64 (measured on gfx950).
+typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  using acc = mfma_f32x4;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+template <>
+struct Mfma16<double> {
+  using acc = mfma_f64x4;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
+
+// p_d = W^T n_d for 16 documents per work-group as one dense product on the
+// matrix cores, and the document coefficients.  The tile's nonzeros e (their
+// documents' CSR ranges, concatenated) are the inner dimension: A[r][e] is the
+// count of e when e belongs to the tile's document r (zero otherwise) and
+// B[e][c] = W[word(e)][c], so P_tile = A B.  Each MFMA step takes four
+// nonzeros; wave w owns the column blocks w and w + 4 of 16 columns (K <= 128).
+// Each lane follows one nonzero per step and keeps its document row by
+// walking the tile's CSR bounds forward.  Counts are integers, exact in R; the
+// document length m_d comes from the same A values.
 template <typename R>
 __global__ __launch_bounds__(256) void k_doc_project(const int32_t* rowptr, const int32_t* col,
                                                      const int32_t* cnt, int D, int K, const R* W,
                                                      R* P, double* cd, double* cpd, double* invm) {
-  for (int d = blockIdx.x; d < D; d += gridDim.x) {
-    const int lo = rowptr[d], hi = rowptr[d + 1];
-    double m = 0.0;
-    for (int e = lo; e < hi; ++e) m += (double)cnt[e];
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-      double p = 0.0;
-      for (int e = lo; e < hi; ++e) p += (double)cnt[e] * (double)W[(size_t)col[e] * K + k];
-      P[(size_t)d * K + k] = (R)p;
+  using M = Mfma16<R>;
+  __shared__ int bnd[17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int c0 = wave * 16 + r16, c1 = c0 + 64;
+  const bool v0 = c0 < K, v1 = c1 < K;
+  const int ntile = (D + 15) >> 4;
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const int d0 = t << 4;
+    __syncthreads();  // the previous tile's readers of bnd are done
+    if (threadIdx.x <= 16) bnd[threadIdx.x] = rowptr[min(d0 + (int)threadIdx.x, D)];
+    __syncthreads();
+    const int lo = bnd[0], hi = bnd[16];
+    typename M::acc acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    R msum = 0;
+    int e = lo + kq;
+    int row = 0;
+    while (row < 16 && e >= bnd[row + 1]) ++row;
+    int e0 = lo;
+    // four steps (16 nonzeros) per round while all are in range
+    for (; e0 + 16 <= hi; e0 += 16) {
+      int w[4], n[4], rw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        w[u] = col[e + 4 * u];
+        n[u] = cnt[e + 4 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rw[u] = row;
+        e += 4;
+        while (row < 16 && e >= bnd[row + 1]) ++row;
+      }
+      R b0[4], b1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        b0[u] = v0 ? W[(size_t)w[u] * K + c0] : (R)0;
+        b1[u] = v1 ? W[(size_t)w[u] * K + c1] : (R)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const R a = rw[u] == r16 ? (R)n[u] : (R)0;
+        acc0 = M::mac(a, b0[u], acc0);
+        acc1 = M::mac(a, b1[u], acc1);
+        msum += a;
+      }
     }
-    if (threadIdx.x == 0) {
-      const bool keep = m >= 3.0;  // documents with fewer than three words are dropped
-      cd[d] = keep ? 1.0 / (m * (m - 1.0) * (m - 2.0)) : 0.0;
-      cpd[d] = keep ? 1.0 / (m * (m - 1.0)) : 0.0;
-      invm[d] = keep ? 1.0 / m : 0.0;
+    for (; e0 < hi; e0 += 4) {
+      const bool ok = e < hi;
+      const int es = ok ? e : lo;
+      const int w = col[es], n = cnt[es];
+      const R a = (ok && row == r16) ? (R)n : (R)0;
+      const R b0 = v0 ? W[(size_t)w * K + c0] : (R)0;
+      const R b1 = v1 ? W[(size_t)w * K + c1] : (R)0;
+      acc0 = M::mac(a, b0, acc0);
+      acc1 = M::mac(a, b1, acc1);
+      msum += a;
+      e += 4;
+      while (row < 16 && e >= bnd[row + 1]) ++row;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int d = d0 + M::row(kq, v);
+      if (d < D) {
+        if (v0) P[(size_t)d * K + c0] = acc0[v];
+        if (v1) P[(size_t)d * K + c1] = acc1[v];
+      }
+    }
+    if (wave == 0) {
+      // lanes r16, r16 + 16, r16 + 32, r16 + 48 hold parts of document r16's length
+      double m = (double)msum;
+      m += __shfl_xor(m, 16);
+      m += __shfl_xor(m, 32);
+      const int d = d0 + r16;
+      if (kq == 0 && d < D) {
+        const bool keep = m >= 3.0;  // documents with fewer than three words are dropped
+        cd[d] = keep ? 1.0 / (m * (m - 1.0) * (m - 2.0)) : 0.0;
+        cpd[d] = keep ? 1.0 / (m * (m - 1.0)) : 0.0;
+        invm[d] = keep ? 1.0 / m : 0.0;
+      }
     }
   }
 }

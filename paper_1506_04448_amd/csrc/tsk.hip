@@ -8,9 +8,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -99,6 +101,14 @@ struct tsk_ctx {
   std::vector<hipEvent_t> gfork_ev;
   void* scratch = nullptr;           // this device's address of `scratch` below
   bool no_alloc = false;             // set while an allocation-free entry point runs
+  // Launch-shape tuning (tsk_tune_config): mode, cache file, the choices by
+  // shape key, the device's name in every key, and a restart-group count
+  // forced while a decomposition's candidates are timed.
+  int tune_mode = 0;
+  std::string tune_path;
+  std::map<std::string, std::vector<int>> tune;
+  std::string tune_dev;
+  int force_groups = 0;
 };
 
 struct tsk_tables {
@@ -129,7 +139,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -622,6 +632,97 @@ struct NoAllocGuard {
   ~NoAllocGuard() { c->no_alloc = false; }
 };
 
+// ---- launch-shape tuning ------------------------------------------------------
+// Shapes the tuner chooses: sketches per work-group and slab count of the
+// dense build (how the buckets are privatised in LDS and how the tensor is
+// split), and the number of restart groups a decomposition runs on parallel
+// graph branches.  A choice is stored under a key naming the device, the
+// entry point, the precision and the sizes that decide it; the cache file has
+// one line per key: the key, then the chosen integers.
+
+std::string tune_key(tsk_ctx_t ctx, const char* what, tsk_dtype dtype, std::initializer_list<long> sizes) {
+  std::ostringstream k;
+  k << what << ':' << ctx->tune_dev << ':' << (dtype == TSK_F32 ? "f32" : "f64");
+  for (long v : sizes) k << ':' << v;
+  return k.str();
+}
+
+void tune_load(tsk_ctx_t ctx) {
+  std::ifstream f(ctx->tune_path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    if (!(ls >> key)) continue;
+    std::vector<int> v;
+    int x;
+    while (ls >> x) v.push_back(x);
+    if (!v.empty()) ctx->tune[key] = v;
+  }
+}
+
+tsk_status tune_save(tsk_ctx_t ctx) {
+  if (ctx->tune_path.empty()) return TSK_OK;
+  const std::string tmp = ctx->tune_path + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return tsk::fail(TSK_EINVAL, "tuning cache %s: cannot write", tmp.c_str());
+    for (const auto& kv : ctx->tune) {
+      f << kv.first;
+      for (int x : kv.second) f << ' ' << x;
+      f << '\n';
+    }
+    if (!f) return tsk::fail(TSK_EINVAL, "tuning cache %s: write failed", tmp.c_str());
+  }
+  if (std::rename(tmp.c_str(), ctx->tune_path.c_str()) != 0)
+    return tsk::fail(TSK_EINVAL, "tuning cache %s: rename failed", ctx->tune_path.c_str());
+  return TSK_OK;
+}
+
+// Mean time in ms of `reps` runs of `run` on stream st, after one untimed run.
+template <typename F>
+tsk_status time_runs(hipStream_t st, int reps, F run, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TSK_HIP(hipEventCreate(&e0));
+  TSK_HIP(hipEventCreate(&e1));
+  tsk_status s = run();
+  if (s == TSK_OK && hipEventRecord(e0, st) != hipSuccess) s = tsk::fail(TSK_EHIP, "tuning: event record");
+  for (int r = 0; r < reps && s == TSK_OK; ++r) s = run();
+  if (s == TSK_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                      hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+    s = tsk::fail(TSK_EHIP, "tuning: event timing");
+  if (s == TSK_OK) *ms /= (float)reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return s;
+}
+
+// The cached choice of `key`, or, in mode 1 and when not cached, the fastest
+// candidate (timed by time_one) recorded under it; nullptr means "use the rule".
+template <typename C, typename F>
+tsk_status tune_choose(tsk_ctx_t ctx, const std::string& key, const std::vector<C>& cands,
+                       std::vector<int> (*encode)(const C&), F time_one, const std::vector<int>** out) {
+  *out = nullptr;
+  if (ctx->tune_mode == 0) return TSK_OK;
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end() && ctx->tune_mode == 1 && !cands.empty()) {
+    float best = 0.0f;
+    size_t bi = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      float ms = 0.0f;
+      TSK_TRY(time_one(cands[i], &ms));
+      if (i == 0 || ms < best) {
+        best = ms;
+        bi = i;
+      }
+    }
+    it = ctx->tune.emplace(key, encode(cands[bi])).first;
+    TSK_TRY(tune_save(ctx));
+  }
+  if (it != ctx->tune.end()) *out = &it->second;
+  return TSK_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -670,6 +771,23 @@ extern "C" void tsk_destroy(tsk_ctx_t c) {
   for (auto s : c->gfork) (void)hipStreamDestroy(s);
   for (auto e : c->gfork_ev) (void)hipEventDestroy(e);
   delete c;
+}
+
+extern "C" tsk_status tsk_tune_config(tsk_ctx_t ctx, int mode, const char* cache_path) {
+  if (!ctx) return tsk::fail(TSK_EINVAL, "tsk_tune_config: null context");
+  if (mode < 0 || mode > 2) return tsk::fail(TSK_EINVAL, "tsk_tune_config: mode %d not in {0, 1, 2}", mode);
+  TSK_TRY(set_device(ctx));
+  hipDeviceProp_t prop;
+  TSK_HIP(hipGetDeviceProperties(&prop, ctx->device));
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  ctx->tune_dev = arch + "_cu" + std::to_string(prop.multiProcessorCount);
+  ctx->tune_mode = mode;
+  ctx->tune_path = cache_path ? cache_path : "";
+  ctx->tune.clear();
+  if (!ctx->tune_path.empty()) tune_load(ctx);
+  return TSK_OK;
 }
 
 extern "C" tsk_status tsk_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint32_t* h_host,
@@ -797,30 +915,59 @@ int absmax_blocks(size_t count) {
   return (int)std::max<size_t>(1, std::min<size_t>(512, (count + 4095) / 4096));
 }
 
+// Launch shape of a dense build: sketches (bin ranges) per work-group and slabs.
+struct BuildPlan {
+  int G = 0;
+  int nslab = 0;
+};
+
+// Bin ranges per sketch: sketches longer than 16384 buckets are split into
+// ranges of 16384, one range per work-group (each range reads the whole tensor).
+int build_nrange(int b) { return b > 16384 ? b / 16384 : 1; }
+
+// Most sketches one work-group's LDS pool holds (1 with split ranges).
+int build_max_g(tsk_tables_t tab) {
+  const int nrange = build_nrange(tab->b);
+  if (nrange > 1) return 1;
+  const size_t per_sketch = (size_t)(tab->b / nrange) * 8;
+  return (int)std::min<size_t>({(size_t)tab->B, (size_t)tsk::kBuildMaxG, (size_t)kBuildPoolLarge * 8 / per_sketch});
+}
+
+// The rule: as many sketches per work-group as the pool holds; slabs in
+// multiples of 8 (one per XCD lane of the grid mapping), as many as fill each
+// XCD's 32 CUs in one round (one work-group per CU with the large pool, two
+// with the small one), never slabs of fewer than 8 fibres.  G <= 0 asks for the
+// largest G.
+BuildPlan build_plan_rule(tsk_tables_t tab, int G = 0) {
+  const int nrange = build_nrange(tab->b);
+  const int Bv = tab->B * nrange;
+  const size_t per_sketch = (size_t)(tab->b / nrange) * 8;
+  BuildPlan p;
+  p.G = G > 0 ? std::min(G, build_max_g(tab)) : build_max_g(tab);
+  const int ngroups = (Bv + p.G - 1) / p.G;
+  const int Gb = (Bv + ngroups - 1) / ngroups;
+  const bool small = (size_t)Gb * per_sketch <= (size_t)kBuildPoolSmall * 8;
+  p.nslab = pick_nslab((long long)tab->n * tab->n, ngroups, small);
+  return p;
+}
+
 template <typename TIn>
 tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipStream_t st,
-                            double** s_time_out) {
+                            double** s_time_out, BuildPlan plan) {
   const int n = tab->n, b = tab->b, B = tab->B;
-  // Sketches longer than 16384 buckets are split into bucket ranges of 16384,
-  // one range per work-group (each range reads the whole tensor).
-  const int nrange = b > 16384 ? b / 16384 : 1;
+  const int nrange = build_nrange(b);
   const int br = b / nrange;
   int lbr = 0;
   while ((1 << lbr) < br) ++lbr;
   const int Bv = B * nrange;                                  // (sketch, range) pairs
   const size_t per_sketch = (size_t)br * 8;  // 64-bit bins
-  int G = nrange > 1 ? 1
-                     : (int)std::min<size_t>({(size_t)B, (size_t)tsk::kBuildMaxG,
-                                              (size_t)kBuildPoolLarge * 8 / per_sketch});
+  int G = std::max(1, std::min(plan.G, build_max_g(tab)));
   const int ngroups = (Bv + G - 1) / G;
   G = (Bv + ngroups - 1) / ngroups;  // balance the groups
   const bool small = (size_t)G * per_sketch <= (size_t)kBuildPoolSmall * 8;
   const long long npairs = (long long)n * n;
-  // Slabs come in multiples of 8 (one per XCD lane of the grid mapping), as
-  // many as fill each XCD's 32 CUs in one round (one work-group per CU with
-  // the large pool, two with the small one), never slabs of fewer than 8
-  // fibres; slab lengths are multiples of 4 fibres (the kernel's items).
-  int nslab = pick_nslab(npairs, ngroups, small);
+  // slab lengths are multiples of 4 fibres (the kernel's items)
+  int nslab = (int)std::max<long long>(1, std::min<long long>(plan.nslab, npairs));
   long long pps = (npairs + nslab - 1) / nslab;
   pps = (pps + 3) / 4 * 4;
   nslab = (int)((npairs + pps - 1) / pps);
@@ -886,6 +1033,51 @@ tsk_status build_dense_impl(tsk_ctx_t ctx, tsk_tables_t tab, const TIn* T, hipSt
 
 }  // namespace
 
+namespace {
+
+std::vector<int> encode_plan(const BuildPlan& p) { return {p.G, p.nslab}; }
+
+// Candidate build plans: every sketches-per-work-group count the pool allows,
+// each with the rule's slab count, half of it and twice it; the rule first.
+std::vector<BuildPlan> build_candidates(tsk_tables_t tab) {
+  std::vector<BuildPlan> out;
+  const long long nfib = (long long)tab->n * tab->n;
+  for (int G = build_max_g(tab); G >= 1; --G) {
+    const BuildPlan r = build_plan_rule(tab, G);
+    for (int q : {4, 2, 8}) {
+      BuildPlan c;
+      c.G = G;
+      c.nslab = (int)std::min<long long>(nfib, std::max(8, (r.nslab * q / 4 + 7) / 8 * 8));
+      bool dup = false;
+      for (const auto& o : out) dup |= (o.G == c.G && o.nslab == c.nslab);
+      if (!dup) out.push_back(c);
+    }
+  }
+  return out;
+}
+
+template <typename TIn>
+tsk_status build_dense_tuned(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const TIn* T, hipStream_t st,
+                             double** stime) {
+  BuildPlan plan = build_plan_rule(tab);
+  if (ctx->tune_mode != 0) {
+    const std::string key = tune_key(ctx, "build", dtype, {tab->n, tab->b, tab->B});
+    const std::vector<int>* ch = nullptr;
+    auto time_one = [&](const BuildPlan& p, float* ms) -> tsk_status {
+      double* scratch_time = nullptr;
+      return time_runs(st, 3, [&]() { return build_dense_impl<TIn>(ctx, tab, T, st, &scratch_time, p); }, ms);
+    };
+    TSK_TRY(tune_choose(ctx, key, build_candidates(tab), encode_plan, time_one, &ch));
+    if (ch && ch->size() == 2) {
+      plan.G = (*ch)[0];
+      plan.nslab = (*ch)[1];
+    }
+  }
+  return build_dense_impl<TIn>(ctx, tab, T, st, stime, plan);
+}
+
+}  // namespace
+
 extern "C" tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, const void* T,
                                              tsk_dtype dtype, double* S64, float* S32,
                                              int accumulate, void* stream) {
@@ -896,9 +1088,9 @@ extern "C" tsk_status tsk_sketch_build_dense(tsk_ctx_t ctx, tsk_tables_t tab, co
   TSK_TRY(set_device(ctx));
   double* stime = nullptr;
   if (dtype == TSK_F32)
-    TSK_TRY(build_dense_impl<float>(ctx, tab, (const float*)T, S(stream), &stime));
+    TSK_TRY(build_dense_tuned<float>(ctx, tab, dtype, (const float*)T, S(stream), &stime));
   else
-    TSK_TRY(build_dense_impl<double>(ctx, tab, (const double*)T, S(stream), &stime));
+    TSK_TRY(build_dense_tuned<double>(ctx, tab, dtype, (const double*)T, S(stream), &stime));
   return r2c_any(ctx, tab->logb, stime, reinterpret_cast<cx<double>*>(S64),
                  reinterpret_cast<cx<float>*>(S32), accumulate ? 1 : 0, tab->B, S(stream));
 }
@@ -1470,7 +1662,7 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   cx<double>* partD = (cx<double>*)at(17);
   cx<double>* partW = (cx<double>*)at(18);
 
-  hipLaunchKernelGGL(tsk::k_doc_project<R>, dim3(std::min(D, 8192)), dim3(128), 0, st, rowptr, col, cnt,
+  hipLaunchKernelGGL(tsk::k_doc_project<R>, dim3(std::min((D + 15) / 16, 8192)), dim3(256), 0, st, rowptr, col, cnt,
                      D, K, W, P, cd, cpd, invm);
   TSK_TRY(check_launch("k_doc_project"));
   hipLaunchKernelGGL(tsk::k_doc_q_partial<R>, dim3(G), dim3(128), 0, st, (const R*)P, (const double*)invm,
@@ -1553,6 +1745,8 @@ extern "C" tsk_status tsk_sketch_build_docs(tsk_ctx_t ctx, tsk_tables_t tab, con
     return tsk::fail(TSK_EUNSUPPORTED, "tsk_sketch_build_docs: b=%d > 16384 is not built", tab->b);
   if (!rowptr || !W || !S64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: null argument");
   if (D < 1 || V < 1) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: D=%d, V=%d must be >= 1", D, V);
+  if (tab->n > 128)
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_sketch_build_docs: K=%d > 128 columns of the projection", tab->n);
   if (wdtype != TSK_F32 && wdtype != TSK_F64) return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: bad dtype");
   if (!(alpha0 >= 0.0) || alpha0 > 1e300)
     return tsk::fail(TSK_EINVAL, "tsk_sketch_build_docs: alpha0=%g must be finite and >= 0", alpha0);
@@ -1936,6 +2130,39 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
   TSK_TRY(set_device(ctx));
   hipStream_t st = S(stream);
   const int n = tab->n;
+  int groups = ctx->force_groups > 0 ? std::min(ctx->force_groups, L) : restart_groups(tab, dtype, L);
+  if (!plain && ctx->force_groups == 0 && ctx->tune_mode != 0 && !needs_power_split(tab, dtype) && L >= 2) {
+    // Restart groups: each candidate times a one-component decomposition of
+    // the same sizes on a copy of the sketch (the choice does not change the
+    // arithmetic of any restart).
+    const std::string key = tune_key(ctx, "decompose", dtype, {n, tab->b, tab->B, L, T});
+    std::vector<int> cands;
+    for (int g = 1; g <= std::min(4, L); ++g) cands.push_back(g);
+    const size_t H1 = (size_t)tab->b / 2 + 1;
+    const size_t b64 = ((size_t)tab->B * H1 * 16 + 255) & ~(size_t)255;
+    const size_t b32 = ((size_t)tab->B * H1 * 8 + 255) & ~(size_t)255;
+    auto time_one = [&](const int& g, float* ms) -> tsk_status {
+      void* tb = nullptr;
+      TSK_TRY(ws_get(ctx, WS_TUNE, b64 + b32 + 8 + (size_t)n * 8 + 256, &tb));
+      double* s64 = (double*)tb;
+      float* s32 = (float*)((char*)tb + b64);
+      double* lam1 = (double*)((char*)tb + b64 + b32);
+      double* u1 = lam1 + 1;
+      TSK_HIP(hipMemcpyAsync(s64, S64, (size_t)tab->B * H1 * 16, hipMemcpyDeviceToDevice, st));
+      if (S32) TSK_HIP(hipMemcpyAsync(s32, S32, (size_t)tab->B * H1 * 8, hipMemcpyDeviceToDevice, st));
+      ctx->force_groups = g;
+      const tsk_status s = time_runs(st, 2, [&]() {
+        return tsk_decompose(ctx, tab, dtype, s64, s32, 1, L, T, nullptr, 0, lam1, u1, nullptr, nullptr, 0,
+                             stream);
+      }, ms);
+      ctx->force_groups = 0;
+      return s;
+    };
+    auto encode = [](const int& g) { return std::vector<int>{g}; };
+    const std::vector<int>* ch = nullptr;
+    TSK_TRY(tune_choose(ctx, key, cands, +encode, time_one, &ch));
+    if (ch && !ch->empty()) groups = std::max(1, std::min((*ch)[0], L));
+  }
   const size_t bytes = decomp_ws_layout(nullptr, tab, dtype, k, L, !flags_out, false, nullptr, nullptr,
                                         nullptr);
   // Generated start vectors live in a slot of their own: other entry points
@@ -1958,7 +2185,6 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
     u0d = u0_ws;
   }
   TSK_TRY(preload_twiddles(ctx, tab, dtype));  // uploads stay outside any capture
-  const int groups = restart_groups(tab, dtype, L);
   if (!plain) TSK_TRY(ensure_branches(ctx->gfork, ctx->gfork_ev, groups));
   auto enqueue = [&](hipStream_t s) -> tsk_status {
     return decompose_all(ctx, tab, dtype, S64, S32, k, L, T, u0d, lam_out, U_out, tau_out, flags, w,
@@ -2595,8 +2821,8 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   }
   // Yout = M2 X
   auto apply = [&](const double* X, double* Yout) -> tsk_status {
-    hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min(D, 8192)), dim3(128), 0, st, rowptr, col, cnt, D,
-                       K, X, P, cd, cpd, invm);
+    hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min((D + 15) / 16, 8192)), dim3(256), 0, st, rowptr,
+                       col, cnt, D, K, X, P, cd, cpd, invm);
     TSK_TRY(check_launch("k_doc_project"));
     hipLaunchKernelGGL(tsk::k_doc_q_partial<double>, dim3(G), dim3(128), 0, st, (const double*)P,
                        (const double*)invm, D, K, per_q, qpart);
