@@ -40,6 +40,13 @@ COPY_BYTES = 256 << 20
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counter runs,
 # stored with the hash of the kernel sources they were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_dense_n200_b16384.txt")
+# Instruction counters (SQ block) per dispatch with the kernel-trace durations
+# of the same run, stored with the same hash.
+SQ_FILE = os.path.join(ROOT, "profiles", "sq_counters_dense_n200_b16384.txt")
+SQ_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVES", "SQ_BUSY_CYCLES",
+               "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_VALU")
+CLOCK_GHZ = 2.4
+NUM_CU = 256
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1506_04448_amd", "csrc", f)
                   for f in ("fft.hpp", "kernels.hpp")]
 
@@ -67,6 +74,72 @@ def stored_traffic(kernel: str):
         return None
     val = kv.get(f"traffic[{kernel}]")
     return float(val) if val is not None else None
+
+
+def _stored_kv(path: str) -> dict:
+    kv = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    key, val = line.split(":", 1)
+                    kv[key.strip()] = val.strip()
+    return kv
+
+
+def stored_sq(kernel: str):
+    """Issue fractions of `kernel` from the stored SQ counter summary, or None
+    when there is none or the kernels changed since it was taken."""
+    kv = _stored_kv(SQ_FILE)
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    out = {}
+    for name in ("valu_issue_frac", "lds_issue_frac", "lds_bank_conflict_frac", "valu_insts_per_wave",
+                 "duration_us"):
+        val = kv.get(f"{name}[{kernel}]")
+        if val is not None:
+            out[name] = float(val)
+    return out or None
+
+
+def summarize_sq(counter_csv: str, trace_csv: str) -> str:
+    """Text summary of an SQ counter run (rocprofv3 --pmc with --kernel-trace):
+    per kernel the mean counters per dispatch, the mean duration, and
+      valu_issue_frac = SQ_INSTS_VALU / (CUs x cycles)   (one wave-wide VALU
+                        instruction per CU per clock is the issue limit of
+                        four SIMD16 units, unpacked FP32),
+      lds_issue_frac  = SQ_INSTS_LDS / (CUs x cycles),
+      lds_bank_conflict_frac = SQ_LDS_BANK_CONFLICT / (CUs x cycles),
+    with cycles = duration x the 2.4 GHz peak clock."""
+    acc = defaultdict(lambda: defaultdict(list))
+    with open(counter_csv) as fh:
+        for r in csv.DictReader(fh):
+            acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = defaultdict(list)
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = [f"kernel_sources_sha256: {kernel_sources_sha256()}",
+           f"# clock {CLOCK_GHZ} GHz, {NUM_CU} CUs; counters are per-dispatch means",
+           "# kernel | dispatches | mean us | " + " | ".join(SQ_COUNTERS)]
+    derived = {}
+    for k in sorted(acc, key=lambda k: -sum(dur.get(k, [0.0])) if k in dur else 0.0):
+        c = {n: sum(v) / len(v) for n, v in acc[k].items()}
+        d = dur.get(k)
+        mean_us = sum(d) / len(d) if d else float("nan")
+        out.append(f"# {k[:90]} | {len(acc[k].get('SQ_WAVES', []))} | {mean_us:.2f} | "
+                   + " | ".join(f"{c.get(n, float('nan')):.4g}" for n in SQ_COUNTERS))
+        cyc = mean_us * 1e-6 * CLOCK_GHZ * 1e9 * NUM_CU
+        for name in (POWER_KERNEL, BUILD_KERNEL, "k_terms<float, 14, false"):
+            if name in k and name not in derived and d:
+                derived[name] = (c, mean_us, cyc)
+    for name, (c, mean_us, cyc) in derived.items():
+        out.append(f"duration_us[{name}]: {mean_us:.3f}")
+        out.append(f"valu_issue_frac[{name}]: {c['SQ_INSTS_VALU'] / cyc:.4f}")
+        out.append(f"lds_issue_frac[{name}]: {c['SQ_INSTS_LDS'] / cyc:.4f}")
+        out.append(f"lds_bank_conflict_frac[{name}]: {c['SQ_LDS_BANK_CONFLICT'] / cyc:.4f}")
+        out.append(f"valu_insts_per_wave[{name}]: {c['SQ_INSTS_VALU'] / max(c['SQ_WAVES'], 1.0):.1f}")
+    return "\n".join(out)
 
 
 def _counter_means(path: str, counter: str):
@@ -227,6 +300,16 @@ def c3_batched(ctx, dev, nrep: int = 3):
     res = [residual_factored(inst.lam, inst.A, p.lam.cpu().numpy(), p.U.cpu().numpy())
            / residual_factored(inst.lam, inst.A, np.zeros(0), np.zeros((0, inst.n)))
            for p, inst in zip(probs, insts)]
+    wrong = [wrong_vectors(inst.A, p.U.cpu().numpy()) for p, inst in zip(probs, insts)]
+    by_b = {}
+    for bb in sorted({inst.b for inst in insts}):
+        sel = [i for i, inst in enumerate(insts) if inst.b == bb]
+        rs = np.array([res[i] for i in sel])
+        by_b[str(bb)] = {"instances": len(sel), "relative_residual_median": float(np.median(rs)),
+                         "fraction_residual_below_1": float(np.mean(rs < 1.0)),
+                         "wrong_vectors": int(sum(wrong[i] for i in sel)),
+                         "planted_vectors": int(sum(insts[i].k for i in sel)),
+                         "n_range": [int(min(insts[i].n for i in sel)), int(max(insts[i].n for i in sel))]}
     ms_b, ms_s = float(np.median(tb)), float(np.median(ts))
     for t in tabs:
         t.close()
@@ -238,6 +321,7 @@ def c3_batched(ctx, dev, nrep: int = 3):
         "sketch_updates_per_s": updates / (ms_b * 1e-3), "speedup_vs_sequential": ms_s / ms_b,
         "same_result_as_sequential": bool(same),
         "relative_residual_median": float(np.median(res)),
+        "recovery_by_b": by_b,
     }
 
 
@@ -306,11 +390,41 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
     alpha_hat, mu = tsk.lda_recover(ctx, Wdat, lam2, U2, alpha0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    mu_t = mu
     mu = mu.cpu().numpy()
     Ph = C.Phi.T
     cos = (Ph / np.linalg.norm(Ph, axis=1, keepdims=True)) @ (mu / np.linalg.norm(mu, axis=1, keepdims=True)).T
     best = cos.max(axis=1)
     tab.close()
+    # Held-out likelihood (Section 5.2) on 1000 of the documents: the topic
+    # matrix of Algorithm 3 at several sketch lengths against the true one.
+    nh, eps = 1000, 1e-3
+    rp_h = rp[:nh + 1].contiguous()
+
+    def topics(mu_rows):
+        P = torch.clamp(mu_rows.T, min=0.0)
+        P = P / torch.clamp(P.sum(dim=0, keepdim=True), min=1e-300)
+        return ((1.0 - eps) * P + eps / V).contiguous()
+
+    def heldout(Phi_d):
+        _, ll = tsk.lda_heldout(ctx, rp_h, col, cnt, V, Phi_d)
+        return float(ll.mean())
+
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    ll_hat = {str(b): heldout(topics(mu_t))}
+    torch.cuda.synchronize()
+    heldout_ms = 1e3 * (time.perf_counter() - th)
+    ll_true = heldout(topics(torch.from_numpy(C.Phi.T.copy()).to(dev)))
+    for bb in (4096, 8192):
+        hb, xb = tsk.hash_generate(3, K, bb, B)
+        tb_ = tsk.Tables(ctx, hb, xb, bb)
+        Sb64, Sb32 = tsk.new_sketch(tb_, dev)
+        tsk.sketch_build_docs(ctx, tb_, rp, col, cnt, V, Wdat.float(), alpha0, Sb64, Sb32)
+        lb, Ub, _, _ = tsk.decompose(ctx, tb_, Sb64, Sb32, K, L, T, dtype=tsk.F32, seed=3)
+        _, mub = tsk.lda_recover(ctx, Wdat, lb, Ub, alpha0)
+        ll_hat[str(bb)] = heldout(topics(mub))
+        tb_.close()
     return {
         "workload": (f"synthetic LDA corpus D={D}, V={V}, K={K} topics (Dirichlet 0.01 topics, 0.1 "
                      f"mixtures, Poisson(150) lengths), population whitening; b={b}, B={B}; "
@@ -325,6 +439,10 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
         "algorithm3_topics_cos_median": float(np.median(best)),
         "algorithm3_alpha_median": float(np.median(alpha_hat.cpu().numpy())),
         "true_alpha": float(C.alpha[0]),
+        "heldout": {"documents": nh, "smoothing": eps,
+                    "note": ("average per-word log-likelihood L_d of the first 1000 documents; topic "
+                             "columns max(mu, 0) normalised, mixed with eps of the uniform distribution"),
+                    "loglik_by_b": ll_hat, "loglik_true_topics": ll_true, "ms": heldout_ms},
     }
 
 
@@ -492,61 +610,192 @@ def x1_als_row(ctx, dev, tab, S32, Tt, X, nrm2, k, sigma, B, j, T=30):
             "paper_als_wrong": ref[1][j] if ref else None}
 
 
-def c5_autograd(ctx, dev, steps: int = 20):
-    """Gradient extensions at the shapes of the differentiation workload:
-    n=1000, k=100 planted orthonormal components (lam ~ U[1,2]), b=65536,
-    B=16, FP32.  The sketches are built from the factors (the 4 GB dense
-    tensor and its noise are not formed).  Timed: the T(u,u,u) estimate with
-    its gradient for 256 vectors, and the sketched CP loss with its
-    gradients; then Adam steps from a perturbed start."""
+def tensor_norm2(Tt, slab: int = 100) -> float:
+    """||T||_F^2 in FP64, slab by slab."""
+    return sum(float((Tt[i0:i0 + slab].double() ** 2).sum()) for i0 in range(0, Tt.shape[0], slab))
+
+
+def dense_residual(Tt, nrm2: float, lam, U, slab: int = 100) -> float:
+    """||T - sum_r lam_r u_r^(x)3||_F^2 in FP64 on the device:
+    ||T||^2 - 2 sum_r lam_r T(u_r,u_r,u_r) + sum_rs lam_r lam_s (u_r.u_s)^3."""
+    import torch
+    n = Tt.shape[0]
+    Ud = U.double()
+    k = Ud.shape[0]
+    tuuu = torch.zeros(k, dtype=torch.float64, device=Ud.device)
+    for i0 in range(0, n, slab):
+        Y = (Tt[i0:i0 + slab].double().reshape(-1, n) @ Ud.T).view(-1, n, k)   # [i][j][r]
+        tuuu += torch.einsum("ijr,jr,ir->r", Y, Ud.T, Ud.T[i0:i0 + slab])
+    lamd = lam.double()
+    G = (Ud @ Ud.T) ** 3
+    return nrm2 - 2.0 * float(lamd @ tuuu) + float(lamd @ G @ lamd)
+
+
+def sketched_cp_grad_fp64(S64, h, xi, lam, U):
+    """FP64 reference of the sketched CP loss and its gradients, written with
+    torch FFTs on the device (measurement code, for the FP32-vs-FP64 error):
+    r^(m) = s^(m)(T) - sum_i lam_i s1(u_i)*s2(u_i)*s3(u_i), loss = mean_m ||r^(m)||^2,
+    dloss/dlam_i = -(2/B) sum_m <r^(m), s^(m)(u_i^(x)3)>,
+    dloss/du_i = -(2/B) lam_i sum_m sum_j xi_j(p) corr(r^(m), s_a(u_i)*s_b(u_i))[h_j(p)]."""
+    import torch
+    B, _, n = h.shape
+    b = 2 * (S64.shape[1] - 1)
+    dev = S64.device
+    lam = lam.double()
+    U = U.double()
+    k = U.shape[0]
+    hd = torch.from_numpy(h.astype(np.int64)).to(dev)
+    xd = torch.from_numpy(xi.astype(np.float64)).to(dev)
+    loss = 0.0
+    g_lam = torch.zeros(k, dtype=torch.float64, device=dev)
+    g_U = torch.zeros((k, n), dtype=torch.float64, device=dev)
+    for m in range(B):
+        F = []
+        for j in range(3):
+            cs = torch.zeros((k, b), dtype=torch.float64, device=dev)
+            cs.index_add_(1, hd[m, j], U * xd[m, j])
+            F.append(torch.fft.rfft(cs, dim=1))
+        P = F[0] * F[1] * F[2]
+        R = torch.view_as_complex(S64[m].contiguous()) - (lam[:, None] * P).sum(0)
+        r = torch.fft.irfft(R, n=b)
+        loss += float((r * r).sum())
+        g_lam += -2.0 / B * (torch.fft.irfft(P, n=b, dim=1) @ r)
+        for j in range(3):
+            Y = F[(j + 1) % 3] * F[(j + 2) % 3]
+            c = torch.fft.irfft(R[None, :] * Y.conj(), n=b, dim=1)             # [k][b]
+            g_U += -2.0 / B * lam[:, None] * xd[m, j][None, :] * c[:, hd[m, j]]
+    return loss / B, g_lam, g_U
+
+
+def dense_cp_grad_fp64(Tt, lam, U):
+    """The CP loss ||T - sum_i lam_i u_i^(x)3||^2 of the dense tensor and its
+    FP64 gradients (T symmetric, so each vector's gradient is three times one
+    mode's contraction)."""
+    import torch
+    lam = lam.double()
+    U = U.double()
+    R = Tt.double() - torch.einsum("r,ri,rj,rk->ijk", lam, U, U, U)
+    RU = torch.einsum("ijk,rk->rij", R, U)                     # R(I, I, u_r)
+    RUU = torch.einsum("rij,rj->ri", RU, U)                    # R(I, u_r, u_r)
+    return (float((R * R).sum()), -2.0 * (RUU * U).sum(1), -6.0 * lam[:, None] * RUU)
+
+
+def rel_err(a, b) -> float:
+    return float((a - b).norm() / b.norm())
+
+
+def c5_differentiation(ctx, dev, adam_steps: int = 200):
+    """The differentiation workload as specified: the dense n=1000, k=100
+    planted tensor (orthonormal components, lam ~ U[1,2]) plus noise 0.1 (std
+    1/n^1.5 per entry, symmetric), FP32 (4 GB); B=16 sketches of b=65536 built
+    from it; Algorithm 1 for the k=100 components (L=T=30); the T(u,u,u)
+    estimate with its gradient for 256 vectors and the sketched CP loss with
+    its gradients, timed; 200 Adam steps from the power method's output; the
+    dense residual before and after.  Then the gradient-check instance
+    (n=100, k=10, seed 5, random hashes): the FP32 sketched gradients against
+    an FP64 reference of the same sketched gradients (the FP32-vs-FP64 error)
+    and against the FP64 dense-tensor gradient (statistical agreement, O(1/sqrt(b)))."""
     import torch
     import paper_1506_04448_amd as tsk
     from paper_1506_04448_amd import autograd as tag
-    n, k, b, B, nb = 1000, 100, 65536, 16, 256
-    rng = np.random.default_rng(4)
-    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
-    lam = rng.uniform(1.0, 2.0, k)
+    from paper_1506_04448_amd.workloads import planted_tensor, planted_tensor_device
+    n, k, b, B, nb, L, Tn = 1000, 100, 65536, 16, 256, 30, 30
+    t0 = time.perf_counter()
+    P = planted_tensor_device(n, k, noise=0.1, seed=4, device=dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    Tt = P.T
+    nrm2 = tensor_norm2(Tt)
     h, xi = tsk.hash_generate(4, n, b, B)
     tab = tsk.Tables(ctx, h, xi, b)
     S64, S32 = tsk.new_sketch(tab, dev)
-    tsk.sketch_build_factors(ctx, tab, torch.from_numpy(lam).to(dev), torch.from_numpy(Q.T.copy()).to(dev),
-                             S64, S32)
-    U = torch.nn.functional.normalize(torch.randn((nb, n), device=dev), dim=1)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tsk.contract_tuuu_grad(ctx, tab, U, S32=S32)
+    tsk.sketch_build_dense(ctx, tab, Tt, S64, S32)
+    e0.record(stream)
+    tsk.sketch_build_dense(ctx, tab, Tt, S64, S32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    S64_0, S32_0 = S64.clone(), S32.clone()
+    e0.record(stream)
+    lam_h, U_h, _, _ = tsk.decompose(ctx, tab, S64, S32, k, L, Tn, dtype=tsk.F32, seed=7)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dec_ms = e0.elapsed_time(e1)
+    res_rtpm = dense_residual(Tt, nrm2, lam_h, U_h)
+    wrong_rtpm = wrong_vectors(P.V, U_h.cpu().numpy())
+    # T(u,u,u) with its gradient for 256 unit vectors, and the CP loss with gradients
+    Ub = torch.nn.functional.normalize(torch.randn((nb, n), device=dev), dim=1)
+    tsk.contract_tuuu_grad(ctx, tab, Ub, S32=S32_0)
     e0.record(stream)
     for _ in range(3):
-        tsk.contract_tuuu_grad(ctx, tab, U, S32=S32)
+        tsk.contract_tuuu_grad(ctx, tab, Ub, S32=S32_0)
     e1.record(stream)
     torch.cuda.synchronize()
     tuuu_ms = e0.elapsed_time(e1) / 3
-    lam0 = torch.from_numpy((lam * (1 + 0.05 * rng.standard_normal(k))).astype(np.float32)).to(dev)
-    U0 = Q.T + 0.02 * rng.standard_normal((k, n))
-    U0 = torch.from_numpy((U0 / np.linalg.norm(U0, axis=1, keepdims=True)).astype(np.float32)).to(dev)
-    tsk.cp_loss(ctx, tab, S64, lam0, U0)
+    lam0, U0 = lam_h.float(), U_h.float()
+    tsk.cp_loss(ctx, tab, S64_0, lam0, U0)
     e0.record(stream)
     for _ in range(3):
-        tsk.cp_loss(ctx, tab, S64, lam0, U0)
+        tsk.cp_loss(ctx, tab, S64_0, lam0, U0)
     e1.record(stream)
     torch.cuda.synchronize()
     loss_ms = e0.elapsed_time(e1) / 3
-    sk = tag.SketchHandle(ctx, tab, S64, None)
-    tag.refine_adam(sk, lam0, U0, steps=2, lr=1e-3)   # workspaces and tables allocated outside the timing
+    sk = tag.SketchHandle(ctx, tab, S64_0, None)
+    tag.refine_adam(sk, lam0, U0, steps=2, lr=1e-3)   # workspaces allocated outside the timing
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lam_r, U_r, losses = tag.refine_adam(sk, lam0, U0, steps=steps, lr=1e-3)
+    lam_r, U_r, losses = tag.refine_adam(sk, lam0, U0, steps=adam_steps, lr=1e-3)
     torch.cuda.synchronize()
     adam_s = time.perf_counter() - t0
     losses = losses.cpu().numpy()
+    res_adam = dense_residual(Tt, nrm2, lam_r, U_r)
+    wrong_adam = wrong_vectors(P.V, U_r.double().cpu().numpy())
     tab.close()
+    del Tt, P, S64, S32, S64_0, S32_0, sk
+    torch.cuda.empty_cache()
+
+    # gradient-check instance
+    nc, kc = 100, 10
+    Pc = planted_tensor(nc, kc, noise=0.1, seed=5)
+    rng = np.random.default_rng(5)
+    lam_c = Pc.lam * (1.0 + 0.05 * rng.standard_normal(kc))
+    U_c = Pc.V + 0.02 * rng.standard_normal(Pc.V.shape)
+    U_c /= np.linalg.norm(U_c, axis=1, keepdims=True)
+    lam_c32 = torch.from_numpy(lam_c.astype(np.float32)).to(dev)
+    U_c32 = torch.from_numpy(U_c.astype(np.float32)).to(dev)
+    hc, xc = tsk.hash_generate(105, nc, b, B)
+    tabc = tsk.Tables(ctx, hc, xc, b)
+    Sc64, Sc32 = tsk.new_sketch(tabc, dev)
+    Tc = torch.from_numpy(Pc.T).to(dev)
+    tsk.sketch_build_dense(ctx, tabc, Tc, Sc64, Sc32)
+    loss32, gl32, gU32 = tsk.cp_loss(ctx, tabc, Sc64, lam_c32, U_c32)
+    loss64, gl64, gU64 = sketched_cp_grad_fp64(Sc64, hc, xc, lam_c32, U_c32)
+    lossd, gld, gUd = dense_cp_grad_fp64(Tc, lam_c32, U_c32)
+    tabc.close()
     return {
-        "workload": (f"n={n}, k={k} planted orthonormal factors, b={b}, B={B}, FP32; sketches from the "
-                     f"factors; T(u,u,u) with gradient for {nb} vectors; CP loss with gradients"),
+        "workload": (f"dense planted tensor n={n}, k={k} orthonormal components, lam~U[1,2], noise 0.1 "
+                     f"(FP32, 4 GB); B={B} sketches of b={b}; Algorithm 1 (L={L}, T={Tn}, FP32 power "
+                     f"steps); T(u,u,u) with gradient for {nb} vectors; CP loss with gradients; "
+                     f"{adam_steps} Adam steps from the power method's output"),
+        "tensor_generation_s": t_gen, "build_ms": build_ms,
+        "build_GBps": build_bytes(n, b, B) / (build_ms * 1e-3) / 1e9,
+        "decompose_ms": dec_ms, "decompose_sketch_updates": k * (Tn + 1) * L * B,
+        "rtpm_residual": res_rtpm, "rtpm_wrong_vectors": int(wrong_rtpm),
         "tuuu_grad_ms": tuuu_ms, "tuuu_grad_vectors_per_s": nb / (tuuu_ms * 1e-3),
         "cp_loss_grad_ms": loss_ms,
-        "adam_steps": steps, "adam_s_per_step": adam_s / steps,
+        "adam_steps": adam_steps, "adam_s_per_step": adam_s / adam_steps,
         "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+        "adam_residual": res_adam, "adam_wrong_vectors": int(wrong_adam),
+        "gradient_check": {
+            "workload": (f"planted n={nc}, k={kc}, noise 0.1, seed 5; B={B}, b={b}, random hashes; "
+                         "(lam, U) = truth perturbed by 5% / 0.02"),
+            "fp32_vs_fp64": {"loss": abs(float(loss32) - loss64) / abs(loss64),
+                             "grad_lam": rel_err(gl32.double(), gl64), "grad_U": rel_err(gU32.double(), gU64)},
+            "sketched_vs_dense_fp64": {"loss": abs(loss64 - lossd) / abs(lossd),
+                                       "grad_lam": rel_err(gl64, gld), "grad_U": rel_err(gU64, gUd)},
+        },
     }
 
 
@@ -599,6 +848,19 @@ def kernels_only(what, reps, ctx, tab, Td, S64, S32, dev):
         y = torch.empty_like(x)
         for _ in range(reps):
             y.copy_(x)
+    if what == "docs":
+        # the LDA document build (k_terms) on the 500k-document corpus, FP32 W
+        from paper_1506_04448_amd.workloads import lda_corpus_fast, population_whitening
+        V, K, b, B = 20000, 100, 16384, 8
+        C = lda_corpus_fast(500000, V, K, seed=3)
+        W = torch.from_numpy(population_whitening(C.Phi, C.alpha).astype(np.float32)).to(dev)
+        h, xi = tsk.hash_generate(3, K, b, B)
+        tb = tsk.Tables(ctx, h, xi, b)
+        Sd64, Sd32 = tsk.new_sketch(tb, dev)
+        rp, col, cnt = (torch.from_numpy(a).to(dev) for a in (C.rowptr, C.col, C.cnt))
+        for _ in range(reps):
+            tsk.sketch_build_docs(ctx, tb, rp, col, cnt, V, W, float(C.alpha.sum()), Sd64, Sd32)
+        tb.close()
     torch.cuda.synchronize()
     print(f"kernels-only {what}: {reps} launches each", flush=True)
 
@@ -617,7 +879,8 @@ def main():
     ap.add_argument("--c4-docs", type=int, default=500000, help="documents in the LDA corpus")
     ap.add_argument("--no-c5", action="store_true", help="skip the gradient-extension leg")
     ap.add_argument("--no-x1", action="store_true", help="skip the paper's synthetic accuracy table")
-    ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy"),
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("COUNTER_CSV", "TRACE_CSV"))
+    ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy", "docs"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
@@ -626,6 +889,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(*args.summarize_pmc))
+        return
+    if args.summarize_sq:
+        print(summarize_sq(*args.summarize_sq))
         return
     if args.summarize_stats:
         print(summarize_stats(*args.summarize_stats))
@@ -723,6 +989,19 @@ def main():
         dec_ms.append(e0.elapsed_time(e1))
     decompose_ms = float(np.median(dec_ms))
     lam_d, U_d = lam.cpu().numpy().copy(), U.cpu().numpy().copy()
+    # FP32-vs-FP64 error per result: the same decomposition with FP64 power
+    # steps from the same sketch and start vectors.
+    S64.copy_(S64_0)
+    S32.copy_(S32_0)
+    l64, U64, _, _ = tsk.decompose(ctx, tab, S64, S32, K, L, T_ITERS, dtype=tsk.F64, seed=SEED)
+    lam_64, U_64 = l64.cpu().numpy(), U64.cpu().numpy()
+    lam_rel = np.abs(lam_d - lam_64) / np.abs(lam_64)
+    u_rel = np.linalg.norm(U_d - U_64, axis=1) / np.linalg.norm(U_64, axis=1)
+    precision = {"workload": ("the timed decomposition (FP32 power steps) against the same decomposition "
+                              "with FP64 power steps, same sketch and start vectors; per component"),
+                 "lam_rel": lam_rel.tolist(), "u_rel": u_rel.tolist(),
+                 "max_lam_rel": float(lam_rel.max()), "max_u_rel": float(u_rel.max()),
+                 "fp64_residual": residual(P.T, lam_64, U_64)}
     plain = None
     if not args.no_plain:
         S64.copy_(S64_0)
@@ -745,8 +1024,11 @@ def main():
 
     c3 = None if args.no_c3 else c3_batched(ctx, dev)
     c4 = None if args.no_c4 else c4_docs(ctx, dev, args.c4_docs)
-    c5 = None if args.no_c5 else c5_autograd(ctx, dev)
+    c5 = None if args.no_c5 else c5_differentiation(ctx, dev)
     x1 = None if args.no_x1 else x1_synthetic(ctx, dev)
+
+    if c5 is not None:
+        precision["c5_gradient"] = c5["gradient_check"]["fp32_vs_fp64"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -775,12 +1057,16 @@ def main():
                      "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
                      "traffic": stored_traffic(POWER_KERNEL), "traffic_unit": "bytes/launch",
-                     "launch_ms": power_ms, "flops_per_launch": flops_launch},
+                     "launch_ms": power_ms, "flops_per_launch": flops_launch,
+                     "frac_unpacked_fp32": achieved_tflops / (PEAK_FP32_VALU_TFLOPS / 2.0),
+                     "counters": stored_sq(POWER_KERNEL)},
         "sketch_build": {"GBps": build_gbps, "ms": build_ms,
                          "frac_hbm": build_gbps / PEAK_HBM_GBPS,
                          "bytes": build_bytes(N, B_LEN, B_CNT),
-                         "traffic": stored_traffic(BUILD_KERNEL)},
+                         "traffic": stored_traffic(BUILD_KERNEL),
+                         "counters": stored_sq(BUILD_KERNEL)},
         "recovery": {"residual": res_b, "wrong_vectors": int(wrong_b)},
+        "precision": precision,
         "plain_path": plain,
         "decompose_ms": decompose_ms,
         "decompose_sketch_updates_per_s": updates / (decompose_ms * 1e-3),

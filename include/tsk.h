@@ -353,6 +353,23 @@ tsk_status tsk_lda_recover(tsk_ctx_t ctx, int V, int K, int k, double alpha0, co
                            const double* lam, const double* U, double* alpha_out, double* mu_out,
                            void* stream);
 
+/* Held-out likelihood of a topic model (Section 5.2).  For each document d
+ * of a CSR corpus (counts n, length m) the mixing vector
+ *   pi_d = argmin { ||n/m - Phi pi||_2 : pi >= 0, sum_k pi_k = 1 }
+ * (simplex-constrained least squares, solved exactly by the primal
+ * active-set method on G = Phi^T Phi, one work-group per document) and its
+ * average log-likelihood L_d = (1/m) sum_i n_i ln(sum_k pi_k Phi[w_i][k]).
+ *   rowptr int32[D+1], col int32[nnz], cnt int32[nnz] (CSR, device);
+ *   Phi double [V][K] topics as columns (full column rank; entries positive
+ *   where documents have words, else L_d = -inf); pi_out double [D][K];
+ *   ll_out double [D]; device.  L_d is NaN for a document without words or
+ *   one the method did not finish in 10 K + 10 steps.  1 <= K <= min(V, 128).
+ *   The call reads rowptr[D] back to the host.
+ * Errors: TSK_EINVAL (null, sizes). */
+tsk_status tsk_lda_heldout(tsk_ctx_t ctx, const int32_t* rowptr, const int32_t* col,
+                           const int32_t* cnt, int D, int V, int K, const double* Phi,
+                           double* pi_out, double* ll_out, void* stream);
+
 /* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
  * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the
  * T(u,u,u) estimate of Eq. (3), and its gradient.  Each count sketch is linear

@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
-    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "tune_config", "contract_tiuu",
+    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "tune_config", "lda_heldout", "contract_tiuu",
     "contract_uuu",
     "decompose", "contract_tuuu_grad", "cp_loss", "Problem", "decompose_batched",
     "workspace_size", "sketch_build_docs",
@@ -63,6 +63,7 @@ _SIGS = {
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "tsk_power_update_noalloc": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_tune_config": ([_P, _I, ctypes.c_char_p], _I),
+    "tsk_lda_heldout": ([_P, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P], _I),
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
     "tsk_sym_tables_create": ([_P, _I, _I, _I, _P, _P, _P], _I),
@@ -325,6 +326,25 @@ def lda_recover(ctx, W, lam, U, alpha0, stream=None):
     _check("tsk_lda_recover", lib().tsk_lda_recover(
         ctx.handle, V, K, k, float(alpha0), _ptr(W), _ptr(lam), _ptr(U), _ptr(alpha), _ptr(mu), _stream(stream)))
     return alpha, mu
+
+
+def lda_heldout(ctx, rowptr, col, cnt, V, Phi, stream=None):
+    """Held-out likelihood (Section 5.2) of the topic matrix Phi [V][K]
+    (float64) on a CSR corpus: the simplex-constrained least-squares mixing
+    vectors pi [D][K] and the per-document average log-likelihoods L [D]."""
+    import torch
+    D = rowptr.shape[0] - 1
+    K = Phi.shape[1]
+    _tensor(rowptr, "rowptr", torch.int32, (D + 1,))
+    _tensor(col, "col", torch.int32)
+    _tensor(cnt, "cnt", torch.int32)
+    _tensor(Phi, "Phi", torch.float64, (V, K))
+    pi = torch.empty((D, K), dtype=torch.float64, device=Phi.device)
+    ll = torch.empty((D,), dtype=torch.float64, device=Phi.device)
+    _check("tsk_lda_heldout", lib().tsk_lda_heldout(
+        ctx.handle, _ptr(rowptr), _ptr(col), _ptr(cnt), D, V, K, _ptr(Phi), _ptr(pi), _ptr(ll),
+        _stream(stream)))
+    return pi, ll
 
 
 def new_sketch(tab: Tables, device="cuda"):

@@ -179,4 +179,273 @@ __global__ __launch_bounds__(256) void k_lda_mu(const double* W, const double* t
   mu[(size_t)i * V + w] = 0.5 * (alpha0 + 2.0) * l * acc;
 }
 
+// ---------------------------------------------------------------------------
+// Held-out likelihood of a topic model (Section 5.2)
+// ---------------------------------------------------------------------------
+
+// Fixed-order sums and an argmin over a 256-thread work-group (red: 8 doubles
+// and 8 ints of LDS); every thread returns the result.  The leading barrier
+// keeps a previous call's readers of red safe.
+__device__ inline double hl_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+__device__ inline void hl_argmin(double& v, int& k, double* red, int* redi) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o);
+    const int ok = __shfl_xor(k, o);
+    if (ov < v || (ov == v && ok < k)) {
+      v = ov;
+      k = ok;
+    }
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v;
+    redi[threadIdx.x >> 6] = k;
+  }
+  __syncthreads();
+  v = red[0];
+  k = redi[0];
+  for (int w = 1; w < 4; ++w)
+    if (red[w] < v || (red[w] == v && redi[w] < k)) {
+      v = red[w];
+      k = redi[w];
+    }
+}
+
+// LDS words (doubles) of k_simplex_ls for K topics.
+__host__ __device__ constexpr size_t simplex_ls_lds_words(int K) { return (size_t)K * K + 4 * (size_t)K + 8; }
+
+// One work-group of 256 threads per document d: the mixing vector
+//   pi = argmin { (1/2) pi^T G pi - c^T pi : pi >= 0, sum pi = 1 },
+// G = Phi^T Phi, c = Phi^T n_d / m_d = P[d] / m_d, by the primal active-set
+// method for convex quadratic programmes: on the free set F the KKT system of
+// min (1/2) x^T G_FF x - c_F^T x, 1^T x = 1 is solved through the Cholesky
+// factor of G_FF (x = y1 - nu y2 with G_FF y1 = c_F, G_FF y2 = 1,
+// nu = (1^T y1 - 1) / 1^T y2); a non-negative x is taken, and the index held at
+// zero with the most negative multiplier mu_k = (G pi - c)_k + nu (lowest index
+// on ties) enters F unless every mu_k >= -1e-12 max diag G; otherwise the step
+// towards x stops where the first weight reaches zero and that index leaves F.
+// The start is the best vertex.  Then L_d = (1/m) sum_i n_i ln(Phi[w_i] . pi).
+// A document with no words, or one not solved in max_iter steps, gets NaN.
+__global__ __launch_bounds__(256) void k_simplex_ls(const double* G, const double* P, const int32_t* rowptr,
+                                                    const int32_t* col, const int32_t* cnt, const double* Phi,
+                                                    int D, int K, int max_iter, double* pi_out,
+                                                    double* ll_out) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* Lf = reinterpret_cast<double*>(lds_raw);  // nf x nf Cholesky factor
+  double* pi = Lf + (size_t)K * K;
+  double* c = pi + K;
+  double* x = c + K;
+  int* fidx = reinterpret_cast<int*>(x + K);          // K ints
+  __shared__ double red[8];
+  __shared__ int redi[8];
+  __shared__ double s_nu;
+  __shared__ int s_nf;
+  const int tid = threadIdx.x;
+  // tolerance of the multipliers: relative to the largest diagonal entry of G
+  double gd = 0.0;
+  for (int k = tid; k < K; k += 256) gd = fmax(gd, G[(size_t)k * K + k]);
+  for (int o = 32; o > 0; o >>= 1) gd = fmax(gd, __shfl_xor(gd, o));
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = gd;
+  __syncthreads();
+  const double tol = 1e-12 * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  for (int d = blockIdx.x; d < D; d += gridDim.x) {
+    const int lo = rowptr[d], hi = rowptr[d + 1];
+    double mloc = 0.0;
+    for (int e = lo + tid; e < hi; e += 256) mloc += (double)cnt[e];
+    const double m = hl_sum(mloc, red);
+    if (!(m > 0.0)) {
+      for (int k = tid; k < K; k += 256) pi_out[(size_t)d * K + k] = 0.0;
+      if (tid == 0) ll_out[d] = __builtin_nan("");
+      continue;
+    }
+    for (int k = tid; k < K; k += 256) {
+      c[k] = P[(size_t)d * K + k] / m;
+      pi[k] = 0.0;
+    }
+    __syncthreads();
+    // best vertex
+    double bv = __builtin_inf();
+    int bk = 0x7fffffff;
+    for (int k = tid; k < K; k += 256) {
+      const double v = 0.5 * G[(size_t)k * K + k] - c[k];
+      if (v < bv) {
+        bv = v;
+        bk = k;
+      }
+    }
+    hl_argmin(bv, bk, red, redi);
+    if (tid == 0) {
+      fidx[0] = bk;
+      pi[bk] = 1.0;
+      s_nf = 1;
+    }
+    __syncthreads();
+    bool done = false;
+    for (int it = 0; it < max_iter && !done; ++it) {
+      const int nf = s_nf;
+      // Cholesky factor of G_FF, right-looking, lower triangle
+      for (int e = tid; e < nf * nf; e += 256) {
+        const int r = e / nf, q = e - r * nf;
+        Lf[e] = G[(size_t)fidx[r] * K + fidx[q]];
+      }
+      __syncthreads();
+      for (int j = 0; j < nf; ++j) {
+        if (tid == 0) Lf[j * nf + j] = sqrt(Lf[j * nf + j]);
+        __syncthreads();
+        for (int r = j + 1 + tid; r < nf; r += 256) Lf[r * nf + j] /= Lf[j * nf + j];
+        __syncthreads();
+        const int t = nf - j - 1;  // trailing block rows j+1 .. nf-1
+        for (int e = tid; e < t * t; e += 256) {
+          const int r = j + 1 + e / t, q = j + 1 + e % t;
+          if (q <= r) Lf[r * nf + q] -= Lf[r * nf + j] * Lf[q * nf + j];
+        }
+        __syncthreads();
+      }
+      // G_FF y1 = c_F and G_FF y2 = 1 by substitution in wave 0: lane l keeps
+      // y[l] and y[l + 64] in registers; each row's dot product is a butterfly
+      // sum, so every lane has the new value and its owner keeps it.
+      if (tid < 64) {
+        double ya[2] = {0.0, 0.0}, yb[2] = {0.0, 0.0};
+        for (int r = 0; r < nf; ++r) {   // L z = b
+          double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = tid + 64 * h;
+            if (j < r) {
+              s1 += Lf[r * nf + j] * ya[h];
+              s2 += Lf[r * nf + j] * yb[h];
+            }
+          }
+          for (int o = 32; o > 0; o >>= 1) {
+            s1 += __shfl_xor(s1, o);
+            s2 += __shfl_xor(s2, o);
+          }
+          const double dr = Lf[r * nf + r];
+          const double v1 = (c[fidx[r]] - s1) / dr, v2 = (1.0 - s2) / dr;
+          if ((r & 63) == tid) {
+            ya[r >> 6] = v1;
+            yb[r >> 6] = v2;
+          }
+        }
+        for (int r = nf - 1; r >= 0; --r) {   // L^T y = z
+          double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = tid + 64 * h;
+            if (j > r && j < nf) {
+              s1 += Lf[j * nf + r] * ya[h];
+              s2 += Lf[j * nf + r] * yb[h];
+            }
+          }
+          for (int o = 32; o > 0; o >>= 1) {
+            s1 += __shfl_xor(s1, o);
+            s2 += __shfl_xor(s2, o);
+          }
+          const double dr = Lf[r * nf + r];
+          const double z1 = __shfl(ya[r >> 6], r & 63), z2 = __shfl(yb[r >> 6], r & 63);
+          const double v1 = (z1 - s1) / dr, v2 = (z2 - s2) / dr;
+          if ((r & 63) == tid) {
+            ya[r >> 6] = v1;
+            yb[r >> 6] = v2;
+          }
+        }
+        double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (tid + 64 * h < nf) {
+            a1 += ya[h];
+            a2 += yb[h];
+          }
+        for (int o = 32; o > 0; o >>= 1) {
+          a1 += __shfl_xor(a1, o);
+          a2 += __shfl_xor(a2, o);
+        }
+        const double nu = (a1 - 1.0) / a2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (tid + 64 * h < nf) x[tid + 64 * h] = ya[h] - nu * yb[h];
+        if (tid == 0) s_nu = nu;
+      }
+      __syncthreads();
+      const double nu = s_nu;
+      bool neg = false;
+      for (int i = tid; i < nf; i += 256) neg |= x[i] < 0.0;
+      const bool infeasible = hl_sum(neg ? 1.0 : 0.0, red) > 0.0;
+      if (!infeasible) {
+        for (int i = tid; i < nf; i += 256) pi[fidx[i]] = x[i];
+        __syncthreads();
+        // multipliers of the indices held at zero
+        double mv = __builtin_inf();
+        int mk = 0x7fffffff;
+        for (int k = tid; k < K; k += 256) {
+          if (pi[k] != 0.0) continue;
+          bool in_f = false;
+          for (int i = 0; i < nf; ++i) in_f |= fidx[i] == k;
+          if (in_f) continue;
+          double g = -c[k] + nu;
+          for (int i = 0; i < nf; ++i) g += G[(size_t)k * K + fidx[i]] * pi[fidx[i]];
+          if (g < mv) {
+            mv = g;
+            mk = k;
+          }
+        }
+        hl_argmin(mv, mk, red, redi);
+        if (!(mv < -tol)) {
+          done = true;
+        } else if (tid == 0) {
+          fidx[nf] = mk;
+          s_nf = nf + 1;
+        }
+      } else {
+        // ratio test: the first free weight to reach zero on the way to x
+        double rv = __builtin_inf();
+        int ri = 0x7fffffff;
+        for (int i = tid; i < nf; i += 256) {
+          if (x[i] < 0.0) {
+            const double cur = pi[fidx[i]];
+            const double r = cur / (cur - x[i]);
+            if (r < rv || (r == rv && fidx[i] < (ri < nf ? fidx[ri] : 0x7fffffff))) {
+              rv = r;
+              ri = i;
+            }
+          }
+        }
+        // ties broken by the lower topic index: compare (ratio, topic)
+        int rk = ri < nf ? fidx[ri] : 0x7fffffff;
+        hl_argmin(rv, rk, red, redi);
+        for (int i = tid; i < nf; i += 256) {
+          const int k = fidx[i];
+          pi[k] = k == rk ? 0.0 : pi[k] + rv * (x[i] - pi[k]);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int pos = 0;
+          while (fidx[pos] != rk) ++pos;
+          fidx[pos] = fidx[nf - 1];
+          s_nf = nf - 1;
+        }
+      }
+      __syncthreads();
+    }
+    for (int k = tid; k < K; k += 256) pi_out[(size_t)d * K + k] = pi[k];
+    double acc = 0.0;
+    for (int e = lo + tid; e < hi; e += 256) {
+      const double* row = Phi + (size_t)col[e] * K;
+      double p = 0.0;
+      for (int k = 0; k < K; ++k) p += row[k] * pi[k];
+      acc += (double)cnt[e] * log(p);
+    }
+    const double ll = hl_sum(acc, red);
+    if (tid == 0) ll_out[d] = done ? ll / m : __builtin_nan("");
+    __syncthreads();
+  }
+}
+
 }  // namespace tsk

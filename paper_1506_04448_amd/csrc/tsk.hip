@@ -139,7 +139,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE, WS_HELD
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -2855,6 +2855,49 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   hipLaunchKernelGGL(tsk::k_whiten_out, dim3(std::min(V, 8192)), dim3(128), 0, st, (const double*)Q,
                      (const double*)E, (const double*)dv, W_out, sigma_out, V, K);
   return check_launch("k_whiten_out");
+}
+
+extern "C" tsk_status tsk_lda_heldout(tsk_ctx_t ctx, const int32_t* rowptr, const int32_t* col,
+                                      const int32_t* cnt, int D, int V, int K, const double* Phi,
+                                      double* pi_out, double* ll_out, void* stream) {
+  if (!ctx || !rowptr || !Phi || !pi_out || !ll_out)
+    return tsk::fail(TSK_EINVAL, "tsk_lda_heldout: null argument");
+  if (D < 1 || V < 1 || K < 1 || K > 128 || K > V)
+    return tsk::fail(TSK_EINVAL, "tsk_lda_heldout: D=%d, V=%d, K=%d (1 <= K <= min(V, 128))", D, V, K);
+  TSK_TRY(set_device(ctx));
+  hipStream_t st = S(stream);
+  int32_t nnz = 0;
+  TSK_HIP(hipMemcpyAsync(&nnz, rowptr + D, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TSK_HIP(hipStreamSynchronize(st));
+  if (nnz < 0) return tsk::fail(TSK_EINVAL, "tsk_lda_heldout: rowptr[D]=%d < 0", nnz);
+  if (nnz > 0 && (!col || !cnt)) return tsk::fail(TSK_EINVAL, "tsk_lda_heldout: null col or cnt");
+  const size_t gb = ((size_t)K * K * 8 + 255) & ~(size_t)255;
+  const size_t pb = ((size_t)D * K * 8 + 255) & ~(size_t)255;
+  const size_t db = ((size_t)D * 8 + 255) & ~(size_t)255;
+  void* base = nullptr;
+  TSK_TRY(ws_get(ctx, WS_HELD, gb + pb + 3 * db, &base));
+  double* Gm = (double*)base;
+  double* P = (double*)((char*)base + gb);
+  double* cd = (double*)((char*)base + gb + pb);
+  double* cpd = (double*)((char*)base + gb + pb + db);
+  double* invm = (double*)((char*)base + gb + pb + 2 * db);
+  hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, Phi, Phi, Gm, V, K);
+  TSK_TRY(check_launch("k_gram2"));
+  hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min((D + 15) / 16, 8192)), dim3(256), 0, st, rowptr,
+                     col, cnt, D, K, Phi, P, cd, cpd, invm);
+  TSK_TRY(check_launch("k_doc_project"));
+  const size_t lds = tsk::simplex_ls_lds_words(K) * sizeof(double);
+  static std::atomic<uint64_t> configured{0};
+  const uint64_t bit = 1ull << (ctx->device & 63);
+  if (!(configured.load() & bit)) {
+    // the kernel's static LDS (reduction scratch) stays below 1 KB
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_simplex_ls),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds - 1024));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL(tsk::k_simplex_ls, dim3(std::min(D, 4096)), dim3(256), lds, st, (const double*)Gm,
+                     (const double*)P, rowptr, col, cnt, Phi, D, K, 10 * K + 10, pi_out, ll_out);
+  return check_launch("k_simplex_ls");
 }
 
 extern "C" tsk_status tsk_lda_recover(tsk_ctx_t ctx, int V, int K, int k, double alpha0, const double* W,

@@ -204,6 +204,19 @@ def full_rank_tensor(n: int, sigma: float, seed: int, device="cpu", chunk: int =
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
     lam = 1.0 / np.arange(1, n + 1, dtype=np.float64)
     lam /= np.linalg.norm(lam)
+    T = _device_symmetric_tensor(Q, lam, float(np.sqrt(sigma / float(n) ** 3)), seed, device, chunk)
+    return FullRankTensor(T=T, lam=lam, V=np.ascontiguousarray(Q.T), sigma=sigma)
+
+
+def _device_symmetric_tensor(Q: np.ndarray, lam: np.ndarray, noise_std: float, seed: int, device,
+                             chunk: int):
+    """FP32 [n][n][n] tensor sum_r lam_r q_r^{(x)3} + E on `device`, with E
+    symmetric Gaussian of standard deviation `noise_std` per entry: drawn
+    once per sorted index triple (a seeded torch generator on the device) and
+    gathered at every permutation.  The signal is formed slab by slab as an
+    FP64 matrix product."""
+    import torch
+    n = Q.shape[0]
     dev = torch.device(device)
     Qd = torch.from_numpy(Q).to(dev)
     QlT = (Qd * torch.from_numpy(lam).to(dev)).T.contiguous()   # [r][k]: lam_r q_k,r
@@ -211,14 +224,14 @@ def full_rank_tensor(n: int, sigma: float, seed: int, device="cpu", chunk: int =
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
     G = torch.randn((n, n, n), generator=gen, dtype=torch.float32, device=dev)
-    G.mul_(float(np.sqrt(sigma / float(n) ** 3)))
+    G.mul_(noise_std)
     Gf = G.view(-1)
     jj = torch.arange(n, device=dev).view(n, 1).expand(n, n)
     kk = torch.arange(n, device=dev).view(1, n).expand(n, n)
     for i0 in range(0, n, chunk):
         i1 = min(n, i0 + chunk)
         # signal: T[i, j, k] = sum_r q_ir q_jr lam_r q_kr
-        A = (Qd[i0:i1, None, :] * Qd[None, :, :]).reshape((i1 - i0) * n, n)
+        A = (Qd[i0:i1, None, :] * Qd[None, :, :]).reshape((i1 - i0) * n, Q.shape[1])
         T[i0:i1] = (A @ QlT).view(i1 - i0, n, n).to(torch.float32)
         # noise: E[i, j, k] = G[sorted(i, j, k)]
         ii = torch.arange(i0, i1, device=dev).view(-1, 1, 1).expand(i1 - i0, n, n)
@@ -229,7 +242,22 @@ def full_rank_tensor(n: int, sigma: float, seed: int, device="cpu", chunk: int =
         mid = ii + j + k - lo - hi
         T[i0:i1] += Gf[(lo * n + mid) * n + hi]
     del G, Gf
-    return FullRankTensor(T=T, lam=lam, V=np.ascontiguousarray(Q.T), sigma=sigma)
+    return T
+
+
+def planted_tensor_device(n: int, k: int, noise: float, seed: int, device="cpu", chunk: int = 50,
+                          lam_range=(1.0, 2.0)):
+    """The planted construction of `planted_tensor` (orthonormal v_i from the
+    QR of a seeded Gaussian n x k matrix, lam_i ~ U[lam_range], plus noise
+    times a symmetric Gaussian E of standard deviation 1/n^1.5 per entry) as
+    an FP32 tensor built with torch on `device`: the n = 1000 tensor of the
+    differentiation workload takes 4 GB.  Returns a `Planted` whose T is that
+    torch tensor."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    lam = rng.uniform(lam_range[0], lam_range[1], size=k)
+    T = _device_symmetric_tensor(Q, lam, noise / float(n) ** 1.5, seed, device, chunk)
+    return Planted(T=T, lam=lam, V=np.ascontiguousarray(Q.T), noise=noise)
 
 
 def sym_tables(seed: int, n: int, b: int, B: int):

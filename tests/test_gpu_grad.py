@@ -173,3 +173,40 @@ def test_adam_refinement_lowers_sketched_and_dense_loss(ctx):
         return float(np.sum(R * R))
     assert dense_res(lam_r.double().cpu().numpy(), U_r.double().cpu().numpy()) <= \
         1.5 * dense_res(lam.cpu().numpy(), U.cpu().numpy())
+
+
+def test_cp_gradient_fp32_at_c5_sketch_size_agrees_with_dense_fp64(ctx):
+    """The differentiation workload's check instance: n = 100, k = 10 planted
+    tensor with noise 0.1, random hashes, B = 16 sketches of b = 65536, FP32
+    vectors.  The sketched gradients estimate the dense FP64 CP-loss gradients
+    without bias with an error that falls as 1/sqrt(b) (about 8/sqrt(b) for U
+    and 3/sqrt(b) for lam on the CPU oracle across hash seeds); the bars are
+    twice that.  The FP32 result also matches the oracle's FP64 sketched
+    gradient on the same sketches at the FP32 bar."""
+    n, k, b, B = 100, 10, 65536, 16
+    print(f"cp grad vs dense n={n} k={k} b={b} B={B}", flush=True)
+    P = planted_tensor(n, k, noise=0.1, seed=5)
+    rng = np.random.default_rng(5)
+    lam = P.lam * (1.0 + 0.05 * rng.standard_normal(k))
+    U = P.V + 0.02 * rng.standard_normal(P.V.shape)
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    lam32, U32 = lam.astype(np.float32), U.astype(np.float32)
+    h, xi = tsk.hash_generate(105, n, b, B)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    loss, g_lam, g_U = tsk.cp_loss(ctx, tab, S64, torch.from_numpy(lam32).to(DEV),
+                                   torch.from_numpy(U32).to(DEV))
+    l64, u64 = lam32.astype(np.float64), U32.astype(np.float64)
+    R = P.T - np.einsum("r,ri,rj,rk->ijk", l64, u64, u64, u64)
+    d_lam = -2.0 * np.einsum("ijk,ri,rj,rk->r", R, u64, u64, u64)
+    d_U = -6.0 * l64[:, None] * np.einsum("ijk,rj,rk->ri", R, u64, u64)
+    assert abs(float(loss) - np.sum(R * R)) / np.sum(R * R) < 2.0 / np.sqrt(b)
+    assert rel(g_lam.cpu().numpy(), d_lam) < 2.0 * 3.0 / np.sqrt(b)
+    assert rel(g_U.cpu().numpy(), d_U) < 2.0 * 8.0 / np.sqrt(b)
+    S_time = tsk.sketch_export(ctx, S64, b).cpu().numpy()
+    rloss, rg_lam, rg_U = G.cp_loss_grad(S_time, h, xi, l64, u64)
+    assert abs(float(loss) - rloss) <= 1e-5 * abs(rloss)
+    assert rel(g_lam.cpu().numpy(), rg_lam) < 1e-5
+    assert rel(g_U.cpu().numpy(), rg_U) < 1e-5
+    tab.close()

@@ -142,3 +142,41 @@ def test_injective_hash_tuuu_gradient_equals_dense_nonsymmetric():
              + np.einsum("ijk,i,j->k", T, u, u))
     np.testing.assert_allclose(G.triple_product_grad(s, h[0], xi[0], u), dense, atol=1e-11)
     assert G.triple_product(s, h[0], xi[0], u) == pytest.approx(np.einsum("ijk,i,j,k->", T, u, u, u))
+
+
+def _dense_cp_grads(T, lam, U):
+    R = T - np.einsum("r,ri,rj,rk->ijk", lam, U, U, U)
+    g_lam = -2.0 * np.einsum("ijk,ri,rj,rk->r", R, U, U, U)
+    g_U = -6.0 * lam[:, None] * np.einsum("ijk,rj,rk->ri", R, U, U)   # T and R symmetric
+    return float(np.sum(R * R)), g_lam, g_U
+
+
+def test_random_hash_cp_gradient_agrees_with_dense_within_sketch_error():
+    """Random hashes, n = 100, k = 10 (the differentiation workload's check
+    instance): every sketched inner product is an unbiased estimate whose
+    standard deviation falls as 1/sqrt(b) (Theorem 1's scale), so the sketched
+    CP loss and gradients approach the dense FP64 ones at that rate.  Across
+    hash seeds the oracle's normwise gradient error is about 8/sqrt(b) for U
+    and 3/sqrt(b) for lam at B = 16; the bars are twice that, and the error must
+    fall by at least 1.4x when b grows 4x (2x expected).  A wrong sign, a
+    dropped mode or a wrong index in the gradient gives errors of order one."""
+    from paper_1506_04448_amd.workloads import planted_tensor
+    n, k, B = 100, 10, 16
+    P = planted_tensor(n, k, noise=0.1, seed=5)
+    rng = np.random.default_rng(5)
+    lam = P.lam * (1.0 + 0.05 * rng.standard_normal(k))
+    U = P.V + 0.02 * rng.standard_normal(P.V.shape)
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    dl, dg_lam, dg_U = _dense_cp_grads(P.T, lam, U)
+    errs = []
+    for b in (4096, 16384):
+        h, xi = oracle.hash_tables(101, n, b, B)
+        S = np.stack([oracle.sketch_dense(P.T, h[m], xi[m], b) for m in range(B)])
+        loss, g_lam, g_U = G.cp_loss_grad(S, h, xi, lam, U)
+        e_lam = np.linalg.norm(g_lam - dg_lam) / np.linalg.norm(dg_lam)
+        e_U = np.linalg.norm(g_U - dg_U) / np.linalg.norm(dg_U)
+        assert abs(loss - dl) / dl < 2.0 * 1.0 / np.sqrt(b), (b, loss, dl)
+        assert e_lam < 2.0 * 3.0 / np.sqrt(b), (b, e_lam)
+        assert e_U < 2.0 * 8.0 / np.sqrt(b), (b, e_U)
+        errs.append(e_U)
+    assert errs[1] < errs[0] / 1.4, errs
