@@ -285,9 +285,10 @@ tsk_status tsk_sym_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint3
                                  const uint8_t* q_host, tsk_sym_tables_t* out);
 void tsk_sym_tables_destroy(tsk_sym_tables_t tab);
 
-/* Dense build of Eq. (5) from the fibres T[i][j][:] with i <= j (weighted 2
- * when i < j; for a tensor symmetric in its first two indices this is the
- * sum over all entries, and only those fibres are read), accumulated in
+/* Dense build of Eq. (5) from the entries T[i][j][k] with i <= j <= k, each
+ * weighted by the number of distinct orderings of (i, j, k) (6, 3 or 1; for a
+ * symmetric tensor, as Section 3.3 assumes, this is the sum over all entries,
+ * and only those entries are read), accumulated in
  * 64-bit fixed point (a power-of-two scale from max |T|; repeated builds are
  * bit-identical), then S64 = F(s64), S32 = (float)S64, s32 = (float)s64
  * (s32, S32 nullable).  T: [n][n][n] row-major, float or double by dtype.

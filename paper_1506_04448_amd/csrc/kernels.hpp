@@ -1260,9 +1260,12 @@ __global__ void k_pair_codes(const uint32_t* __restrict__ hq, int n, int B, long
 // One static pool of POOL 64-bit words holds the G sketches' bins.
 // SPLIT: a sketch has more bins than one range (then G = 1).
 // SYM: colliding-hash sketches of a symmetric tensor (Section 3.3, Eq. (5)):
-// the fibres are T[i][j][:] for the pairs i <= j, weighted 2 when i < j (the
-// sum over all index triples), each sketch has 2b real bins (sym_code), and
-// the sign of an entry is (-1)^(r >> 1) for its summed rotation r.
+// every index triple of one multiset falls in the same bucket with the same
+// sign, so only the entries i <= j <= k are read, weighted by the number of
+// distinct orderings of (i, j, k) (6, 3 or 1): the fibres T[i][j][:] of the
+// pairs i <= j from k = j on (a fibre's chunks of 64 below j are skipped).
+// Each sketch has 2b real bins (sym_code), and the sign of an entry is
+// (-1)^(r >> 1) for its summed rotation r.
 template <typename TIn, int POOL, bool SPLIT, bool SYM>
 __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   __shared__ __align__(16) unsigned long long pool[POOL];
@@ -1286,11 +1289,14 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
   const int tid = threadIdx.x;
   for (int t = tid; t < G * br; t += blockDim.x) bins[t] = 0ull;
 
-  const long long p0 = (long long)slab * a.pairs_per_slab;
-  const long long p1 = min(a.nfib, p0 + a.pairs_per_slab);
+  // A slab is a range of fibres; with SYM its items of NF pairs are dealt
+  // round-robin over the slabs instead (the pairs of small j have entries in
+  // more blocks of k than those of large j, so ranges would be unbalanced).
+  const long long p0 = SYM ? 0 : (long long)slab * a.pairs_per_slab;
+  const long long p1 = SYM ? a.nfib : min(a.nfib, p0 + a.pairs_per_slab);
   const double m = reduce_absmax(a.absmax, a.nabs, red);  // contains a barrier
   const bool bad = !(m < __builtin_inf());
-  const int F = bad ? 0 : fixed_scale(SYM ? 2.0 * m : m, (p1 - p0) * n);
+  const int F = bad ? 0 : fixed_scale(SYM ? 6.0 * m : m, (SYM ? a.pairs_per_slab : p1 - p0) * n);
   const double up = ldexp(1.0, F), down = ldexp(1.0, -F);
   __syncthreads();
 
@@ -1304,17 +1310,22 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
     constexpr unsigned SZ = sizeof(TIn);
     const uint32_t pmask = ((uint32_t)b - 1u) << (SYM ? 4 : 3);
     const uint32_t lmask = ((uint32_t)br - 1u) << 3;
-    const long long step = (long long)NF * nw;
+    const long long step = SYM ? (long long)NF * a.nslab * nw : (long long)NF * nw;
     const __amdgpu_buffer_rsrc_t efr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t*>(a.ef + (size_t)sk0 * a.efs), 0, (int)(Gc * a.efs * 4), kBufferWord3);
     // The item of fibres q .. q+3: their ef words (per sketch), entries and
-    // (SYM) which of them are diagonal pairs.
+    // (SYM) which of them are diagonal pairs and their second index j.
     struct Item {
       uint32_t ef[GM][NF];
       TIn x[NF][NC];
       uint32_t diag;
+      int jf[NF];
     };
     for (int kb = 0; kb < n; kb += 64 * NC) {
+      // (SYM) pairs (i, j) with j >= kb + 64 NC have no entry k >= j in this
+      // block of k: they come last in pair order and are not visited
+      const long long pe =
+          SYM ? min(p1, (long long)(kb + 64 * NC) * (long long)(kb + 64 * NC + 1) / 2) : p1;
       unsigned voff[NC];
       bool kin[NC];
       uint32_t e3[GM][NC];
@@ -1352,11 +1363,12 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
         it.diag = 0u;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-          const bool live = q + f < p1;
+          const bool live = q + f < pe;
           long long row = q + f;
           if (SYM) {
             row = (long long)pi * n + pj;
             it.diag |= (pi == pj ? 1u : 0u) << f;
+            it.jf[f] = pj;
             if (++pi > pj) {
               ++pj;
               pi = 0;
@@ -1367,6 +1379,11 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
               kBufferWord3);
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
+            // (SYM) a chunk wholly below k = j is never used: not loaded (wave-uniform)
+            if (SYM && kb + 64 * c + 63 < it.jf[f]) {
+              it.x[f][c] = TIn(0);
+              continue;
+            }
             if constexpr (sizeof(TIn) == 4)
               it.x[f][c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(tr, voff[c], 0u, 0));
             else
@@ -1374,14 +1391,14 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
           }
         }
       };
-      long long q0 = p0 + NF * wv;
+      long long q0 = SYM ? (long long)NF * (slab + (long long)a.nslab * wv) : p0 + NF * wv;
       Item cur;
       load(q0, cur);
-      while (q0 < p1) {
+      while (q0 < pe) {
         const long long qn = q0 + step;
         Item nxt;
         load(qn, nxt);
-        const int nf = (int)min((long long)NF, p1 - q0);
+        const int nf = (int)min((long long)NF, pe - q0);
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
           if (g < Gc) {
@@ -1389,11 +1406,16 @@ __global__ __launch_bounds__(1024) void k_build_dense(BuildArgs<TIn> a) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
               if (f < nf) {
-                // off-diagonal pairs stand for (i, j) and (j, i)
-                const double upf = (SYM && !((cur.diag >> f) & 1u)) ? 2.0 * up : up;
+                // orderings of (i, j, k): 6 for i < j < k, 3 with one equality, 1 for i = j = k
+                const bool dg = SYM && ((cur.diag >> f) & 1u);
+                const int jf = SYM ? cur.jf[f] : 0;
+                const double wo = dg ? 3.0 * up : 6.0 * up, wj = dg ? up : 3.0 * up;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                  if (kin[c]) {
+                  if (SYM && kb + 64 * c + 63 < jf) continue;  // wave-uniform: chunk below j
+                  const int kk = kb + 64 * c + lane;
+                  if (kin[c] && (!SYM || kk >= jf)) {
+                    const double upf = !SYM ? up : (kk == jf ? wj : wo);
                     const uint32_t sg = cur.ef[g][f] + e3[g][c];
                     const uint32_t off = SYM ? ((sg & pmask) | ((sg & 1u) << 3)) : (sg & pmask);
                     const unsigned long long v =

@@ -2518,8 +2518,9 @@ tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, cons
 namespace {
 
 // The fixed-point LDS build of the symmetric sketches into s64 (written, or
-// added to with accumulate): the dense build's kernel with the pairs i <= j
-// as fibres and 2b real bins per sketch.
+// added to with accumulate): the dense build's kernel over the entries
+// i <= j <= k (the pairs i <= j as fibres, from k = j on) and 2b real bins
+// per sketch.
 template <typename TIn>
 tsk_status sym_build_impl(tsk_ctx_t ctx, tsk_sym_tables_t tab, const TIn* T, double* s64, int accumulate,
                           hipStream_t st) {

@@ -22,7 +22,9 @@ DEV = "cuda:0"
 # (n, k, b, B, dtype, L, T)
 SHAPES = [(40, 3, 1024, 4, tsk.F64, 6, 10), (150, 6, 4096, 8, tsk.F32, 12, 8),
           (90, 4, 16384, 5, tsk.F32, 10, 6), (300, 5, 4096, 3, tsk.F32, 7, 9),
-          (25, 2, 256, 6, tsk.F64, 5, 12), (1000, 7, 16384, 8, tsk.F32, 16, 5)]
+          (25, 2, 256, 6, tsk.F64, 5, 12), (1000, 7, 16384, 8, tsk.F32, 16, 5),
+          # the split transforms of b = 65536, as in the batched workload
+          (700, 4, 65536, 8, tsk.F32, 6, 4)]
 
 
 @pytest.fixture(scope="module")
