@@ -531,8 +531,8 @@ def x1_synthetic(ctx, dev, sigmas=(0.01, 0.1), Bs=(20, 30, 40), logbs=(12, 13, 1
                       f"(paper {rows[-1]['paper_wrong']}), decompose {rows[-1]['decompose_ms']:.1f} ms",
                       file=sys.stderr, flush=True)
                 rows[-1].update(x1_als_row(ctx, dev, tab, S32_als, Tt, X, nrm2, k, sigma, B, logbs.index(logb)))
-                if logb <= 14:   # colliding-hash sketches: complex transforms of b <= 16384
-                    rows[-1].update(x1_sym_row(ctx, dev, Tt, X, nrm2, k, L, T, B, b, logb))
+                # colliding-hash sketches (complex transforms; split above b = 16384)
+                rows[-1].update(x1_sym_row(ctx, dev, Tt, X, nrm2, k, L, T, B, b, logb))
                 tab.close()
                 del S64, S32, S32_als
         del X, Tt
@@ -820,8 +820,15 @@ def cpu_baseline(P, h, xi, budget_s: float):
     t_step = (time.perf_counter() - t1) / steps
     t_whole = t_build + K * (T_ITERS + 1) * t_step
     updates = K * (T_ITERS + 1) * L * B_CNT
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": updates / t_whole, "unit": "sketch-updates/s", "cores": 1, "kind": "oracle",
+        "host_cores": len(os.sched_getaffinity(0)), "host_cpu": cpu_model,
         "sample": (f"FP64 numpy oracle, 1 thread: dense build of {B_CNT} sketches "
                    f"({t_build:.2f} s) + {steps} power steps over L={L} restarts "
                    f"({t_step:.3f} s each), scaled to one step of k={K} components x "

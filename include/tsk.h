@@ -279,8 +279,10 @@ tsk_status tsk_als(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, const doubl
  *   s(t) = sum over (h(i)+h(j)+h(k)) mod b == t of sigma(i) sigma(j) sigma(k) T_ijk
  * is complex; it is kept in the time domain (s64 FP64, s32 FP32 copy,
  * [B][b][2]) and as its full spectrum (S64, S32, [B][b][2]), all device,
- * caller-owned.  b a power of two in [256, 16384].  Errors: TSK_EINVAL,
- * TSK_EUNSUPPORTED (b). */
+ * caller-owned.  b a power of two in [256, 65536] (from 32768 on the power
+ * step runs through split transforms and a device buffer of
+ * 6 L B 16384 (b = 32768) or 12 L B 16384 (b = 65536) bytes of workspace).
+ * Errors: TSK_EINVAL, TSK_EUNSUPPORTED (b). */
 tsk_status tsk_sym_tables_create(tsk_ctx_t ctx, int n, int b, int B, const uint32_t* h_host,
                                  const uint8_t* q_host, tsk_sym_tables_t* out);
 void tsk_sym_tables_destroy(tsk_sym_tables_t tab);
@@ -307,7 +309,7 @@ tsk_status tsk_sym_sketch_build_dense(tsk_ctx_t ctx, tsk_sym_tables_t tab, const
  *   c1 + c2 = F^-1(S o (conj(U1)^2 + conj(U2))), c3 = F^-1(S o conj(U1)),
  *   U1 = F(sum_{h(i)=t} s_i u_i), U2 = F(sum_{2h(i)=t} s_i^2 u_i^2).
  * S32, s32: [B][b][2]; U: float [L][n]; V: float [L][B][n]; device.
- * n at most about 2800 at b = 16384 (LDS).  Errors: TSK_EINVAL,
+ * n at most about 2800 at b >= 16384 (LDS).  Errors: TSK_EINVAL,
  * TSK_EUNSUPPORTED. */
 tsk_status tsk_sym_contract_tiuu(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32,
                                  const float* s32, int L, const float* U, float* V, void* stream);

@@ -98,21 +98,24 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGN)) void k_c2c64(const cx<
   for (int k = threadIdx.x; k < N; k += NT) dst[k] = buf.get(k);
 }
 
-// Radix-2 combination of the two half transforms E = rows 2r, O = rows 2r+1
-// (N points each) into the 2N-point transform of row r:
-// X[k] = E[k mod N] + W^k O[k mod N], W = e^{-2 pi i / 2N} (conjugate for INV);
-// W^k from the full-circle table of 2N points.  Optional FP32 copy.
+// Radix-R combination of the R sub-transforms E_s = rows R r + s (N points
+// each, s < R) of the residue classes s mod R into the RN-point transform of
+// row r: X[k] = sum_s W^{s k} E_s[k mod N], W = e^{-2 pi i / RN} (conjugate for
+// INV), W^x from the full-circle table of RN points.  Optional FP32 copy.
 __global__ void k_c2c_combine(const cx<double>* half, cx<double>* out, cx<float>* out32, const cx<double>* wb,
-                              int N, int rows, int inv) {
-  const size_t total = (size_t)rows * 2 * N;
+                              int N, int R, int rows, int inv) {
+  const int RN = R * N;
+  const size_t total = (size_t)rows * RN;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t r = e / (2 * N);
-    const int k = (int)(e % (2 * N));
+    const size_t r = e / RN;
+    const int k = (int)(e % RN);
     const int km = k & (N - 1);
-    const cx<double> E = half[(2 * r) * N + km], O = half[(2 * r + 1) * N + km];
-    cx<double> w = wb[k];
-    if (inv) w.y = -w.y;
-    const cx<double> x = cadd(E, cmul(w, O));
+    cx<double> x = half[(R * r) * N + km];
+    for (int q = 1; q < R; ++q) {
+      cx<double> w = wb[(int)(((long)q * k) & (RN - 1))];
+      if (inv) w.y = -w.y;
+      x = cadd(x, cmul(w, half[(R * r + q) * N + km]));
+    }
     out[e] = x;
     if (out32) out32[e] = cx<float>{(float)x.x, (float)x.y};
   }
@@ -268,6 +271,197 @@ __global__ __launch_bounds__(sym_threads(LOGB)) void k_sym_power(SymPowerArgs a)
     const cx<float> c3 = rot(c3e, (8 - 2 * qq) & 3);  // c_3[2h mod b]
     const cx<float> s3 = rot(sm[(3u * h) & (uint32_t)(b - 1)], (12 - 3 * qq) & 3);
     const float v = vp[i] + (ui * c3.x * sc + ui * ui * s3.x) * (1.f / 3.f);
+    a.V[((size_t)tau * B + m) * n + i] = v;
+    acc += (double)ui * (double)v;
+  }
+  if (a.mode == 1) {
+    __shared__ double red[NT / 64];
+    const double lam = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) a.lam_per[(size_t)tau * B + m] = lam;
+  }
+}
+
+// ---- power step at b = R M, M = 16384 (FP32, split transforms) -------------
+// At b = 32768 and 65536 the complex b-point sequence does not fit one
+// work-group's LDS.  The step runs as three launches through a global buffer
+// E of NR = R + R/2 rows of M complex values per (restart, sketch):
+//   k_sym_split_fwd: row r < R is the M-point transform of the residue class r
+//     mod R of s_u (its positions h / R); row R + r2 that of the residue class r2
+//     mod R/2 of the even-position sketch s_2 halved (positions (2h mod b)/2);
+//   k_sym_split_mid: per bin k < M, U_1 and U_2 at the R bins j = k + qM by
+//     recombination, P_1 = S o (conj U_1^2 + conj U_2) and P_2 = S o conj U_1,
+//     then the folds that the inverses need:
+//       A_rho[k]   = sum_q W_b^{-rho (k + qM)} P_1[k + qM]           (rho < R),
+//       A2_rho2[k] = sum_q' W_b^{-2 rho2 (k + q'M)} (P_2 + P_2[. + b/2])[k + q'M]  (rho2 < R/2),
+//     written over the same rows;
+//   k_sym_split_out: the R + R/2 inverse M-point transforms, one after the
+//     other in LDS; c_12[R t + rho] = IFFT(A_rho)[t] / b and
+//     c_3[2 ((R/2) t + rho2)] = IFFT(A2_rho2)[t] / b are read at h and at
+//     2h mod b, and s at 3h mod b, into the read-off of the one-launch kernel.
+constexpr int kSymSplitLogM = 14;
+
+struct SymSplitArgs {
+  const uint32_t* hq;     // [B][n] (h << 2) | q
+  const uint32_t* srt1;   // [B][n] sorted (h << 2) | q
+  const uint32_t* ord1;
+  const uint32_t* srt2;   // [B][n] sorted (2h mod b << 2) | 2q mod 4
+  const uint32_t* ord2;
+  int n, B, b;
+  const cx<float>* S;     // [B][b] spectra
+  const cx<float>* s;     // [B][b] time-domain sketches
+  const cx<float>* twM;   // pass table of the M-point transform
+  const cx<float>* Wb;    // W_b^x, x < b
+  const float* U;         // [L][n]
+  cx<float>* E;           // [L][B][NR][M]
+  float* V;               // [L][B][n]  Re v
+  double* lam_per;        // [L][B] u . Re v (mode 1)
+  int mode;
+};
+
+// LDS of the split forward and output kernels: the padded M-point sequence,
+// then u and the partial read-offs (n floats each).
+constexpr size_t sym_split_lds(int n) {
+  return align16(sizeof(float) * 2 * (size_t)padded_len(1 << kSymSplitLogM)) + 2 * align16(sizeof(float) * (size_t)n);
+}
+
+template <int R>
+__global__ __launch_bounds__(sym_threads(kSymSplitLogM)) void k_sym_split_fwd(SymSplitArgs a) {
+  constexpr int LOGM = kSymSplitLogM, M = 1 << LOGM, NT = sym_threads(LOGM), PL = padded_len(M);
+  constexpr int NR = R + R / 2;
+  extern __shared__ __align__(16) unsigned char lds[];
+  float* re = reinterpret_cast<float*>(lds);
+  const Soa<float> buf{re, re + PL};
+  float* u = reinterpret_cast<float*>(lds + align16(sizeof(float) * 2 * (size_t)PL));
+  const int n = a.n, m = blockIdx.x, tau = blockIdx.y, row = blockIdx.z;
+  const size_t tb = (size_t)m * n;
+  for (int e = threadIdx.x; e < n; e += NT) u[e] = a.U[(size_t)tau * n + e];
+  for (int t = threadIdx.x; t < 2 * PL; t += NT) re[t] = 0.f;
+  __syncthreads();
+  if (row < R) {
+    sym_count_sketch<float>(a.srt1 + tb, a.ord1 + tb, n, NT, [&](uint32_t i) { return u[i]; },
+                            [&](uint32_t t, cx<float> v) {
+                              if ((int)(t & (uint32_t)(R - 1)) == row) buf.put((int)(t / R), v);
+                            });
+  } else {
+    constexpr int R2 = R / 2;
+    const int r2 = row - R;
+    sym_count_sketch<float>(a.srt2 + tb, a.ord2 + tb, n, NT, [&](uint32_t i) { return u[i] * u[i]; },
+                            [&](uint32_t t, cx<float> v) {
+                              const uint32_t th = t >> 1;
+                              if ((int)(th & (uint32_t)(R2 - 1)) == r2) buf.put((int)(th / R2), v);
+                            });
+  }
+  __syncthreads();
+  const Twid<float> tw{a.twM, nullptr};
+  fft_soa<float, LOGM, NT, false>(buf, tw);
+  cx<float>* dst = a.E + (((size_t)tau * a.B + m) * NR + row) * M;
+  for (int k = threadIdx.x; k < M; k += NT) dst[k] = buf.get(k);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_sym_split_mid(SymSplitArgs a) {
+  constexpr int M = 1 << kSymSplitLogM, NR = R + R / 2, R2 = R / 2;
+  const int m = blockIdx.x, tau = blockIdx.y;
+  const int k = blockIdx.z * 256 + threadIdx.x;
+  if (k >= M) return;
+  const int b = a.b;
+  const uint32_t bm = (uint32_t)b - 1u;
+  cx<float>* Er = a.E + ((size_t)tau * a.B + m) * NR * M;
+  auto W = [&](long x) { return a.Wb[(uint32_t)x & bm]; };
+  cx<float> e[R], e2[R2];
+#pragma unroll
+  for (int r = 0; r < R; ++r) e[r] = Er[(size_t)r * M + k];
+#pragma unroll
+  for (int r = 0; r < R2; ++r) e2[r] = Er[(size_t)(R + r) * M + k];
+  const cx<float>* Sm = a.S + (size_t)m * b;
+  cx<float> P1[R], P2[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const long j = k + (long)q * M;
+    cx<float> u1 = e[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) u1 = cadd(u1, cmul(W((long)r * j), e[r]));
+    const long jp = k + (long)(q % R2) * M;  // j mod b/2
+    cx<float> u2 = e2[0];
+#pragma unroll
+    for (int r = 1; r < R2; ++r) u2 = cadd(u2, cmul(W(2L * r * jp), e2[r]));
+    const cx<float> sk = Sm[j];
+    const cx<float> c1 = cconj(u1);
+    P1[q] = cmul(sk, cadd(cmul(c1, c1), cconj(u2)));
+    P2[q] = cmul(sk, c1);
+  }
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) {
+    cx<float> acc = {0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      acc = cadd(acc, rho == 0 ? P1[q] : cmulc(P1[q], W((long)rho * (k + (long)q * M))));
+    Er[(size_t)rho * M + k] = acc;
+  }
+#pragma unroll
+  for (int r2 = 0; r2 < R2; ++r2) {
+    cx<float> acc = {0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+      const cx<float> f = cadd(P2[q], P2[q + R2]);
+      acc = cadd(acc, r2 == 0 ? f : cmulc(f, W(2L * r2 * (k + (long)q * M))));
+    }
+    Er[(size_t)(R + r2) * M + k] = acc;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(sym_threads(kSymSplitLogM)) void k_sym_split_out(SymSplitArgs a) {
+  constexpr int LOGM = kSymSplitLogM, M = 1 << LOGM, NT = sym_threads(LOGM), PL = padded_len(M);
+  constexpr int NR = R + R / 2, R2 = R / 2;
+  extern __shared__ __align__(16) unsigned char lds[];
+  float* re = reinterpret_cast<float*>(lds);
+  const Soa<float> buf{re, re + PL};
+  float* u = reinterpret_cast<float*>(lds + align16(sizeof(float) * 2 * (size_t)PL));
+  float* vp = u + align16(sizeof(float) * (size_t)a.n) / sizeof(float);
+  const int n = a.n, B = a.B, b = a.b, m = blockIdx.x, tau = blockIdx.y;
+  const size_t tb = (size_t)m * n;
+  const uint32_t* hq = a.hq + tb;
+  const float sc = 1.f / (float)b;
+  for (int e = threadIdx.x; e < n; e += NT) {
+    u[e] = a.U[(size_t)tau * n + e];
+    vp[e] = 0.f;
+  }
+  const Twid<float> tw{a.twM, nullptr};
+  const cx<float>* Er = a.E + ((size_t)tau * B + m) * NR * M;
+  for (int row = 0; row < NR; ++row) {
+    __syncthreads();  // the previous row's readers of the buffer are done
+    for (int k = threadIdx.x; k < M; k += NT) buf.put(k, Er[(size_t)row * M + k]);
+    __syncthreads();
+    fft_soa<float, LOGM, NT, true>(buf, tw);
+    for (int i = threadIdx.x; i < n; i += NT) {
+      const uint32_t e = hq[i];
+      const uint32_t h = sym_pos(e);
+      const int qq = sym_rot(e);
+      if (row < R) {
+        if ((int)(h & (uint32_t)(R - 1)) == row) {  // conj(sigma) c_12[h]
+          const cx<float> c = rot(buf.get((int)(h / R)), (4 - qq) & 3);
+          vp[i] += c.x * (sc / 6.f);
+        }
+      } else {
+        const uint32_t t = h & (uint32_t)(b / 2 - 1);  // c_3 at 2h mod b = 2t
+        if ((int)(t & (uint32_t)(R2 - 1)) == row - R) {
+          const cx<float> c3 = rot(buf.get((int)(t / R2)), (8 - 2 * qq) & 3);
+          vp[i] += u[i] * c3.x * sc * (1.f / 3.f);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const cx<float>* sm = a.s + (size_t)m * b;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const uint32_t e = hq[i];
+    const uint32_t h = sym_pos(e);
+    const int qq = sym_rot(e);
+    const float ui = u[i];
+    const cx<float> s3 = rot(sm[(3u * h) & (uint32_t)(b - 1)], (12 - 3 * qq) & 3);
+    const float v = vp[i] + ui * ui * s3.x * (1.f / 3.f);
     a.V[((size_t)tau * B + m) * n + i] = v;
     acc += (double)ui * (double)v;
   }

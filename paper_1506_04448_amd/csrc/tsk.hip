@@ -139,7 +139,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE, WS_HELD
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE, WS_HELD, WS_SYMSPLIT
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -2330,8 +2330,8 @@ extern "C" tsk_status tsk_sym_tables_create(tsk_ctx_t ctx, int n, int b, int B, 
   if (!ctx || !h_host || !q_host || !out) return tsk::fail(TSK_EINVAL, "tsk_sym_tables_create: null argument");
   if (n < 1 || n > 65535 || B < 1 || B > 64)
     return tsk::fail(TSK_EINVAL, "tsk_sym_tables_create: n=%d, B=%d out of range", n, B);
-  if (b < 256 || b > 16384 || (b & (b - 1)))
-    return tsk::fail(TSK_EUNSUPPORTED, "tsk_sym_tables_create: b=%d (powers of two in [256, 16384])", b);
+  if (b < 256 || b > 65536 || (b & (b - 1)))
+    return tsk::fail(TSK_EUNSUPPORTED, "tsk_sym_tables_create: b=%d (powers of two in [256, 65536])", b);
   const size_t cnt = (size_t)B * n;
   std::vector<uint32_t> hq(cnt), srt(3 * cnt), ord(3 * cnt);
   for (size_t e = 0; e < cnt; ++e) {
@@ -2417,20 +2417,30 @@ tsk_status launch_c2c64_t(tsk_ctx_t ctx, const cx<double>* in, cx<double>* out, 
 
 // Complex FFT (unnormalised; inverse with conjugate twiddles) of `rows` rows
 // of b = 2^logb points, FP64, with an optional FP32 copy of the result:
-// one work-group per row up to 8192 points, a radix-2 split above.
+// one work-group per row up to 8192 points; above, R = b / 8192 transforms of
+// the residue classes mod R per row and a radix-R combination.
 tsk_status fft64_rows(tsk_ctx_t ctx, int logb, const cx<double>* in, cx<double>* out, cx<float>* out32, int rows,
                       bool inv, hipStream_t st) {
   const size_t count = (size_t)rows << logb;
-  if (logb == 14) {
+  if (logb >= 14 && logb <= 16) {
+    const int R = 1 << (logb - 13);
     void* half = nullptr;
     TSK_TRY(ws_get(ctx, WS_SYM, count * sizeof(cx<double>), &half));
     const cx<double>* wb = nullptr;
-    TSK_TRY(get_wb<double>(ctx, 14, &wb));
+    TSK_TRY(get_wb<double>(ctx, logb, &wb));
     cx<double>* hb = reinterpret_cast<cx<double>*>(half);
-    if (inv) TSK_TRY((launch_c2c64_t<13, true, 2>(ctx, in, hb, 2 * rows, st)));
-    else TSK_TRY((launch_c2c64_t<13, false, 2>(ctx, in, hb, 2 * rows, st)));
+    if (R == 2) {
+      if (inv) TSK_TRY((launch_c2c64_t<13, true, 2>(ctx, in, hb, R * rows, st)));
+      else TSK_TRY((launch_c2c64_t<13, false, 2>(ctx, in, hb, R * rows, st)));
+    } else if (R == 4) {
+      if (inv) TSK_TRY((launch_c2c64_t<13, true, 4>(ctx, in, hb, R * rows, st)));
+      else TSK_TRY((launch_c2c64_t<13, false, 4>(ctx, in, hb, R * rows, st)));
+    } else {
+      if (inv) TSK_TRY((launch_c2c64_t<13, true, 8>(ctx, in, hb, R * rows, st)));
+      else TSK_TRY((launch_c2c64_t<13, false, 8>(ctx, in, hb, R * rows, st)));
+    }
     hipLaunchKernelGGL(tsk::k_c2c_combine, dim3(grid_for(count, 256)), dim3(256), 0, st, (const cx<double>*)hb,
-                       out, out32, wb, 1 << 13, rows, inv ? 1 : 0);
+                       out, out32, wb, 1 << 13, R, rows, inv ? 1 : 0);
     return check_launch("k_c2c_combine");
   }
 #define TSK_C2C(L)                                                                                      \
@@ -2473,10 +2483,72 @@ tsk_status launch_sym_power_t(const tsk::SymPowerArgs& a, int L, hipStream_t st)
   return check_launch("k_sym_power");
 }
 
+template <typename K>
+tsk_status allow_lds(K* kernel, size_t bytes) {
+  (void)bytes;
+  TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(kMaxLds - 256)));
+  return TSK_OK;
+}
+
+// The symmetric step at b = R 16384 through the split transforms (three
+// launches, buffer E of L B (R + R/2) rows of 16384 complex values).
+template <int R>
+tsk_status sym_power_split_t(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, const float* s32, int L,
+                             const float* U, float* V, double* lam_per, int mode, hipStream_t st) {
+  constexpr int M = 1 << tsk::kSymSplitLogM, NR = R + R / 2;
+  constexpr int NT = tsk::sym_threads(tsk::kSymSplitLogM);
+  const size_t lds = tsk::sym_split_lds(tab->n);
+  if (lds > kMaxLds - 256)
+    return tsk::fail(TSK_EUNSUPPORTED, "symmetric power step: n=%d too large for b=%d", tab->n, tab->b);
+  const cx<float>* twM = nullptr;
+  const cx<float>* Wb = nullptr;
+  TSK_TRY(get_tw<float>(ctx, tsk::kSymSplitLogM + 1, &twM, NT));
+  TSK_TRY(get_wb<float>(ctx, tab->logb, &Wb));
+  void* E = nullptr;
+  TSK_TRY(ws_get(ctx, WS_SYMSPLIT, (size_t)L * tab->B * NR * M * sizeof(cx<float>), &E));
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_TRY(allow_lds(&tsk::k_sym_split_fwd<R>, lds));
+    TSK_TRY(allow_lds(&tsk::k_sym_split_out<R>, lds));
+    configured.fetch_or(bit);
+  }
+  tsk::SymSplitArgs a;
+  const size_t cnt = (size_t)tab->B * tab->n;
+  a.hq = tab->hq;
+  a.srt1 = tab->srt;
+  a.ord1 = tab->ord;
+  a.srt2 = tab->srt + cnt;
+  a.ord2 = tab->ord + cnt;
+  a.n = tab->n;
+  a.B = tab->B;
+  a.b = tab->b;
+  a.S = reinterpret_cast<const cx<float>*>(S32);
+  a.s = reinterpret_cast<const cx<float>*>(s32);
+  a.twM = twM;
+  a.Wb = Wb;
+  a.U = U;
+  a.E = reinterpret_cast<cx<float>*>(E);
+  a.V = V;
+  a.lam_per = lam_per;
+  a.mode = mode;
+  hipLaunchKernelGGL((tsk::k_sym_split_fwd<R>), dim3(tab->B, L, NR), dim3(NT), lds, st, a);
+  TSK_TRY(check_launch("k_sym_split_fwd"));
+  hipLaunchKernelGGL((tsk::k_sym_split_mid<R>), dim3(tab->B, L, M / 256), dim3(256), 0, st, a);
+  TSK_TRY(check_launch("k_sym_split_mid"));
+  hipLaunchKernelGGL((tsk::k_sym_split_out<R>), dim3(tab->B, L), dim3(NT), lds, st, a);
+  return check_launch("k_sym_split_out");
+}
+
 // The FP32 read-off of T(I,u,u) for L vectors on every sketch (mode 1: also
 // lam_per = u . Re v).
 tsk_status sym_power(tsk_ctx_t ctx, tsk_sym_tables_t tab, const float* S32, const float* s32, int L,
                      const float* U, float* V, double* lam_per, int mode, hipStream_t st) {
+  if (tab->logb == 15) return sym_power_split_t<2>(ctx, tab, S32, s32, L, U, V, lam_per, mode, st);
+  if (tab->logb == 16) return sym_power_split_t<4>(ctx, tab, S32, s32, L, U, V, lam_per, mode, st);
   if (tsk::sym_power_lds(tab->logb, tab->n) > kMaxLds - 256)
     return tsk::fail(TSK_EUNSUPPORTED, "symmetric power step: n=%d too large for b=%d", tab->n, tab->b);
   const cx<float>* tw = nullptr;

@@ -37,7 +37,8 @@ def _c(x):
 
 
 @pytest.mark.parametrize("n,b,B,dt", [(7, 256, 3, np.float64), (40, 1024, 2, np.float64),
-                                      (60, 8192, 2, np.float32), (50, 16384, 2, np.float64)])
+                                      (60, 8192, 2, np.float32), (50, 16384, 2, np.float64),
+                                      (40, 32768, 2, np.float32), (30, 65536, 2, np.float64)])
 def test_sym_build_matches_eq5(ctx, n, b, B, dt):
     print(f"sym build n={n} b={b} B={B}", flush=True)
     P = planted_tensor(n, 3, noise=0.05, seed=n, dtype=dt)
@@ -56,7 +57,7 @@ def test_sym_build_matches_eq5(ctx, n, b, B, dt):
 
 
 @pytest.mark.parametrize("n,b,B,dt", [(30, 512, 3, np.float32), (24, 8192, 2, np.float32),
-                                      (45, 16384, 2, np.float64)])
+                                      (45, 16384, 2, np.float64), (20, 65536, 2, np.float32)])
 def test_sym_build_of_integer_tensor_is_exact(ctx, n, b, B, dt):
     """A symmetric tensor of small integers makes every bucket sum exact on both
     sides: the time-domain sketch must equal Eq. (5) exactly (codes, rotations,
@@ -97,7 +98,10 @@ def test_sym_build_is_deterministic_and_accumulates(ctx):
 # before their last two passes (n small against b), including 32 groups
 # (b = 8192, n <= 512) and the ragged n just above and below that bound.
 @pytest.mark.parametrize("n,b,B,L", [(9, 256, 3, 2), (100, 2048, 3, 4), (200, 16384, 2, 3), (1000, 8192, 2, 2),
-                                     (200, 8192, 3, 3), (512, 8192, 2, 2), (513, 8192, 2, 2)])
+                                     (200, 8192, 3, 3), (512, 8192, 2, 2), (513, 8192, 2, 2),
+                                     # the split transforms (b = 2 x 16384 and 4 x 16384)
+                                     (150, 32768, 2, 3), (1000, 32768, 2, 2), (120, 65536, 3, 2),
+                                     (1000, 65536, 2, 2)])
 def test_sym_tiuu_matches_appendix_b(ctx, n, b, B, L):
     print(f"sym tiuu n={n} b={b}", flush=True)
     rng = np.random.default_rng(n)
@@ -130,7 +134,8 @@ def test_sym_tiuu_matches_appendix_b(ctx, n, b, B, L):
     tab.close()
 
 
-@pytest.mark.parametrize("n,k,b,B,L,T,seed", [(40, 3, 2048, 5, 6, 25, 21), (50, 3, 16384, 3, 4, 15, 22)])
+@pytest.mark.parametrize("n,k,b,B,L,T,seed", [(40, 3, 2048, 5, 6, 25, 21), (50, 3, 16384, 3, 4, 15, 22),
+                                               (50, 3, 32768, 3, 4, 12, 23), (40, 2, 65536, 3, 3, 10, 24)])
 def test_sym_decompose_matches_oracle_and_recovers(ctx, n, k, b, B, L, T, seed):
     """Algorithm 1 on symmetric sketches: every component against the FP64
     oracle (1e-5; a near-tie in the oracle's selection values is reported, not
@@ -215,7 +220,7 @@ def test_decompose_after_sym_decompose_on_one_context(ctx):
 def test_sym_argument_errors(ctx):
     h, q = sym_tables(1, 10, 256, 2)
     with pytest.raises(tsk.TskError, match="EUNSUPPORTED"):
-        tsk.SymTables(ctx, sym_tables(1, 10, 32768, 2)[0], sym_tables(1, 10, 32768, 2)[1], 32768)
+        tsk.SymTables(ctx, sym_tables(1, 10, 131072, 2)[0], sym_tables(1, 10, 131072, 2)[1], 131072)
     bad = q.copy()
     bad[0, 0] = 4
     with pytest.raises(tsk.TskError, match="out of range"):
