@@ -373,7 +373,7 @@ tsk_status tsk_lda_heldout(tsk_ctx_t ctx, const int32_t* rowptr, const int32_t* 
                            const int32_t* cnt, int D, int V, int K, const double* Phi,
                            double* pi_out, double* ll_out, void* stream);
 
-/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
+/* ---- Gradients (extensions built on Eq. (3) and Proposition 1) ----------
  * f(u) = med_m f^(m)(u) with f^(m)(u) = <s^(m), s_1(u) * s_2(u) * s_3(u)>, the
  * T(u,u,u) estimate of Eq. (3), and its gradient.  Each count sketch is linear
  * in u, so

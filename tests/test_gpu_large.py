@@ -67,6 +67,88 @@ def test_split_dense_build(ctx, b, dt):
         assert rel(got[m], ref) < tol
 
 
+@pytest.mark.parametrize("b,dt,n,mode", [(65536, np.float32, 300, "clustered"),
+                                         (32768, np.float64, 260, "clustered"),
+                                         (65536, np.float64, 130, "uniform"),
+                                         (32768, np.float32, 67, "uniform"),
+                                         (65536, np.float32, 1, "uniform")])
+def test_bucket_range_build_of_integer_tensor_is_exact(ctx, b, dt, n, mode):
+    """Sketches longer than one work-group's 16384 buckets: each work-group
+    owns one range of buckets and keeps the entries that land in it.  Small
+    integer entries make every bucket sum exact on both sides.  With h3
+    clustered around zero ([b - 20, b) and [0, 20)) a fibre's entries all fall
+    in one or two ranges, on both sides of the wrap from bucket b - 1 to 0."""
+    print(f"range build b={b} n={n} {mode} {np.dtype(dt).name}", flush=True)
+    rng = np.random.default_rng(n + b)
+    T = rng.integers(-7, 8, size=(n, n, n)).astype(dt)
+    B = 2
+    h, xi = tsk.hash_generate(31 + n, n, b, B)
+    if mode == "clustered":
+        near = rng.integers(-20, 20, size=(B, n))
+        h[:, 2, :] = (near % b).astype(np.uint32)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    Td = torch.from_numpy(T).to(DEV)
+    tsk.sketch_build_dense(ctx, tab, Td, S64, S32)
+    got = tsk.sketch_export(ctx, S64, b).cpu().numpy()
+    ref = np.stack([oracle.sketch_dense(T.astype(np.float64), h[m], xi[m], b) for m in range(B)])
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9)
+    S64b, S32b = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, Td, S64b, S32b)
+    np.testing.assert_array_equal(S64b.cpu().numpy(), S64.cpu().numpy())
+    tab.close()
+
+
+def _buckets_by_definition(Tdev, h, xi, b, ts):
+    """s(t) of Eq. (1) for the buckets ts, one by one: the entries (i, j, k)
+    with h1(i) + h2(j) + h3(k) = t mod b, read from the device tensor."""
+    n = Tdev.shape[0]
+    h1, h2, h3 = (h[j].astype(np.int64) for j in range(3))
+    order = np.argsort(h3, kind="stable")
+    hs = h3[order]
+    c = (h1[:, None] + h2[None, :]) % b
+    out = []
+    flat = Tdev.reshape(-1)
+    for t in ts:
+        v = (t - c) % b
+        lo = np.searchsorted(hs, v, side="left").ravel()
+        hi = np.searchsorted(hs, v, side="right").ravel()
+        cnt = hi - lo
+        pair = np.repeat(np.arange(n * n), cnt)
+        first = np.repeat(lo, cnt)
+        offs = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        k = order[first + offs]
+        i, j = pair // n, pair % n
+        idx = torch.from_numpy(i * n * n + j * n + k).to(Tdev.device)
+        vals = flat[idx].double().cpu().numpy()
+        sg = xi[0][i].astype(np.float64) * xi[1][j] * xi[2][k]
+        out.append(float(np.sum(sg * vals)))
+    return np.array(out)
+
+
+def test_bucket_range_build_full_size_sampled(ctx):
+    """The differentiation workload's build shape (n = 1000, FP32, b = 65536,
+    four ranges per sketch) at full size: 48 sampled buckets per sketch
+    against Eq. (1) summed bucket by bucket in FP64."""
+    from paper_1506_04448_amd.workloads import planted_tensor_device
+    n, b, B = 1000, 65536, 2
+    print(f"range build full size n={n} b={b}", flush=True)
+    X = planted_tensor_device(n, 100, 0.1, seed=3, device=DEV)
+    Tdev = X.T
+    h, xi = tsk.hash_generate(77, n, b, B)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, Tdev, S64, S32)
+    got = tsk.sketch_export(ctx, S64, b).cpu().numpy()
+    rng = np.random.default_rng(5)
+    for m in range(B):
+        ts = np.concatenate([[0, 16383, 16384, 32767, 32768, 49151, 49152, 65535],
+                             rng.integers(0, b, size=40)])
+        ref = _buckets_by_definition(Tdev, h[m], xi[m], b, ts)
+        assert rel(got[m][ts], ref) < 1e-5, (m, rel(got[m][ts], ref))
+    tab.close()
+
+
 @pytest.mark.parametrize("b", [32768, 65536])
 def test_split_factor_build_and_deflate(ctx, b):
     print(f"large factors b={b}", flush=True)
