@@ -213,138 +213,223 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGM)) void k_c2r_split_b(con
 }
 
 // ---------------------------------------------------------------------------
-// FP32 power step at b = 65536 (H = 2M, R = 2) in three launches:
-//   k_sub_cs        E_j,r = FFT_M of the count sketches of u (modes sa, sb)
-//   k_power_split_mid  per quad of bins {k', M-k', M+k', H-k'}: Z, X_j, the
-//                   product P = S conj(X_sa) conj(X_sb), its c2r packing Y
-//                   and the inverse split A_r
-//   k_power_split_out  z_r = IFFT_M(A_r) and the read-off of the coordinates
-//                   whose packed position has residue r.
+// FP32 power step at b = 65536 (H = 2M, R = 2) in one launch, one work-group
+// per (sketch m, restart tau); the LDS holds one M-point transform at a time:
+//   for each count-sketch mode j: E_j,0 = FFT_M(residue 0) in LDS, parked in
+//   a global scratch row at the bins k' and M - k' of the quads the thread
+//   owns; then E_j,1 = FFT_M(residue 1) in LDS, and per quad of bins
+//   {k', H - k', M - k', M + k'} the recombination Z[k] = E_0[k mod M] +-
+//   W_H^k E_1[k mod M], the real-input bins X_j and the product
+//   P = S conj(X_sa) conj(X_sb) (the first mode's partial product waits in
+//   the scratch row);
+//   then per quad the c2r packing Y and the inverse split A_r; A_0 goes to
+//   LDS (at the positions the thread read, so no other thread is disturbed)
+//   and A_1 to the scratch row while z_0 = IFFT_M(A_0) is read off, then
+//   z_1 = IFFT_M(A_1) and the read-off of the coordinates whose packed
+//   position has residue 1.
+// With PRE the work-group first forms u = normalised median of Vprev[tau]
+// itself (the median prologue of k_power), so no launch of its own is needed.
 // ---------------------------------------------------------------------------
-struct SplitMidArgs {
-  const cx<float>* E;   // [nvec][B][2][2][M]
-  const cx<float>* S;   // [B][H+1]
-  const cx<float>* Wb;  // [b]
-  int B, b, M;
-  cx<float>* A;         // [nvec][B][2][M]
+struct SplitOneArgs {
+  const uint32_t* hx;
+  const uint32_t* hxs;
+  const uint32_t* ord;
+  int n, B;
+  const cx<float>* S;    // [B][H+1]
+  const cx<float>* Wb;   // [b]
+  const cx<float>* twM;  // pass table of the M-point transform
+  const float* Uprev;    // [L][n]
+  const float* Uy;       // [L][n] or null (second count sketch's vector; not with PRE)
+  const float* Vprev;    // [L][B][n] (PRE)
+  float* Ucur;           // [L][n]    (PRE, written by m == 0)
+  int32_t* flags;        // [L]       (PRE, nullable)
+  float* V;              // [L][B][n]
+  double* lam_per;       // [L][B]    (mode 1)
+  cx<float>* P;          // [nrest][B][6][M/2 + 1] scratch
+  int tau0, mode, u_lds;
+  int rd, sa, sb;
 };
 
-__global__ __launch_bounds__(256) void k_power_split_mid(SplitMidArgs a) {
-  const int m = blockIdx.x, vec = blockIdx.y;
-  const int M = a.M, H = 2 * M;
-  const cx<float>* E2 = a.E + (((size_t)vec * a.B + m) * 2 + 0) * 2 * (size_t)M;
-  const cx<float>* E3 = a.E + (((size_t)vec * a.B + m) * 2 + 1) * 2 * (size_t)M;
-  const cx<float>* S = a.S + (size_t)m * (H + 1);
-  cx<float>* A0 = a.A + (((size_t)vec * a.B + m) * 2 + 0) * (size_t)M;
-  cx<float>* A1 = A0 + M;
-  // Z[km] and Z[km + M] from the two sub-transforms (W_H^km E_1[km] added or
-  // subtracted), km < M.
-  auto zpair = [&](const cx<float>* E, int km, cx<float>& lo, cx<float>& hi) {
-    const cx<float> t = cmul(a.Wb[2 * km], E[M + km]);
-    lo = cadd(E[km], t);
-    hi = csub(E[km], t);
-  };
-  auto Y = [&](int k, cx<float> Pk, cx<float> PHk) -> cx<float> { return c2r_pack(Pk, PHk, a.Wb[k]); };
-  for (int kp = blockIdx.z * blockDim.x + threadIdx.x; kp <= M / 2; kp += gridDim.z * blockDim.x) {
-    // The quad k', H - k', M - k', M + k' needs Z at those four bins, which
-    // come from the sub-transform bins k' and M - k' (mod M).
-    const int km2 = (M - kp) % M;
-    cx<float> P[4];  // at k', H - k', M - k', M + k'
-    const cx<float>* Es[2] = {E2, E3};
-    cx<float> X[2][4];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cx<float> a0, a1, b0, b1;
-      zpair(Es[j], kp, a0, a1);    // Z[k'], Z[M + k']
-      zpair(Es[j], km2, b0, b1);   // Z[M - k'], Z[H - k'] (k' > 0); Z[0], Z[M] (k' = 0)
-      const cx<float> zk = a0, zMk = kp ? b0 : b1, zHk = kp ? b1 : b0, zMpk = a1;
-      X[j][0] = r2c_post(zk, zHk, a.Wb[kp]);
-      X[j][1] = r2c_post(zHk, zk, a.Wb[H - kp]);
-      X[j][2] = r2c_post(zMk, zMpk, a.Wb[M - kp]);
-      X[j][3] = r2c_post(zMpk, zMk, a.Wb[M + kp]);
-    }
-    const int ks[4] = {kp, H - kp, M - kp, M + kp};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) P[q] = cmulc(cmulc(S[ks[q]], X[0][q]), X[1][q]);
-    const cx<float> Pa = P[0], Pd = P[1], Pb = P[2], Pc = P[3];
-    const cx<float> Ya = Y(kp, Pa, Pd);              // Y[k']
-    const cx<float> Yc = Y(M + kp, Pc, Pb);          // Y[M + k']
-    A0[kp] = cadd(Ya, Yc);
-    A1[kp] = cmulc(csub(Ya, Yc), a.Wb[2 * kp]);      // * W_H^(-k')
-    if (kp > 0 && kp < M / 2) {
-      const cx<float> Yb = Y(M - kp, Pb, Pc);        // Y[M - k']
-      const cx<float> Yd = Y(H - kp, Pd, Pa);        // Y[H - k']
-      A0[M - kp] = cadd(Yb, Yd);
-      A1[M - kp] = cmulc(csub(Yb, Yd), a.Wb[2 * (M - kp)]);
-    }
-  }
+// LDS of k_power_split1: the reduction words, the M-point buffer and (u_lds) u.
+constexpr size_t split1_lds_bytes(int logm, int n, bool u_lds) {
+  return 128 + 2 * (size_t)padded_len(1 << logm) * sizeof(float) + (u_lds ? (size_t)n * sizeof(float) : 0);
 }
 
-struct SplitOutArgs {
-  const cx<float>* A;     // [nvec][B][2][M]
-  const uint32_t* hx;
-  int n, B, rd, M, b;
-  const cx<float>* twM;
-  float* V;               // [nvec][B][n]
-};
+// Threads of k_power_split1 (one work-group per CU: the M-point buffer takes
+// most of the LDS).
+constexpr int kSplit1Threads = 1024;
 
-template <int LOGM>
-__global__ __launch_bounds__(threads_for_h<float>(LOGM)) void k_power_split_out(SplitOutArgs a) {
+template <int LOGM, bool PRE>
+__global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a) {
   constexpr int M = 1 << LOGM;
-  constexpr int NT = threads_for_h<float>(LOGM);
+  constexpr int H = 2 * M;
+  constexpr int NT = kSplit1Threads;
   constexpr int PL = padded_len(M);
-  __shared__ __align__(16) float re[2 * PL];
+  constexpr int QH = M / 2 + 1;        // quads k' = 0 .. M/2
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* red = reinterpret_cast<double*>(lds);
+  float* re = reinterpret_cast<float*>(lds + 128);
   float* im = re + PL;
+  float* ul = re + 2 * PL;
   const Soa<float> buf{re, im};
-  const int m = blockIdx.x, vec = blockIdx.y, r = blockIdx.z;
-  const cx<float>* src = a.A + (((size_t)vec * a.B + m) * 2 + r) * (size_t)M;
-  for (int k = threadIdx.x; k < M; k += NT) buf.put(k, src[k]);
-  __syncthreads();
+  const int tid = threadIdx.x;
+  const int m = blockIdx.x;
+  const int tl = blockIdx.y;
+  const int tau = a.tau0 + tl;
+  const int n = a.n, B = a.B;
   const Twid<float> tw{a.twM, nullptr};
-  const int n = a.n;
-  // With n small against M the transform leaves out its last two passes and
-  // the read-off forms each output it needs from the groups before them.
+  const cx<float>* S = a.S + (size_t)m * (H + 1);
+  const cx<float>* Wb = a.Wb;
+  cx<float>* Pq = a.P + ((size_t)tl * B + m) * 6 * (size_t)QH;
+  const float* ug = a.Uprev + (size_t)tau * n;
+
+  if constexpr (PRE) {
+    const bool ok = median_prologue<float, NT>(a.Vprev, a.Uprev, tau, n, B, ul, re, 2 * PL, red, false);
+    if (m == 0) {
+      for (int i = tid; i < n; i += NT) a.Ucur[(size_t)tau * n + i] = ul[i];
+      if (tid == 0 && !ok && a.flags) a.flags[tau] |= 1;
+    }
+  } else if (a.u_lds) {
+    for (int i = tid; i < n; i += NT) ul[i] = ug[i];
+    __syncthreads();
+  }
+  const bool u_lds = PRE || a.u_lds;
+
+  // Z and X_j of quad {k', H - k', M - k', M + k'} from E_j,0 (ea at k', eb
+  // at M - k') and E_j,1 (LDS).
+  auto quad_x = [&](int kp, const cx<float> ea, const cx<float> eb, cx<float> (&X)[4]) {
+    const int km2 = (M - kp) & (M - 1);
+    const cx<float> fa = buf.get(kp), fb = buf.get(km2);
+    const cx<float> ta = cmul(Wb[2 * kp], fa), tb = cmul(Wb[2 * km2], fb);
+    const cx<float> a0 = cadd(ea, ta), a1 = csub(ea, ta);  // Z[k'], Z[M + k']
+    const cx<float> b0 = cadd(eb, tb), b1 = csub(eb, tb);  // Z[M - k'], Z[H - k'] (k' > 0)
+    const cx<float> zk = a0, zMk = kp ? b0 : b1, zHk = kp ? b1 : b0, zMpk = a1;
+    X[0] = r2c_post(zk, zHk, Wb[kp]);
+    X[1] = r2c_post(zHk, zk, Wb[H - kp]);
+    X[2] = r2c_post(zMk, zMpk, Wb[M - kp]);
+    X[3] = r2c_post(zMpk, zMk, Wb[M + kp]);
+  };
+  // First mode: P = S conj(X_sa) into the scratch row.
+  auto quad_first = [&](int kp, const cx<float> ea, const cx<float> eb) {
+    cx<float> X[4];
+    quad_x(kp, ea, eb, X);
+    const int ks[4] = {kp, H - kp, M - kp, M + kp};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Pq[(size_t)q * QH + kp] = cmulc(S[ks[q]], X[q]);
+  };
+  // Second mode: P *= conj(X_sb), the packing Y and the inverse split; A_0
+  // into LDS at k' and M - k' (the positions this thread read), A_1 into the
+  // scratch row in place of the P values just read (slots 0 and 1).
+  auto quad_second = [&](int kp, const cx<float> ea, const cx<float> eb) {
+    cx<float> X[4];
+    quad_x(kp, ea, eb, X);
+    cx<float> P[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[q] = cmulc(Pq[(size_t)q * QH + kp], X[q]);
+    auto Y = [&](int k, cx<float> Pk, cx<float> PHk) -> cx<float> { return c2r_pack(Pk, PHk, Wb[k]); };
+    const cx<float> Ya = Y(kp, P[0], P[1]);      // Y[k']
+    const cx<float> Yc = Y(M + kp, P[3], P[2]);  // Y[M + k']
+    buf.put(kp, cadd(Ya, Yc));
+    Pq[kp] = cmulc(csub(Ya, Yc), Wb[2 * kp]);    // A_1[k'] = (Ya - Yc) W_H^(-k')
+    if (kp > 0 && kp < M / 2) {
+      const cx<float> Yb = Y(M - kp, P[2], P[3]);  // Y[M - k']
+      const cx<float> Yd = Y(H - kp, P[1], P[0]);  // Y[H - k']
+      buf.put(M - kp, cadd(Yb, Yd));
+      Pq[QH + kp] = cmulc(csub(Yb, Yd), Wb[2 * (M - kp)]);  // A_1[M - k']
+    }
+  };
+  // Count sketch of residue r of mode `mode` (vector uy, else u) and its
+  // forward M-point transform in LDS (ends with a barrier).
+  auto forward = [&](int mode, const float* uy, int r) {
+    zero_lds<NT>(re, 2 * PL * (int)sizeof(float));
+    __syncthreads();
+    const size_t tb = ((size_t)m * 3 + mode) * n;
+    auto getu = [&](uint32_t i) -> float { return uy ? uy[i] : (u_lds ? ul[i] : ug[i]); };
+    auto store = [&](uint32_t t, float v) {
+      const unsigned p = t >> 1;
+      if ((int)(p & 1u) == r) {
+        const int q = pidx((int)(p >> 1));
+        if (t & 1u) im[q] = v;
+        else re[q] = v;
+      }
+    };
+    count_sketch<float>(a.hxs + tb, a.ord + tb, n, NT, getu, store);
+    __syncthreads();
+    fft_soa<float, LOGM, NT, false>(buf, tw);
+  };
+
+  // E_j,0 at the bins k' and M - k' of each quad waits in slots 4 and 5 of
+  // the scratch row (each thread reads back what it wrote).
+  auto keep_e0 = [&]() {
+    for (int kp = tid; kp <= M / 2; kp += NT) {
+      Pq[4 * (size_t)QH + kp] = buf.get(kp);
+      Pq[5 * (size_t)QH + kp] = buf.get((M - kp) & (M - 1));
+    }
+    __syncthreads();  // before the next count sketch clears the buffer
+  };
+  forward(a.sa, nullptr, 0);
+  keep_e0();
+  forward(a.sa, nullptr, 1);
+#pragma unroll 2
+  for (int kp = tid; kp <= M / 2; kp += NT) quad_first(kp, Pq[4 * (size_t)QH + kp], Pq[5 * (size_t)QH + kp]);
+  __syncthreads();
+  const float* uy = a.Uy ? a.Uy + (size_t)tau * n : nullptr;
+  forward(a.sb, uy, 0);
+  keep_e0();
+  forward(a.sb, uy, 1);
+#pragma unroll 2
+  for (int kp = tid; kp <= M / 2; kp += NT) quad_second(kp, Pq[4 * (size_t)QH + kp], Pq[5 * (size_t)QH + kp]);
+
+  // z_r = IFFT_M(A_r) and the read-off of the coordinates of residue r.
   constexpr int RMX = fft_rmax(M, NT);
   constexpr bool PRUNABLE = output_from_groups_ok(M, NT);
   constexpr int NS3 = pass_stride(M, NT, 1);
   const bool prune = PRUNABLE && n * pass_radix(M, NS3, RMX) <= M;
-  if constexpr (PRUNABLE) {
-    fft_soa<float, LOGM, NT, true, true, 2>(buf, tw);
-    if (!prune) fft_soa_from<float, LOGM, NT, true, NS3, 0, true>(buf, tw);
-  } else {
-    fft_soa<float, LOGM, NT, true>(buf, tw);
-  }
-  const uint32_t* hx1 = a.hx + ((size_t)m * 3 + a.rd) * n;
-  float* Vrow = a.V + ((size_t)vec * a.B + m) * n;
-  const float scale = 2.0f / (float)a.b;
-  for (int i = threadIdx.x; i < n; i += NT) {
-    const uint32_t e = hx1[i];
-    const uint32_t t = e >> 1, p = t >> 1;
-    if ((int)(p & 1u) != r) continue;
-    float val;
-    if (PRUNABLE && prune) {
-      const cx<float> z = inverse_output_from_groups<float, LOGM, NT>(buf, a.twM, (int)(p >> 1));
-      val = (t & 1u) ? z.y : z.x;
-    } else {
-      const int q = pidx((int)(p >> 1));
-      val = (t & 1u) ? im[q] : re[q];
-    }
-    val *= scale;
-    Vrow[i] = (e & 1u) ? -val : val;
-  }
-}
-
-// lam_per[vec][m] = sum_i u_vec[i] V[vec][m][i] (FP64 sum); one block per (m, vec).
-template <typename R>
-__global__ __launch_bounds__(256) void k_rowdot(const R* U, const R* V, int n, int B, double* lam_per) {
-  __shared__ double red[4];
-  const int m = blockIdx.x, vec = blockIdx.y;
-  const R* u = U + (size_t)vec * n;
-  const R* v = V + ((size_t)vec * B + m) * n;
+  int om = m, otau = tau;
+  asm volatile("" : "+s"(om), "+s"(otau));
+  const uint32_t* hx1 = a.hx + ((size_t)om * 3 + a.rd) * n;
+  float* Vrow = a.V + ((size_t)otau * B + om) * n;
+  const float scale = 2.0f / (float)(2 * H);
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += (double)u[i] * (double)v[i];
-  const double s = block_sum<256>(acc, red);
-  if (threadIdx.x == 0) lam_per[(size_t)vec * B + m] = s;
+#pragma unroll 1
+  for (int r = 0; r < 2; ++r) {
+    __syncthreads();  // A_0 complete in LDS / the residue-0 read-off done
+    if (r == 1) {
+      // A_1 back from the scratch row (written by this thread, program order)
+      for (int kp = tid; kp <= M / 2; kp += NT) {
+        buf.put(kp, Pq[kp]);
+        if (kp > 0 && kp < M / 2) buf.put(M - kp, Pq[QH + kp]);
+      }
+      __syncthreads();
+    }
+    if constexpr (PRUNABLE) {
+      fft_soa<float, LOGM, NT, true, false, 2>(buf, tw);
+      if (!prune) fft_soa_from<float, LOGM, NT, true, NS3, 0, false>(buf, tw);
+    } else {
+      fft_soa<float, LOGM, NT, true>(buf, tw);
+    }
+    for (int i = tid; i < n; i += NT) {
+      const uint32_t e = hx1[i];
+      const uint32_t t = e >> 1, p = t >> 1;
+      if ((int)(p & 1u) != r) continue;
+      float val;
+      if (PRUNABLE && prune) {
+        const cx<float> z = inverse_output_from_groups<float, LOGM, NT>(buf, a.twM, (int)(p >> 1));
+        val = (t & 1u) ? z.y : z.x;
+      } else {
+        const int q = pidx((int)(p >> 1));
+        val = (t & 1u) ? im[q] : re[q];
+      }
+      val *= scale;
+      const float v = (e & 1u) ? -val : val;
+      Vrow[i] = v;
+      acc += (double)(u_lds ? ul[i] : ug[i]) * (double)v;
+    }
+  }
+  if (a.mode == 1) {
+    const double lam = block_sum<NT>(acc, red);
+    if (tid == 0) a.lam_per[(size_t)tau * B + m] = lam;
+  }
 }
 
 }  // namespace tsk

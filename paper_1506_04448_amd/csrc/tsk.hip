@@ -467,7 +467,7 @@ tsk_status preload_split_tables(tsk_ctx_t ctx, int logb, bool fp32_power) {
   if (fp32_power) {
     const cx<float>* t32 = nullptr;
     const cx<float>* w32 = nullptr;
-    TSK_TRY(get_tw<float>(ctx, kSubLogM32 + 1, &t32, tsk::threads_for_h<float>(kSubLogM32)));
+    TSK_TRY(get_tw<float>(ctx, kSubLogM32 + 1, &t32, tsk::kSplit1Threads));
     TSK_TRY(get_wb<float>(ctx, logb, &w32));
   }
   return TSK_OK;
@@ -564,16 +564,14 @@ tsk_status c2r_any(tsk_ctx_t ctx, int logb, const cx<double>* S64, double* s, in
   return check_launch("k_c2r_split_b");
 }
 
-// Buffers of the FP32 split power step (b = 65536) for nvec vectors.
+// Buffer of the FP32 split power step (b = 65536) for nvec vectors: per
+// (vector, sketch) 6 (M/2 + 1) values (the first mode's partial spectral
+// product, the residue-0 sub-transform between its two uses, A_1).
 struct SplitBufs {
-  void* E = nullptr;  // cx<float>[nvec][B][2][2][M]
-  void* A = nullptr;  // cx<float>[nvec][B][2][M]
+  void* A = nullptr;  // cx<float>[nvec][B][6][M/2 + 1]
 };
-size_t power_split_bytes_E(tsk_tables_t tab, int nvec) {
-  return (size_t)nvec * tab->B * 4 * ((size_t)1 << kSubLogM32) * sizeof(cx<float>);
-}
 size_t power_split_bytes_A(tsk_tables_t tab, int nvec) {
-  return (size_t)nvec * tab->B * 2 * ((size_t)1 << kSubLogM32) * sizeof(cx<float>);
+  return (size_t)nvec * tab->B * 6 * (((size_t)1 << kSubLogM32) / 2 + 1) * sizeof(cx<float>);
 }
 bool needs_power_split(tsk_tables_t tab, tsk_dtype dtype) {
   return dtype == TSK_F32 && tab->logb > kLdsLogB + 1;
@@ -1190,71 +1188,72 @@ extern "C" tsk_status tsk_sketch_deflate(tsk_ctx_t ctx, tsk_tables_t tab, const 
 namespace {
 
 
-// FP32 power step at b = 65536 through the split transforms (large.hpp); the
-// median of the previous step (prefix) is a launch of its own here.
+// FP32 power step at b = 65536 through the split transforms (large.hpp), one
+// launch (k_power_split1).  The median of the previous step (prefix) is the
+// kernel's prologue when u fits the LDS beside the buffer and B <= 16 (the
+// sorting-network median); otherwise a launch of its own before the step.
+// n whose u fits the LDS beside the M-point buffer
+constexpr int kSplit1MaxULds = (int)((kMaxLds - tsk::split1_lds_bytes(kSubLogM32, 0, false)) / sizeof(float));
+
 tsk_status power_split(tsk_ctx_t ctx, tsk_tables_t tab, const cx<float>* spec, int nrest, int tau0,
                        int prefix, int mode, const float* Uprev, const float* Vprev, float* Ucur,
                        int32_t* flags, float* V, double* lam_per, hipStream_t st, int perm,
                        const SplitBufs* sb, const float* Uy = nullptr) {
-  if (!sb || !sb->E || !sb->A) return tsk::fail(TSK_EHIP, "internal: split power buffers missing");
-  const int n = tab->n, B = tab->B, b = tab->b, M = 1 << kSubLogM32;
+  if (!sb || !sb->A) return tsk::fail(TSK_EHIP, "internal: split power buffers missing");
+  const int n = tab->n, B = tab->B;
   const cx<float>* twM = nullptr;
   const cx<float>* Wb = nullptr;
-  TSK_TRY(get_tw<float>(ctx, kSubLogM32 + 1, &twM, tsk::threads_for_h<float>(kSubLogM32)));
+  TSK_TRY(get_tw<float>(ctx, kSubLogM32 + 1, &twM, tsk::kSplit1Threads));
   TSK_TRY(get_wb<float>(ctx, tab->logb, &Wb));
-  const size_t on = (size_t)tau0 * n, obn = (size_t)tau0 * B * n;
-  const float* U = Uprev + on;
-  if (prefix) {
+  const bool u_lds = n <= kSplit1MaxULds;
+  const bool pre = prefix && u_lds && B <= 16;
+  if (prefix && !pre) {
+    const size_t on = (size_t)tau0 * n, obn = (size_t)tau0 * B * n;
     TSK_TRY(median_norm_launch<float>(Vprev + obn, Uprev + on, Ucur + on, flags ? flags + tau0 : nullptr,
                                       nrest, n, B, st));
-    U = Ucur + on;
+    Uprev = Ucur;
   }
-  tsk::SubCsArgs<float, float> a1;
-  a1.hxs = tab->hxs;
-  a1.ord = tab->ord;
-  a1.n = n;
-  a1.B = B;
-  a1.Rr = 2;
-  a1.nmodes = 2;
-  a1.mode[0] = (perm + 1) % 3;
-  a1.mode[1] = (perm + 2) % 3;
-  a1.mode[2] = 0;
-  a1.U = U;
-  a1.U2 = Uy ? Uy + on : nullptr;
-  a1.twM = twM;
-  a1.E = reinterpret_cast<cx<float>*>(sb->E);
-  hipLaunchKernelGGL((tsk::k_sub_cs<float, kSubLogM32, float>), dim3(B, nrest, 4),
-                     dim3(tsk::threads_for_h<float>(kSubLogM32)), 0, st, a1);
-  TSK_TRY(check_launch("k_sub_cs"));
-  tsk::SplitMidArgs a2;
-  a2.E = reinterpret_cast<const cx<float>*>(sb->E);
-  a2.S = spec;
-  a2.Wb = Wb;
-  a2.B = B;
-  a2.b = b;
-  a2.M = M;
-  a2.A = reinterpret_cast<cx<float>*>(sb->A);
-  hipLaunchKernelGGL(tsk::k_power_split_mid, dim3(B, nrest, (M / 2 + 1 + 255) / 256), dim3(256), 0, st, a2);
-  TSK_TRY(check_launch("k_power_split_mid"));
-  tsk::SplitOutArgs a3;
-  a3.A = reinterpret_cast<const cx<float>*>(sb->A);
-  a3.hx = tab->hx;
-  a3.n = n;
-  a3.B = B;
-  a3.rd = perm;
-  a3.M = M;
-  a3.b = b;
-  a3.twM = twM;
-  a3.V = V + obn;
-  hipLaunchKernelGGL((tsk::k_power_split_out<kSubLogM32>), dim3(B, nrest, 2),
-                     dim3(tsk::threads_for_h<float>(kSubLogM32)), 0, st, a3);
-  TSK_TRY(check_launch("k_power_split_out"));
-  if (mode == 1) {
-    hipLaunchKernelGGL(tsk::k_rowdot<float>, dim3(B, nrest), dim3(256), 0, st, U, (const float*)(V + obn), n,
-                       B, lam_per + (size_t)tau0 * B);
-    TSK_TRY(check_launch("k_rowdot"));
+  tsk::SplitOneArgs a;
+  a.hx = tab->hx;
+  a.hxs = tab->hxs;
+  a.ord = tab->ord;
+  a.n = n;
+  a.B = B;
+  a.S = spec;
+  a.Wb = Wb;
+  a.twM = twM;
+  a.Uprev = Uprev;
+  a.Uy = Uy;
+  a.Vprev = Vprev;
+  a.Ucur = Ucur;
+  a.flags = flags;
+  a.V = V;
+  a.lam_per = lam_per;
+  a.P = reinterpret_cast<cx<float>*>(sb->A);
+  a.tau0 = tau0;
+  a.mode = mode;
+  a.u_lds = u_lds ? 1 : 0;
+  a.rd = perm;
+  a.sa = (perm + 1) % 3;
+  a.sb = (perm + 2) % 3;
+  const size_t lds = tsk::split1_lds_bytes(kSubLogM32, n, u_lds);
+  const int dev = ctx->device;
+  static std::atomic<uint64_t> configured{0};
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_power_split1<kSubLogM32, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_power_split1<kSubLogM32, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    configured.fetch_or(bit);
   }
-  return TSK_OK;
+  if (pre)
+    hipLaunchKernelGGL((tsk::k_power_split1<kSubLogM32, true>), dim3(B, nrest), dim3(tsk::kSplit1Threads), lds,
+                       st, a);
+  else
+    hipLaunchKernelGGL((tsk::k_power_split1<kSubLogM32, false>), dim3(B, nrest), dim3(tsk::kSplit1Threads), lds,
+                       st, a);
+  return check_launch("k_power_split1");
 }
 
 template <typename R>
@@ -1299,10 +1298,8 @@ tsk_status power_launch(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int n
 tsk_status eager_split_bufs(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype, int nvec, SplitBufs* sb) {
   if (!needs_power_split(tab, dtype)) return TSK_OK;
   void* p = nullptr;
-  const size_t e = power_split_bytes_E(tab, nvec), a = power_split_bytes_A(tab, nvec);
-  TSK_TRY(ws_get(ctx, WS_SPLIT, ((e + 255) & ~(size_t)255) + a, &p));
-  sb->E = p;
-  sb->A = (char*)p + ((e + 255) & ~(size_t)255);
+  TSK_TRY(ws_get(ctx, WS_SPLIT, power_split_bytes_A(tab, nvec), &p));
+  sb->A = p;
   return TSK_OK;
 }
 
@@ -1364,12 +1361,8 @@ extern "C" tsk_status tsk_power_update_noalloc(tsk_ctx_t ctx, tsk_tables_t tab, 
   const int n = tab->n, B = tab->B;
   const size_t es = dtype == TSK_F32 ? 4 : 8;
   const size_t vbytes = ((size_t)L * B * n * es + 255) & ~(size_t)255;
-  size_t ebytes = 0, abytes = 0;
-  if (needs_power_split(tab, dtype)) {
-    ebytes = (power_split_bytes_E(tab, L) + 255) & ~(size_t)255;
-    abytes = power_split_bytes_A(tab, L);
-  }
-  const size_t need = vbytes + ebytes + abytes;
+  const size_t abytes = needs_power_split(tab, dtype) ? power_split_bytes_A(tab, L) : 0;
+  const size_t need = vbytes + abytes;
   if (need > kScratchBytes)
     return tsk::fail(TSK_EINVAL,
                      "tsk_power_update_noalloc: L=%d, B=%d, n=%d, b=%d needs %zu bytes of scratch, more than "
@@ -1380,10 +1373,7 @@ extern "C" tsk_status tsk_power_update_noalloc(tsk_ctx_t ctx, tsk_tables_t tab, 
   char* base = reinterpret_cast<char*>(ctx->scratch);
   void* vbuf = base;
   SplitBufs sb;
-  if (ebytes) {
-    sb.E = base + vbytes;
-    sb.A = base + vbytes + ebytes;
-  }
+  if (abytes) sb.A = base + vbytes;
   if (dtype == TSK_F32) {
     TSK_TRY(power_launch<float>(ctx, tab, S32, L, 0, 0, 0, (const float*)U_in, nullptr, nullptr,
                                 nullptr, (float*)vbuf, nullptr, S(stream), 0, &sb));
@@ -2023,7 +2013,6 @@ size_t decomp_ws_layout(char* base, tsk_tables_t tab, tsk_dtype dtype, int k, in
   d.u0 = u0 ? (double*)take((size_t)k * L * n * 8) : nullptr;
   d.esplit = rank1_split_path(tab->logb) ? take(rank1_split_bytes(tab, 1)) : nullptr;
   if (needs_power_split(tab, dtype)) {
-    d.sb.E = take(power_split_bytes_E(tab, L));
     d.sb.A = take(power_split_bytes_A(tab, L));
   }
   if (w) *w = d;
