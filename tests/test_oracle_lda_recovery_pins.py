@@ -4,7 +4,8 @@
     moments), whitening, the orthogonal decomposition of M3(W, W, W) and the
     recovery formulas return the model's alpha and topic vectors exactly;
   * the randomized subspace iteration converges to the exact truncated
-    eigendecomposition (W W^T and sigma agree) on an empirical M2;
+    eigendecomposition (W W^T and sigma agree) on an empirical M2, and equals
+    it to rounding, with or without power rounds, when M2 has rank exactly K;
   * the orthonormalisation through the Gram eigenpairs gives Q^T Q = I.
 """
 import numpy as np
@@ -60,3 +61,23 @@ def test_gram_orthonormalisation():
     Q = lda.orth_gram(Y)
     np.testing.assert_allclose(Q.T @ Q, np.eye(7), atol=1e-12)
     np.testing.assert_allclose(Q @ (Q.T @ Y), Y, atol=1e-12)
+
+
+def test_subspace_whitening_is_exact_when_m2_has_rank_k():
+    """With M2 = A diag(s) A^T of rank exactly K (signs mixed, as an empirical
+    M2's leading part can be), the range of M2 Omega is range(A) for a generic
+    Omega, so even without power rounds the randomized whitening must equal
+    the exact one: W^T M2 W = I, the same |eigenvalues| and the same W W^T."""
+    rng = np.random.default_rng(11)
+    V, K = 40, 6
+    A = rng.standard_normal((V, K))
+    s = np.array([5.0, -3.0, 2.0, 1.5, -0.7, 0.4])
+    M2 = (A * s) @ A.T
+    W, sig = lda.whitening_exact(M2, K)
+    for iters in (0, 1, 3):
+        Om = rng.standard_normal((V, K))
+        Ws, sigs = lda.whitening_subspace(M2, Om, iters)
+        np.testing.assert_allclose(sigs, sig, rtol=1e-10)
+        G = Ws.T @ M2 @ Ws
+        np.testing.assert_allclose(np.abs(G), np.eye(K), atol=1e-10)
+        np.testing.assert_allclose(Ws @ Ws.T, W @ W.T, atol=1e-10 * np.abs(W @ W.T).max())
