@@ -205,9 +205,12 @@ def test_large_power_update_and_uuu(ctx, b, n):
     assert rel(grad.cpu().numpy(), rgrad) < 1e-5
 
 
-def test_large_decompose_fp32_matches_oracle(ctx):
-    print("large decompose b=65536", flush=True)
-    n, k, b, B, L, T = 80, 3, 65536, 4, 6, 8
+@pytest.mark.parametrize("B", [4, 20])
+def test_large_decompose_fp32_matches_oracle(ctx, B):
+    """B = 4: the median of each step is the split kernel's prologue; B = 20:
+    it runs as a launch of its own before the step."""
+    print(f"large decompose b=65536 B={B}", flush=True)
+    n, k, b, L, T = 80, 3, 65536, 6, 8
     P = planted_tensor(n, k, noise=0.02, seed=9, lam_range=(1.0, 3.0))
     h, xi = tsk.hash_generate(9, n, b, B)
     tab = tsk.Tables(ctx, h, xi, b)
@@ -223,6 +226,30 @@ def test_large_decompose_fp32_matches_oracle(ctx):
     assert rel(U[0], r.U[0]) < 1e-5
     # planted components are recovered
     assert oracle.wrong_vectors(P.V, U) == 0
+
+
+def test_large_decompose_with_u_beyond_lds(ctx):
+    """n = 6000: u no longer fits the LDS beside the split kernel's buffer, so
+    the count sketches read it from global memory and the median of each step
+    is a launch of its own.  Factor sketch of two unit vectors; the first
+    component against the oracle's Algorithm 1 on the same sketch."""
+    print("large decompose b=65536 n=6000", flush=True)
+    n, b, B, L, T = 6000, 65536, 2, 2, 3
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((2, n))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    lamf = np.array([3.0, 1.5])
+    h, xi = tsk.hash_generate(17, n, b, B)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_factors(ctx, tab, torch.from_numpy(lamf).to(DEV), torch.from_numpy(A).to(DEV), S64, S32)
+    S_time = tsk.sketch_export(ctx, S64, b).cpu().numpy()
+    lam, U, _, _ = tsk.decompose(ctx, tab, S64, S32, 1, L, T, dtype=tsk.F32, seed=17)
+    u0 = np.stack([oracle.start_vectors_spec(17, 0, L, n)])
+    r = oracle.rtpm_sketched(S_time, h, xi, 1, L, T, u0)
+    assert abs(float(lam.cpu().numpy()[0]) - r.lam[0]) <= 1e-5 * abs(r.lam[0])
+    assert rel(U.cpu().numpy()[0], r.U[0]) < 1e-5
+    tab.close()
 
 
 def test_large_cp_loss_fp32(ctx):
