@@ -58,6 +58,25 @@ def test_heldout_matches_oracle(ctx, D, V, K, L, eps):
         assert H.kkt_residual(G, c, pi[d]) < 1e-10
 
 
+def test_heldout_at_topic_model_shape(ctx):
+    """The topic-model workload's shape (V = 20000, K = 100 topics from
+    Dirichlet(0.01), Poisson(150) lengths) on 300 documents, every document
+    against the oracle."""
+    D, V, K = 300, 20000, 100
+    print(f"heldout C4 shape D={D} V={V} K={K}", flush=True)
+    C = lda_corpus(D=D, V=V, K=K, seed=5, mean_len=150.0, min_len=1)
+    Phi = _smooth(C.Phi, 1e-3)
+    rp = torch.from_numpy(C.rowptr.astype(np.int32)).to(DEV)
+    col = torch.from_numpy(C.col.astype(np.int32)).to(DEV)
+    cnt = torch.from_numpy(C.cnt.astype(np.int32)).to(DEV)
+    pi, ll = tsk.lda_heldout(ctx, rp, col, cnt, V, torch.from_numpy(Phi).to(DEV))
+    pi, ll = pi.cpu().numpy(), ll.cpu().numpy()
+    rpi, rll = H.heldout_fit(C, Phi)
+    for d in range(D):
+        assert rel(pi[d], rpi[d]) < 1e-12, (d, rel(pi[d], rpi[d]))
+        assert abs(ll[d] - rll[d]) <= 1e-12 * abs(rll[d]), (d, ll[d], rll[d])
+
+
 def test_heldout_true_topics_beat_uniform(ctx):
     """The generating topics explain held-out documents better than a topic
     matrix of uniform columns perturbed at random (average L_d)."""
