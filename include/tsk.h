@@ -200,11 +200,11 @@ tsk_status tsk_power_update(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dtype,
  * serving loops, harnesses that forbid hipMalloc): the power step of
  * tsk_power_update, same kernels and bit-identical results, without the
  * per-sketch estimates argument.  It allocates nothing: the estimates (and, at
- * b = 65536 in FP32, the split transforms' buffers) live in a static 32 MiB
+ * b = 65536 in FP32, the split step's scratch rows) live in a static 32 MiB
  * device array of the library, one per GPU, held until the process ends; the
  * twiddle tables were made by tsk_tables_create.  Needs
  * L*B*n*sizeof(dtype) bytes (rounded up to 256), plus at b = 65536 in FP32
- * L*B*768 KiB; more than 32 MiB is TSK_EINVAL.  Every call on one GPU shares
+ * L*B*393264 bytes; more than 32 MiB is TSK_EINVAL.  Every call on one GPU shares
  * that array and leaves its contents behind, so calls that overlap on one GPU
  * (other streams, other threads, other contexts) race: serialise them.  Other
  * arguments and errors as tsk_power_update; a path that would allocate
