@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 from collections import defaultdict
 
@@ -890,6 +891,9 @@ def main():
     ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy", "docs"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--tune", type=int, choices=(0, 1), default=1,
+                    help="launch shapes of the main leg: 1 = the tuner times the candidates in one untimed "
+                         "step before the warmup, 0 = fixed rules")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--summarize-stats", nargs="+", metavar="CSV",
                     help="kernel_stats.csv [kernel_trace.csv]")
@@ -936,6 +940,11 @@ def main():
         tsk.decompose(ctx, tab, S64, S32, K, L, T_ITERS, dtype=tsk.F32, seed=SEED,
                       lam_out=lam, U_out=U, tau_out=tau, flags_out=flags)
 
+    tune_path = None
+    if args.tune:
+        tune_path = os.path.join(tempfile.mkdtemp(prefix="tsk_tune_"), "tune.txt")
+        tsk.tune_config(ctx, 1, tune_path)
+        step()  # the tuning step: every new build and decomposition shape times its candidates
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -1029,6 +1038,16 @@ def main():
             "same_result_as_batched": bool(np.array_equal(lam_p, lam_d) and np.array_equal(U_p, U_d)),
         }
 
+    tuning = {"mode": args.tune}
+    if args.tune:
+        # the other legs keep the fixed rules (their first calls are timed)
+        tsk.tune_config(ctx, 0)
+        with open(tune_path) as fh:
+            tuning["choices"] = {ln.split()[0]: [int(x) for x in ln.split()[1:]]
+                                 for ln in fh if ln.strip()}
+        tuning["note"] = ("build: (sketches per work-group, slabs); decompose: restart groups on parallel "
+                          "graph branches; chosen by timing the candidates on this GPU")
+
     c3 = None if args.no_c3 else c3_batched(ctx, dev)
     c4 = None if args.no_c4 else c4_docs(ctx, dev, args.c4_docs)
     c5 = None if args.no_c5 else c5_differentiation(ctx, dev)
@@ -1074,6 +1093,7 @@ def main():
                          "counters": stored_sq(BUILD_KERNEL)},
         "recovery": {"residual": res_b, "wrong_vectors": int(wrong_b)},
         "precision": precision,
+        "tuning": tuning,
         "plain_path": plain,
         "decompose_ms": decompose_ms,
         "decompose_sketch_updates_per_s": updates / (decompose_ms * 1e-3),
