@@ -295,24 +295,43 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
   }
   const bool u_lds = PRE || a.u_lds;
 
+  // The twiddles of quad k' from two table entries, w1 = W_b^k' and
+  // w2 = W_b^2k': W_b^(H-k') = -conj(w1), W_b^(M-k') = -i conj(w1),
+  // W_b^(M+k') = -i w1 (W_b^H = -1, W_b^M = -i), W_b^(2(M-k')) = -conj(w2)
+  // for 0 < k' (W_b^0 = 1 for k' = 0).
+  struct QuadTw {
+    cx<float> k, Hk, Mk, Mpk, k2, Mk2;
+  };
+  auto quad_tw = [&](int kp) -> QuadTw {
+    const cx<float> w1 = Wb[kp], w2 = Wb[2 * kp];
+    QuadTw t;
+    t.k = w1;
+    t.Hk = {-w1.x, w1.y};
+    t.Mk = {-w1.y, -w1.x};
+    t.Mpk = {w1.y, -w1.x};
+    t.k2 = w2;
+    t.Mk2 = kp ? cx<float>{-w2.x, w2.y} : w2;
+    return t;
+  };
   // Z and X_j of quad {k', H - k', M - k', M + k'} from E_j,0 (ea at k', eb
   // at M - k') and E_j,1 (LDS).
-  auto quad_x = [&](int kp, const cx<float> ea, const cx<float> eb, cx<float> (&X)[4]) {
+  auto quad_x = [&](int kp, const QuadTw& w, const cx<float> ea, const cx<float> eb, cx<float> (&X)[4]) {
     const int km2 = (M - kp) & (M - 1);
     const cx<float> fa = buf.get(kp), fb = buf.get(km2);
-    const cx<float> ta = cmul(Wb[2 * kp], fa), tb = cmul(Wb[2 * km2], fb);
+    const cx<float> ta = cmul(w.k2, fa), tb = cmul(w.Mk2, fb);
     const cx<float> a0 = cadd(ea, ta), a1 = csub(ea, ta);  // Z[k'], Z[M + k']
     const cx<float> b0 = cadd(eb, tb), b1 = csub(eb, tb);  // Z[M - k'], Z[H - k'] (k' > 0)
     const cx<float> zk = a0, zMk = kp ? b0 : b1, zHk = kp ? b1 : b0, zMpk = a1;
-    X[0] = r2c_post(zk, zHk, Wb[kp]);
-    X[1] = r2c_post(zHk, zk, Wb[H - kp]);
-    X[2] = r2c_post(zMk, zMpk, Wb[M - kp]);
-    X[3] = r2c_post(zMpk, zMk, Wb[M + kp]);
+    X[0] = r2c_post(zk, zHk, w.k);
+    X[1] = r2c_post(zHk, zk, w.Hk);
+    X[2] = r2c_post(zMk, zMpk, w.Mk);
+    X[3] = r2c_post(zMpk, zMk, w.Mpk);
   };
   // First mode: P = S conj(X_sa) into the scratch row.
   auto quad_first = [&](int kp, const cx<float> ea, const cx<float> eb) {
+    const QuadTw w = quad_tw(kp);
     cx<float> X[4];
-    quad_x(kp, ea, eb, X);
+    quad_x(kp, w, ea, eb, X);
     const int ks[4] = {kp, H - kp, M - kp, M + kp};
 #pragma unroll
     for (int q = 0; q < 4; ++q) Pq[(size_t)q * QH + kp] = cmulc(S[ks[q]], X[q]);
@@ -321,21 +340,21 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
   // into LDS at k' and M - k' (the positions this thread read), A_1 into the
   // scratch row in place of the P values just read (slots 0 and 1).
   auto quad_second = [&](int kp, const cx<float> ea, const cx<float> eb) {
+    const QuadTw w = quad_tw(kp);
     cx<float> X[4];
-    quad_x(kp, ea, eb, X);
+    quad_x(kp, w, ea, eb, X);
     cx<float> P[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) P[q] = cmulc(Pq[(size_t)q * QH + kp], X[q]);
-    auto Y = [&](int k, cx<float> Pk, cx<float> PHk) -> cx<float> { return c2r_pack(Pk, PHk, Wb[k]); };
-    const cx<float> Ya = Y(kp, P[0], P[1]);      // Y[k']
-    const cx<float> Yc = Y(M + kp, P[3], P[2]);  // Y[M + k']
+    const cx<float> Ya = c2r_pack(P[0], P[1], w.k);     // Y[k']
+    const cx<float> Yc = c2r_pack(P[3], P[2], w.Mpk);   // Y[M + k']
     buf.put(kp, cadd(Ya, Yc));
-    Pq[kp] = cmulc(csub(Ya, Yc), Wb[2 * kp]);    // A_1[k'] = (Ya - Yc) W_H^(-k')
+    Pq[kp] = cmulc(csub(Ya, Yc), w.k2);                 // A_1[k'] = (Ya - Yc) W_H^(-k')
     if (kp > 0 && kp < M / 2) {
-      const cx<float> Yb = Y(M - kp, P[2], P[3]);  // Y[M - k']
-      const cx<float> Yd = Y(H - kp, P[1], P[0]);  // Y[H - k']
+      const cx<float> Yb = c2r_pack(P[2], P[3], w.Mk);  // Y[M - k']
+      const cx<float> Yd = c2r_pack(P[1], P[0], w.Hk);  // Y[H - k']
       buf.put(M - kp, cadd(Yb, Yd));
-      Pq[QH + kp] = cmulc(csub(Yb, Yd), Wb[2 * (M - kp)]);  // A_1[M - k']
+      Pq[QH + kp] = cmulc(csub(Yb, Yd), w.Mk2);         // A_1[M - k']
     }
   };
   // Count sketch of residue r of mode `mode` (vector uy, else u) and its
@@ -391,23 +410,15 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
   float* Vrow = a.V + ((size_t)otau * B + om) * n;
   const float scale = 2.0f / (float)(2 * H);
   double acc = 0.0;
-#pragma unroll 1
-  for (int r = 0; r < 2; ++r) {
-    __syncthreads();  // A_0 complete in LDS / the residue-0 read-off done
-    if (r == 1) {
-      // A_1 back from the scratch row (written by this thread, program order)
-      for (int kp = tid; kp <= M / 2; kp += NT) {
-        buf.put(kp, Pq[kp]);
-        if (kp > 0 && kp < M / 2) buf.put(M - kp, Pq[QH + kp]);
-      }
-      __syncthreads();
-    }
+  auto inverse = [&]() {
     if constexpr (PRUNABLE) {
       fft_soa<float, LOGM, NT, true, false, 2>(buf, tw);
       if (!prune) fft_soa_from<float, LOGM, NT, true, NS3, 0, false>(buf, tw);
     } else {
       fft_soa<float, LOGM, NT, true>(buf, tw);
     }
+  };
+  auto readoff = [&](int r) {
     for (int i = tid; i < n; i += NT) {
       const uint32_t e = hx1[i];
       const uint32_t t = e >> 1, p = t >> 1;
@@ -425,7 +436,33 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
       Vrow[i] = v;
       acc += (double)(u_lds ? ul[i] : ug[i]) * (double)v;
     }
+  };
+  constexpr int QP = (M / 2) / NT;  // quads per thread below M/2; k' = M/2 is thread 0's extra
+  static_assert((M / 2) % NT == 0, "whole quads per thread");
+  __syncthreads();  // A_0 complete in LDS
+  inverse();
+  // A_1 from the scratch row (written by this thread, program order) into
+  // registers; the loads are in flight during the residue-0 read-off.
+  cx<float> a1a[QP], a1b[QP], a1m{0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < QP; ++q) {
+    const int kp = tid + q * NT;
+    a1a[q] = Pq[kp];
+    a1b[q] = kp > 0 ? Pq[QH + kp] : cx<float>{0.f, 0.f};
   }
+  if (tid == 0) a1m = Pq[M / 2];
+  readoff(0);
+  __syncthreads();  // the residue-0 read-off done
+#pragma unroll
+  for (int q = 0; q < QP; ++q) {
+    const int kp = tid + q * NT;
+    buf.put(kp, a1a[q]);
+    if (kp > 0) buf.put(M - kp, a1b[q]);
+  }
+  if (tid == 0) buf.put(M / 2, a1m);
+  __syncthreads();
+  inverse();
+  readoff(1);
   if (a.mode == 1) {
     const double lam = block_sum<NT>(acc, red);
     if (tid == 0) a.lam_per[(size_t)tau * B + m] = lam;
