@@ -62,7 +62,9 @@ const char* tsk_last_error(void);
 
 /* Create a context on HIP device `device`; the device is made current.
  * Destroy frees its workspace.  A context is not thread-safe: calls that
- * share one must be serialised by the caller. */
+ * share one must be serialised by the caller.  Calls on one context share its
+ * internal workspace, so their device work must not overlap either: issue
+ * them on one stream, or synchronise between calls on different streams. */
 tsk_status tsk_create(tsk_ctx_t* out, int device);
 void tsk_destroy(tsk_ctx_t ctx);
 
