@@ -448,7 +448,7 @@ typedef struct {
 
 /* Algorithm 1 for `ninst` independent instances of different sizes (n, k, b,
  * B, dtype may all differ), each exactly as tsk_decompose computes it.  The
- * instances are spread, longest first, over up to eight branches of one HIP
+ * instances are spread, longest first, over up to 32 branches of one HIP
  * graph (recorded once per set of shapes and buffers and replayed), so the
  * device runs several instances' launches at once.  probs: host array of
  * `ninst` problems; the library keeps one workspace for all of them.

@@ -2244,9 +2244,12 @@ extern "C" tsk_status tsk_decompose_batched(tsk_ctx_t ctx, int ninst, const tsk_
                                      const_cast<double*>(u0d[i]), st));
     ctx->u0b_key = u0key;
   }
-  // Longest-first assignment of instances to at most 8 graph branches by
-  // their sketch-update work k L (T+1) B b log2 b.
-  const int nb = std::min(ninst, 8);
+  // Longest-first assignment of instances to at most 32 graph branches by
+  // their sketch-update work k L (T+1) B b log2 b.  More branches keep more
+  // of the small instances' launches in flight beside the large ones (64
+  // uneven instances: 4, 8, 16, 32, 64 branches took 2.20, 1.94, 1.76, 1.70,
+  // 1.69 s).
+  const int nb = std::min(ninst, 32);
   TSK_TRY(ensure_branches(ctx->fork, ctx->fork_ev, nb));
   std::vector<int> order(ninst);
   std::vector<double> work(ninst);
