@@ -245,7 +245,7 @@ struct SplitOneArgs {
   int32_t* flags;        // [L]       (PRE, nullable)
   float* V;              // [L][B][n]
   double* lam_per;       // [L][B]    (mode 1)
-  cx<float>* P;          // [nrest][B][6][M/2 + 1] scratch
+  cx<float>* P;          // [L][B][6][M/2 + 1] scratch, by restart tau (tau0 + blockIdx.y)
   int tau0, mode, u_lds;
   int rd, sa, sb;
 };
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
   const Twid<float> tw{a.twM, nullptr};
   const cx<float>* S = a.S + (size_t)m * (H + 1);
   const cx<float>* Wb = a.Wb;
-  cx<float>* Pq = a.P + ((size_t)tl * B + m) * 6 * (size_t)QH;
+  cx<float>* Pq = a.P + ((size_t)tau * B + m) * 6 * (size_t)QH;
   const float* ug = a.Uprev + (size_t)tau * n;
 
   if constexpr (PRE) {

@@ -2054,12 +2054,15 @@ tsk_status ensure_branches(std::vector<hipStream_t>& streams, std::vector<hipEve
 
 // Parallel restart groups of one decomposition.  Two halves of the restarts
 // on two branches measured fastest (their launches overlap each other's
-// start-up and tail; three or four branches gained less).  The split
-// transforms (b = 65536) keep one group: their buffers are indexed by restart
-// within a launch.
+// start-up and tail; three or four branches gained less).  The split power
+// step (one work-group per CU) takes two groups only when one launch would
+// need more than one round of the 256 CUs (B = 16, L = 30: 22.9 -> 21.3 ms per
+// decomposition; B = 8, L = 30: 8.3 -> 8.5 ms with two); its scratch rows are
+// indexed by restart, so the groups share nothing.
 int restart_groups(tsk_tables_t tab, tsk_dtype dtype, int L) {
-  if (needs_power_split(tab, dtype)) return 1;
-  return L >= 2 ? 2 : 1;
+  if (L < 2) return 1;
+  if (needs_power_split(tab, dtype)) return (long)tab->B * L > 256 ? 2 : 1;
+  return 2;
 }
 
 // Everything one decomposition enqueues: clear its flags (a fill kernel, so a
@@ -2120,7 +2123,7 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
   hipStream_t st = S(stream);
   const int n = tab->n;
   int groups = ctx->force_groups > 0 ? std::min(ctx->force_groups, L) : restart_groups(tab, dtype, L);
-  if (!plain && ctx->force_groups == 0 && ctx->tune_mode != 0 && !needs_power_split(tab, dtype) && L >= 2) {
+  if (!plain && ctx->force_groups == 0 && ctx->tune_mode != 0 && L >= 2) {
     // Restart groups: each candidate times a one-component decomposition of
     // the same sizes on a copy of the sketch (the choice does not change the
     // arithmetic of any restart).
