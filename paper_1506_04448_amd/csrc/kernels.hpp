@@ -992,6 +992,28 @@ __global__ __launch_bounds__(threads_for_h<double>(LOGB - 1)) void k_rank1(Rank1
   }
 }
 
+// Deflation by one component: lam = the median over the B per-sketch values
+// lam_per[0..B-1] (every wave forms it, as k_median_scalar does; B <= 64),
+// written to *lam_out by the first thread; S64[m][k] -= lam prod[m][k],
+// S32 = (float)S64.  Whole waves only (blockDim a multiple of 64).
+__global__ void k_spec_deflate(cx<double>* S64, cx<float>* S32, const cx<double>* prod, const double* lam_per,
+                               int B, int H1, double* lam_out) {
+  const int lane = threadIdx.x & 63;
+  const double med = wave_median<double>(lane < B ? lam_per[lane] : 0.0, B);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *lam_out = med;
+  const double cf = -1.0 * med;
+  const size_t total = (size_t)B * H1;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    cx<double> s = S64[e];
+    const cx<double> p = prod[e];
+    s.x += cf * p.x;
+    s.y += cf * p.y;
+    S64[e] = s;
+    if (S32) S32[e] = cx<float>{(float)s.x, (float)s.y};
+  }
+}
+
 // S64[m][k] += sum_r coef_r prod[r][m][k]; S32 = (float)S64; coef_r = sign * lam[r].
 __global__ void k_spec_update(cx<double>* S64, cx<float>* S32, const cx<double>* prod,
                               const double* lam, double sign, int c, int B, int H1) {

@@ -1867,6 +1867,7 @@ extern "C" tsk_status tsk_cp_loss(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype dty
 namespace {
 
 struct DecompWs {
+  void* U0r;      // R[k][L][n] the start vectors in the power steps' precision
   void* U0;       // R[L][n]
   void* U1;       // R[L][n]
   void* V0;       // R[L][B][n]
@@ -1888,19 +1889,19 @@ struct DecompWs {
 // buffer holding u_T.
 template <typename R>
 tsk_status power_chain(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, int nrest, int tau0, int T,
-                       R* const Ub[2], R* const Vb[2], double* lam_per, int32_t* fl, R** u_final,
-                       hipStream_t st, const SplitBufs* sb) {
-  TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 0, 0, Ub[0], nullptr, nullptr, nullptr, Vb[0],
+                       const R* u_start, R* const Ub[2], R* const Vb[2], double* lam_per, int32_t* fl,
+                       R** u_final, hipStream_t st, const SplitBufs* sb) {
+  TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 0, 0, u_start, nullptr, nullptr, nullptr, Vb[0],
                           nullptr, st, 0, sb));
-  int cu = 0, cv = 0;
+  const R* uprev = u_start;  // the fallback of a step whose median is unusable
   for (int t = 1; t <= T; ++t) {
     const int mode = (t == T) ? 1 : 0;
-    TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 1, mode, Ub[cu], Vb[cv], Ub[cu ^ 1], fl,
-                            Vb[cv ^ 1], mode ? lam_per : nullptr, st, 0, sb));
-    cu ^= 1;
-    cv ^= 1;
+    R* ucur = Ub[t & 1];
+    TSK_TRY(power_launch<R>(ctx, tab, spec, nrest, tau0, 1, mode, uprev, Vb[(t - 1) & 1], ucur, fl,
+                            Vb[t & 1], mode ? lam_per : nullptr, st, 0, sb));
+    uprev = ucur;
   }
-  *u_final = Ub[cu];
+  *u_final = Ub[T & 1];
   return TSK_OK;
 }
 
@@ -1915,11 +1916,15 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
   if (tab->logb <= kLdsLogB) TSK_TRY(get_tw<double>(ctx, tab->logb, &tw64));
   R* const Ub[2] = {reinterpret_cast<R*>(w.U0), reinterpret_cast<R*>(w.U1)};
   R* const Vb[2] = {reinterpret_cast<R*>(w.V0), reinterpret_cast<R*>(w.V1)};
+  // The start vectors of every component in the power steps' precision, in
+  // one launch ahead of the component loop (off the chain of dependent steps).
+  const size_t LN = (size_t)L * n;
+  R* const U0r = reinterpret_cast<R*>(w.U0r);
+  hipLaunchKernelGGL(tsk::k_cvt<R>, dim3(grid_for((size_t)k * LN, 256)), dim3(256), 0, st, u0, U0r,
+                     (size_t)k * LN);
+  TSK_TRY(check_launch("k_cvt"));
   for (int c = 0; c < k; ++c) {
-    const size_t LN = (size_t)L * n;
-    hipLaunchKernelGGL(tsk::k_cvt<R>, dim3(grid_for(LN, 256)), dim3(256), 0, st,
-                       u0 + (size_t)c * LN, Ub[0], LN);
-    TSK_TRY(check_launch("k_cvt"));
+    const R* us = U0r + (size_t)c * LN;
     int32_t* fl = flags + (size_t)c * L;
     R* ufin = nullptr;
     if (!plain && groups > 1) {
@@ -1931,15 +1936,15 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
         const int t0 = (int)((long)L * g / groups), t1 = (int)((long)L * (g + 1) / groups);
         hipStream_t s = ctx->gfork[g];
         TSK_HIP(hipStreamWaitEvent(s, ctx->gfork_ev[groups], 0));
-        TSK_TRY(power_chain<R>(ctx, tab, spec, t1 - t0, t0, T, Ub, Vb, w.lam_per, fl, &ufin, s, &w.sb));
+        TSK_TRY(power_chain<R>(ctx, tab, spec, t1 - t0, t0, T, us, Ub, Vb, w.lam_per, fl, &ufin, s, &w.sb));
         TSK_HIP(hipEventRecord(ctx->gfork_ev[g], s));
         TSK_HIP(hipStreamWaitEvent(st, ctx->gfork_ev[g], 0));
       }
     } else if (!plain) {
-      TSK_TRY(power_chain<R>(ctx, tab, spec, L, 0, T, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
+      TSK_TRY(power_chain<R>(ctx, tab, spec, L, 0, T, us, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
     } else {
       for (int tau = 0; tau < L; ++tau)
-        TSK_TRY(power_chain<R>(ctx, tab, spec, 1, tau, T, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
+        TSK_TRY(power_chain<R>(ctx, tab, spec, 1, tau, T, us, Ub, Vb, w.lam_per, fl, &ufin, st, &w.sb));
     }
     TSK_TRY(lam_median_launch(w.lam_per, w.lam_med, L, B, st));
     hipLaunchKernelGGL(tsk::k_select<R>, dim3(1), dim3(256), 0, st, (const double*)w.lam_med, L,
@@ -1958,13 +1963,10 @@ tsk_status decompose_enqueue(tsk_ctx_t ctx, tsk_tables_t tab, const void* spec, 
     a.S64 = reinterpret_cast<const cx<double>*>(S64);
     a.lam_per = w.lam64;
     TSK_TRY(launch_rank1_any(ctx, tab, a, 1, w.esplit, st));
-    hipLaunchKernelGGL(tsk::k_median_scalar, dim3(1), dim3(64), 0, st, (const double*)w.lam64, B,
-                       lam_out + c);
-    TSK_TRY(check_launch("k_median_scalar"));
-    hipLaunchKernelGGL(tsk::k_spec_update, dim3(grid_for((size_t)B * H1, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(tsk::k_spec_deflate, dim3(grid_for((size_t)B * H1, 256)), dim3(256), 0, st,
                        reinterpret_cast<cx<double>*>(S64), reinterpret_cast<cx<float>*>(S32),
-                       (const cx<double>*)w.prod, (const double*)(lam_out + c), -1.0, 1, B, H1);
-    TSK_TRY(check_launch("k_spec_update"));
+                       (const cx<double>*)w.prod, (const double*)w.lam64, B, H1, lam_out + c);
+    TSK_TRY(check_launch("k_spec_deflate"));
   }
   return TSK_OK;
 }
@@ -2000,6 +2002,7 @@ size_t decomp_ws_layout(char* base, tsk_tables_t tab, tsk_dtype dtype, int k, in
     return p;
   };
   DecompWs d;
+  d.U0r = take((size_t)k * L * n * es);
   d.U0 = take(L * n * es);
   d.U1 = take(L * n * es);
   d.V0 = take(L * B * n * es);
