@@ -72,10 +72,11 @@ void tsk_destroy(tsk_ctx_t ctx);
  * default) or from a tuner the library runs on the caller's own data: the
  * dense build's sketches per work-group and slab count (how the buckets are
  * privatised in LDS and how the tensor is split), and the number of restart
- * groups a decomposition runs on parallel graph branches (not at b = 65536 in
- * FP32).  Mode 1: the first call of an uncached shape times every candidate
- * (blocking on its stream; a decomposition times one-component runs on a copy
- * of the sketch), keeps the fastest, and records it; mode 2: cached choices
+ * groups a decomposition runs on parallel graph branches.  Mode 1: the first
+ * call of an uncached shape times every candidate twice (blocking on its
+ * stream; a decomposition times one-component runs on a copy of the sketch),
+ * keeps the rule's shape unless another is faster by more than 3%, and
+ * records the choice; mode 2: cached choices
  * only, the rules elsewhere.  cache_path (host, nullable) names a text file,
  * read now and rewritten after each new choice: one line per shape, the key
  * (entry point, device name and CU count, precision, sizes) and the chosen

@@ -704,16 +704,20 @@ tsk_status tune_choose(tsk_ctx_t ctx, const std::string& key, const std::vector<
   if (ctx->tune_mode == 0) return TSK_OK;
   auto it = ctx->tune.find(key);
   if (it == ctx->tune.end() && ctx->tune_mode == 1 && !cands.empty()) {
-    float best = 0.0f;
-    size_t bi = 0;
-    for (size_t i = 0; i < cands.size(); ++i) {
-      float ms = 0.0f;
-      TSK_TRY(time_one(cands[i], &ms));
-      if (i == 0 || ms < best) {
-        best = ms;
-        bi = i;
+    // Two passes over the candidates, each keeping its faster time (drift
+    // between candidates averages out); cands[0] is the rule, and another
+    // candidate replaces it only when faster by more than 3% (timing noise
+    // of a few per cent must not move the choice off the rule).
+    std::vector<float> t(cands.size(), 0.0f);
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t i = 0; i < cands.size(); ++i) {
+        float ms = 0.0f;
+        TSK_TRY(time_one(cands[i], &ms));
+        t[i] = pass == 0 ? ms : std::min(t[i], ms);
       }
-    }
+    size_t bi = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+      if (t[i] < 0.97f * t[0] && t[i] < t[bi]) bi = i;
     it = ctx->tune.emplace(key, encode(cands[bi])).first;
     TSK_TRY(tune_save(ctx));
   }
@@ -2131,8 +2135,9 @@ extern "C" tsk_status tsk_decompose(tsk_ctx_t ctx, tsk_tables_t tab, tsk_dtype d
     // the same sizes on a copy of the sketch (the choice does not change the
     // arithmetic of any restart).
     const std::string key = tune_key(ctx, "decompose", dtype, {n, tab->b, tab->B, L, T});
-    std::vector<int> cands;
-    for (int g = 1; g <= std::min(4, L); ++g) cands.push_back(g);
+    std::vector<int> cands = {groups};  // the rule first
+    for (int g = 1; g <= std::min(4, L); ++g)
+      if (g != groups) cands.push_back(g);
     const size_t H1 = (size_t)tab->b / 2 + 1;
     const size_t b64 = ((size_t)tab->B * H1 * 16 + 255) & ~(size_t)255;
     const size_t b32 = ((size_t)tab->B * H1 * 8 + 255) & ~(size_t)255;
