@@ -228,6 +228,25 @@ def test_large_decompose_fp32_matches_oracle(ctx, B):
     assert oracle.wrong_vectors(P.V, U) == 0
 
 
+def test_split_step_single_sketch_single_vector(ctx):
+    """The smallest split-step launch (b = 65536, B = 1, L = 1, n = 5): one
+    work-group, the median of one estimate, against the oracle."""
+    n, b = 5, 65536
+    rng = np.random.default_rng(23)
+    h, xi = tsk.hash_generate(23, n, b, 1)
+    tab = tsk.Tables(ctx, h, xi, b)
+    S_time = rng.standard_normal((1, b))
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_from_time(ctx, torch.from_numpy(S_time).to(DEV), S64, S32)
+    U = rng.standard_normal((1, n))
+    U /= np.linalg.norm(U)
+    Uf = U.astype(np.float32).astype(np.float64)
+    got = tsk.power_update(ctx, tab, torch.from_numpy(U.astype(np.float32)).to(DEV), S32=S32).cpu().numpy()
+    _, Unew, _ = oracle.power_update(S_time, h, xi, Uf)
+    assert rel(got, Unew) < 1e-5
+    tab.close()
+
+
 def test_large_decompose_with_u_beyond_lds(ctx):
     """n = 6000: u no longer fits the LDS beside the split kernel's buffer, so
     the count sketches read it from global memory and the median of each step

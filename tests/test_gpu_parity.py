@@ -568,6 +568,27 @@ def test_median_normalize_matches_oracle(ctx, B, dtype):
                 np.testing.assert_array_equal(out[tau], U_in[tau])
 
 
+@pytest.mark.parametrize("B", [1, 64])
+def test_decompose_at_one_and_the_most_sketches(ctx, B):
+    """B = 1 (the median is the single estimate) and B = 64 (the most a table
+    set holds: every lane of a wave carries a value in the medians of the
+    selection and deflation): the whole of Algorithm 1 in FP64 against the
+    oracle."""
+    print(f"decompose B={B}", flush=True)
+    n, k, b, L, T = 30, 2, 512, 3, 4
+    P = planted_tensor(n, 2, noise=0.01, seed=13)
+    tab, h, xi = _tables(ctx, 14, n, b, B)
+    S64, S32 = tsk.new_sketch(tab, DEV)
+    tsk.sketch_build_dense(ctx, tab, torch.from_numpy(P.T).to(DEV), S64, S32)
+    u0 = np.stack([oracle.start_vectors_spec(5, c, L, n) for c in range(k)])
+    lam, U, tau, flags = tsk.decompose(ctx, tab, S64, S32, k, L, T, dtype=tsk.F64,
+                                       u0=torch.from_numpy(u0).to(DEV))
+    ref = oracle.rtpm_sketched(_oracle_sketches(P.T, h, xi, b), h, xi, k, L, T, u0)
+    assert rel(lam.cpu().numpy(), ref.lam) < 1e-12
+    assert rel(U.cpu().numpy(), ref.U) < 1e-12
+    np.testing.assert_array_equal(tau.cpu().numpy(), ref.tau)
+
+
 @pytest.mark.parametrize("B,dtype,T,tol", [(20, tsk.F64, 6, 1e-12), (40, tsk.F32, 25, 1e-5)])
 def test_decompose_with_separate_median_launch(ctx, B, dtype, T, tol):
     """B > 16: the median of each step is a launch of its own inside the graph
