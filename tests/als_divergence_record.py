@@ -7,8 +7,8 @@ the sketches, exports them in FP64 and runs its FP32 ALS for T = 1 .. 30
 sweeps; the oracle then runs its FP64 ALS from the same start factors on the
 same exported sketches.  Both lambda sequences are printed sweep by sweep.
 
-  python tests/als_divergence_record.py gpu gpurun_out/als_cell.npz     (GPU machine)
-  python tests/als_divergence_record.py oracle gpurun_out/als_cell.npz  (CPU)
+  python tests/als_divergence_record.py gpu /tmp/als_cell.npz     (on the GPU)
+  python tests/als_divergence_record.py oracle /tmp/als_cell.npz  (CPU, the file the first run wrote)
 """
 import os
 import sys
