@@ -1978,6 +1978,8 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
   constexpr int PL = padded_len(H);
   constexpr int PK = (H / 2 + NT - 1) / NT;
   constexpr int PKP = (PK + NPART - 1) / NPART;
+  // every slot of every round is a valid bin pair when the pairs split evenly
+  constexpr bool ALL = (H / 2) % NT == 0 && PK % NPART == 0;
   // With a last pass of radix 2 the transforms stop before it and the bins
   // are formed from its inputs: Z[k] = A[k] + W_H^k A[k + H/2] and, for
   // j = H/2 - k, Z[H-k] = A[j] + conj(W_H^k) A[j + H/2], W_H^k = (W_b^k)^2.
@@ -2015,10 +2017,9 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
     __syncthreads();
     fft_soa<R, LOGH, NT, false, false, FUSE>(buf, tw);
   };
-  // Z[k] and Z[H-k] for 0 <= k < H/2 (Z[H] = Z[0]), and Z[H/2]
-  auto zpair = [&](int k, cx<R>& Za, cx<R>& Zb) {
+  // Z[k] and Z[H-k] for 0 <= k < H/2 (Z[H] = Z[0]), and Z[H/2]; w = W_b^k
+  auto zpair = [&](int k, cx<R> w, cx<R>& Za, cx<R>& Zb) {
     if constexpr (FUSE) {
-      const cx<R> w = tw.w(k);
       const cx<R> wH = cmul(w, w);
       Za = cadd(buf.get(k), cmul(wH, buf.get(k + H / 2)));
       Zb = k == 0 ? Za : cadd(buf.get(H / 2 - k), cmulc(buf.get(H - k), wH));
@@ -2038,61 +2039,93 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
     acc.x += c * (double)v.x;
     acc.y += c * (double)v.y;
   };
+  // Spectra of the transform in the buffer at the owned bins: X[k] and X[H-k]
+  // (W_b^{H-k} = -conj W_b^k, since W_b^H = -1), and X[H/2] on thread 0.
+  auto spectra = [&](int part, const cx<R>* w, cx<R>* X0, cx<R>* X1, cx<R>& Xm) {
+#pragma unroll
+    for (int s = 0; s < PKP; ++s) {
+      const int k = bin_k(part, s);
+      if (!ALL && k >= H / 2) break;
+      cx<R> Za, Zb;
+      zpair(k, w[s], Za, Zb);
+      X0[s] = r2c_post(Za, Zb, w[s]);
+      X1[s] = r2c_post(Zb, Za, cx<R>{-w[s].x, w[s].y});
+    }
+    if (tid == 0 && part == 0) {
+      const cx<R> Z = zmid();
+      Xm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
+    }
+  };
+  // prefetch of the next item's vector and weights (threads e < n, e < NT)
+  auto load_item = [&](int it, R& x, R& y, double& al, double& be) {
+    if (it < i1) {
+      if (tid < n) {
+        x = X[(size_t)it * n + tid];
+        if (HAS_Y) y = Y[(size_t)it * n + tid];
+      }
+      al = a.sa * a.arrA[it];
+      be = a.sb * a.arrB[it];
+    }
+  };
 #pragma unroll 1
   for (int part = 0; part < NPART; ++part) {
     cx<double> acc0[PKP], acc1[PKP], accm = {0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < PKP; ++s) acc0[s] = acc1[s] = cx<double>{0.0, 0.0};
+    cx<R> wv[PKP];  // W_b^k of the owned bins, the same for every item and mode
+#pragma unroll
+    for (int s = 0; s < PKP; ++s) {
+      const int k = bin_k(part, s);
+      if (!ALL && k >= H / 2) break;
+      wv[s] = tw.w(k);
+    }
+    R xn = R(0), yn = R(0);
+    double alpha_n = 0.0, beta_n = 0.0;
+    load_item(i0, xn, yn, alpha_n, beta_n);
 #pragma unroll 1
     for (int it = i0; it < i1; ++it) {
-      const double alpha = a.sa * a.arrA[it];
-      const double beta = a.sb * a.arrB[it];
-      if (alpha == 0.0 && beta == 0.0) continue;  // uniform: an empty word or a dropped document
+      const double alpha = alpha_n, beta = beta_n;
       __syncthreads();  // the previous item's readers of xv / yv are done
-      for (int e = tid; e < n; e += NT) {
+      if (tid < n) {
+        xv[tid] = xn;
+        if (HAS_Y) yv[tid] = yn;
+      }
+      for (int e = tid + NT; e < n; e += NT) {
         xv[e] = X[(size_t)it * n + e];
         if (HAS_Y) yv[e] = Y[(size_t)it * n + e];
       }
+      load_item(it + 1, xn, yn, alpha_n, beta_n);
+      if (alpha == 0.0 && beta == 0.0) continue;  // uniform: an empty word or a dropped document
       cx<R> P0[PKP], P1[PKP], S0[PKP], S1[PKP], D0[PKP], D1[PKP], Pm, Sm, Dm;
-#pragma unroll 1
-      for (int j = 0; j < 3; ++j) {
+      // One mode: F_j x (and F_j y) at the owned bins, then the product rule.
+      auto mode = [&](int j, auto first) {
+        constexpr bool FIRST = decltype(first)::value;
+        const cx<R>* Qj = Q + (size_t)j * (H + 1);
         fft_mode(xv, j);
-        cx<R> F0[PKP], F1[PKP], Fm;
-#pragma unroll
-        for (int s = 0; s < PKP; ++s) {
-          const int k = bin_k(part, s);
-          if (k >= H / 2) break;
-          cx<R> Za, Zb;
-          zpair(k, Za, Zb);
-          F0[s] = r2c_post(Za, Zb, tw.w(k));
-          F1[s] = r2c_post(Zb, Za, tw.w(H - k));
-        }
-        if (tid == 0 && part == 0) {
-          const cx<R> Z = zmid();
-          Fm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
-        }
-        __syncthreads();
-        cx<R> G0[PKP], G1[PKP], Gm;  // F_j y
-        if constexpr (HAS_Y) {
-          fft_mode(yv, j);
+        cx<R> qa[PKP], qb[PKP], qm = {R(0), R(0)};
+        auto load_q = [&]() {
 #pragma unroll
           for (int s = 0; s < PKP; ++s) {
             const int k = bin_k(part, s);
-            if (k >= H / 2) break;
-            cx<R> Za, Zb;
-            zpair(k, Za, Zb);
-            G0[s] = r2c_post(Za, Zb, tw.w(k));
-            G1[s] = r2c_post(Zb, Za, tw.w(H - k));
+            if (!ALL && k >= H / 2) break;
+            qa[s] = Qj[k];
+            qb[s] = Qj[H - k];
           }
-          if (tid == 0 && part == 0) {
-            const cx<R> Z = zmid();
-            Gm = r2c_post(Z, Z, cx<R>{R(0), R(-1)});
-          }
+          if (tid == 0 && part == 0) qm = Qj[H / 2];
+        };
+        if (!HAS_Y) load_q();  // in flight while the spectra are formed
+        cx<R> F0[PKP], F1[PKP], Fm = {R(0), R(0)};
+        spectra(part, wv, F0, F1, Fm);
+        __syncthreads();
+        cx<R> G0[PKP], G1[PKP], Gm = {R(0), R(0)};  // F_j y
+        if constexpr (HAS_Y) {
+          fft_mode(yv, j);
+          load_q();
+          spectra(part, wv, G0, G1, Gm);
           __syncthreads();
         }
-        const cx<R>* Qj = Q + (size_t)j * (H + 1);
         auto step = [&](cx<R>& P, cx<R>& S, cx<R>& Dy, cx<R> F, cx<R> G, cx<R> q) {
-          if (j == 0) {
+          if constexpr (FIRST) {
             if (HAS_Y) Dy = G;
             S = q;
             P = F;
@@ -2105,17 +2138,20 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
 #pragma unroll
         for (int s = 0; s < PKP; ++s) {
           const int k = bin_k(part, s);
-          if (k >= H / 2) break;
-          step(P0[s], S0[s], D0[s], F0[s], HAS_Y ? G0[s] : F0[s], Qj[k]);
-          step(P1[s], S1[s], D1[s], F1[s], HAS_Y ? G1[s] : F1[s], Qj[H - k]);
+          if (!ALL && k >= H / 2) break;
+          step(P0[s], S0[s], D0[s], F0[s], HAS_Y ? G0[s] : F0[s], qa[s]);
+          step(P1[s], S1[s], D1[s], F1[s], HAS_Y ? G1[s] : F1[s], qb[s]);
         }
-        if (tid == 0 && part == 0) step(Pm, Sm, Dm, Fm, HAS_Y ? Gm : Fm, Qj[H / 2]);
-      }
+        if (tid == 0 && part == 0) step(Pm, Sm, Dm, Fm, HAS_Y ? Gm : Fm, qm);
+      };
+      mode(0, std::true_type{});
+#pragma unroll 1
+      for (int j = 1; j < 3; ++j) mode(j, std::false_type{});
       const double gam = a.gam;
 #pragma unroll
       for (int s = 0; s < PKP; ++s) {
         const int k = bin_k(part, s);
-        if (k >= H / 2) break;
+        if (!ALL && k >= H / 2) break;
         addc(acc0[s], alpha, P0[s]);
         addc(acc0[s], beta, S0[s]);
         addc(acc1[s], alpha, P1[s]);
@@ -2134,7 +2170,7 @@ __global__ __launch_bounds__(threads_for_h<R>(LOGB - 1)) void k_terms(TermArgs a
 #pragma unroll
     for (int s = 0; s < PKP; ++s) {
       const int k = bin_k(part, s);
-      if (k >= H / 2) break;
+      if (!ALL && k >= H / 2) break;
       out[k] = acc0[s];
       out[H - k] = acc1[s];  // k = 0 pairs with the Nyquist bin H
     }
