@@ -85,6 +85,17 @@ void tsk_destroy(tsk_ctx_t ctx);
  * (null context, mode). */
 tsk_status tsk_tune_config(tsk_ctx_t ctx, int mode, const char* cache_path);
 
+/* Route of the document build (tsk_sketch_build_docs).  Route 1: the
+ * per-document transforms of Section 3.2 (three real b-point transforms per
+ * document and sketch, six per word).  Route 2: the whitened moment M3(W,W,W)
+ * formed as a K^3 FP64 tensor on the matrix cores (about D K^3 / 2
+ * multiply-adds over the documents, the same per word), then sketched by
+ * Eq. (1) as a dense tensor.  Route 0 (the default) takes the one a cost rule
+ * estimates faster: route 2 whenever K^3 is small against B b log2 b.  Both
+ * give the same sketch up to rounding.  Errors: TSK_EINVAL (null context,
+ * route outside {0, 1, 2}). */
+tsk_status tsk_docs_route(tsk_ctx_t ctx, int route);
+
 /* ---- Randomness (host only, no device work) ------------------------------
  * Hash and sign tables h_j^(m): [n] -> [b], xi_j^(m): [n] -> {+1,-1} for
  * sketch m < B and mode j in {0,1,2} (Algorithm 1, initialisation; the tensor
@@ -144,8 +155,8 @@ tsk_status tsk_sketch_build_factors(tsk_ctx_t ctx, tsk_tables_t tab, const doubl
                                     int accumulate, void* stream);
 
 /* Document build (Appendix D): the B sketches of the whitened third-order
- * moment of spectral LDA, M3(W, W, W), from word counts, without forming any
- * K^3 or V^3 tensor.  With n the counts of a document of length m >= 3 (shorter
+ * moment of spectral LDA, M3(W, W, W), from word counts, never forming a
+ * V^3 tensor.  With n the counts of a document of length m >= 3 (shorter
  * documents are dropped), p = W^T n, w_i the i-th row of W, q = W^T M1 (M1
  * the mean of n / m over the kept documents, D of them), a = alpha0/(alpha0+2),
  * c = 2 alpha0^2 / ((alpha0+1)(alpha0+2)):
@@ -154,18 +165,20 @@ tsk_status tsk_sketch_build_factors(tsk_ctx_t ctx, tsk_tables_t tab, const doubl
  *                      - a (p p^T - sum_i n_i w_i w_i^T) / (m (m-1)) (x) q  (and its two
  *                        mode permutations) ] + c q^(x)3,
  * the per-document terms by Eq. (td) and the moment combination of
- * Eq. (moment3).  Each document costs three transforms per sketch; the terms
- * in w_i are gathered per word first (sums over the documents holding it)
- * and cost six per word.  Every rank-1 term is sketched by Eq. (2).
+ * Eq. (moment3).  The terms in w_i are gathered per word first (sums over the
+ * documents holding it).  Two routes (tsk_docs_route): every rank-1 term
+ * sketched by Eq. (2), three transforms per document and sketch and six per
+ * word (Section 3.2); or the K^3 tensor formed in FP64 on the matrix cores
+ * and sketched by Eq. (1).
  *   rowptr: int32[D+1], col: int32[nnz] word ids in [0, V) (unique within a
  *   document), cnt: int32[nnz] counts >= 1 -- CSR, device.
  *   W: [V][K] in wdtype (TSK_F32 or TSK_F64; the projections p = W^T n, on
  *   the matrix cores, and the transforms run in that precision, the sums over
- *   documents in FP64), K = the tables' n.
+ *   documents and the moment tensor in FP64), K = the tables' n.
  *   accumulate != 0 adds to S64.  The call reads rowptr[D] back to the host.
  * Errors: TSK_EINVAL (null, D < 1, V < 1, alpha0 < 0 or not finite, dtype),
- * TSK_EUNSUPPORTED (K above 128, or too large for one work-group's LDS at
- * this b). */
+ * TSK_EUNSUPPORTED (K above 128, or, on the transform route, too large for
+ * one work-group's LDS at this b). */
 tsk_status tsk_sketch_build_docs(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowptr,
                                  const int32_t* col, const int32_t* cnt, int D, int V,
                                  const void* W, tsk_dtype wdtype, double alpha0, double* S64,

@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "TskError", "lib", "library_path", "Context", "Tables", "hash_generate", "init_vectors",
     "new_sketch", "sketch_build_dense", "sketch_build_factors", "sketch_from_time",
-    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "tune_config", "lda_heldout", "contract_tiuu",
+    "sketch_export", "sketch_deflate", "power_update", "power_update_noalloc", "tune_config", "docs_route", "lda_heldout", "contract_tiuu",
     "contract_uuu",
     "decompose", "contract_tuuu_grad", "cp_loss", "Problem", "decompose_batched",
     "workspace_size", "sketch_build_docs",
@@ -63,6 +63,7 @@ _SIGS = {
     "tsk_power_update": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], _I),
     "tsk_power_update_noalloc": ([_P, _P, _I, _P, _P, _I, _P, _P, _P, _P], _I),
     "tsk_tune_config": ([_P, _I, ctypes.c_char_p], _I),
+    "tsk_docs_route": ([_P, _I], _I),
     "tsk_lda_heldout": ([_P, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P], _I),
     "tsk_median_normalize": ([_P, _I, _I, _I, _I, _P, _P, _P, _P, _P], _I),
     "tsk_contract_two": ([_P, _P, _I, _P, _P, _I, _I, _P, _P, _P, _P], _I),
@@ -456,6 +457,12 @@ def tune_config(ctx, mode, cache_path=None):
     written to."""
     path = None if cache_path is None else os.fsencode(cache_path)
     _check("tsk_tune_config", lib().tsk_tune_config(ctx.handle, int(mode), path))
+
+
+def docs_route(ctx, route):
+    """Route of ``sketch_build_docs`` on this context: 0 a cost rule, 1 the
+    per-document transforms, 2 the moment tensor on the matrix cores."""
+    _check("tsk_docs_route", lib().tsk_docs_route(ctx.handle, int(route)))
 
 
 def power_update_noalloc(ctx, tab, U_in, U_out, S64=None, S32=None, flags=None, stream=None):

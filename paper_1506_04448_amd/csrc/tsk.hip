@@ -21,6 +21,7 @@
 #include "large.hpp"
 #include "symmetric.hpp"
 #include "spectral.hpp"
+#include "moment.hpp"
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include "status.hpp"
@@ -109,6 +110,7 @@ struct tsk_ctx {
   std::map<std::string, std::vector<int>> tune;
   std::string tune_dev;
   int force_groups = 0;
+  int docs_route = 0;  // tsk_docs_route: 0 rule, 1 transforms, 2 moment tensor
 };
 
 struct tsk_tables {
@@ -789,6 +791,13 @@ extern "C" tsk_status tsk_tune_config(tsk_ctx_t ctx, int mode, const char* cache
   ctx->tune_path = cache_path ? cache_path : "";
   ctx->tune.clear();
   if (!ctx->tune_path.empty()) tune_load(ctx);
+  return TSK_OK;
+}
+
+extern "C" tsk_status tsk_docs_route(tsk_ctx_t ctx, int route) {
+  if (!ctx) return tsk::fail(TSK_EINVAL, "tsk_docs_route: null context");
+  if (route < 0 || route > 2) return tsk::fail(TSK_EINVAL, "tsk_docs_route: route %d not in {0, 1, 2}", route);
+  ctx->docs_route = route;
   return TSK_OK;
 }
 
@@ -1601,6 +1610,91 @@ tsk_status launch_mode_spectra(int logb, tsk_tables_t tab, const double* q, cons
   return tsk::fail(TSK_EUNSUPPORTED, "document sketch: b=2^%d not built", logb);
 }
 
+// Shapes of the moment route's products: the pair rows padded to whole
+// work-group blocks, the column groups, and the item chunks that fill two
+// work-groups per CU.
+struct MomentShape {
+  int np = 0, rows = 0, nrb = 0;
+  int ncg_d = 0, ld_d = 0, nch_d = 0, per_d = 0;
+  int ncg_w = 0, ld_w = 0, nch_w = 0, per_w = 0;
+  size_t part_bytes_d = 0, part_bytes_w = 0;
+};
+
+MomentShape moment_shape(int K, int D, int V) {
+  MomentShape m;
+  m.np = K * (K + 1) / 2;
+  m.nrb = (m.np + tsk::kMomRows - 1) / tsk::kMomRows;
+  m.rows = m.nrb * tsk::kMomRows;
+  auto cols = [&](int ncol, int nitem, int& ncg, int& ld, int& nch, int& per) {
+    ncg = (ncol + tsk::kMomCols - 1) / tsk::kMomCols;
+    ld = ncg * tsk::kMomCols;
+    const int wgs = m.nrb * ncg;
+    nch = std::max(1, std::min(64, 512 / wgs));
+    nch = std::max(1, std::min(nch, (nitem + 63) / 64));  // at least 64 items per chunk
+    per = (nitem + nch - 1) / nch;
+    per = (per + 3) & ~3;
+    nch = std::max(1, (nitem + per - 1) / per);
+  };
+  cols(K + 1, D, m.ncg_d, m.ld_d, m.nch_d, m.per_d);
+  cols(2 * K + 1, V, m.ncg_w, m.ld_w, m.nch_w, m.per_w);
+  m.part_bytes_d = (size_t)m.nch_d * m.rows * m.ld_d * sizeof(double);
+  m.part_bytes_w = (size_t)m.nch_w * m.rows * m.ld_w * sizeof(double);
+  return m;
+}
+
+// Route of the document build: the moment tensor when its matrix-core work
+// (FP64, about 40 TFLOP/s sustained) is estimated below the per-document
+// transforms (2.5 b log2 b flops per real transform, about 16 TFLOP/s in FP32
+// and 6 in FP64 on the vector units); tsk_docs_route overrides the rule.
+bool docs_use_moment(const tsk_ctx* ctx, int K, int B, int b, int D, int V, bool fp64) {
+  if (ctx->docs_route == 1) return false;
+  if (ctx->docs_route == 2) return true;
+  const MomentShape m = moment_shape(K, D, V);
+  const double mflop = 2.0 * m.rows * ((double)m.ld_d * D + (double)m.ld_w * V);
+  const double tflop = (3.0 * D + 6.0 * V) * B * 2.5 * b * std::log2((double)b);
+  return mflop / 40e12 < tflop / (fp64 ? 6e12 : 16e12);
+}
+
+// One product of the moment route (documents, or words with HAS_Y) and the
+// sum of its chunks into C [np][ncol].
+template <typename R, bool HAS_Y>
+tsk_status launch_moment(const MomentShape& ms, const R* X, const R* Y, const double* cA, const double* cB,
+                         double sa, double sb, double gam, int K, int nitem, double* part, double* C,
+                         hipStream_t st) {
+  tsk::MomentArgs m;
+  m.X = X;
+  m.Y = Y;
+  m.cA = cA;
+  m.cB = cB;
+  m.sa = sa;
+  m.sb = sb;
+  m.gam = gam;
+  m.K = K;
+  m.nitem = nitem;
+  m.per = HAS_Y ? ms.per_w : ms.per_d;
+  m.np = ms.np;
+  m.ncol = HAS_Y ? 2 * K + 1 : K + 1;
+  m.rows = ms.rows;
+  m.ld = HAS_Y ? ms.ld_w : ms.ld_d;
+  m.part = part;
+  const int ncg = HAS_Y ? ms.ncg_w : ms.ncg_d, nch = HAS_Y ? ms.nch_w : ms.nch_d;
+  const size_t lds = tsk::moment_lds_bytes(K);
+  static std::atomic<uint64_t> configured{0};
+  int dev = 0;
+  TSK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = 1ull << (dev & 63);
+  if (!(configured.load() & bit)) {
+    TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_moment3<R, HAS_Y>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsk::moment_lds_bytes(128)));
+    configured.fetch_or(bit);
+  }
+  hipLaunchKernelGGL((tsk::k_moment3<R, HAS_Y>), dim3(ms.nrb * ncg, nch), dim3(256), lds, st, m);
+  TSK_TRY(check_launch("k_moment3"));
+  hipLaunchKernelGGL(tsk::k_moment_reduce, dim3(grid_for((size_t)ms.np * m.ncol, 256)), dim3(256), 0, st,
+                     (const double*)part, nch, ms.rows, m.ld, ms.np, m.ncol, C);
+  return check_launch("k_moment_reduce");
+}
+
 template <typename R>
 tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowptr, const int32_t* col,
                            const int32_t* cnt, int D, int V, int nnz, const R* W, double alpha0,
@@ -1639,9 +1733,16 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   take((size_t)V * K * sizeof(R));              // 13 R_i
   take((size_t)V * 8);                          // 14 g
   take((size_t)V * 8);                          // 15 g'
-  take((size_t)B * 3 * H1 * sizeof(cx<R>));     // 16 Q spectra
-  take((size_t)B * ncD * H1 * 16);              // 17 document partials
-  take((size_t)B * ncW * H1 * 16);              // 18 word partials
+  const bool moment = docs_use_moment(ctx, K, B, b, D, V, sizeof(R) == 8);
+  const MomentShape ms = moment_shape(K, D, V);
+  take(moment ? 0 : (size_t)B * 3 * H1 * sizeof(cx<R>));   // 16 Q spectra
+  take(moment ? 0 : (size_t)B * ncD * H1 * 16);            // 17 document partials
+  take(moment ? 0 : (size_t)B * ncW * H1 * 16);            // 18 word partials
+  take(moment ? ms.part_bytes_d : 0);                       // 19 document products per chunk
+  take(moment ? ms.part_bytes_w : 0);                       // 20 word products per chunk
+  take(moment ? (size_t)ms.np * (K + 1) * 8 : 0);           // 21 Cd
+  take(moment ? (size_t)ms.np * (2 * K + 1) * 8 : 0);       // 22 Cw
+  take(moment ? (size_t)K * K * K * 8 : 0);                 // 23 the K^3 tensor
   void* base = nullptr;
   TSK_TRY(ws_get(ctx, WS_DOCS, off, &base));
   auto at = [&](int i) { return reinterpret_cast<char*>(base) + offs[i]; };
@@ -1687,9 +1788,21 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
                      (const int32_t*)scnt, (const int32_t*)colptr, (const R*)P, (const double*)cd,
                      (const double*)cpd, V, K, Rw, g, gp);
   TSK_TRY(check_launch("k_word_accum"));
-  TSK_TRY(launch_mode_spectra<R>(logb, tab, q, tw, Qs, st));
   const double a = alpha0 / (alpha0 + 2.0);
   const double c3 = 2.0 * alpha0 * alpha0 / ((alpha0 + 1.0) * (alpha0 + 2.0));
+  if (moment) {
+    // documents: c_d p^(x)3 and -a c'_d p p^T; words: 2 g w^(x)3, -(w w R) and a g' w w^T
+    double* Cd = (double*)at(21);
+    double* Cw = (double*)at(22);
+    double* T = (double*)at(23);
+    TSK_TRY((launch_moment<R, false>(ms, P, nullptr, cd, cpd, 1.0, -a, 0.0, K, D, (double*)at(19), Cd, st)));
+    TSK_TRY((launch_moment<R, true>(ms, W, Rw, g, gp, 2.0, a, -1.0, K, V, (double*)at(20), Cw, st)));
+    hipLaunchKernelGGL(tsk::k_moment_assemble, dim3(grid_for((size_t)K * K * K, 256)), dim3(256), 0, st,
+                       (const double*)Cd, (const double*)Cw, (const double*)q, (const double*)deff, c3, K, T);
+    TSK_TRY(check_launch("k_moment_assemble"));
+    return tsk_sketch_build_dense(ctx, tab, T, TSK_F64, S64, S32, accumulate, st);
+  }
+  TSK_TRY(launch_mode_spectra<R>(logb, tab, q, tw, Qs, st));
   tsk::TermArgs ta;
   ta.hxs = tab->hxs;
   ta.ord = tab->ord;

@@ -1,7 +1,9 @@
 """Parity of the document build (sketches of the whitened LDA moment
 M3(W,W,W) from CSR word counts, HIP path through the C ABI) with the oracle,
 which forms the K^3 tensor from the per-document terms and sketches it by
-Eq. (1).
+Eq. (1).  Both routes of the library run every case: route 1 sketches each
+rank-1 term through transforms (Section 3.2), route 2 forms the moment
+tensor on the matrix cores and sketches it by Eq. (1).
 
 Bars: FP64 W within 1e-12 normwise relative per sketch; FP32 W within 1e-5.
 Inputs: seeded synthetic LDA corpora (Dirichlet topics and mixtures,
@@ -44,8 +46,10 @@ def _dev(C):
                                             # the LDA workload's sketch shape: K = 100, b = 16384, B = 8
                                             (12, 300, 100, 40.0, 16384, 8, np.float32),
                                             (12, 300, 100, 40.0, 16384, 8, np.float64)])
-def test_docs_build_matches_oracle(ctx, D, V, K, L, b, B, dt):
-    print(f"docs D={D} V={V} K={K} b={b} B={B} {np.dtype(dt).name}", flush=True)
+@pytest.mark.parametrize("route", [1, 2])
+def test_docs_build_matches_oracle(ctx, D, V, K, L, b, B, dt, route):
+    print(f"docs D={D} V={V} K={K} b={b} B={B} {np.dtype(dt).name} route {route}", flush=True)
+    tsk.docs_route(ctx, route)
     C = lda_corpus(D=D, V=V, K=K, seed=D + V, mean_len=L, min_len=1)
     alpha0 = float(C.alpha.sum())
     rng = np.random.default_rng(K)
@@ -66,9 +70,12 @@ def test_docs_build_matches_oracle(ctx, D, V, K, L, b, B, dt):
                           accumulate=True)
     got2 = tsk.sketch_export(ctx, S64, b).cpu().numpy()
     assert rel(got2, 2 * ref) < tol
+    tsk.docs_route(ctx, 0)
 
 
-def test_docs_build_all_short_documents_give_zero(ctx):
+@pytest.mark.parametrize("route", [1, 2])
+def test_docs_build_all_short_documents_give_zero(ctx, route):
+    tsk.docs_route(ctx, route)
     C = lda_corpus(D=20, V=10, K=3, seed=1, mean_len=0.5, min_len=1)
     lens = np.array([C.cnt[C.rowptr[d]:C.rowptr[d + 1]].sum() for d in range(20)])
     keep = lens < 3
@@ -84,6 +91,7 @@ def test_docs_build_all_short_documents_give_zero(ctx):
     tsk.sketch_build_docs(ctx, tab, torch.from_numpy(rowptr).to(DEV),
                           torch.from_numpy(C.col[idx].astype(np.int32)).to(DEV),
                           torch.from_numpy(C.cnt[idx].astype(np.int32)).to(DEV), 10, W, 1.0, S64, S32)
+    tsk.docs_route(ctx, 0)
     assert float(S64.abs().max()) == 0.0
 
 
@@ -99,3 +107,5 @@ def test_docs_build_argument_errors(ctx):
         tsk.sketch_build_docs(ctx, tab, rp, col, cnt, 5, W, -1.0, S64, S32)
     with pytest.raises(ValueError):
         tsk.sketch_build_docs(ctx, tab, rp, col, cnt, 5, W[:, :3].contiguous(), 1.0, S64, S32)
+    with pytest.raises(tsk.TskError, match="route"):
+        tsk.docs_route(ctx, 3)

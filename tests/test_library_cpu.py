@@ -62,6 +62,7 @@ def test_host_argument_errors_return_status():
     assert L.tsk_power_update(None, None, 0, None, None, 1, None, None, None, None, None) == -1
     assert L.tsk_power_update_noalloc(None, None, 0, None, None, 1, None, None, None, None) == -1
     assert L.tsk_tune_config(None, 1, None) == -1
+    assert L.tsk_docs_route(None, 1) == -1
     assert L.tsk_decompose(None, None, 0, None, None, 1, 1, 1, None, 0, None, None, None, None,
                            0, None) == -1
     assert L.tsk_sketch_build_dense(None, None, None, 0, None, None, 0, None) == -1
