@@ -120,26 +120,36 @@ def summarize_sq(counter_csv: str, trace_csv: str) -> str:
     with open(trace_csv) as fh:
         for r in csv.DictReader(fh):
             dur[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    names = sorted({n for k in acc for n in acc[k]}) if any(
+        n not in SQ_COUNTERS for k in acc for n in acc[k]) else list(SQ_COUNTERS)
     out = [f"kernel_sources_sha256: {kernel_sources_sha256()}",
            f"# clock {CLOCK_GHZ} GHz, {NUM_CU} CUs; counters are per-dispatch means",
-           "# kernel | dispatches | mean us | " + " | ".join(SQ_COUNTERS)]
+           "# kernel | dispatches | mean us | " + " | ".join(names)]
     derived = {}
     for k in sorted(acc, key=lambda k: -sum(dur.get(k, [0.0])) if k in dur else 0.0):
         c = {n: sum(v) / len(v) for n, v in acc[k].items()}
         d = dur.get(k)
         mean_us = sum(d) / len(d) if d else float("nan")
-        out.append(f"# {k[:90]} | {len(acc[k].get('SQ_WAVES', []))} | {mean_us:.2f} | "
-                   + " | ".join(f"{c.get(n, float('nan')):.4g}" for n in SQ_COUNTERS))
+        ndisp = max(len(v) for v in acc[k].values())
+        out.append(f"# {k[:90]} | {ndisp} | {mean_us:.2f} | "
+                   + " | ".join(f"{c.get(n, float('nan')):.4g}" for n in names))
         cyc = mean_us * 1e-6 * CLOCK_GHZ * 1e9 * NUM_CU
-        for name in (POWER_KERNEL, BUILD_KERNEL, "k_terms<float, 14, false"):
+        for name in (POWER_KERNEL, BUILD_KERNEL, "k_terms<float, 14, false", "k_moment3<float, false"):
             if name in k and name not in derived and d:
                 derived[name] = (c, mean_us, cyc)
     for name, (c, mean_us, cyc) in derived.items():
         out.append(f"duration_us[{name}]: {mean_us:.3f}")
-        out.append(f"valu_issue_frac[{name}]: {c['SQ_INSTS_VALU'] / cyc:.4f}")
-        out.append(f"lds_issue_frac[{name}]: {c['SQ_INSTS_LDS'] / cyc:.4f}")
-        out.append(f"lds_bank_conflict_frac[{name}]: {c['SQ_LDS_BANK_CONFLICT'] / cyc:.4f}")
-        out.append(f"valu_insts_per_wave[{name}]: {c['SQ_INSTS_VALU'] / max(c['SQ_WAVES'], 1.0):.1f}")
+        if "SQ_INSTS_VALU" in c:
+            out.append(f"valu_issue_frac[{name}]: {c['SQ_INSTS_VALU'] / cyc:.4f}")
+        if "SQ_INSTS_LDS" in c:
+            out.append(f"lds_issue_frac[{name}]: {c['SQ_INSTS_LDS'] / cyc:.4f}")
+        if "SQ_LDS_BANK_CONFLICT" in c:
+            out.append(f"lds_bank_conflict_frac[{name}]: {c['SQ_LDS_BANK_CONFLICT'] / cyc:.4f}")
+        if "SQ_INSTS_VALU" in c and "SQ_WAVES" in c:
+            out.append(f"valu_insts_per_wave[{name}]: {c['SQ_INSTS_VALU'] / max(c['SQ_WAVES'], 1.0):.1f}")
+        if c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) > 0.0:
+            # summed over the four SIMDs of every CU
+            out.append(f"mfma_busy_frac[{name}]: {c['SQ_VALU_MFMA_BUSY_CYCLES'] / (4 * cyc):.4f}")
     return "\n".join(out)
 
 
@@ -358,6 +368,21 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
         tb.append(e0.elapsed_time(e1))
     build_ms = float(np.median(tb))
     S64_0, S32_0 = S64.clone(), S32.clone()
+    # each route on its own: 1 = per-document transforms (Section 3.2), 2 = the
+    # moment tensor on the matrix cores; the default above takes the cost rule's
+    by_route = {}
+    for route, name in ((1, "transforms"), (2, "moment_tensor")):
+        tsk.docs_route(ctx, route)
+        tr = []
+        for _ in range(2):
+            e0.record(stream)
+            tsk.sketch_build_docs(ctx, tab, rp, col, cnt, V, Wd, alpha0, S64, S32)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tr.append(e0.elapsed_time(e1))
+        by_route[name] = {"build_ms": min(tr),
+                          "sketch_rel_diff_vs_default": float((S64 - S64_0).norm() / S64_0.norm())}
+    tsk.docs_route(ctx, 0)
     td = []
     for r in range(nrep + 1):
         S64.copy_(S64_0)
@@ -432,6 +457,7 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
                      f"decomposition k={K}, L={L}, T={T}"),
         "documents": D, "nnz": nnz, "words": int(C.cnt.sum()), "corpus_generation_s": gen_s,
         "build_ms": build_ms, "documents_per_s": D / (build_ms * 1e-3),
+        "build_by_route": by_route,
         "decompose_ms": dec_ms, "sketch_updates_per_s": updates / (dec_ms * 1e-3),
         "topics_matched_0.9": matched,
         "data_whitening_ms": 1e3 * (t1 - t0),
@@ -856,8 +882,10 @@ def kernels_only(what, reps, ctx, tab, Td, S64, S32, dev):
         y = torch.empty_like(x)
         for _ in range(reps):
             y.copy_(x)
-    if what == "docs":
-        # the LDA document build (k_terms) on the 500k-document corpus, FP32 W
+    if what in ("docs", "docs_moment"):
+        # the LDA document build on the 500k-document corpus, FP32 W: through the
+        # per-document transforms (k_terms) or through the moment tensor (k_moment3)
+        tsk.docs_route(ctx, 1 if what == "docs" else 2)
         from paper_1506_04448_amd.workloads import lda_corpus_fast, population_whitening
         V, K, b, B = 20000, 100, 16384, 8
         C = lda_corpus_fast(500000, V, K, seed=3)
@@ -888,7 +916,7 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the gradient-extension leg")
     ap.add_argument("--no-x1", action="store_true", help="skip the paper's synthetic accuracy table")
     ap.add_argument("--summarize-sq", nargs=2, metavar=("COUNTER_CSV", "TRACE_CSV"))
-    ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy", "docs"),
+    ap.add_argument("--kernels-only", choices=("all", "power", "build", "copy", "docs", "docs_moment"),
                     help="launch only these kernels --reps times (for counter runs) and exit")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--tune", type=int, choices=(0, 1), default=1,

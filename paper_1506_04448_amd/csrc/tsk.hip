@@ -1611,8 +1611,10 @@ tsk_status launch_mode_spectra(int logb, tsk_tables_t tab, const double* q, cons
 }
 
 // Shapes of the moment route's products: the pair rows padded to whole
-// work-group blocks, the column groups, and the item chunks that fill two
-// work-groups per CU.
+// work-group blocks, the column groups, and the item chunks.  A wave leaves
+// out the column tiles below its rows' smallest b, so the work of a row block
+// falls with b; about four rounds of work-groups over two per CU let the
+// dispatcher even that out (the chunk partials are capped at 256 MB).
 struct MomentShape {
   int np = 0, rows = 0, nrb = 0;
   int ncg_d = 0, ld_d = 0, nch_d = 0, per_d = 0;
@@ -1629,8 +1631,10 @@ MomentShape moment_shape(int K, int D, int V) {
     ncg = (ncol + tsk::kMomCols - 1) / tsk::kMomCols;
     ld = ncg * tsk::kMomCols;
     const int wgs = m.nrb * ncg;
-    nch = std::max(1, std::min(64, 512 / wgs));
-    nch = std::max(1, std::min(nch, (nitem + 63) / 64));  // at least 64 items per chunk
+    const size_t chunk_bytes = (size_t)m.rows * ld * sizeof(double);
+    nch = std::max(1, std::min(64, 4 * 512 / wgs));
+    nch = std::max(1, std::min<int>(nch, (int)((256u << 20) / chunk_bytes)));
+    nch = std::max(1, std::min(nch, (nitem + 255) / 256));  // at least 256 items per chunk
     per = (nitem + nch - 1) / nch;
     per = (per + 3) & ~3;
     nch = std::max(1, (nitem + per - 1) / per);
@@ -1643,16 +1647,19 @@ MomentShape moment_shape(int K, int D, int V) {
 }
 
 // Route of the document build: the moment tensor when its matrix-core work
-// (FP64, about 40 TFLOP/s sustained) is estimated below the per-document
-// transforms (2.5 b log2 b flops per real transform, about 16 TFLOP/s in FP32
-// and 6 in FP64 on the vector units); tsk_docs_route overrides the rule.
+// (FP64, about 15 TFLOP/s measured on the useful multiply-adds) is estimated
+// below the per-document transforms (2.5 b log2 b flops per real transform,
+// about 16 TFLOP/s measured in FP32, 6 in FP64, on the vector units);
+// tsk_docs_route overrides the rule.
 bool docs_use_moment(const tsk_ctx* ctx, int K, int B, int b, int D, int V, bool fp64) {
   if (ctx->docs_route == 1) return false;
   if (ctx->docs_route == 2) return true;
-  const MomentShape m = moment_shape(K, D, V);
-  const double mflop = 2.0 * m.rows * ((double)m.ld_d * D + (double)m.ld_w * V);
+  // about K^3 / 6 + K^2 / 2 multiply-adds per document (the x^(x)3 columns at
+  // c >= b, the second-order column) and K^3 / 6 + K^3 / 2 + K^2 / 2 per word
+  const double k3 = (double)K * K * K, k2 = (double)K * K;
+  const double mflop = 2.0 * ((k3 / 6 + k2 / 2) * D + (2 * k3 / 3 + k2 / 2) * V);
   const double tflop = (3.0 * D + 6.0 * V) * B * 2.5 * b * std::log2((double)b);
-  return mflop / 40e12 < tflop / (fp64 ? 6e12 : 16e12);
+  return mflop / 15e12 < tflop / (fp64 ? 6e12 : 16e12);
 }
 
 // One product of the moment route (documents, or words with HAS_Y) and the
@@ -1678,14 +1685,14 @@ tsk_status launch_moment(const MomentShape& ms, const R* X, const R* Y, const do
   m.ld = HAS_Y ? ms.ld_w : ms.ld_d;
   m.part = part;
   const int ncg = HAS_Y ? ms.ncg_w : ms.ncg_d, nch = HAS_Y ? ms.nch_w : ms.nch_d;
-  const size_t lds = tsk::moment_lds_bytes(K);
+  const size_t lds = tsk::moment_lds_bytes(K, HAS_Y);
   static std::atomic<uint64_t> configured{0};
   int dev = 0;
   TSK_HIP(hipGetDevice(&dev));
   const uint64_t bit = 1ull << (dev & 63);
   if (!(configured.load() & bit)) {
     TSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tsk::k_moment3<R, HAS_Y>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsk::moment_lds_bytes(128)));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)tsk::moment_lds_bytes(128, true)));
     configured.fetch_or(bit);
   }
   hipLaunchKernelGGL((tsk::k_moment3<R, HAS_Y>), dim3(ms.nrb * ncg, nch), dim3(256), lds, st, m);
