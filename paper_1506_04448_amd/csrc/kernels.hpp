@@ -1876,31 +1876,48 @@ __global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const i
                                                     const int32_t* colptr, const R* P, const double* cd,
                                                     const double* cpd, int V, int K, R* Rw, double* g,
                                                     double* gp) {
-  // sdoc, scnt: document and count of each nonzero in word order, so four
-  // documents per step keep four rows of P in flight (four partial sums)
+  // sdoc, scnt: document and count of each nonzero in word order.  Sixteen
+  // documents per step keep sixteen rows of P in flight (as many partial sums), and
+  // the next step's document indices are loaded with this step's rows.
+  constexpr int U = 16;
   for (int w = blockIdx.x; w < V; w += gridDim.x) {
     const int lo = colptr[w], hi = colptr[w + 1];
     for (int kb = 0; kb < K; kb += blockDim.x) {
       const int k = kb + threadIdx.x;
       const int kc = k < K ? k : K - 1;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0}, ga = 0.0, gc = 0.0;
-      int e = lo;
-      for (; e + 4 <= hi; e += 4) {
-        int d[4];
-        double n[4], p[4];
+      double acc[U], ga = 0.0, gc = 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          d[u] = sdoc[e + u];
-          n[u] = (double)scnt[e + u];
+      for (int u = 0; u < U; ++u) acc[u] = 0.0;
+      int dn[U], nn[U];
+      auto load_idx = [&](int e0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          dn[u] = sdoc[e0 + u];
+          nn[u] = scnt[e0 + u];
+        }
+      };
+      int e = lo;
+      if (e + U <= hi) load_idx(e);
+      for (; e + U <= hi; e += U) {
+        double n[U], p[U], c[U], c2[U];
+        int d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          d[u] = dn[u];
+          n[u] = (double)nn[u];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] = (double)P[(size_t)d[u] * K + kc];
+        for (int u = 0; u < U; ++u) {
+          p[u] = (double)P[(size_t)d[u] * K + kc];
+          c[u] = cd[d[u]];
+          c2[u] = cpd[d[u]];
+        }
+        if (e + 2 * U <= hi) load_idx(e + U);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double c = cd[d[u]];
-          acc[u] += c * n[u] * p[u];
-          ga += c * n[u];
-          gc += cpd[d[u]] * n[u];
+        for (int u = 0; u < U; ++u) {
+          acc[u] += c[u] * n[u] * p[u];
+          ga += c[u] * n[u];
+          gc += c2[u] * n[u];
         }
       }
       for (; e < hi; ++e) {
@@ -1911,7 +1928,12 @@ __global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const i
         ga += c * n;
         gc += cpd[d] * n;
       }
-      if (k < K) Rw[(size_t)w * K + k] = (R)((acc[0] + acc[1]) + (acc[2] + acc[3]));
+      // the partial sums pairwise, in a fixed order
+#pragma unroll
+      for (int h = 1; h < U; h *= 2)
+#pragma unroll
+        for (int u = 0; u < U; u += 2 * h) acc[u] += acc[u + h];
+      if (k < K) Rw[(size_t)w * K + k] = (R)acc[0];
       if (kb == 0 && threadIdx.x == 0) {
         g[w] = ga;
         gp[w] = gc;

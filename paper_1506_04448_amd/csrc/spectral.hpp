@@ -16,8 +16,9 @@
 
 namespace tsk {
 
-// Y = M2 X (rows w, K <= 128 columns); grid over words, 128 threads.  Four
-// documents per step, with four partial sums, keep four rows of P in flight.
+// Y = M2 X (rows w, K <= 128 columns); grid over words, 128 threads.  Sixteen
+// documents per step, with as many partial sums, keep sixteen rows of P in flight,
+// and the next step's document indices are loaded with this step's rows.
 __global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const int32_t* scnt,
                                                       const int32_t* colptr, const double* P, const double* cpd,
                                                       const double* invm, const double* X, const double* q,
@@ -30,22 +31,39 @@ __global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const
   for (int w = blockIdx.x; w < V; w += gridDim.x) {
     const int lo = colptr[w], hi = colptr[w + 1];
     const double xw = X[(size_t)w * K + kc];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0}, m1 = 0.0;
-    int e = lo;
-    for (; e + 4 <= hi; e += 4) {
-      int d[4];
-      double n[4], p[4];
+    constexpr int U = 16;
+    double acc[U], m1 = 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        d[u] = sdoc[e + u];
-        n[u] = (double)scnt[e + u];
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    int dn[U], nn[U];
+    auto load_idx = [&](int e0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        dn[u] = sdoc[e0 + u];
+        nn[u] = scnt[e0 + u];
+      }
+    };
+    int e = lo;
+    if (e + U <= hi) load_idx(e);
+    for (; e + U <= hi; e += U) {
+      int d[U];
+      double n[U], p[U], c[U], im[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        d[u] = dn[u];
+        n[u] = (double)nn[u];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) p[u] = P[(size_t)d[u] * K + kc];
+      for (int u = 0; u < U; ++u) {
+        p[u] = P[(size_t)d[u] * K + kc];
+        c[u] = cpd[d[u]];
+        im[u] = invm[d[u]];
+      }
+      if (e + 2 * U <= hi) load_idx(e + U);  // the next step's indices, with this step's rows
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        m1 += invm[d[u]] * n[u];
-        acc[u] += cpd[d[u]] * n[u] * (p[u] - xw);
+      for (int u = 0; u < U; ++u) {
+        m1 += im[u] * n[u];
+        acc[u] += c[u] * n[u] * (p[u] - xw);
       }
     }
     for (; e < hi; ++e) {
@@ -54,7 +72,12 @@ __global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const
       m1 += invm[d] * n;
       acc[0] += cpd[d] * n * (P[(size_t)d * K + kc] - xw);
     }
-    if (k < K) Y[(size_t)w * K + k] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * inv - a * (m1 * inv) * q[k];
+    // the partial sums pairwise, in a fixed order
+#pragma unroll
+    for (int h = 1; h < U; h *= 2)
+#pragma unroll
+      for (int u = 0; u < U; u += 2 * h) acc[u] += acc[u + h];
+    if (k < K) Y[(size_t)w * K + k] = acc[0] * inv - a * (m1 * inv) * q[k];
   }
 }
 
