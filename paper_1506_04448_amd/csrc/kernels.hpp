@@ -1835,13 +1835,16 @@ __global__ void k_doc_q_final(const double* part, int G, int K, double* q, doubl
   if (threadIdx.x == 0) deff[0] = D;
 }
 
-// Document index of every nonzero, and the identity permutation.
-__global__ void k_rowof(const int32_t* rowptr, int D, int32_t* rowof, int32_t* iota) {
-  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < D; d += gridDim.x * blockDim.x)
-    for (int e = rowptr[d]; e < rowptr[d + 1]; ++e) {
-      rowof[e] = d;
-      iota[e] = e;
-    }
+// packed[e] = (d << 32) | cnt[e] for the nonzeros e of document d, the values
+// the sort by word carries along; one wave per document, so that a
+// document's writes are consecutive.
+__global__ void k_pack_entries(const int32_t* rowptr, const int32_t* cnt, int D, unsigned long long* packed) {
+  const int lane = threadIdx.x & 63, wpb = blockDim.x >> 6;
+  for (int d = blockIdx.x * wpb + (threadIdx.x >> 6); d < D; d += gridDim.x * wpb) {
+    const int lo = rowptr[d], hi = rowptr[d + 1];
+    for (int e = lo + lane; e < hi; e += 64)
+      packed[e] = ((unsigned long long)(uint32_t)d << 32) | (uint32_t)cnt[e];
+  }
 }
 
 // colptr[i] = first position of word i in the sorted word ids (binary search).
@@ -1858,14 +1861,14 @@ __global__ void k_col_bounds(const int32_t* skeys, int nnz, int V, int32_t* colp
 }
 
 // sdoc[e], scnt[e]: document and count of the e-th nonzero in word order
-// (svals: the nonzeros sorted by word, stable in document order), so that
-// the per-word kernels read them without a chain of dependent loads.
-__global__ void k_sorted_entries(const int32_t* svals, const int32_t* rowof, const int32_t* cnt, int nnz,
-                                 int32_t* sdoc, int32_t* scnt) {
+// (packed: the values of k_pack_entries sorted by word, stable in document
+// order), so that the per-word kernels read them without a chain of
+// dependent loads.
+__global__ void k_unpack_entries(const unsigned long long* packed, int nnz, int32_t* sdoc, int32_t* scnt) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) {
-    const int idx = svals[e];
-    sdoc[e] = rowof[idx];
-    scnt[e] = cnt[idx];
+    const unsigned long long v = packed[e];
+    sdoc[e] = (int32_t)(v >> 32);
+    scnt[e] = (int32_t)(uint32_t)v;
   }
 }
 

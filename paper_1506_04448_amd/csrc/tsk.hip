@@ -1610,6 +1610,46 @@ tsk_status launch_mode_spectra(int logb, tsk_tables_t tab, const double* q, cons
   return tsk::fail(TSK_EUNSUPPORTED, "document sketch: b=2^%d not built", logb);
 }
 
+// Bit width of the word ids 0..V-1: the radix sort by word reads only those bits.
+int word_bits(int V) {
+  int b = 1;
+  while (b < 31 && (1 << b) < V) ++b;
+  return b;
+}
+
+// Temporary storage of the stable sort of the nonzeros by word.
+hipError_t word_sort_tmp(size_t* bytes, int nnz, int V, hipStream_t st) {
+  return rocprim::radix_sort_pairs(nullptr, *bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                   (const unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                   (size_t)std::max(nnz, 1), 0, word_bits(V), st);
+}
+
+// The nonzeros in word order, stable in document order: the sorted word ids
+// skeys, the first position of every word colptr[V+1], and the document and
+// count of each nonzero (sdoc, scnt).  pin, pout: 8 nnz bytes each; scnt may
+// share pin's memory (pin is free once the sort has read it).
+tsk_status word_order(const int32_t* rowptr, const int32_t* col, const int32_t* cnt, int D, int V, int nnz,
+                      unsigned long long* pin, unsigned long long* pout, uint32_t* skeys, void* tmp,
+                      size_t tmp_bytes, int32_t* colptr, int32_t* sdoc, int32_t* scnt, hipStream_t st) {
+  if (nnz > 0) {
+    hipLaunchKernelGGL(tsk::k_pack_entries, dim3(std::min((D + 3) / 4, 65536)), dim3(256), 0, st, rowptr, cnt, D,
+                       pin);
+    TSK_TRY(check_launch("k_pack_entries"));
+    size_t t = tmp_bytes;
+    TSK_HIP(rocprim::radix_sort_pairs(tmp, t, reinterpret_cast<const uint32_t*>(col), skeys,
+                                      (const unsigned long long*)pin, pout, (size_t)nnz, 0, word_bits(V), st));
+  }
+  hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const int32_t*>(skeys), nnz, V, colptr);
+  TSK_TRY(check_launch("k_col_bounds"));
+  if (nnz > 0) {
+    hipLaunchKernelGGL(tsk::k_unpack_entries, dim3(grid_for((size_t)nnz, 256)), dim3(256), 0, st,
+                       (const unsigned long long*)pout, nnz, sdoc, scnt);
+    TSK_TRY(check_launch("k_unpack_entries"));
+  }
+  return TSK_OK;
+}
+
 // Shapes of the moment route's products: the pair rows padded to whole
 // work-group blocks, the column groups, and the item chunks.  A wave leaves
 // out the column tiles below its rows' smallest b, so the work of a row block
@@ -1715,8 +1755,7 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   const int ncD = std::max(1, std::min(128, (D + 63) / 64));
   const int ncW = std::max(1, std::min(64, (V + 63) / 64));
   size_t sort_tmp = 0;
-  TSK_HIP(rocprim::radix_sort_pairs(nullptr, sort_tmp, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                    (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)nnz, 0, 32, st));
+  TSK_HIP(word_sort_tmp(&sort_tmp, nnz, V, st));
   // one workspace, 256-byte aligned pieces
   size_t off = 0;
   std::vector<size_t> offs;
@@ -1731,10 +1770,10 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   take((size_t)G * (K + 1) * 8);                // 4 q partials
   take((size_t)K * 8);                          // 5 q
   take(8);                                      // 6 D_eff
-  take((size_t)nnz * 4);                        // 7 rowof
-  take((size_t)nnz * 4);                        // 8 iota
+  take((size_t)nnz * 8);                        // 7 packed entries (then the counts in word order)
+  take((size_t)nnz * 8);                        // 8 packed entries in word order
   take((size_t)nnz * 4);                        // 9 sorted word ids
-  take((size_t)nnz * 4);                        // 10 sorted nonzero index
+  take((size_t)nnz * 4);                        // 10 documents in word order
   take(sort_tmp);                               // 11 sort scratch
   take((size_t)(V + 1) * 4);                    // 12 colptr
   take((size_t)V * K * sizeof(R));              // 13 R_i
@@ -1756,8 +1795,7 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   R* P = (R*)at(0);
   double *cd = (double*)at(1), *cpd = (double*)at(2), *invm = (double*)at(3);
   double *qpart = (double*)at(4), *q = (double*)at(5), *deff = (double*)at(6);
-  int32_t *rowof = (int32_t*)at(7), *iota = (int32_t*)at(8), *skeys = (int32_t*)at(9);
-  int32_t *svals = (int32_t*)at(10), *colptr = (int32_t*)at(12);
+  int32_t* colptr = (int32_t*)at(12);
   R* Rw = (R*)at(13);
   double *g = (double*)at(14), *gp = (double*)at(15);
   cx<R>* Qs = (cx<R>*)at(16);
@@ -1772,25 +1810,9 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
   TSK_TRY(check_launch("k_doc_q"));
   // words: documents containing each word, in document order (stable sort by word)
-  if (nnz > 0) {
-    hipLaunchKernelGGL(tsk::k_rowof, dim3(grid_for((size_t)D, 256)), dim3(256), 0, st, rowptr, D, rowof,
-                       iota);
-    TSK_TRY(check_launch("k_rowof"));
-    size_t tmp = sort_tmp;
-    TSK_HIP(rocprim::radix_sort_pairs(at(11), tmp, col, skeys, (const int32_t*)iota, svals, (size_t)nnz, 0,
-                                      32, st));
-  }
-  hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
-                     (const int32_t*)skeys, nnz, V, colptr);
-  TSK_TRY(check_launch("k_col_bounds"));
-  // documents and counts of the nonzeros in word order (the sort's input
-  // values and the sorted keys are no longer needed: their buffers take them)
-  int32_t *sdoc = iota, *scnt = skeys;
-  if (nnz > 0) {
-    hipLaunchKernelGGL(tsk::k_sorted_entries, dim3(grid_for((size_t)nnz, 256)), dim3(256), 0, st,
-                       (const int32_t*)svals, (const int32_t*)rowof, cnt, nnz, sdoc, scnt);
-    TSK_TRY(check_launch("k_sorted_entries"));
-  }
+  int32_t *sdoc = (int32_t*)at(10), *scnt = (int32_t*)at(7);
+  TSK_TRY(word_order(rowptr, col, cnt, D, V, nnz, (unsigned long long*)at(7), (unsigned long long*)at(8),
+                     (uint32_t*)at(9), at(11), sort_tmp, colptr, sdoc, scnt, st));
   hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)sdoc,
                      (const int32_t*)scnt, (const int32_t*)colptr, (const R*)P, (const double*)cd,
                      (const double*)cpd, V, K, Rw, g, gp);
@@ -2958,9 +2980,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   const int G = std::max(1, std::min(1024, (D + 255) / 256));
   const int per_q = (D + G - 1) / G;
   size_t sort_tmp = 0;
-  TSK_HIP(rocprim::radix_sort_pairs(nullptr, sort_tmp, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                    (const int32_t*)nullptr, (int32_t*)nullptr, (size_t)std::max(nnz, 1), 0, 32,
-                                    st));
+  TSK_HIP(word_sort_tmp(&sort_tmp, nnz, V, st));
   size_t off = 0;
   std::vector<size_t> offs;
   auto take = [&](size_t bytes) {
@@ -2975,10 +2995,10 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   take((size_t)G * (K + 1) * 8);    // 4 q partials
   take((size_t)K * 8);              // 5 q
   take(8);                          // 6 D_eff
-  take((size_t)nnz * 4 + 4);        // 7 rowof
-  take((size_t)nnz * 4 + 4);        // 8 iota
+  take((size_t)nnz * 8 + 8);        // 7 packed entries
+  take((size_t)nnz * 8 + 8);        // 8 packed entries in word order
   take((size_t)nnz * 4 + 4);        // 9 sorted word ids
-  take((size_t)nnz * 4 + 4);        // 10 sorted nonzero index
+  take((size_t)nnz * 4 + 4);        // 10 documents in word order
   take(sort_tmp);                   // 11 sort scratch
   take((size_t)(V + 1) * 4);        // 12 colptr
   take(VK * 8);                     // 13 Y
@@ -2993,28 +3013,13 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   double* P = (double*)at(0);
   double *cd = (double*)at(1), *cpd = (double*)at(2), *invm = (double*)at(3);
   double *qpart = (double*)at(4), *q = (double*)at(5), *deff = (double*)at(6);
-  int32_t *rowof = (int32_t*)at(7), *iota = (int32_t*)at(8), *skeys = (int32_t*)at(9);
-  int32_t *svals = (int32_t*)at(10), *colptr = (int32_t*)at(12);
+  int32_t* colptr = (int32_t*)at(12);
   double *Y = (double*)at(13), *Q = (double*)at(14), *Gm = (double*)at(15), *E = (double*)at(16);
   double* dv = (double*)at(17);
-  if (nnz > 0) {
-    hipLaunchKernelGGL(tsk::k_rowof, dim3(grid_for((size_t)D, 256)), dim3(256), 0, st, rowptr, D, rowof, iota);
-    TSK_TRY(check_launch("k_rowof"));
-    size_t tmp = sort_tmp;
-    TSK_HIP(rocprim::radix_sort_pairs(at(11), tmp, col, skeys, (const int32_t*)iota, svals, (size_t)nnz, 0, 32,
-                                      st));
-  }
-  hipLaunchKernelGGL(tsk::k_col_bounds, dim3(grid_for((size_t)V + 1, 256)), dim3(256), 0, st,
-                     (const int32_t*)skeys, nnz, V, colptr);
-  TSK_TRY(check_launch("k_col_bounds"));
-  // documents and counts of the nonzeros in word order (the sort's input
-  // values are no longer needed: their buffer takes the documents)
-  int32_t *sdoc = iota, *scnt = (int32_t*)at(18);
-  if (nnz > 0) {
-    hipLaunchKernelGGL(tsk::k_sorted_entries, dim3(grid_for((size_t)nnz, 256)), dim3(256), 0, st,
-                       (const int32_t*)svals, (const int32_t*)rowof, cnt, nnz, sdoc, scnt);
-    TSK_TRY(check_launch("k_sorted_entries"));
-  }
+  // documents and counts of the nonzeros in word order
+  int32_t *sdoc = (int32_t*)at(10), *scnt = (int32_t*)at(18);
+  TSK_TRY(word_order(rowptr, col, cnt, D, V, nnz, (unsigned long long*)at(7), (unsigned long long*)at(8),
+                     (uint32_t*)at(9), at(11), sort_tmp, colptr, sdoc, scnt, st));
   // Yout = M2 X
   auto apply = [&](const double* X, double* Yout) -> tsk_status {
     hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min((D + 15) / 16, 8192)), dim3(256), 0, st, rowptr,
