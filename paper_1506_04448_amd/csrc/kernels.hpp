@@ -1823,16 +1823,24 @@ __global__ __launch_bounds__(256) void k_doc_q_partial(const R* P, const double*
   }
 }
 
-// q = (sum of partials) / D_eff, and D_eff itself; one block, fixed order.
-__global__ void k_doc_q_final(const double* part, int G, int K, double* q, double* deff) {
-  double D = 0.0;
-  for (int g = 0; g < G; ++g) D += part[(size_t)g * (K + 1) + K];
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += part[(size_t)g * (K + 1) + k];
-    q[k] = D > 0.0 ? s / D : 0.0;
+// q = (sum of partials) / D_eff, and D_eff itself: one work-group of 256
+// threads per column k <= K (column K is the kept-document count, which every
+// work-group sums again for its division); fixed strided sums and a fixed tree.
+__global__ __launch_bounds__(256) void k_doc_q_final(const double* part, int G, int K, double* q,
+                                                     double* deff) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  double s = 0.0, c = 0.0;
+  for (int g = threadIdx.x; g < G; g += 256) {
+    s += part[(size_t)g * (K + 1) + k];
+    c += part[(size_t)g * (K + 1) + K];
   }
-  if (threadIdx.x == 0) deff[0] = D;
+  s = block_sum<256>(s, red);
+  const double D = block_sum<256>(c, red);
+  if (threadIdx.x == 0) {
+    if (k < K) q[k] = D > 0.0 ? s / D : 0.0;
+    else deff[0] = D;
+  }
 }
 
 // packed[e] = (d << 32) | cnt[e] for the nonzeros e of document d, the values

@@ -1807,7 +1807,7 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   TSK_TRY(check_launch("k_doc_project"));
   hipLaunchKernelGGL(tsk::k_doc_q_partial<R>, dim3(G), dim3(128), 0, st, (const R*)P, (const double*)invm,
                      D, K, per_q, qpart);
-  hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
+  hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(K + 1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
   TSK_TRY(check_launch("k_doc_q"));
   // words: documents containing each word, in document order (stable sort by word)
   int32_t *sdoc = (int32_t*)at(10), *scnt = (int32_t*)at(7);
@@ -3027,7 +3027,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
     TSK_TRY(check_launch("k_doc_project"));
     hipLaunchKernelGGL(tsk::k_doc_q_partial<double>, dim3(G), dim3(128), 0, st, (const double*)P,
                        (const double*)invm, D, K, per_q, qpart);
-    hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
+    hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(K + 1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
     TSK_TRY(check_launch("k_doc_q"));
     hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)sdoc,
                        (const int32_t*)scnt, (const int32_t*)colptr, (const double*)P, (const double*)cpd,
