@@ -1090,6 +1090,13 @@ def main():
         cpu.pop("t_build_s")
         cpu.pop("t_power_step_s")
 
+    # LDS scatter-adds of k_build_dense (B n^3 per build) per CU-clock, from the
+    # kernel duration recorded with the committed counters (None when stale)
+    build_counters = stored_sq(BUILD_KERNEL)
+    if build_counters and build_counters.get("duration_us"):
+        build_counters = dict(build_counters)
+        build_counters["scatter_adds_per_cu_clock"] = (
+            B_CNT * float(N) ** 3 / (build_counters["duration_us"] * 1e-6 * CLOCK_GHZ * 1e9 * NUM_CU))
     out = {
         "metric": METRIC,
         "value": value,
@@ -1118,7 +1125,7 @@ def main():
                          "frac_hbm": build_gbps / PEAK_HBM_GBPS,
                          "bytes": build_bytes(N, B_LEN, B_CNT),
                          "traffic": stored_traffic(BUILD_KERNEL),
-                         "counters": stored_sq(BUILD_KERNEL)},
+                         "counters": build_counters},
         "recovery": {"residual": res_b, "wrong_vectors": int(wrong_b)},
         "precision": precision,
         "tuning": tuning,

@@ -92,7 +92,9 @@ tsk_status tsk_tune_config(tsk_ctx_t ctx, int mode, const char* cache_path);
  * multiply-adds over the documents, the same per word), then sketched by
  * Eq. (1) as a dense tensor.  Route 0 (the default) takes the one a cost rule
  * estimates faster: route 2 whenever K^3 is small against B b log2 b.  Both
- * give the same sketch up to rounding.  Errors: TSK_EINVAL (null context,
+ * give the same sketch up to rounding.  Route 2 keeps its chunk partial
+ * products (at most 256 MB each for the documents and the words) and the K^3
+ * tensor in the context's workspace.  Errors: TSK_EINVAL (null context,
  * route outside {0, 1, 2}). */
 tsk_status tsk_docs_route(tsk_ctx_t ctx, int route);
 
