@@ -302,17 +302,6 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
   struct QuadTw {
     cx<float> k, Hk, Mk, Mpk, k2, Mk2;
   };
-  auto quad_tw = [&](int kp) -> QuadTw {
-    const cx<float> w1 = Wb[kp], w2 = Wb[2 * kp];
-    QuadTw t;
-    t.k = w1;
-    t.Hk = {-w1.x, w1.y};
-    t.Mk = {-w1.y, -w1.x};
-    t.Mpk = {w1.y, -w1.x};
-    t.k2 = w2;
-    t.Mk2 = kp ? cx<float>{-w2.x, w2.y} : w2;
-    return t;
-  };
   // Z and X_j of quad {k', H - k', M - k', M + k'} from E_j,0 (ea at k', eb
   // at M - k') and E_j,1 (LDS).
   auto quad_x = [&](int kp, const QuadTw& w, const cx<float> ea, const cx<float> eb, cx<float> (&X)[4]) {
@@ -327,25 +316,59 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
     X[2] = r2c_post(zMk, zMpk, w.Mk);
     X[3] = r2c_post(zMpk, zMk, w.Mpk);
   };
-  // First mode: P = S conj(X_sa) into the scratch row.
-  auto quad_first = [&](int kp, const cx<float> ea, const cx<float> eb) {
-    const QuadTw w = quad_tw(kp);
-    cx<float> X[4];
-    quad_x(kp, w, ea, eb, X);
-    const int ks[4] = {kp, H - kp, M - kp, M + kp};
+  // Global inputs of one quad: W_b^k', W_b^2k', two values from the scratch
+  // row (the parked E_j,0 in slots 4 and 5, or in the second mode the first
+  // mode's products in slots 0 to 3 as well), and in the first mode S at the
+  // quad's four bins.  The quad loops load quad k' + NT before they store
+  // quad k', so that waiting for the loads never waits for the stores.
+  struct QuadIn {
+    cx<float> w1, w2, ea, eb, v[4];
+  };
+  auto quad_load = [&](int kp, bool first) -> QuadIn {
+    QuadIn in;
+    in.w1 = Wb[kp];
+    in.w2 = Wb[2 * kp];
+    in.ea = Pq[4 * (size_t)QH + kp];
+    in.eb = Pq[5 * (size_t)QH + kp];
+    if (first) {
+      in.v[0] = S[kp];
+      in.v[1] = S[H - kp];
+      in.v[2] = S[M - kp];
+      in.v[3] = S[M + kp];
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Pq[(size_t)q * QH + kp] = cmulc(S[ks[q]], X[q]);
+      for (int q = 0; q < 4; ++q) in.v[q] = Pq[(size_t)q * QH + kp];
+    }
+    return in;
+  };
+  auto quad_tw_of = [&](int kp, const QuadIn& in) -> QuadTw {
+    QuadTw t;
+    t.k = in.w1;
+    t.Hk = {-in.w1.x, in.w1.y};
+    t.Mk = {-in.w1.y, -in.w1.x};
+    t.Mpk = {in.w1.y, -in.w1.x};
+    t.k2 = in.w2;
+    t.Mk2 = kp ? cx<float>{-in.w2.x, in.w2.y} : in.w2;
+    return t;
+  };
+  // First mode: P = S conj(X_sa) into the scratch row.
+  auto quad_first = [&](int kp, const QuadIn& in) {
+    const QuadTw w = quad_tw_of(kp, in);
+    cx<float> X[4];
+    quad_x(kp, w, in.ea, in.eb, X);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Pq[(size_t)q * QH + kp] = cmulc(in.v[q], X[q]);
   };
   // Second mode: P *= conj(X_sb), the packing Y and the inverse split; A_0
   // into LDS at k' and M - k' (the positions this thread read), A_1 into the
   // scratch row in place of the P values just read (slots 0 and 1).
-  auto quad_second = [&](int kp, const cx<float> ea, const cx<float> eb) {
-    const QuadTw w = quad_tw(kp);
+  auto quad_second = [&](int kp, const QuadIn& in) {
+    const QuadTw w = quad_tw_of(kp, in);
     cx<float> X[4];
-    quad_x(kp, w, ea, eb, X);
+    quad_x(kp, w, in.ea, in.eb, X);
     cx<float> P[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) P[q] = cmulc(Pq[(size_t)q * QH + kp], X[q]);
+    for (int q = 0; q < 4; ++q) P[q] = cmulc(in.v[q], X[q]);
     const cx<float> Ya = c2r_pack(P[0], P[1], w.k);     // Y[k']
     const cx<float> Yc = c2r_pack(P[3], P[2], w.Mpk);   // Y[M + k']
     buf.put(kp, cadd(Ya, Yc));
@@ -355,6 +378,18 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
       const cx<float> Yd = c2r_pack(P[1], P[0], w.Hk);  // Y[H - k']
       buf.put(M - kp, cadd(Yb, Yd));
       Pq[QH + kp] = cmulc(csub(Yb, Yd), w.Mk2);         // A_1[M - k']
+    }
+  };
+  // The quads of this thread, the next one's loads ahead of this one's stores.
+  auto quad_pass = [&](bool first) {
+    int kp = tid;
+    QuadIn cur = quad_load(kp, first);
+    for (; kp <= M / 2; kp += NT) {
+      QuadIn nxt = cur;
+      if (kp + NT <= M / 2) nxt = quad_load(kp + NT, first);
+      if (first) quad_first(kp, cur);
+      else quad_second(kp, cur);
+      cur = nxt;
     }
   };
   // Count sketch of residue r of mode `mode` (vector uy, else u) and its
@@ -389,15 +424,13 @@ __global__ __launch_bounds__(kSplit1Threads) void k_power_split1(SplitOneArgs a)
   forward(a.sa, nullptr, 0);
   keep_e0();
   forward(a.sa, nullptr, 1);
-#pragma unroll 2
-  for (int kp = tid; kp <= M / 2; kp += NT) quad_first(kp, Pq[4 * (size_t)QH + kp], Pq[5 * (size_t)QH + kp]);
+  quad_pass(true);
   __syncthreads();
   const float* uy = a.Uy ? a.Uy + (size_t)tau * n : nullptr;
   forward(a.sb, uy, 0);
   keep_e0();
   forward(a.sb, uy, 1);
-#pragma unroll 2
-  for (int kp = tid; kp <= M / 2; kp += NT) quad_second(kp, Pq[4 * (size_t)QH + kp], Pq[5 * (size_t)QH + kp]);
+  quad_pass(false);
 
   // z_r = IFFT_M(A_r) and the read-off of the coordinates of residue r.
   constexpr int RMX = fft_rmax(M, NT);
