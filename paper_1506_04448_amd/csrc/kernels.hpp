@@ -1883,22 +1883,31 @@ __global__ void k_unpack_entries(const unsigned long long* packed, int nnz, int3
 // Per-word sums over the documents containing the word (in document order):
 // R_i = sum_d c_d n_di p_d, g_i = sum_d c_d n_di, g'_i = sum_d c'_d n_di.
 template <typename R>
-__global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const int32_t* scnt,
-                                                    const int32_t* colptr, const R* P, const double* cd,
-                                                    const double* cpd, int V, int K, R* Rw, double* g,
-                                                    double* gp) {
-  // sdoc, scnt: document and count of each nonzero in word order.  Sixteen
-  // documents per step keep sixteen rows of P in flight (as many partial sums), and
-  // the next step's document indices are loaded with this step's rows.
-  constexpr int U = 16;
+__global__ __launch_bounds__(64) void k_word_accum(const int32_t* sdoc, const int32_t* scnt,
+                                                   const int32_t* colptr, const R* P, const double* cd,
+                                                   const double* cpd, int V, int K, R* Rw, double* g,
+                                                   double* gp) {
+  // sdoc, scnt: document and count of each nonzero in word order.  One wave
+  // per word, two columns per lane (k and k + 64), sixteen documents per step:
+  // 32 loads of P in flight per lane (sixteen partial sums per column), and the
+  // next step's document indices loaded with this step's rows.
+  constexpr int U = 16, CPT = 2;
   for (int w = blockIdx.x; w < V; w += gridDim.x) {
     const int lo = colptr[w], hi = colptr[w + 1];
-    for (int kb = 0; kb < K; kb += blockDim.x) {
-      const int k = kb + threadIdx.x;
-      const int kc = k < K ? k : K - 1;
-      double acc[U], ga = 0.0, gc = 0.0;
+    for (int kb = 0; kb < K; kb += CPT * (int)blockDim.x) {
+      int kc[CPT];
+      bool kv[CPT];
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[u] = 0.0;
+      for (int j = 0; j < CPT; ++j) {
+        const int k = kb + (int)threadIdx.x + j * (int)blockDim.x;
+        kv[j] = k < K;
+        kc[j] = kv[j] ? k : K - 1;
+      }
+      double acc[CPT][U], ga = 0.0, gc = 0.0;
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[j][u] = 0.0;
       int dn[U], nn[U];
       auto load_idx = [&](int e0) {
 #pragma unroll
@@ -1910,7 +1919,8 @@ __global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const i
       int e = lo;
       if (e + U <= hi) load_idx(e);
       for (; e + U <= hi; e += U) {
-        double n[U], p[U], c[U], c2[U];
+        double n[U], c[U], c2[U];
+        R p[CPT][U];
         int d[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1919,14 +1929,16 @@ __global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const i
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          p[u] = (double)P[(size_t)d[u] * K + kc];
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) p[j][u] = P[(size_t)d[u] * K + kc[j]];
           c[u] = cd[d[u]];
           c2[u] = cpd[d[u]];
         }
         if (e + 2 * U <= hi) load_idx(e + U);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          acc[u] += c[u] * n[u] * p[u];
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) acc[j][u] += c[u] * n[u] * (double)p[j][u];
           ga += c[u] * n[u];
           gc += c2[u] * n[u];
         }
@@ -1935,16 +1947,20 @@ __global__ __launch_bounds__(128) void k_word_accum(const int32_t* sdoc, const i
         const int d = sdoc[e];
         const double n = (double)scnt[e];
         const double c = cd[d];
-        acc[0] += c * n * (double)P[(size_t)d * K + kc];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) acc[j][0] += c * n * (double)P[(size_t)d * K + kc[j]];
         ga += c * n;
         gc += cpd[d] * n;
       }
-      // the partial sums pairwise, in a fixed order
 #pragma unroll
-      for (int h = 1; h < U; h *= 2)
+      for (int j = 0; j < CPT; ++j) {
+        // the partial sums pairwise, in a fixed order
 #pragma unroll
-        for (int u = 0; u < U; u += 2 * h) acc[u] += acc[u + h];
-      if (k < K) Rw[(size_t)w * K + k] = (R)acc[0];
+        for (int h = 1; h < U; h *= 2)
+#pragma unroll
+          for (int u = 0; u < U; u += 2 * h) acc[j][u] += acc[j][u + h];
+        if (kv[j]) Rw[(size_t)w * K + kc[j]] = (R)acc[j][0];
+      }
       if (kb == 0 && threadIdx.x == 0) {
         g[w] = ga;
         gp[w] = gc;

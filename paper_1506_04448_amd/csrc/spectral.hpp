@@ -16,25 +16,35 @@
 
 namespace tsk {
 
-// Y = M2 X (rows w, K <= 128 columns); grid over words, 128 threads.  Sixteen
-// documents per step, with as many partial sums, keep sixteen rows of P in flight,
-// and the next step's document indices are loaded with this step's rows.
-__global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const int32_t* scnt,
-                                                      const int32_t* colptr, const double* P, const double* cpd,
-                                                      const double* invm, const double* X, const double* q,
-                                                      const double* deff, double alpha0, int V, int K, double* Y) {
+// Y = M2 X (rows w, K <= 128 columns); one wave per word, two columns per
+// lane (k and k + 64).  Sixteen documents per step, with as many partial sums
+// per column, keep 32 loads of P in flight per lane, and the next step's
+// document indices are loaded with this step's rows.
+__global__ __launch_bounds__(64) void k_lda_m2_apply(const int32_t* sdoc, const int32_t* scnt,
+                                                     const int32_t* colptr, const double* P, const double* cpd,
+                                                     const double* invm, const double* X, const double* q,
+                                                     const double* deff, double alpha0, int V, int K, double* Y) {
+  constexpr int U = 16, CPT = 2;
   const double Dk = deff[0];
   const double inv = Dk > 0.0 ? 1.0 / Dk : 0.0;
   const double a = alpha0 / (alpha0 + 1.0);
-  const int k = threadIdx.x;
-  const int kc = k < K ? k : 0;  // lanes past K read column 0 and discard it
+  int kc[CPT];
+  bool kv[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int k = (int)threadIdx.x + j * 64;
+    kv[j] = k < K;
+    kc[j] = kv[j] ? k : 0;  // lanes past K read column 0 and discard it
+  }
   for (int w = blockIdx.x; w < V; w += gridDim.x) {
     const int lo = colptr[w], hi = colptr[w + 1];
-    const double xw = X[(size_t)w * K + kc];
-    constexpr int U = 16;
-    double acc[U], m1 = 0.0;
+    double xw[CPT], acc[CPT][U], m1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    for (int j = 0; j < CPT; ++j) {
+      xw[j] = X[(size_t)w * K + kc[j]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[j][u] = 0.0;
+    }
     int dn[U], nn[U];
     auto load_idx = [&](int e0) {
 #pragma unroll
@@ -47,7 +57,7 @@ __global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const
     if (e + U <= hi) load_idx(e);
     for (; e + U <= hi; e += U) {
       int d[U];
-      double n[U], p[U], c[U], im[U];
+      double n[U], p[CPT][U], c[U], im[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         d[u] = dn[u];
@@ -55,7 +65,8 @@ __global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        p[u] = P[(size_t)d[u] * K + kc];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) p[j][u] = P[(size_t)d[u] * K + kc[j]];
         c[u] = cpd[d[u]];
         im[u] = invm[d[u]];
       }
@@ -63,21 +74,26 @@ __global__ __launch_bounds__(128) void k_lda_m2_apply(const int32_t* sdoc, const
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         m1 += im[u] * n[u];
-        acc[u] += c[u] * n[u] * (p[u] - xw);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) acc[j][u] += c[u] * n[u] * (p[j][u] - xw[j]);
       }
     }
     for (; e < hi; ++e) {
       const int d = sdoc[e];
       const double n = (double)scnt[e];
       m1 += invm[d] * n;
-      acc[0] += cpd[d] * n * (P[(size_t)d * K + kc] - xw);
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) acc[j][0] += cpd[d] * n * (P[(size_t)d * K + kc[j]] - xw[j]);
     }
-    // the partial sums pairwise, in a fixed order
 #pragma unroll
-    for (int h = 1; h < U; h *= 2)
+    for (int j = 0; j < CPT; ++j) {
+      // the partial sums pairwise, in a fixed order
 #pragma unroll
-      for (int u = 0; u < U; u += 2 * h) acc[u] += acc[u + h];
-    if (k < K) Y[(size_t)w * K + k] = acc[0] * inv - a * (m1 * inv) * q[k];
+      for (int h = 1; h < U; h *= 2)
+#pragma unroll
+        for (int u = 0; u < U; u += 2 * h) acc[j][u] += acc[j][u + h];
+      if (kv[j]) Y[(size_t)w * K + kc[j]] = acc[j][0] * inv - a * (m1 * inv) * q[kc[j]];
+    }
   }
 }
 

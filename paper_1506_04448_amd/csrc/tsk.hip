@@ -1813,7 +1813,7 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   int32_t *sdoc = (int32_t*)at(10), *scnt = (int32_t*)at(7);
   TSK_TRY(word_order(rowptr, col, cnt, D, V, nnz, (unsigned long long*)at(7), (unsigned long long*)at(8),
                      (uint32_t*)at(9), at(11), sort_tmp, colptr, sdoc, scnt, st));
-  hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)sdoc,
+  hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 16384)), dim3(64), 0, st, (const int32_t*)sdoc,
                      (const int32_t*)scnt, (const int32_t*)colptr, (const R*)P, (const double*)cd,
                      (const double*)cpd, V, K, Rw, g, gp);
   TSK_TRY(check_launch("k_word_accum"));
@@ -3029,7 +3029,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
                        (const double*)invm, D, K, per_q, qpart);
     hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(K + 1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
     TSK_TRY(check_launch("k_doc_q"));
-    hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, (const int32_t*)sdoc,
+    hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 16384)), dim3(64), 0, st, (const int32_t*)sdoc,
                        (const int32_t*)scnt, (const int32_t*)colptr, (const double*)P, (const double*)cpd,
                        (const double*)invm, X, (const double*)q, (const double*)deff, alpha0, V, K, Yout);
     return check_launch("k_lda_m2_apply");
