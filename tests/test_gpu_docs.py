@@ -45,7 +45,11 @@ def _dev(C):
                                             (150, 80, 9, 6.0, 8192, 2, np.float64),
                                             # the LDA workload's sketch shape: K = 100, b = 16384, B = 8
                                             (12, 300, 100, 40.0, 16384, 8, np.float32),
-                                            (12, 300, 100, 40.0, 16384, 8, np.float64)])
+                                            (12, 300, 100, 40.0, 16384, 8, np.float64),
+                                            # the largest K the build takes (two column groups of the
+                                            # moment route's word product, 129 columns for its documents)
+                                            (6, 130, 128, 12.0, 1024, 2, np.float32),
+                                            (6, 130, 128, 12.0, 1024, 2, np.float64)])
 @pytest.mark.parametrize("route", [1, 2])
 def test_docs_build_matches_oracle(ctx, D, V, K, L, b, B, dt, route):
     print(f"docs D={D} V={V} K={K} b={b} B={B} {np.dtype(dt).name} route {route}", flush=True)
