@@ -62,7 +62,8 @@ __device__ inline int moment_pair_b(int p) {
 // columns c < K are needed only for c >= b (the tensor is symmetric, the
 // assembly reads them with sorted indices), so a wave leaves out the column
 // tiles below the smallest b of its rows.  Rows past np compute on pair
-// (0, 0) and are never read back; left-out tiles are not written.  The next
+// (0, 0) and are never read back; left-out tiles are written as zeros, so
+// every partial the chunk sums read is defined.  The next
 // stage's items are loaded while the current one runs, and B is formed from
 // the staged x (and y) at each step.
 template <typename R, bool HAS_Y>
@@ -194,12 +195,10 @@ __global__ __launch_bounds__(256) void k_moment3(MomentArgs a) {
   for (int rt = 0; rt < kMomRT; ++rt) {
     const int rbase = rb * kMomRows + (wave * kMomRT + rt) * 16;
 #pragma unroll
-    for (int ct = 0; ct < kMomCT; ++ct) {
-      if (act & (1u << ct)) {
-        const int c = c0 + ct * 16 + r16;
+    for (int ct = 0; ct < kMomCT; ++ct) {  // left-out tiles hold their zeros
+      const int c = c0 + ct * 16 + r16;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[(size_t)(rbase + kq + 4 * v) * a.ld + c] = acc[rt][ct][v];
-      }
+      for (int v = 0; v < 4; ++v) out[(size_t)(rbase + kq + 4 * v) * a.ld + c] = acc[rt][ct][v];
     }
   }
 }
