@@ -383,6 +383,8 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
         by_route[name] = {"build_ms": min(tr),
                           "sketch_rel_diff_vs_default": float((S64 - S64_0).norm() / S64_0.norm())}
     tsk.docs_route(ctx, 0)
+    # the route the cost rule took: the one whose sketch the default build reproduces
+    default_route = min(by_route, key=lambda r: by_route[r]["sketch_rel_diff_vs_default"])
     td = []
     for r in range(nrep + 1):
         S64.copy_(S64_0)
@@ -457,7 +459,7 @@ def c4_docs(ctx, dev, D: int, nrep: int = 3):
                      f"decomposition k={K}, L={L}, T={T}"),
         "documents": D, "nnz": nnz, "words": int(C.cnt.sum()), "corpus_generation_s": gen_s,
         "build_ms": build_ms, "documents_per_s": D / (build_ms * 1e-3),
-        "build_by_route": by_route,
+        "build_by_route": by_route, "build_route_default": default_route,
         "decompose_ms": dec_ms, "sketch_updates_per_s": updates / (dec_ms * 1e-3),
         "topics_matched_0.9": matched,
         "data_whitening_ms": 1e3 * (t1 - t0),
