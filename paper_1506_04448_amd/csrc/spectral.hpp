@@ -97,14 +97,51 @@ __global__ __launch_bounds__(64) void k_lda_m2_apply(const int32_t* sdoc, const 
   }
 }
 
-// G[r][c] = sum_w X[w][r] Y[w][c] (X, Y: [V][K]); grid (K, K), 256 threads.
-__global__ __launch_bounds__(256) void k_gram2(const double* X, const double* Y, double* G, int V, int K) {
-  __shared__ double red[4];
-  const int r = blockIdx.x, c = blockIdx.y;
+// Partial Gram products over word chunks: part[z][r][c] = sum over the words
+// w of chunk z of X[w][r] Y[w][c] (X, Y: [V][K]); work-group (16 x 16 tile of
+// G, chunk z), the chunk's rows staged 64 at a time in LDS from clamped
+// addresses (all loads in flight together), each entry summed in word order.
+__global__ __launch_bounds__(256) void k_gram2(const double* X, const double* Y, double* part, int V, int K,
+                                               int Z) {
+  constexpr int TW = 64;
+  __shared__ double xs[TW][16], ys[TW][16];
+  const int r0 = blockIdx.x * 16, c0 = blockIdx.y * 16, z = blockIdx.z;
+  const int per = (V + Z - 1) / Z, w_lo = z * per, w_hi = min(V, w_lo + per);
+  const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
   double s = 0.0;
-  for (int w = threadIdx.x; w < V; w += 256) s += X[(size_t)w * K + r] * Y[(size_t)w * K + c];
-  const double g = block_sum<256>(s, red);
-  if (threadIdx.x == 0) G[(size_t)r * K + c] = g;
+  for (int w0 = w_lo; w0 < w_hi; w0 += TW) {
+    __syncthreads();  // the previous stage's readers are done
+    double vx[TW * 16 / 256], vy[TW * 16 / 256];
+#pragma unroll
+    for (int u = 0; u < TW * 16 / 256; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int w = min(w0 + (e >> 4), V - 1), q = e & 15;
+      vx[u] = X[(size_t)w * K + min(r0 + q, K - 1)];
+      vy[u] = Y[(size_t)w * K + min(c0 + q, K - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < TW * 16 / 256; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const bool ok = w0 + (e >> 4) < w_hi;
+      xs[e >> 4][e & 15] = ok ? vx[u] : 0.0;
+      ys[e >> 4][e & 15] = ok ? vy[u] : 0.0;
+    }
+    __syncthreads();
+    const int nw = min(TW, w_hi - w0);
+    for (int t = 0; t < nw; ++t) s += xs[t][i] * ys[t][j];
+  }
+  const int r = r0 + i, c = c0 + j;
+  if (r < K && c < K) part[((size_t)z * K + r) * K + c] = s;
+}
+
+// G = the sum of the chunk partials, in chunk order.
+__global__ void k_gram2_sum(const double* part, int Z, int K, double* G) {
+  const size_t kk = (size_t)K * K;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < kk; e += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < Z; ++z) s += part[(size_t)z * kk + e];
+    G[e] = s;
+  }
 }
 
 // Eigenpairs of the symmetric part of the k x k matrix G (k <= 100), one

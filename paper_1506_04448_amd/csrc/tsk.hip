@@ -141,7 +141,7 @@ namespace {
 enum WsId {
   WS_PARTIAL = 0, WS_STIME, WS_PROD, WS_U, WS_V, WS_LAMPER, WS_LAMMED, WS_CNT, WS_FLAGS,
   WS_UHAT, WS_LAM64, WS_U0, WS_LAMHAT, WS_AMAX, WS_V3, WS_R64, WS_R32, WS_LAMD, WS_UD, WS_BATCH,
-  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE, WS_HELD, WS_SYMSPLIT
+  WS_DOCS, WS_SPLIT, WS_SPLITP, WS_ALS, WS_SYM, WS_LDA, WS_LDAR, WS_TUNE, WS_HELD, WS_SYMSPLIT, WS_GRAM
 };
 
 void clear_graphs(tsk_ctx* c) {
@@ -1610,6 +1610,20 @@ tsk_status launch_mode_spectra(int logb, tsk_tables_t tab, const double* q, cons
   return tsk::fail(TSK_EUNSUPPORTED, "document sketch: b=2^%d not built", logb);
 }
 
+// G = X^T Y for X, Y: [V][K] in FP64: 16 x 16 tiles over word chunks (about
+// 512 words each, at most 32), the chunks' partials summed in chunk order.
+tsk_status gram2(tsk_ctx_t ctx, const double* X, const double* Y, double* G, int V, int K, hipStream_t st) {
+  const int nt = (K + 15) / 16;
+  const int Z = std::max(1, std::min(32, V / 512));
+  void* part = nullptr;
+  TSK_TRY(ws_get(ctx, WS_GRAM, (size_t)Z * K * K * sizeof(double), &part));
+  hipLaunchKernelGGL(tsk::k_gram2, dim3(nt, nt, Z), dim3(256), 0, st, X, Y, (double*)part, V, K, Z);
+  TSK_TRY(check_launch("k_gram2"));
+  hipLaunchKernelGGL(tsk::k_gram2_sum, dim3(grid_for((size_t)K * K, 256)), dim3(256), 0, st, (const double*)part,
+                     Z, K, G);
+  return check_launch("k_gram2_sum");
+}
+
 // Bit width of the word ids 0..V-1: the radix sort by word reads only those bits.
 int word_bits(int V) {
   int b = 1;
@@ -3036,8 +3050,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   };
   // Q = orth(Yin)
   auto orth = [&](const double* Yin, double* Qout) -> tsk_status {
-    hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, Yin, Yin, Gm, V, K);
-    TSK_TRY(check_launch("k_gram2"));
+    TSK_TRY(gram2(ctx, Yin, Yin, Gm, V, K, st));
     TSK_TRY(jacobi_eig(Gm, K, E, dv, st));
     hipLaunchKernelGGL(tsk::k_orth_apply, dim3(std::min(V, 8192)), dim3(128), 0, st, Yin, (const double*)E,
                        (const double*)dv, Qout, V, K);
@@ -3050,8 +3063,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   }
   TSK_TRY(orth(Y, Q));
   TSK_TRY(apply(Q, Y));
-  hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, (const double*)Q, (const double*)Y, Gm, V, K);
-  TSK_TRY(check_launch("k_gram2"));
+  TSK_TRY(gram2(ctx, (const double*)Q, (const double*)Y, Gm, V, K, st));
   TSK_TRY(jacobi_eig(Gm, K, E, dv, st));
   hipLaunchKernelGGL(tsk::k_whiten_out, dim3(std::min(V, 8192)), dim3(128), 0, st, (const double*)Q,
                      (const double*)E, (const double*)dv, W_out, sigma_out, V, K);
@@ -3082,8 +3094,7 @@ extern "C" tsk_status tsk_lda_heldout(tsk_ctx_t ctx, const int32_t* rowptr, cons
   double* cd = (double*)((char*)base + gb + pb);
   double* cpd = (double*)((char*)base + gb + pb + db);
   double* invm = (double*)((char*)base + gb + pb + 2 * db);
-  hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, Phi, Phi, Gm, V, K);
-  TSK_TRY(check_launch("k_gram2"));
+  TSK_TRY(gram2(ctx, Phi, Phi, Gm, V, K, st));
   hipLaunchKernelGGL(tsk::k_doc_project<double>, dim3(std::min((D + 15) / 16, 8192)), dim3(256), 0, st, rowptr,
                      col, cnt, D, K, Phi, P, cd, cpd, invm);
   TSK_TRY(check_launch("k_doc_project"));
@@ -3116,8 +3127,7 @@ extern "C" tsk_status tsk_lda_recover(tsk_ctx_t ctx, int V, int K, int k, double
   double* E = (double*)((char*)base + kk);
   double* dv = (double*)((char*)base + 2 * kk);
   double* t = (double*)((char*)base + 2 * kk + kv);
-  hipLaunchKernelGGL(tsk::k_gram2, dim3(K, K), dim3(256), 0, st, W, W, Gm, V, K);
-  TSK_TRY(check_launch("k_gram2"));
+  TSK_TRY(gram2(ctx, W, W, Gm, V, K, st));
   TSK_TRY(jacobi_eig(Gm, K, E, dv, st));
   hipLaunchKernelGGL(tsk::k_lda_tvec, dim3(k), dim3(128), 0, st, (const double*)E, (const double*)dv, U, K, t);
   TSK_TRY(check_launch("k_lda_tvec"));
