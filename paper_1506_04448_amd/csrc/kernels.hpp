@@ -799,32 +799,50 @@ __device__ inline void jacobi_sweeps(double* A, double* E, int k, double* red) {
         rs[tid] = s;
       }
       __syncthreads();
-      // A <- J^T A J: columns p, q of A and of E, every pair at once ...
+      // A <- J^T A J over the 2 x 2 blocks (rows of pair i, columns of pair
+      // j), every block at once: the column rotation of pair j, then the row
+      // rotation of pair i on its result; E <- E J.  One pass, so a round
+      // takes two barriers.
+      for (int e = tid; e < np * np; e += 256) {
+        const int i = e / np, j = e - i * np;
+        const double si = rs[i], sj = rs[j];
+        if (si == 0.0 && sj == 0.0) continue;
+        const int p = rp[i], q = rq[i], u = rp[j], v = rq[j];
+        const bool qi = q < k, vj = v < k;  // a dummy player has no row / column
+        double apu = A[p * k + u], apv = vj ? A[p * k + v] : 0.0;
+        double aqu = qi ? A[q * k + u] : 0.0, aqv = (qi && vj) ? A[q * k + v] : 0.0;
+        if (sj != 0.0) {
+          const double cj = rc[j];
+          const double tpu = cj * apu - sj * apv, tpv = sj * apu + cj * apv;
+          const double tqu = cj * aqu - sj * aqv, tqv = sj * aqu + cj * aqv;
+          apu = tpu;
+          apv = tpv;
+          aqu = tqu;
+          aqv = tqv;
+        }
+        if (si != 0.0) {
+          const double ci = rc[i];
+          const double npu = ci * apu - si * aqu, nqu = si * apu + ci * aqu;
+          const double npv = ci * apv - si * aqv, nqv = si * apv + ci * aqv;
+          apu = npu;
+          aqu = nqu;
+          apv = npv;
+          aqv = nqv;
+        }
+        A[p * k + u] = apu;
+        if (vj) A[p * k + v] = apv;
+        if (qi) A[q * k + u] = aqu;
+        if (qi && vj) A[q * k + v] = aqv;
+      }
       for (int e = tid; e < np * k; e += 256) {
-        const int i = e / k, r = e - i * k;
-        const double s = rs[i];
+        const int j = e / k, r = e - j * k;
+        const double s = rs[j];
         if (s != 0.0) {
-          const double c = rc[i];
-          const int p = rp[i], q = rq[i];
-          const double ap = A[r * k + p], aq = A[r * k + q];
-          A[r * k + p] = c * ap - s * aq;
-          A[r * k + q] = s * ap + c * aq;
+          const double c = rc[j];
+          const int p = rp[j], q = rq[j];
           const double ep = E[r * k + p], eq = E[r * k + q];
           E[r * k + p] = c * ep - s * eq;
           E[r * k + q] = s * ep + c * eq;
-        }
-      }
-      __syncthreads();
-      // ... then rows p, q of A
-      for (int e = tid; e < np * k; e += 256) {
-        const int i = e / k, r = e - i * k;
-        const double s = rs[i];
-        if (s != 0.0) {
-          const double c = rc[i];
-          const int p = rp[i], q = rq[i];
-          const double ap = A[p * k + r], aq = A[q * k + r];
-          A[p * k + r] = c * ap - s * aq;
-          A[q * k + r] = s * ap + c * aq;
         }
       }
       __syncthreads();
