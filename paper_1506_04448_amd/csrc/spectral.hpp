@@ -16,14 +16,22 @@
 
 namespace tsk {
 
+// wk[d] = (cpd[d], invm[d]): the two per-document weights of M2 X in one
+// 16-byte word, so that a document costs one load of them, not two.
+__global__ void k_pack_doc_weights(const double* cpd, const double* invm, int D, double2* wk) {
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < D; d += gridDim.x * blockDim.x)
+    wk[d] = make_double2(cpd[d], invm[d]);
+}
+
 // Y = M2 X (rows w, K <= 128 columns); one wave per word, two columns per
 // lane (k and k + 64).  Sixteen documents per step, with as many partial sums
 // per column, keep 32 loads of P in flight per lane, and the next step's
-// document indices are loaded with this step's rows.
+// document indices are loaded with this step's rows.  wk: the packed
+// per-document weights (c'_d, 1/m_d) of k_pack_doc_weights.
 __global__ __launch_bounds__(64) void k_lda_m2_apply(const int32_t* sdoc, const int32_t* scnt,
-                                                     const int32_t* colptr, const double* P, const double* cpd,
-                                                     const double* invm, const double* X, const double* q,
-                                                     const double* deff, double alpha0, int V, int K, double* Y) {
+                                                     const int32_t* colptr, const double* P, const double2* wk,
+                                                     const double* X, const double* q, const double* deff,
+                                                     double alpha0, int V, int K, double* Y) {
   constexpr int U = 16, CPT = 2;
   const double Dk = deff[0];
   const double inv = Dk > 0.0 ? 1.0 / Dk : 0.0;
@@ -67,8 +75,9 @@ __global__ __launch_bounds__(64) void k_lda_m2_apply(const int32_t* sdoc, const 
       for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int j = 0; j < CPT; ++j) p[j][u] = P[(size_t)d[u] * K + kc[j]];
-        c[u] = cpd[d[u]];
-        im[u] = invm[d[u]];
+        const double2 wd = wk[d[u]];
+        c[u] = wd.x;
+        im[u] = wd.y;
       }
       if (e + 2 * U <= hi) load_idx(e + U);  // the next step's indices, with this step's rows
 #pragma unroll
@@ -81,9 +90,10 @@ __global__ __launch_bounds__(64) void k_lda_m2_apply(const int32_t* sdoc, const 
     for (; e < hi; ++e) {
       const int d = sdoc[e];
       const double n = (double)scnt[e];
-      m1 += invm[d] * n;
+      const double2 wd = wk[d];
+      m1 += wd.y * n;
 #pragma unroll
-      for (int j = 0; j < CPT; ++j) acc[j][0] += cpd[d] * n * (P[(size_t)d * K + kc[j]] - xw[j]);
+      for (int j = 0; j < CPT; ++j) acc[j][0] += wd.x * n * (P[(size_t)d * K + kc[j]] - xw[j]);
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {

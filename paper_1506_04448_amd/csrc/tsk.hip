@@ -3021,6 +3021,7 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
   take((size_t)K * K * 8);          // 16 eigenvectors
   take((size_t)K * 8);              // 17 eigenvalues
   take((size_t)nnz * 4 + 4);        // 18 counts in word order
+  take((size_t)D * 16);             // 19 packed (cpd, invm) per document
   void* base = nullptr;
   TSK_TRY(ws_get(ctx, WS_LDA, off, &base));
   auto at = [&](int i) { return reinterpret_cast<char*>(base) + offs[i]; };
@@ -3043,9 +3044,13 @@ extern "C" tsk_status tsk_lda_whiten(tsk_ctx_t ctx, const int32_t* rowptr, const
                        (const double*)invm, D, K, per_q, qpart);
     hipLaunchKernelGGL(tsk::k_doc_q_final, dim3(K + 1), dim3(256), 0, st, (const double*)qpart, G, K, q, deff);
     TSK_TRY(check_launch("k_doc_q"));
+    double2* wk = (double2*)at(19);
+    hipLaunchKernelGGL(tsk::k_pack_doc_weights, dim3(grid_for((size_t)D, 256)), dim3(256), 0, st,
+                       (const double*)cpd, (const double*)invm, D, wk);
+    TSK_TRY(check_launch("k_pack_doc_weights"));
     hipLaunchKernelGGL(tsk::k_lda_m2_apply, dim3(std::min(V, 16384)), dim3(64), 0, st, (const int32_t*)sdoc,
-                       (const int32_t*)scnt, (const int32_t*)colptr, (const double*)P, (const double*)cpd,
-                       (const double*)invm, X, (const double*)q, (const double*)deff, alpha0, V, K, Yout);
+                       (const int32_t*)scnt, (const int32_t*)colptr, (const double*)P, (const double2*)wk, X,
+                       (const double*)q, (const double*)deff, alpha0, V, K, Yout);
     return check_launch("k_lda_m2_apply");
   };
   // Q = orth(Yin)
