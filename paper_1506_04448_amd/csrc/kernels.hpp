@@ -1900,11 +1900,11 @@ __global__ void k_unpack_entries(const unsigned long long* packed, int nnz, int3
 
 // Per-word sums over the documents containing the word (in document order):
 // R_i = sum_d c_d n_di p_d, g_i = sum_d c_d n_di, g'_i = sum_d c'_d n_di.
+// wcd[d] = (c_d, c'_d), packed so that a document costs one load of them.
 template <typename R>
 __global__ __launch_bounds__(64) void k_word_accum(const int32_t* sdoc, const int32_t* scnt,
-                                                   const int32_t* colptr, const R* P, const double* cd,
-                                                   const double* cpd, int V, int K, R* Rw, double* g,
-                                                   double* gp) {
+                                                   const int32_t* colptr, const R* P, const double2* wcd,
+                                                   int V, int K, R* Rw, double* g, double* gp) {
   // sdoc, scnt: document and count of each nonzero in word order.  One wave
   // per word, two columns per lane (k and k + 64), sixteen documents per step:
   // 32 loads of P in flight per lane (sixteen partial sums per column), and the
@@ -1949,8 +1949,9 @@ __global__ __launch_bounds__(64) void k_word_accum(const int32_t* sdoc, const in
         for (int u = 0; u < U; ++u) {
 #pragma unroll
           for (int j = 0; j < CPT; ++j) p[j][u] = P[(size_t)d[u] * K + kc[j]];
-          c[u] = cd[d[u]];
-          c2[u] = cpd[d[u]];
+          const double2 wd = wcd[d[u]];
+          c[u] = wd.x;
+          c2[u] = wd.y;
         }
         if (e + 2 * U <= hi) load_idx(e + U);
 #pragma unroll
@@ -1964,11 +1965,12 @@ __global__ __launch_bounds__(64) void k_word_accum(const int32_t* sdoc, const in
       for (; e < hi; ++e) {
         const int d = sdoc[e];
         const double n = (double)scnt[e];
-        const double c = cd[d];
+        const double2 wd = wcd[d];
+        const double c = wd.x;
 #pragma unroll
         for (int j = 0; j < CPT; ++j) acc[j][0] += c * n * (double)P[(size_t)d * K + kc[j]];
         ga += c * n;
-        gc += cpd[d] * n;
+        gc += wd.y * n;
       }
 #pragma unroll
       for (int j = 0; j < CPT; ++j) {

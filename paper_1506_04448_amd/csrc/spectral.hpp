@@ -16,11 +16,12 @@
 
 namespace tsk {
 
-// wk[d] = (cpd[d], invm[d]): the two per-document weights of M2 X in one
-// 16-byte word, so that a document costs one load of them, not two.
-__global__ void k_pack_doc_weights(const double* cpd, const double* invm, int D, double2* wk) {
+// wk[d] = (w0[d], w1[d]): two per-document weights in one 16-byte word, so
+// that a document costs one load of them, not two (the weights (c'_d, 1/m_d)
+// of M2 X here, (c_d, c'_d) of the document build's per-word sums).
+__global__ void k_pack_doc_weights(const double* w0, const double* w1, int D, double2* wk) {
   for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < D; d += gridDim.x * blockDim.x)
-    wk[d] = make_double2(cpd[d], invm[d]);
+    wk[d] = make_double2(w0[d], w1[d]);
 }
 
 // Y = M2 X (rows w, K <= 128 columns); one wave per word, two columns per

@@ -1803,6 +1803,7 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   take(moment ? (size_t)ms.np * (K + 1) * 8 : 0);           // 21 Cd
   take(moment ? (size_t)ms.np * (2 * K + 1) * 8 : 0);       // 22 Cw
   take(moment ? (size_t)K * K * K * 8 : 0);                 // 23 the K^3 tensor
+  take((size_t)D * 16);                                     // 24 packed (cd, cpd) per document
   void* base = nullptr;
   TSK_TRY(ws_get(ctx, WS_DOCS, off, &base));
   auto at = [&](int i) { return reinterpret_cast<char*>(base) + offs[i]; };
@@ -1827,9 +1828,13 @@ tsk_status build_docs_impl(tsk_ctx_t ctx, tsk_tables_t tab, const int32_t* rowpt
   int32_t *sdoc = (int32_t*)at(10), *scnt = (int32_t*)at(7);
   TSK_TRY(word_order(rowptr, col, cnt, D, V, nnz, (unsigned long long*)at(7), (unsigned long long*)at(8),
                      (uint32_t*)at(9), at(11), sort_tmp, colptr, sdoc, scnt, st));
+  double2* wcd = (double2*)at(24);
+  hipLaunchKernelGGL(tsk::k_pack_doc_weights, dim3(grid_for((size_t)D, 256)), dim3(256), 0, st, (const double*)cd,
+                     (const double*)cpd, D, wcd);
+  TSK_TRY(check_launch("k_pack_doc_weights"));
   hipLaunchKernelGGL(tsk::k_word_accum<R>, dim3(std::min(V, 16384)), dim3(64), 0, st, (const int32_t*)sdoc,
-                     (const int32_t*)scnt, (const int32_t*)colptr, (const R*)P, (const double*)cd,
-                     (const double*)cpd, V, K, Rw, g, gp);
+                     (const int32_t*)scnt, (const int32_t*)colptr, (const R*)P, (const double2*)wcd, V, K, Rw, g,
+                     gp);
   TSK_TRY(check_launch("k_word_accum"));
   const double a = alpha0 / (alpha0 + 2.0);
   const double c3 = 2.0 * alpha0 * alpha0 / ((alpha0 + 1.0) * (alpha0 + 2.0));
